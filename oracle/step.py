@@ -1,0 +1,243 @@
+"""One IMEX step of the spherical QG equations, integration method + tau
+(oracle; test infrastructure only).
+
+Equations (paper Sect. 2 and 3.2), no Ekman pumping:
+  Psi, m >= 1 (eq. psi_int):
+    d/dt A_m Psi - B_m Psi = C [ (Ra/Pr)(i m/s_o) theta_m + N_omega,m ]
+  theta, m >= 0 (eq. temp_int):
+    d/dt D theta - (1/Pr) F_m theta = -D [ i m (h^2/s dTc/ds Psi)_m + N_theta,m ]
+  zonal flow (eq. uphi_int):
+    d/dt D u - E u = -D [ N_uphi ],   N_uphi = mean over phi of u_s omega
+with tau boundary rows on top of every matrix.
+
+Readings (where the paper is silent or inconsistent):
+  * Nonlinear terms are evaluated pointwise on the (s, phi) grid.  By QG
+    continuity (eq. cont) div(u f) = u.grad f - beta u_s f, and
+    -beta u_s = dPsi/dphi exactly (beta h^2/s = -1), so
+      N_omega = u_s d_s omega + (u_phi/s) d_phi omega + omega dPsi/dphi,
+      N_theta = u_s (d_s theta + dTc/ds) + (u_phi/s) d_phi theta,
+    the second one carrying the background advection u_s dTc/ds of eq. temp.
+  * Buoyancy and background advection are explicit (allowed by Sect. 4).
+  * Chebyshev coefficients n >= N_c of every nonlinear term are zeroed
+    (radial dealiasing, Sect. 3.2.1); N_c = floor(2(N_r-1)/3) by default.
+  * Multistep schemes carry the mass matrix (A_m or D) on both sides of
+    eq. (multistep1), as the paper shows for the DIRK case (Sect. 4).
+  * CNAB2 starts with E^{n-1} := E^n.
+  * BPR353: the tableau of Boscarino, Pareschi & Russo (2013, Sect. 8.3),
+    five stages, a_ii = 1/2, first stage explicit, stiffly accurate.
+"""
+import numpy as np
+
+from . import grid, transforms as tr
+from .bordered import BorderedSolver
+from .operators import (D1, IntegrationOperators, bordered_lhs, evaluate_op,
+                        mono, mult, op_compose, qg_operators,
+                        tau_rows_dirichlet, tau_rows_psi)
+
+# CNAB2 (Sect. 4, eq. multistep1): a = (1, 0), b^I = (1/2, 1/2),
+# b^E = (3/2, -1/2).
+CNAB2_BI0 = 0.5
+
+# BPR353 Butcher tables (explicit A^E, implicit A^I), stiffly accurate.
+BPR353_AE = np.array([[0, 0, 0, 0, 0],
+                      [1, 0, 0, 0, 0],
+                      [4 / 9, 2 / 9, 0, 0, 0],
+                      [1 / 4, 0, 3 / 4, 0, 0],
+                      [1 / 4, 0, 3 / 4, 0, 0]], dtype=np.float64)
+BPR353_AI = np.array([[0, 0, 0, 0, 0],
+                      [1 / 2, 1 / 2, 0, 0, 0],
+                      [5 / 18, -1 / 9, 1 / 2, 0, 0],
+                      [1 / 2, 0, 0, 1 / 2, 0],
+                      [1 / 4, 0, 3 / 4, -1 / 2, 1 / 2]], dtype=np.float64)
+
+
+class QGOracle:
+    def __init__(self, E, Ra, Pr, eta, n_phi, n_r, n_c=None):
+        if n_phi % 3:
+            raise ValueError("N_phi must be a multiple of 3 (N_m = N_phi/3)")
+        self.E, self.Ra, self.Pr, self.eta = E, Ra, Pr, eta
+        self.n_phi, self.n_r = n_phi, n_r
+        self.M = n_phi // 3 + 1
+        self.K = (2 * (n_r - 1)) // 3 if n_c is None else n_c
+        self.s_i, self.s_o = grid.radii(eta)
+        self.s = grid.s_nodes(eta, n_r)
+        self.h2 = self.s_o**2 - self.s**2
+        self.dtc = grid.dtc_ds(self.s, eta)
+        self.mvec = np.arange(self.M)
+        self.ops = IntegrationOperators(eta, self.K)
+        defs = qg_operators(eta)
+        self.L_I = defs["L_I"]
+        self.dL_I = op_compose(D1, self.L_I)
+        # zonal vorticity omega_0 = (1/s) d(s u)/ds and its s-derivative
+        self.om0 = op_compose(mult(mono(-1)), op_compose(D1, mult(mono(1))))
+        self.dom0 = op_compose(D1, self.om0)
+        self.bc_psi = tau_rows_psi(self.K)
+        self.bc_dir = tau_rows_dirichlet(self.K)
+        self._factors = {}
+        self.t = 0.0
+        self.nstep = 0
+        self._hist = None
+
+    # ---------------------------------------------------------------- state
+    def set_state(self, psi, theta, uphi0):
+        self.psi = np.array(psi, np.complex128, copy=True)
+        self.theta = np.array(theta, np.complex128, copy=True)
+        self.uphi = np.array(uphi0, np.float64, copy=True)
+        self._hist = None
+
+    # ------------------------------------------------------------ operators
+    def mass(self, psi, theta, uphi):
+        o = self.ops
+        mp = np.zeros_like(psi)
+        for m in range(1, self.M):
+            mp[m] = o.A(m) @ psi[m]
+        return mp, theta @ o.D.T, o.D @ uphi
+
+    def linear(self, psi, theta, uphi):
+        """Implicit operator L y: B_m Psi, F_m theta / Pr, E u."""
+        o = self.ops
+        lp = np.zeros_like(psi)
+        lt = np.zeros_like(theta)
+        for m in range(self.M):
+            if m:
+                lp[m] = o.B(m, self.E) @ psi[m]
+            lt[m] = o.F(m) @ theta[m] / self.Pr
+        return lp, lt, o.E @ uphi
+
+    def factor(self, a_dt):
+        """Bordered LU of (mass - a dt L) for every m (Appendix A)."""
+        key = float(a_dt)
+        if key in self._factors:
+            return self._factors[key]
+        o = self.ops
+        fp = [None]
+        for m in range(1, self.M):
+            fp.append(BorderedSolver(
+                bordered_lhs(self.bc_psi, o.A(m) - a_dt * o.B(m, self.E)), 4))
+        ft = [BorderedSolver(bordered_lhs(
+            self.bc_dir, o.D - a_dt * o.F(m) / self.Pr), 2)
+            for m in range(self.M)]
+        fu = BorderedSolver(bordered_lhs(self.bc_dir, o.D - a_dt * o.E), 2)
+        self._factors = {key: (fp, ft, fu)}
+        return self._factors[key]
+
+    def solve(self, a_dt, rp, rt, ru):
+        fp, ft, fu = self.factor(a_dt)
+        rp = rp.copy()
+        rt = rt.copy()
+        ru = ru.copy()
+        rp[:, :4] = 0
+        rt[:, :2] = 0
+        ru[:2] = 0
+        psi = np.zeros_like(rp)
+        for m in range(1, self.M):
+            psi[m] = fp[m].solve(rp[m])
+        theta = np.stack([ft[m].solve(rt[m]) for m in range(self.M)])
+        theta[0] = theta[0].real
+        return psi, theta, fu.solve(ru)
+
+    # ------------------------------------------------------- explicit terms
+    def spectral_fields(self, psi, theta, uphi):
+        """Fourier coefficients on the radial grid, arrays (M, N_r): u_s,
+        u_phi, omega, d_s omega, theta, d_s theta, dPsi/dphi."""
+        R = self.n_r
+        s = self.s[None, :]
+        m = self.mvec[:, None]
+        P = [tr.cheb_to_grid(tr.cheb_ds(psi, p), R) for p in range(4)]
+        T = [tr.cheb_to_grid(tr.cheb_ds(theta, p), R) for p in range(2)]
+        U = [tr.cheb_to_grid(tr.cheb_ds(uphi, p), R) for p in range(3)]
+        im = 1j * m
+        us = (self.h2 / self.s)[None, :] * im * P[0]
+        uph = -self.h2[None, :] * P[1] + 3.0 * s * P[0]
+        uph[0] += U[0]
+        om = -evaluate_op(self.L_I, m, P, s)
+        dom = -evaluate_op(self.dL_I, m, P, s)
+        om[0] += evaluate_op(self.om0, 0, U, self.s)
+        dom[0] += evaluate_op(self.dom0, 0, U, self.s)
+        return dict(us=us, uphi=uph, om=om, dom=dom, th=T[0], dth=T[1],
+                    dphi_psi=im * P[0])
+
+    def explicit(self, psi, theta, uphi):
+        """Explicit right-hand sides (K-vectors, rows >= q meaningful):
+        E_psi = C[(Ra/Pr)(i m/s_o) theta + N_omega], E_theta = -D[N_theta],
+        E_u = -D[N_uphi]."""
+        f = self.spectral_fields(psi, theta, uphi)
+        M, K, n_phi = self.M, self.K, self.n_phi
+        im = 1j * self.mvec[:, None]
+
+        def to_grid(c):          # (M, R) -> (R, N_phi), eq. (fft)
+            return tr.phi_to_grid(c.T, n_phi)
+        us, uph = to_grid(f["us"]), to_grid(f["uphi"])
+        om, dom = to_grid(f["om"]), to_grid(f["dom"])
+        dpom = to_grid(im * f["om"])
+        th, dth = to_grid(f["th"]), to_grid(f["dth"])
+        dpth = to_grid(im * f["th"])
+        divu = to_grid(f["dphi_psi"])          # = -beta u_s
+        s = self.s[:, None]
+        n_om = us * dom + uph / s * dpom + om * divu
+        n_th = us * (dth + self.dtc[:, None]) + uph / s * dpth
+        n_u = np.mean(us * om, axis=1)
+
+        def to_spec(g):          # (R, N_phi) -> (M, K), eq. (ifft), (icheb)
+            return tr.grid_to_cheb(tr.grid_to_phi(g, M).T, K)
+        Nom = to_spec(n_om)
+        Nth = to_spec(n_th)
+        Nth[0] = Nth[0].real
+        Nu = tr.grid_to_cheb(n_u, K)
+        o = self.ops
+        buoy = (self.Ra / self.Pr) * im / self.s_o * theta
+        Ep = (buoy + Nom) @ o.C.T
+        Ep[0] = 0
+        Et = -(Nth @ o.D.T)
+        Eu = -(o.D @ Nu)
+        return Ep, Et, Eu
+
+    # ---------------------------------------------------------------- steps
+    def step_cnab2(self, dt):
+        y = (self.psi, self.theta, self.uphi)
+        Ex = self.explicit(*y)
+        prev = Ex if self._hist is None else self._hist
+        My = self.mass(*y)
+        Ly = self.linear(*y)
+        rhs = [My[i] + 0.5 * dt * Ly[i] + dt * (1.5 * Ex[i] - 0.5 * prev[i])
+               for i in range(3)]
+        self.psi, self.theta, self.uphi = self.solve(CNAB2_BI0 * dt, *rhs)
+        self._hist = Ex
+        self.t += dt
+        self.nstep += 1
+
+    def step_bpr353(self, dt):
+        AE, AI = BPR353_AE, BPR353_AI
+        nu = AE.shape[0]
+        y = [(self.psi, self.theta, self.uphi)]
+        My = self.mass(*y[0])
+        Ex, Ly = [], []
+        for i in range(1, nu):
+            j = i - 1
+            if np.any(AE[:, j] != 0):
+                Ex.append(self.explicit(*y[j]))
+            else:
+                Ex.append(None)
+            Ly.append(self.linear(*y[j]))
+            rhs = []
+            for f in range(3):
+                r = My[f].copy()
+                for jj in range(i):
+                    if AE[i, jj]:
+                        r = r + dt * AE[i, jj] * Ex[jj][f]
+                    if AI[i, jj]:
+                        r = r + dt * AI[i, jj] * Ly[jj][f]
+                rhs.append(r)
+            y.append(self.solve(AI[i, i] * dt, *rhs))
+        self.psi, self.theta, self.uphi = y[-1]
+        self.t += dt
+        self.nstep += 1
+
+    def step(self, dt, scheme="cnab2", n=1):
+        for _ in range(n):
+            if scheme == "cnab2":
+                self.step_cnab2(dt)
+            elif scheme == "bpr353":
+                self.step_bpr353(dt)
+            else:
+                raise ValueError(scheme)

@@ -1,0 +1,21 @@
+import os
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+
+def pytest_configure(config):
+    config.addinivalue_line(
+        "markers", "gpu: needs an MI355X (HIP device) and the built library")
+    config.addinivalue_line(
+        "markers", "slow: CPU test taking more than a few seconds")
+
+
+@pytest.fixture(scope="session")
+def rng():
+    import numpy as np
+    return np.random.Generator(np.random.PCG64(12345))

@@ -1,0 +1,183 @@
+"""Pins of the oracle's solver and time stepper against what the paper and
+the mathematics fix."""
+import numpy as np
+import pytest
+import scipy.linalg as sla
+
+from oracle import eigen, grid, transforms as tr
+from oracle.bordered import BorderedSolver
+from oracle.diagnostics import diagnostics
+from oracle.operators import bordered_lhs, tau_rows_dirichlet, tau_rows_psi
+from oracle.step import BPR353_AE, BPR353_AI, QGOracle
+from paper_1902_07092_amd import inputs
+
+# Table 3, eigen-solver row, without Ekman pumping: E = 3e-6, Ra = 1e7,
+# Pr = 0.025, eta = 0.35, m = 12.
+TAB3_TAU = 6.149994e2
+TAB3_OMEGA = -9.536952e3
+
+
+def test_bordered_solve_equals_dense():
+    o = QGOracle(1e-3, 8e4, 1.0, 0.35, 96, 33)
+    rng = np.random.Generator(np.random.PCG64(11))
+    K = o.K
+    for m in (1, 4, 32):
+        L = bordered_lhs(tau_rows_psi(K),
+                         o.ops.A(m) - 0.5e-4 * o.ops.B(m, o.E))
+        f = rng.standard_normal(K) + 1j * rng.standard_normal(K)
+        x = BorderedSolver(L, 4).solve(f)
+        # reference: dense LU of the row-equilibrated matrix (the raw tau
+        # matrix mixes rows of size ~n^6 and ~k^-4)
+        r = 1.0 / np.abs(L).max(axis=1)
+        ref = np.linalg.solve(L * r[:, None], f * r)
+        assert np.max(np.abs(x - ref)) < 1e-13 * np.abs(ref).max()
+        Lt = bordered_lhs(tau_rows_dirichlet(K), o.ops.D
+                          - 0.5e-4 * o.ops.F(m))
+        xt = BorderedSolver(Lt, 2).solve(f)
+        r = 1.0 / np.abs(Lt).max(axis=1)
+        ref = np.linalg.solve(Lt * r[:, None], f * r)
+        assert np.max(np.abs(xt - ref)) < 1e-13 * np.abs(ref).max()
+        # Fig. 1b: four full rows, then a band of 8 sub/super-diagonals
+        nz = np.argwhere(np.abs(L[4:]) > 0)
+        off = nz[:, 1] - (nz[:, 0] + 4)
+        assert off.min() == -8 and off.max() == 8
+
+
+@pytest.mark.parametrize("N", [97, 129])
+def test_collocation_eigen_matches_table3(N):
+    lam = eigen.leading(3e-6, 1e7, 0.025, 0.35, 12, N)
+    assert abs(lam.real - TAB3_TAU) < 2e-3
+    assert abs(lam.imag - TAB3_OMEGA) < 3e-3
+
+
+@pytest.mark.slow
+def test_integration_eigen_matches_table3():
+    lam = eigen.integration_leading(3e-6, 1e7, 0.025, 0.35, 12, 256)
+    assert abs(lam.real - TAB3_TAU) < 2e-3
+    assert abs(lam.imag - TAB3_OMEGA) < 3e-3
+
+
+def _eigen_state(o, m, K):
+    A, B = eigen.integration_operator(o.E, o.Ra, o.Pr, o.eta, m, K)
+    sc = 1 / np.maximum(np.abs(A).max(1), np.abs(B).max(1))
+    lam, V = sla.eig(A * sc[:, None], B * sc[:, None])
+    ok = np.isfinite(lam)
+    i = np.flatnonzero(ok)[np.argmax(lam[ok].real)]
+    v = V[:, i] * 1e-8 / np.abs(V[:, i]).max()
+    psi = np.zeros((o.M, K), complex)
+    th = np.zeros_like(psi)
+    psi[m], th[m] = v[:K], v[K:]
+    return lam[i], psi, th
+
+
+@pytest.mark.parametrize("scheme,dt,n,tol", [("bpr353", 1e-6, 30, 3e-7),
+                                             ("cnab2", 1e-7, 120, 1e-6)])
+def test_dns_growth_rate_matches_eigenvalue(scheme, dt, n, tol):
+    """Paper Sect. 6.1: a DNS started from the m = 12 eigenmode grows and
+    drifts at the eigenvalue (Table 3 compares pizza to the eigen-solver)."""
+    K = 64
+    o = QGOracle(3e-6, 1e7, 0.025, 0.35, 39, 97, K)
+    lam0, psi, th = _eigen_state(o, 12, K)
+    o.set_state(psi, th, np.zeros(K))
+    o.step(dt, scheme, n)
+    y1 = np.concatenate([o.psi[12], o.theta[12]])
+    o.step(dt, scheme, n)
+    y2 = np.concatenate([o.psi[12], o.theta[12]])
+    lam = np.log(np.vdot(y1, y2) / np.vdot(y1, y1)) / (n * dt)
+    assert abs(lam - lam0) / abs(lam0) < tol
+    # and the eigenvalue itself is the paper's to a few 1e-4 at this K
+    assert abs(lam.real - TAB3_TAU) / TAB3_TAU < 5e-4
+    assert abs(lam.imag - TAB3_OMEGA) / abs(TAB3_OMEGA) < 5e-5
+
+
+def test_bpr353_order_conditions():
+    """IMEX order-3 conditions (explicit, implicit and coupling) and the
+    stiffly accurate property (Sect. 4) of the BPR353 tables."""
+    AE, AI = BPR353_AE, BPR353_AI
+    bE, bI = AE[-1], AI[-1]
+    c = AE.sum(axis=1)
+    assert np.allclose(c, AI.sum(axis=1))
+    for b in (bE, bI):
+        assert np.isclose(b.sum(), 1)
+        assert np.isclose(b @ c, 1 / 2)
+        assert np.isclose(b @ c**2, 1 / 3)
+    for b in (bE, bI):
+        for A in (AE, AI):
+            assert np.isclose(b @ A @ c, 1 / 6)
+    assert np.allclose(np.diag(AI)[1:], 0.5) and AI[0, 0] == 0
+
+
+def _small_oracle(scale=1.0):
+    o = QGOracle(1e-3, 8e4, 1.0, 0.35, 24, 17, 10)
+    st = inputs.make_state(o.M, o.K, "decaying", 5)
+    o.set_state(100 * scale * st.psi, 1e3 * scale * st.theta,
+                np.zeros(o.K))
+    return o
+
+
+def _run(scheme, dt, T):
+    o = _small_oracle()
+    o.step(dt, scheme, int(round(T / dt)))
+    return np.concatenate([o.psi.ravel(), o.theta.ravel(), o.uphi])
+
+
+@pytest.mark.parametrize("scheme,order", [("cnab2", 2), ("bpr353", 3)])
+def test_temporal_order(scheme, order):
+    """Fig. 2: errors fall with the theoretical order of each scheme."""
+    T = 2e-3
+    ref = _run("bpr353", T / 640, T)
+    errs = [np.linalg.norm(_run(scheme, T / n, T) - ref)
+            for n in (20, 40, 80)]
+    slopes = np.log2(np.array(errs[:-1]) / np.array(errs[1:]))
+    assert np.all(slopes > order - 0.3), slopes
+
+
+def test_dealiased_azimuthal_product_is_convolution(rng):
+    """With N_phi = 3 N_m the grid product of two band-limited fields,
+    taken back with eq. (ifft), equals the truncated convolution of their
+    coefficients (Sect. 3, anti-aliasing) for m < N_m; the top mode m = N_m
+    also receives the alias of the product's mode 2 N_m (= -N_m modulo
+    N_phi), which N_phi = 3 N_m does not remove."""
+    n_phi = 48
+    M = n_phi // 3 + 1
+    a = rng.standard_normal(M) + 1j * rng.standard_normal(M)
+    b = rng.standard_normal(M) + 1j * rng.standard_normal(M)
+    a[0], b[0] = a[0].real, b[0].real
+    prod = tr.grid_to_phi(tr.phi_to_grid(a, n_phi) * tr.phi_to_grid(b, n_phi),
+                          M)
+
+    def full(c):
+        return {**{m: c[m] for m in range(M)},
+                **{-m: np.conj(c[m]) for m in range(1, M)}}
+    A, B = full(a), full(b)
+    conv = np.array([sum(A[p] * B[m - p] for p in A if (m - p) in B)
+                     for m in range(M)])
+    assert np.allclose(prod[:-1], conv[:-1], atol=1e-13)
+    top = M - 1
+    alias = np.conj(A[top] * B[top])
+    assert np.isclose(prod[-1], conv[-1] + alias, atol=1e-13)
+
+
+def test_diagnostics_parseval_and_zero_state():
+    o = _small_oracle()
+    d = diagnostics(o)
+    # E_K by Parseval over m, Clenshaw-Curtis in s, against the grid sum
+    f = o.spectral_fields(o.psi, o.theta, o.uphi)
+    w = grid.clenshaw_curtis(o.n_r) * 0.5 * o.s
+    wm = np.where(np.arange(o.M) == 0, 1.0, 2.0)[:, None]
+    ek = np.pi * np.sum(w * wm * (np.abs(f["us"]) ** 2
+                                  + np.abs(f["uphi"]) ** 2))
+    assert np.isclose(d["E_kin"], ek, rtol=1e-12)
+    o.set_state(0 * o.psi, 0 * o.theta, 0 * o.uphi)
+    d0 = diagnostics(o)
+    assert d0["E_kin"] == 0 and d0["E_therm"] == 0 and d0["nonfinite"] == 0
+
+
+def test_inputs_satisfy_boundary_conditions():
+    for ic, seed in (("theta_noise", 1), ("decaying", 2), ("kolmogorov", 3)):
+        st = inputs.make_state(17, 21, ic, seed)
+        for rows, a in ((tau_rows_psi(21), st.psi),
+                        (tau_rows_dirichlet(21), st.theta)):
+            scale = np.abs(rows) @ np.abs(a).T
+            assert np.all(np.abs(rows @ a.T) <= 1e-14 * scale + 1e-300)
+        assert np.all(st.psi[0] == 0) and np.all(st.theta[0].imag == 0)
