@@ -1,0 +1,141 @@
+/*
+ * qg.h - C ABI of the MI355X one-step solver for spherical quasi-geostrophic
+ * convection (Gastine, "pizza", arXiv:1902.07092).
+ *
+ * The method (paper Sect. 2-4): the regularised streamfunction Psi
+ * (psi = h^2 Psi, Sect. 3.2.1), the temperature perturbation theta and the
+ * axisymmetric zonal flow <u_phi> are expanded in Fourier modes m = 0..N_m in
+ * azimuth (N_phi = 3 N_m grid points, eq. fft/ifft) and in N_c Chebyshev
+ * polynomials on N_r Gauss-Lobatto points in radius (eq. cheb/icheb).  The
+ * equations are multiplied by s^4 (Psi) or s^2 (theta, zonal flow) and
+ * integrated four or two times (eq. psi_int, uphi_int, temp_int), giving
+ * banded operators; boundary conditions are imposed as tau rows on top
+ * (eq. bc_d3psi_coll and Fig. 1b), and every m is solved as a bordered
+ * band system (Appendix A).  Nonlinear advection is pseudo-spectral.  Time
+ * stepping is IMEX: CNAB2 (eq. multistep1) or BPR353 (Table 1, eq. dirks).
+ * No Ekman pumping.
+ *
+ * Conventions shared by every entry point
+ *   - Coefficients are standard Chebyshev coefficients a_n, f(x) =
+ *     sum_n a_n T_n(x), x = +1 at the outer radius s_o, with
+ *     s_o = 1/(1-eta), s_i = eta/(1-eta) (unit gap).
+ *   - psi, theta: M x N_c complex128 (interleaved re, im doubles), row
+ *     m = 0..M-1, M = N_phi/3 + 1.  Row m = 0 of psi is ignored on input and
+ *     returned as zeros (Psi carries the non-axisymmetric motions only).
+ *     Row 0 of theta must be real.
+ *   - uphi: N_c real doubles, the zonal flow <u_phi>.
+ *   - Pointers flagged on_device = 1 are device pointers on the context's
+ *     device; on_device = 0 means host memory.  The caller owns them; the
+ *     library copies in or out and keeps nothing.
+ *   - Every call is asynchronous on the context's stream except those that
+ *     return host data (qg_get_state into host memory, qg_diagnostics) or
+ *     that refactor (qg_step after a change of dt), which synchronise it.
+ *   - Errors are returned as qg_status; qg_last_error gives a message.
+ *     Nothing is thrown across the ABI.  A context must not be used from
+ *     two threads at once; distinct contexts are independent.
+ */
+#ifndef QG_H
+#define QG_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct qg_ctx qg_ctx;
+
+typedef enum {
+  QG_OK = 0,
+  QG_EINVAL = -1,       /* bad parameter, size or pointer */
+  QG_ENOMEM = -2,       /* workspace too small */
+  QG_EDEVICE = -3,      /* a HIP call failed */
+  QG_ENONFINITE = -4,   /* NaN or Inf in a state */
+  QG_ESTATE = -5,       /* state violates the boundary conditions */
+  QG_EUNSUPPORTED = -6  /* valid for the method, not for this build's kernels */
+} qg_status;
+
+typedef enum { QG_CNAB2 = 0, QG_BPR353 = 1 } qg_scheme;
+
+typedef struct {
+  double E;      /* Ekman number  nu / (Omega d^2)            (eq. controls) */
+  double Ra;     /* Rayleigh number                          (eq. controls) */
+  double Pr;     /* Prandtl number                           (eq. controls) */
+  double eta;    /* radius ratio s_i / s_o, 0 < eta < 1      (Sect. 2) */
+  int n_phi;     /* azimuthal grid points, multiple of 3; this build needs
+                    n_phi = 3 * 2^a >= 24 */
+  int n_r;       /* radial Gauss-Lobatto points; this build needs
+                    n_r - 1 = 2^a >= 16.  Sizes whose per-workgroup LDS
+                    needs exceed the device limit give QG_EUNSUPPORTED */
+  int n_c;       /* Chebyshev modes kept, 8 <= n_c < n_r; 0 selects
+                    floor(2 (n_r - 1) / 3) (radial dealiasing, Sect. 3.2.1) */
+  int precision; /* 0 = FP64 (the only value accepted by this build) */
+} qg_params;
+
+typedef struct {
+  double t;         /* simulated time since the last qg_set_state */
+  double E_kin;     /* (1/2) <u_s^2 + u_phi^2>              (Sect. 6.2) */
+  double E_zon;     /* (1/2) <<u_phi>^2>                     (Sect. 6.2) */
+  double E_therm;   /* (1/2) <theta^2> */
+  double enstrophy; /* <omega^2>                            (Sect. 4) */
+  double Re;        /* [2 E_kin / (pi (s_o^2 - s_i^2))]^1/2  (Sect. 6.3) */
+  double Ro;        /* Re E                                  (Sect. 6.3) */
+  double dt_cfl;    /* right side of eq. (cfl) with alpha = 1 */
+  long long step;   /* steps taken since the last qg_set_state */
+  int nonfinite;    /* 1 if the state holds NaN or Inf */
+} qg_diag;
+
+/* Device bytes the caller must provide to qg_create for these parameters.
+ * Returns QG_EINVAL for invalid or unsupported parameters. */
+qg_status qg_workspace_size(const qg_params *p, size_t *bytes);
+
+/* Create a context on the current HIP device.  workspace: device memory
+ * of at least qg_workspace_size bytes, 256-byte aligned, owned by the
+ * caller and kept alive until qg_destroy.  stream: a hipStream_t (NULL =
+ * default stream).  Builds the integration operators on the host
+ * (Sect. 3.2) and uploads them.  The state starts at zero. */
+qg_status qg_create(qg_ctx **ctx, const qg_params *p, void *workspace,
+                    size_t workspace_bytes, void *stream);
+
+/* Copy a state in.  Host inputs are checked: non-finite values give
+ * QG_ENONFINITE, boundary-condition residuals above 1e-10 relative give
+ * QG_ESTATE (tau conditions, Sect. 3.2.2).  Resets t, the step counter and
+ * the CNAB2 history. */
+qg_status qg_set_state(qg_ctx *ctx, const double *psi, const double *theta,
+                       const double *uphi, int on_device);
+
+/* Copy the current state out (row m = 0 of psi is written as zeros). */
+qg_status qg_get_state(qg_ctx *ctx, double *psi, double *theta, double *uphi,
+                       int on_device);
+
+/* Advance nsteps steps of size dt with the given scheme (qg_scheme).  The
+ * bordered LU factors of every m are rebuilt on the host whenever dt
+ * changes (Sect. 3.1: factorisation at start-up and on a time-step
+ * change).  CNAB2 uses E^{n-1} := E^n on its first step after
+ * qg_set_state. */
+qg_status qg_step(qg_ctx *ctx, double dt, int scheme, int nsteps);
+
+/* Diagnostics of the current state (synchronises the stream). */
+qg_status qg_diagnostics(qg_ctx *ctx, qg_diag *out);
+
+/* Message of the last error on this context ("" if none). */
+const char *qg_last_error(const qg_ctx *ctx);
+
+/* Release the context (not the caller's workspace). */
+void qg_destroy(qg_ctx *ctx);
+
+/* Host-only: the banded integration operators qg_create builds for radius
+ * ratio eta and n_c modes (eq. psi_int, uphi_int, temp_int), for checking
+ * against a reference without a device.  which = 0..8 selects A0, A2, B0,
+ * B2, B4, C, D, F0, F2 with A_m = A0 + m^2 A2 (int^4 s^4 L_I),
+ * B_m = B0 + m^2 B2 + m^4 B4 (int^4 s^4 Lap_m L_I, Coriolis term excluded),
+ * C = int^4 s^4, D = int^2 s^2, F_m = F0 + m^2 F2 (int^2 s^2 Lap_m).
+ * out: host array of n_c x 17 doubles, entry [k][n - k + 8]; rows below
+ * the tau rows (k < 4 for A, B, C; k < 2 for D, F) are zero. */
+qg_status qg_operator_band(double eta, int n_c, int which, double *out);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* QG_H */

@@ -1,0 +1,709 @@
+// C ABI of the QG step: context, workspace layout, host-side factorisation,
+// and the kernel sequence of the CNAB2 and BPR353 schemes.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <thread>
+#include <type_traits>
+#include <vector>
+
+#include "../../include/qg.h"
+#include "host_ops.h"
+#include "kernels.h"
+
+namespace qg {
+void launch_synth(const Geom& g, const double2* psi, const double2* th, double2* X, double* diag,
+                  int threads, hipStream_t st);
+void launch_ring(const Geom& g, const double2* X, double2* NL, double* zonal, double* rate,
+                 int threads, hipStream_t st);
+void launch_analysis(const Geom& g, const Bands& b, const double2* NL, const double* zonal,
+                     const double2* th_state, double2* Epsi, double2* Eth, int threads,
+                     hipStream_t st);
+void launch_solve_psi(const Geom& g, const Bands& b, const FactorSet<double2>& F,
+                      const RhsSpec& rs, hipStream_t st);
+void launch_solve_real(const Geom& g, const Bands& b, const FactorSet<double>& F,
+                       const RhsSpec& rs, hipStream_t st);
+}  // namespace qg
+
+using namespace qg;
+
+namespace {
+
+// BPR353 Butcher tables (Boscarino, Pareschi & Russo 2013, Sect. 8.3):
+// explicit and implicit, five stages, a_ii = 1/2 after an explicit first
+// stage, stiffly accurate (paper Table 1, eq. dirks).
+const double BPR_AE[5][5] = {{0, 0, 0, 0, 0},
+                             {1, 0, 0, 0, 0},
+                             {4.0 / 9, 2.0 / 9, 0, 0, 0},
+                             {0.25, 0, 0.75, 0, 0},
+                             {0.25, 0, 0.75, 0, 0}};
+const double BPR_AI[5][5] = {{0, 0, 0, 0, 0},
+                             {0.5, 0.5, 0, 0, 0},
+                             {5.0 / 18, -1.0 / 9, 0.5, 0, 0},
+                             {0.5, 0, 0, 0.5, 0},
+                             {0.25, 0, 0.75, -0.5, 0.5}};
+
+bool is_pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
+
+struct Plan {
+  int n = 0, npass = 0, radix[24] = {0};
+  int max_nb = 0;
+};
+
+bool make_plan(int n, Plan& p) {
+  p.n = n;
+  p.npass = 0;
+  int rest = n;
+  if (rest % 3 == 0) { p.radix[p.npass++] = 3; rest /= 3; }
+  if (!is_pow2(rest)) return false;
+  int L = 0;
+  while ((1 << L) < rest) ++L;
+  if (L % 2) p.radix[p.npass++] = 2;
+  for (int i = 0; i < L / 2; ++i) p.radix[p.npass++] = 4;
+  p.max_nb = 0;
+  for (int i = 0; i < p.npass; ++i) p.max_nb = std::max(p.max_nb, n / p.radix[i]);
+  return true;
+}
+
+int round64(int v) { return ((v + 63) / 64) * 64; }
+
+struct Layout {
+  size_t total = 0;
+  size_t take(size_t bytes) {
+    size_t off = total;
+    total += (bytes + 255) / 256 * 256;
+    return off;
+  }
+};
+
+struct Sizes {
+  int M, K, R, nphi, n4, n2, Sr;
+};
+
+bool sizes_of(const qg_params* p, Sizes& z, std::string& why) {
+  if (!p) { why = "null parameters"; return false; }
+  if (!(p->E > 0 && p->Ra > 0 && p->Pr > 0)) { why = "E, Ra and Pr must be positive"; return false; }
+  if (!(p->eta > 0 && p->eta < 1)) { why = "eta must lie in (0, 1)"; return false; }
+  if (p->n_phi % 3 || p->n_phi < 24) { why = "n_phi must be a multiple of 3, >= 24"; return false; }
+  if (p->n_r < 17) { why = "n_r must be >= 17"; return false; }
+  int K = p->n_c ? p->n_c : (2 * (p->n_r - 1)) / 3;
+  if (K < 8 || K >= p->n_r) { why = "n_c must satisfy 8 <= n_c < n_r"; return false; }
+  if (p->precision != 0) { why = "only precision = 0 (FP64) is supported"; return false; }
+  z.M = p->n_phi / 3 + 1;
+  z.K = K;
+  z.R = p->n_r;
+  z.nphi = p->n_phi;
+  z.n4 = K - 4;
+  z.n2 = K - 2;
+  z.Sr = z.M + 1;
+  return true;
+}
+
+struct WsMap {
+  size_t state, ybuf, eslot, lslot, X, NL, zonal, rate, diag, xk, wq, dsk, twd, twp, bands;
+  size_t p_piv, p_L, p_U, p_W, p_C, p_Mi;
+  size_t r_piv, r_L, r_U, r_W, r_C, r_Mi;
+  size_t total;
+};
+
+WsMap map_workspace(const Sizes& z) {
+  Layout L;
+  WsMap w;
+  const size_t MK = (size_t)z.M * z.K * sizeof(double2);
+  const size_t RM = (size_t)z.R * z.M * sizeof(double2);
+  const size_t Sp = z.M - 1;
+  w.state = L.take(2 * MK);
+  w.ybuf = L.take(4 * MK);
+  w.eslot = L.take(6 * MK);
+  w.lslot = L.take(8 * MK);
+  w.X = L.take(6 * RM);
+  w.NL = L.take(2 * RM);
+  w.zonal = L.take(z.R * sizeof(double));
+  w.rate = L.take(z.R * sizeof(double));
+  w.diag = L.take((size_t)z.M * 8 * sizeof(double));
+  w.xk = L.take(z.R * sizeof(double));
+  w.wq = L.take(z.R * sizeof(double));
+  w.dsk = L.take(z.R * sizeof(double));
+  w.twd = L.take((size_t)2 * (z.R - 1) * sizeof(double2));
+  w.twp = L.take((size_t)z.nphi * sizeof(double2));
+  w.bands = L.take((size_t)9 * z.K * BANDW * sizeof(double));
+  w.p_piv = L.take(Sp * z.n4 * sizeof(int));
+  w.p_L = L.take(Sp * z.n4 * 8 * sizeof(double2));
+  w.p_U = L.take(Sp * z.n4 * 17 * sizeof(double2));
+  w.p_W = L.take(Sp * 4 * z.n4 * sizeof(double2));
+  w.p_C = L.take(Sp * 8 * 4 * sizeof(double2));
+  w.p_Mi = L.take(Sp * 16 * sizeof(double2));
+  const size_t Sr = z.Sr;
+  w.r_piv = L.take(Sr * z.n2 * sizeof(int));
+  w.r_L = L.take(Sr * z.n2 * 4 * sizeof(double));
+  w.r_U = L.take(Sr * z.n2 * 9 * sizeof(double));
+  w.r_W = L.take(Sr * 2 * z.n2 * sizeof(double));
+  w.r_C = L.take(Sr * 4 * 2 * sizeof(double));
+  w.r_Mi = L.take(Sr * 4 * sizeof(double));
+  w.total = L.total;
+  return w;
+}
+
+}  // namespace
+
+struct qg_ctx {
+  qg_params p;
+  Sizes z;
+  WsMap w;
+  char* ws = nullptr;
+  hipStream_t st = nullptr;
+  Operators ops;
+  Geom g;
+  Bands b;
+  FactorSet<double2> Fp;
+  FactorSet<double> Fr;
+  int t_synth = 64, t_ring = 64, t_ana = 64;
+  double factored_adt = -1.0;
+  int have_prev = 0, cur = 0;
+  double t = 0.0;
+  long long step = 0;
+  std::string err;
+  double2* ptr2(size_t off) { return reinterpret_cast<double2*>(ws + off); }
+  double* ptrd(size_t off) { return reinterpret_cast<double*>(ws + off); }
+  double2* psi() { return ptr2(w.state); }
+  double2* th() { return ptr2(w.state) + (size_t)z.M * z.K; }
+  double2* slot(size_t base, int i, int field) {
+    return ptr2(base) + ((size_t)(2 * i + field)) * z.M * z.K;
+  }
+};
+
+#define HIPCHK(expr)                                                           \
+  do {                                                                         \
+    hipError_t e_ = (expr);                                                    \
+    if (e_ != hipSuccess) {                                                    \
+      ctx->err = std::string(#expr) + ": " + hipGetErrorString(e_);            \
+      return QG_EDEVICE;                                                       \
+    }                                                                          \
+  } while (0)
+
+namespace {
+
+qg_status fail(qg_ctx* ctx, qg_status s, const std::string& msg) {
+  if (ctx) ctx->err = msg;
+  return s;
+}
+
+std::vector<double2> twiddles(int n) {
+  std::vector<double2> tw(n);
+  for (int k = 0; k < n; ++k) {
+    long double a = -2.0L * 3.14159265358979323846264338327950288L * k / n;
+    tw[k] = make_double2((double)cosl(a), (double)sinl(a));
+  }
+  return tw;
+}
+
+// Clenshaw-Curtis weights on x_k = cos(pi k / N), k = 0..N.
+std::vector<double> cc_weights(int nr) {
+  const int N = nr - 1;
+  std::vector<double> w(nr, 0.0);
+  const double pi = 3.14159265358979323846;
+  for (int k = 0; k <= N; ++k) {
+    double th = pi * k / N, v = 1.0;
+    for (int j = 1; j <= N / 2; ++j) {
+      double bj = (2 * j == N) ? 1.0 : 2.0;
+      v -= bj * std::cos(2.0 * j * th) / (4.0 * j * j - 1.0);
+    }
+    double ck = (k == 0 || k == N) ? 1.0 : 2.0;
+    w[k] = ck * v / N;
+  }
+  return w;
+}
+
+// Full K x K tau matrix of one system, dense rows (host), from the bands.
+template <typename T>
+void assemble(const qg_ctx* ctx, int kind, int m, double adt, std::vector<T>& full, int& p) {
+  const int K = ctx->z.K;
+  const Operators& o = ctx->ops;
+  full.assign((size_t)K * K, T(0));
+  p = (kind == 0) ? 4 : 2;
+  std::vector<double> row(K);
+  for (int r = 0; r < p; ++r) {
+    tau_row(r, K, row.data());
+    for (int n = 0; n < K; ++n) full[(size_t)r * K + n] = T(row[n]);
+  }
+  const double m2 = (double)m * m;
+  for (int k = p; k < K; ++k)
+    for (int off = -8; off <= 8; ++off) {
+      int n = k + off;
+      if (n < 0 || n >= K) continue;
+      size_t i = (size_t)k * BANDW + off + BANDC;
+      T v;
+      if (kind == 0) {
+        double re = o.A0[i] + m2 * o.A2[i] - adt * (o.B0[i] + m2 * o.B2[i] + m2 * m2 * o.B4[i]);
+        double im = -adt * (2.0 * m / ctx->p.E) * o.C[i];
+        if constexpr (std::is_same<T, cplx>::value) v = cplx(re, im);
+        else v = T(re);
+      } else if (kind == 1) {  // zonal flow: D - a dt E, E = F0 + F2
+        v = T(o.D[i] - adt * (o.F0[i] + o.F2[i]));
+      } else {                 // theta: D - a dt F_m / Pr
+        v = T(o.D[i] - adt * (o.F0[i] + m2 * o.F2[i]) / ctx->p.Pr);
+      }
+      full[(size_t)k * K + n] = v;
+    }
+}
+
+template <typename T, typename D2>
+void pack(const BorderedFactor<T>& f, size_t s, int kl, int wu, int p, int* piv, D2* L, D2* U,
+          D2* W, D2* C, D2* Mi) {
+  const int n = f.n;
+  auto cvt = [](const T& v) -> D2 {
+    if constexpr (std::is_same<T, cplx>::value) return make_double2(v.real(), v.imag());
+    else return v;
+  };
+  for (int j = 0; j < n; ++j) piv[s * n + j] = f.piv[j];
+  for (size_t i = 0; i < (size_t)n * kl; ++i) L[s * n * kl + i] = cvt(f.Lc[i]);
+  for (size_t i = 0; i < (size_t)n * wu; ++i) U[s * n * wu + i] = cvt(f.Uc[i]);
+  for (size_t i = 0; i < (size_t)p * n; ++i) W[s * p * n + i] = cvt(f.W[i]);
+  for (size_t i = 0; i < (size_t)kl * p; ++i) C[s * kl * p + i] = cvt(f.Cb[i]);
+  for (size_t i = 0; i < (size_t)p * p; ++i) Mi[s * p * p + i] = cvt(f.Minv[i]);
+}
+
+template <typename F>
+void parallel_for(int count, F fn) {
+  unsigned hw = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+  std::vector<std::thread> th;
+  for (unsigned w = 0; w < hw; ++w)
+    th.emplace_back([&, w] {
+      for (int i = (int)w; i < count; i += (int)hw) fn(i);
+    });
+  for (auto& x : th) x.join();
+}
+
+qg_status refactor(qg_ctx* ctx, double adt) {
+  const Sizes& z = ctx->z;
+  const size_t Sp = z.M - 1, Sr = z.Sr;
+  std::vector<int> ppiv(Sp * z.n4), rpiv(Sr * z.n2);
+  std::vector<double2> pL(Sp * z.n4 * 8), pU(Sp * z.n4 * 17), pW(Sp * 4 * z.n4), pC(Sp * 32),
+      pM(Sp * 16);
+  std::vector<double> rL(Sr * z.n2 * 4), rU(Sr * z.n2 * 9), rW(Sr * 2 * z.n2), rC(Sr * 8),
+      rM(Sr * 4);
+  std::vector<int> ok(Sp + Sr, 1);
+  parallel_for((int)(Sp + Sr), [&](int idx) {
+    if (idx < (int)Sp) {
+      int m = idx + 1, p;
+      std::vector<cplx> full;
+      assemble<cplx>(ctx, 0, m, adt, full, p);
+      BorderedFactor<cplx> f;
+      if (!factor_bordered<cplx>(full, z.K, 4, 8, 8, f)) { ok[idx] = 0; return; }
+      pack<cplx, double2>(f, idx, 8, 17, 4, ppiv.data(), pL.data(), pU.data(), pW.data(),
+                          pC.data(), pM.data());
+    } else {
+      int s = idx - (int)Sp, p;
+      int kind = (s == 0) ? 1 : 2, m = (s == 0) ? 0 : s - 1;
+      std::vector<double> full;
+      assemble<double>(ctx, kind, m, adt, full, p);
+      BorderedFactor<double> f;
+      if (!factor_bordered<double>(full, z.K, 2, 4, 4, f)) { ok[idx] = 0; return; }
+      pack<double, double>(f, s, 4, 9, 2, rpiv.data(), rL.data(), rU.data(), rW.data(), rC.data(),
+                           rM.data());
+    }
+  });
+  for (int v : ok)
+    if (!v) return fail(ctx, QG_EINVAL, "singular tau matrix (dt too large or bad parameters)");
+  const WsMap& w = ctx->w;
+  auto up = [&](size_t off, const void* src, size_t bytes) {
+    return hipMemcpyAsync(ctx->ws + off, src, bytes, hipMemcpyHostToDevice, ctx->st);
+  };
+  HIPCHK(up(w.p_piv, ppiv.data(), ppiv.size() * sizeof(int)));
+  HIPCHK(up(w.p_L, pL.data(), pL.size() * sizeof(double2)));
+  HIPCHK(up(w.p_U, pU.data(), pU.size() * sizeof(double2)));
+  HIPCHK(up(w.p_W, pW.data(), pW.size() * sizeof(double2)));
+  HIPCHK(up(w.p_C, pC.data(), pC.size() * sizeof(double2)));
+  HIPCHK(up(w.p_Mi, pM.data(), pM.size() * sizeof(double2)));
+  HIPCHK(up(w.r_piv, rpiv.data(), rpiv.size() * sizeof(int)));
+  HIPCHK(up(w.r_L, rL.data(), rL.size() * sizeof(double)));
+  HIPCHK(up(w.r_U, rU.data(), rU.size() * sizeof(double)));
+  HIPCHK(up(w.r_W, rW.data(), rW.size() * sizeof(double)));
+  HIPCHK(up(w.r_C, rC.data(), rC.size() * sizeof(double)));
+  HIPCHK(up(w.r_Mi, rM.data(), rM.size() * sizeof(double)));
+  HIPCHK(hipStreamSynchronize(ctx->st));
+  ctx->factored_adt = adt;
+  return QG_OK;
+}
+
+qg_status explicit_terms(qg_ctx* ctx, const double2* psi, const double2* th, double2* Ep,
+                         double2* Et) {
+  launch_synth(ctx->g, psi, th, ctx->ptr2(ctx->w.X), nullptr, ctx->t_synth, ctx->st);
+  launch_ring(ctx->g, ctx->ptr2(ctx->w.X), ctx->ptr2(ctx->w.NL), ctx->ptrd(ctx->w.zonal), nullptr,
+              ctx->t_ring, ctx->st);
+  launch_analysis(ctx->g, ctx->b, ctx->ptr2(ctx->w.NL), ctx->ptrd(ctx->w.zonal), th, Ep, Et,
+                  ctx->t_ana, ctx->st);
+  HIPCHK(hipGetLastError());
+  return QG_OK;
+}
+
+qg_status implicit_solve(qg_ctx* ctx, const RhsSpec& rs) {
+  launch_solve_psi(ctx->g, ctx->b, ctx->Fp, rs, ctx->st);
+  launch_solve_real(ctx->g, ctx->b, ctx->Fr, rs, ctx->st);
+  HIPCHK(hipGetLastError());
+  return QG_OK;
+}
+
+qg_status step_cnab2(qg_ctx* ctx, double dt) {
+  const int cur = ctx->cur, prev = 1 - cur;
+  double2 *Ep = ctx->slot(ctx->w.eslot, cur, 0), *Et = ctx->slot(ctx->w.eslot, cur, 1);
+  qg_status s = explicit_terms(ctx, ctx->psi(), ctx->th(), Ep, Et);
+  if (s != QG_OK) return s;
+  RhsSpec rs{};
+  rs.base_psi = ctx->psi();
+  rs.base_th = ctx->th();
+  rs.cL = 0.5 * dt;
+  rs.nterm = 2;
+  rs.term_psi[0] = Ep;
+  rs.term_th[0] = Et;
+  rs.coef[0] = 1.5 * dt;
+  rs.term_psi[1] = ctx->have_prev ? ctx->slot(ctx->w.eslot, prev, 0) : Ep;
+  rs.term_th[1] = ctx->have_prev ? ctx->slot(ctx->w.eslot, prev, 1) : Et;
+  rs.coef[1] = -0.5 * dt;
+  rs.out_psi = ctx->psi();
+  rs.out_th = ctx->th();
+  s = implicit_solve(ctx, rs);
+  if (s != QG_OK) return s;
+  ctx->have_prev = 1;
+  ctx->cur = prev;
+  return QG_OK;
+}
+
+qg_status step_bpr353(qg_ctx* ctx, double dt) {
+  // y_1 = y_n (explicit first stage); stages 2..5 solve (M - dt/2 L) y_i =
+  // M y_n + dt sum_{j<i} (aE_ij E_j + aI_ij L y_j); y_{n+1} = y_5.
+  const double2* y0p = ctx->psi();
+  const double2* y0t = ctx->th();
+  const double2* yp[5] = {y0p, nullptr, nullptr, nullptr, nullptr};
+  const double2* yt[5] = {y0t, nullptr, nullptr, nullptr, nullptr};
+  for (int i = 1; i < 5; ++i) {
+    const int j = i - 1;
+    bool need_e = false;
+    for (int r = 0; r < 5; ++r) need_e = need_e || BPR_AE[r][j] != 0.0;
+    if (need_e) {
+      qg_status s = explicit_terms(ctx, yp[j], yt[j], ctx->slot(ctx->w.eslot, j, 0),
+                                   ctx->slot(ctx->w.eslot, j, 1));
+      if (s != QG_OK) return s;
+    }
+    RhsSpec rs{};
+    rs.base_psi = y0p;
+    rs.base_th = y0t;
+    rs.cL = dt * BPR_AI[i][0];
+    rs.nterm = 0;
+    for (int jj = 0; jj < i; ++jj) {
+      if (BPR_AE[i][jj] != 0.0) {
+        rs.term_psi[rs.nterm] = ctx->slot(ctx->w.eslot, jj, 0);
+        rs.term_th[rs.nterm] = ctx->slot(ctx->w.eslot, jj, 1);
+        rs.coef[rs.nterm++] = dt * BPR_AE[i][jj];
+      }
+      if (jj >= 1 && BPR_AI[i][jj] != 0.0) {
+        rs.term_psi[rs.nterm] = ctx->slot(ctx->w.lslot, jj, 0);
+        rs.term_th[rs.nterm] = ctx->slot(ctx->w.lslot, jj, 1);
+        rs.coef[rs.nterm++] = dt * BPR_AI[i][jj];
+      }
+    }
+    double2 *op, *ot;
+    if (i == 4) {
+      op = ctx->psi();
+      ot = ctx->th();
+    } else {
+      int b = (i - 1) % 2;
+      op = ctx->slot(ctx->w.ybuf, b, 0);
+      ot = ctx->slot(ctx->w.ybuf, b, 1);
+    }
+    rs.out_psi = op;
+    rs.out_th = ot;
+    bool need_l = false;
+    for (int r = i + 1; r < 5; ++r) need_l = need_l || BPR_AI[r][i] != 0.0;
+    rs.lin_psi = need_l ? ctx->slot(ctx->w.lslot, i, 0) : nullptr;
+    rs.lin_th = need_l ? ctx->slot(ctx->w.lslot, i, 1) : nullptr;
+    qg_status s = implicit_solve(ctx, rs);
+    if (s != QG_OK) return s;
+    yp[i] = op;
+    yt[i] = ot;
+  }
+  return QG_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+qg_status qg_workspace_size(const qg_params* p, size_t* bytes) {
+  Sizes z;
+  std::string why;
+  if (!bytes || !sizes_of(p, z, why)) return QG_EINVAL;
+  *bytes = map_workspace(z).total;
+  return QG_OK;
+}
+
+qg_status qg_create(qg_ctx** out, const qg_params* p, void* workspace, size_t workspace_bytes,
+                    void* stream) {
+  if (!out) return QG_EINVAL;
+  *out = nullptr;
+  Sizes z;
+  std::string why;
+  if (!sizes_of(p, z, why)) return QG_EINVAL;
+  Plan pd, pp;
+  if (!is_pow2(z.R - 1) || !make_plan(2 * (z.R - 1), pd) || !make_plan(z.nphi, pp) ||
+      z.nphi % 3)
+    return QG_EUNSUPPORTED;
+  if (!workspace || ((uintptr_t)workspace & 255)) return QG_EINVAL;
+  WsMap w = map_workspace(z);
+  if (workspace_bytes < w.total) return QG_ENOMEM;
+
+  qg_ctx* ctx = new qg_ctx();
+  ctx->p = *p;
+  ctx->p.n_c = z.K;
+  ctx->z = z;
+  ctx->w = w;
+  ctx->ws = static_cast<char*>(workspace);
+  ctx->st = static_cast<hipStream_t>(stream);
+
+  // launch shapes: FFT passes need MAXB (4) butterflies per thread at most
+  const int MAXB = 4, MAXP = 5, MAXJ = 16;
+  ctx->t_synth = round64(std::max({64, (z.R + MAXP - 1) / MAXP, (pd.max_nb + MAXB - 1) / MAXB}));
+  ctx->t_ana = ctx->t_synth;
+  ctx->t_ring = round64(std::max({64, (z.nphi + MAXJ - 1) / MAXJ, (pp.max_nb + MAXB - 1) / MAXB}));
+  int dev = 0;
+  hipDeviceProp_t prop;
+  if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess) {
+    delete ctx;
+    return QG_EDEVICE;
+  }
+  const size_t lds_synth = sizeof(double2) * (2 * z.K + 2 * (z.R - 1) + 2 * ctx->t_synth);
+  const size_t lds_ring = sizeof(double2) * z.nphi;
+  const size_t lds_solve = sizeof(double2) * (2 * z.K) + sizeof(double2) * 32 * 25 + 128;
+  if (ctx->t_synth > 1024 || ctx->t_ring > 1024 ||
+      std::max({lds_synth, lds_ring, lds_solve}) > (size_t)prop.sharedMemPerBlock) {
+    delete ctx;
+    return QG_EUNSUPPORTED;
+  }
+
+  ctx->ops = build_operators(p->eta, z.K);
+  const double s_i = p->eta / (1 - p->eta), s_o = 1 / (1 - p->eta);
+  // host tables
+  std::vector<double> xk(z.R), wq(z.R), dsk(z.R);
+  std::vector<double> cc = cc_weights(z.R);
+  const double pi = 3.14159265358979323846;
+  for (int k = 0; k < z.R; ++k) xk[k] = std::cos(pi * k / (z.R - 1));
+  for (int k = 0; k < z.R; ++k) {
+    double s = 0.5 * (s_o - s_i) * xk[k] + 0.5 * (s_o + s_i);
+    wq[k] = cc[k] * 0.5 * (s_o - s_i) * s;
+  }
+  for (int k = 0; k < z.R; ++k) {
+    auto sk = [&](int i) { return 0.5 * (s_o - s_i) * xk[i] + 0.5 * (s_o + s_i); };
+    double a = (k > 0) ? std::fabs(sk(k - 1) - sk(k)) : 1e300;
+    double b = (k + 1 < z.R) ? std::fabs(sk(k) - sk(k + 1)) : 1e300;
+    dsk[k] = std::min(a, b);
+  }
+  std::vector<double2> twd = twiddles(2 * (z.R - 1)), twp = twiddles(z.nphi);
+  std::vector<double> bandbuf((size_t)9 * z.K * BANDW);
+  const std::vector<double>* bl[9] = {&ctx->ops.A0, &ctx->ops.A2, &ctx->ops.B0,
+                                      &ctx->ops.B2, &ctx->ops.B4, &ctx->ops.C,
+                                      &ctx->ops.D,  &ctx->ops.F0, &ctx->ops.F2};
+  for (int i = 0; i < 9; ++i)
+    std::copy(bl[i]->begin(), bl[i]->end(), bandbuf.begin() + (size_t)i * z.K * BANDW);
+  auto up = [&](size_t off, const void* src, size_t bytes) {
+    return hipMemcpyAsync(ctx->ws + off, src, bytes, hipMemcpyHostToDevice, ctx->st);
+  };
+  if (up(w.xk, xk.data(), xk.size() * 8) != hipSuccess ||
+      up(w.wq, wq.data(), wq.size() * 8) != hipSuccess ||
+      up(w.dsk, dsk.data(), dsk.size() * 8) != hipSuccess ||
+      up(w.twd, twd.data(), twd.size() * 16) != hipSuccess ||
+      up(w.twp, twp.data(), twp.size() * 16) != hipSuccess ||
+      up(w.bands, bandbuf.data(), bandbuf.size() * 8) != hipSuccess ||
+      hipMemsetAsync(ctx->ws + w.state, 0, 2 * (size_t)z.M * z.K * sizeof(double2), ctx->st) !=
+          hipSuccess ||
+      hipStreamSynchronize(ctx->st) != hipSuccess) {
+    delete ctx;
+    return QG_EDEVICE;
+  }
+  Geom& g = ctx->g;
+  g.M = z.M; g.K = z.K; g.R = z.R; g.nphi = z.nphi;
+  g.s_o = s_o; g.s_i = s_i;
+  g.mid = 0.5 * (s_o + s_i); g.half = 0.5 * (s_o - s_i);
+  const double r = std::sqrt(1 - p->eta * p->eta);
+  const double alpha = p->eta / (1 - p->eta) * (std::asinh(r / p->eta) / r - 1.0);
+  g.dtc_coef = alpha / std::log(p->eta);
+  g.Ra_Pr = p->Ra / p->Pr;
+  g.inv_Pr = 1.0 / p->Pr;
+  g.two_over_E = 2.0 / p->E;
+  g.xk = ctx->ptrd(w.xk);
+  g.wq = ctx->ptrd(w.wq);
+  g.dsk = ctx->ptrd(w.dsk);
+  g.dct.n = pd.n; g.dct.npass = pd.npass;
+  std::copy(pd.radix, pd.radix + 24, g.dct.radix);
+  g.dct.tw = ctx->ptr2(w.twd);
+  g.phi.n = pp.n; g.phi.npass = pp.npass;
+  std::copy(pp.radix, pp.radix + 24, g.phi.radix);
+  g.phi.tw = ctx->ptr2(w.twp);
+  const double* bd = ctx->ptrd(w.bands);
+  const size_t bs = (size_t)z.K * BANDW;
+  ctx->b = Bands{bd, bd + bs, bd + 2 * bs, bd + 3 * bs, bd + 4 * bs,
+                 bd + 5 * bs, bd + 6 * bs, bd + 7 * bs, bd + 8 * bs};
+  ctx->Fp = FactorSet<double2>{reinterpret_cast<const int*>(ctx->ws + w.p_piv), ctx->ptr2(w.p_L),
+                               ctx->ptr2(w.p_U), ctx->ptr2(w.p_W), ctx->ptr2(w.p_C),
+                               ctx->ptr2(w.p_Mi)};
+  ctx->Fr = FactorSet<double>{reinterpret_cast<const int*>(ctx->ws + w.r_piv), ctx->ptrd(w.r_L),
+                              ctx->ptrd(w.r_U), ctx->ptrd(w.r_W), ctx->ptrd(w.r_C),
+                              ctx->ptrd(w.r_Mi)};
+  *out = ctx;
+  return QG_OK;
+}
+
+qg_status qg_set_state(qg_ctx* ctx, const double* psi, const double* theta, const double* uphi,
+                       int on_device) {
+  if (!ctx) return QG_EINVAL;
+  if (!psi || !theta || !uphi) return fail(ctx, QG_EINVAL, "null state pointer");
+  const Sizes& z = ctx->z;
+  const size_t MK = (size_t)z.M * z.K;
+  std::vector<double2> hp(MK), ht(MK);
+  std::vector<double> hu(z.K);
+  const hipMemcpyKind kind = on_device ? hipMemcpyDeviceToHost : hipMemcpyHostToHost;
+  HIPCHK(hipMemcpyAsync(hp.data(), psi, MK * 16, kind, ctx->st));
+  HIPCHK(hipMemcpyAsync(ht.data(), theta, MK * 16, kind, ctx->st));
+  HIPCHK(hipMemcpyAsync(hu.data(), uphi, z.K * 8, kind, ctx->st));
+  HIPCHK(hipStreamSynchronize(ctx->st));
+  for (size_t i = 0; i < MK; ++i)
+    if (!std::isfinite(hp[i].x) || !std::isfinite(hp[i].y) || !std::isfinite(ht[i].x) ||
+        !std::isfinite(ht[i].y))
+      return fail(ctx, QG_ENONFINITE, "non-finite value in the state");
+  for (int n = 0; n < z.K; ++n)
+    if (!std::isfinite(hu[n])) return fail(ctx, QG_ENONFINITE, "non-finite zonal flow");
+  // boundary conditions (tau rows) per row
+  std::vector<double> rows(4 * z.K);
+  for (int r = 0; r < 4; ++r) tau_row(r, z.K, rows.data() + r * z.K);
+  auto check = [&](const double2* a, int p, bool real_only) {
+    for (int r = 0; r < p; ++r) {
+      double sr = 0, si = 0, mr = 0, mi = 0;
+      for (int n = 0; n < z.K; ++n) {
+        double c = rows[r * z.K + n];
+        sr += c * a[n].x; si += c * a[n].y;
+        mr += std::fabs(c * a[n].x); mi += std::fabs(c * a[n].y);
+      }
+      if (std::fabs(sr) > 1e-10 * mr + 1e-300 || std::fabs(si) > 1e-10 * mi + 1e-300) return false;
+    }
+    if (real_only)
+      for (int n = 0; n < z.K; ++n)
+        if (a[n].y != 0.0) return false;
+    return true;
+  };
+  for (int m = 1; m < z.M; ++m)
+    if (!check(&hp[(size_t)m * z.K], 4, false))
+      return fail(ctx, QG_ESTATE, "Psi violates the boundary conditions at m=" + std::to_string(m));
+  for (int m = 0; m < z.M; ++m)
+    if (!check(&ht[(size_t)m * z.K], 2, m == 0))
+      return fail(ctx, QG_ESTATE,
+                  "theta violates the boundary conditions (or is complex) at m=" + std::to_string(m));
+  std::vector<double2> hu2(z.K);
+  for (int n = 0; n < z.K; ++n) hu2[n] = make_double2(hu[n], 0.0);
+  if (!check(hu2.data(), 2, true))
+    return fail(ctx, QG_ESTATE, "zonal flow violates the boundary conditions");
+  for (int n = 0; n < z.K; ++n) hp[n] = hu2[n];  // row 0 of the psi array holds the zonal flow
+  HIPCHK(hipMemcpyAsync(ctx->psi(), hp.data(), MK * 16, hipMemcpyHostToDevice, ctx->st));
+  HIPCHK(hipMemcpyAsync(ctx->th(), ht.data(), MK * 16, hipMemcpyHostToDevice, ctx->st));
+  HIPCHK(hipStreamSynchronize(ctx->st));
+  ctx->t = 0.0;
+  ctx->step = 0;
+  ctx->have_prev = 0;
+  ctx->cur = 0;
+  ctx->err.clear();
+  return QG_OK;
+}
+
+qg_status qg_get_state(qg_ctx* ctx, double* psi, double* theta, double* uphi, int on_device) {
+  if (!ctx) return QG_EINVAL;
+  if (!psi || !theta || !uphi) return fail(ctx, QG_EINVAL, "null state pointer");
+  const Sizes& z = ctx->z;
+  const size_t MK = (size_t)z.M * z.K;
+  std::vector<double2> hp(MK);
+  HIPCHK(hipMemcpyAsync(hp.data(), ctx->psi(), MK * 16, hipMemcpyDeviceToHost, ctx->st));
+  HIPCHK(hipStreamSynchronize(ctx->st));
+  std::vector<double> hu(z.K);
+  for (int n = 0; n < z.K; ++n) {
+    hu[n] = hp[n].x;
+    hp[n] = make_double2(0.0, 0.0);
+  }
+  const hipMemcpyKind k1 = on_device ? hipMemcpyHostToDevice : hipMemcpyHostToHost;
+  const hipMemcpyKind k2 = on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+  HIPCHK(hipMemcpyAsync(psi, hp.data(), MK * 16, k1, ctx->st));
+  HIPCHK(hipMemcpyAsync(theta, ctx->th(), MK * 16, k2, ctx->st));
+  HIPCHK(hipMemcpyAsync(uphi, hu.data(), z.K * 8, k1, ctx->st));
+  HIPCHK(hipStreamSynchronize(ctx->st));
+  return QG_OK;
+}
+
+qg_status qg_step(qg_ctx* ctx, double dt, int scheme, int nsteps) {
+  if (!ctx) return QG_EINVAL;
+  if (!(dt > 0) || !std::isfinite(dt)) return fail(ctx, QG_EINVAL, "dt must be positive");
+  if (scheme != QG_CNAB2 && scheme != QG_BPR353) return fail(ctx, QG_EINVAL, "unknown scheme");
+  if (nsteps < 0) return fail(ctx, QG_EINVAL, "nsteps must be >= 0");
+  const double adt = 0.5 * dt;   // b_0^I of CNAB2 and a_ii of BPR353
+  if (adt != ctx->factored_adt) {
+    qg_status s = refactor(ctx, adt);
+    if (s != QG_OK) return s;
+    ctx->have_prev = 0;   // the multistep history belongs to the old dt
+  }
+  for (int i = 0; i < nsteps; ++i) {
+    qg_status s = (scheme == QG_CNAB2) ? step_cnab2(ctx, dt) : step_bpr353(ctx, dt);
+    if (s != QG_OK) return s;
+    ctx->t += dt;
+    ctx->step += 1;
+  }
+  return QG_OK;
+}
+
+qg_status qg_diagnostics(qg_ctx* ctx, qg_diag* out) {
+  if (!ctx || !out) return QG_EINVAL;
+  const Sizes& z = ctx->z;
+  launch_synth(ctx->g, ctx->psi(), ctx->th(), ctx->ptr2(ctx->w.X), ctx->ptrd(ctx->w.diag),
+               ctx->t_synth, ctx->st);
+  launch_ring(ctx->g, ctx->ptr2(ctx->w.X), ctx->ptr2(ctx->w.NL), ctx->ptrd(ctx->w.zonal),
+              ctx->ptrd(ctx->w.rate), ctx->t_ring, ctx->st);
+  HIPCHK(hipGetLastError());
+  std::vector<double> d((size_t)z.M * 8), rate(z.R);
+  HIPCHK(hipMemcpyAsync(d.data(), ctx->ptrd(ctx->w.diag), d.size() * 8, hipMemcpyDeviceToHost,
+                        ctx->st));
+  HIPCHK(hipMemcpyAsync(rate.data(), ctx->ptrd(ctx->w.rate), rate.size() * 8,
+                        hipMemcpyDeviceToHost, ctx->st));
+  HIPCHK(hipStreamSynchronize(ctx->st));
+  double ek = 0, ez = 0, et = 0, en = 0, bad = 0, rmax = 0;
+  for (int m = 0; m < z.M; ++m) {
+    ek += d[m * 8 + 0];
+    ez += d[m * 8 + 1];
+    et += d[m * 8 + 2];
+    en += d[m * 8 + 3];
+    bad = std::max(bad, d[m * 8 + 4]);
+  }
+  for (int k = 0; k < z.R; ++k) rmax = std::max(rmax, rate[k]);
+  const double s_o = ctx->g.s_o, s_i = ctx->g.s_i, pi = 3.14159265358979323846;
+  out->t = ctx->t;
+  out->E_kin = ek;
+  out->E_zon = ez;
+  out->E_therm = et;
+  out->enstrophy = en;
+  out->Re = std::sqrt(2.0 * ek / (pi * (s_o * s_o - s_i * s_i)));
+  out->Ro = out->Re * ctx->p.E;
+  out->dt_cfl = rmax > 0 ? 1.0 / rmax : INFINITY;
+  out->step = ctx->step;
+  out->nonfinite = bad > 0 ? 1 : 0;
+  return QG_OK;
+}
+
+const char* qg_last_error(const qg_ctx* ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+
+void qg_destroy(qg_ctx* ctx) { delete ctx; }
+
+qg_status qg_operator_band(double eta, int n_c, int which, double* out) {
+  if (!(eta > 0 && eta < 1) || n_c < 8 || which < 0 || which > 8 || !out) return QG_EINVAL;
+  Operators o = build_operators(eta, n_c);
+  const std::vector<double>* bl[9] = {&o.A0, &o.A2, &o.B0, &o.B2, &o.B4, &o.C, &o.D, &o.F0, &o.F2};
+  std::copy(bl[which]->begin(), bl[which]->end(), out);
+  return QG_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,52 @@
+// Host-side construction of the Chebyshev-integration operators and of the
+// per-wavenumber bordered factorisations (run once per time-step size).
+#pragma once
+#include <complex>
+#include <cstdint>
+#include <vector>
+
+namespace qg {
+
+using cplx = std::complex<double>;
+
+// Width of every stored operator band: offsets -8..+8 around the diagonal.
+constexpr int BANDW = 17;
+constexpr int BANDC = 8;  // centre index of a stored band row
+
+// m-independent banded operators, rows k = 0..K-1, entry [k*BANDW + (n-k+8)]
+// (rows below the number of tau rows are meaningless and stored as zero).
+struct Operators {
+  int K = 0;
+  std::vector<double> A0, A2;            // int^4 s^4 L_I = A0 + m^2 A2
+  std::vector<double> B0, B2, B4;        // int^4 s^4 Lap_m L_I
+  std::vector<double> C;                 // int^4 s^4
+  std::vector<double> D;                 // int^2 s^2
+  std::vector<double> F0, F2;            // int^2 s^2 Lap_m = F0 + m^2 F2
+};
+
+Operators build_operators(double eta, int K);
+
+// Factorisation of one bordered system (p tau rows on top of a band with
+// kl sub- and ku super-diagonals).  Band LU with partial pivoting of the
+// band block D (positions 0..n-1, n = K - p), Schur data for the border.
+template <typename T>
+struct BorderedFactor {
+  int p = 0, n = 0, kl = 0, ku = 0;
+  std::vector<int32_t> piv;   // [n] pivot offset (row swapped with j at step j)
+  std::vector<T> Lc;          // [n][kl] multipliers of column j, rows j+1..j+kl
+  std::vector<T> Uc;          // [n][kl+ku+1] e=0: 1/U(j,j); e>=1: U(j-e, j)
+  std::vector<T> W;           // [p][n]  w = B D^-1
+  std::vector<T> Cb;          // [kl][p] first kl rows of the border column C
+  std::vector<T> Minv;        // [p][p]  (A - w C)^-1
+};
+
+// Full bordered K x K matrix given as dense rows; builds the factor.
+template <typename T>
+bool factor_bordered(const std::vector<T>& full, int K, int p, int kl, int ku,
+                     BorderedFactor<T>& out);
+
+// Tau rows: Dirichlet at s_o, Dirichlet at s_i, third derivative at s_o,
+// Neumann at s_i (first p of them).
+void tau_row(int which, int K, double* row);
+
+}  // namespace qg

@@ -1,0 +1,215 @@
+"""Thin Python binding of libqg.so (argument marshalling only).
+
+Every step of the solver runs in the HIP library; PyTorch provides the
+device workspace and the stream.  Functions carry the C ABI names of
+include/qg.h; QGSolver wraps one context.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libqg.so")
+
+QG_OK, QG_EINVAL, QG_ENOMEM, QG_EDEVICE = 0, -1, -2, -3
+QG_ENONFINITE, QG_ESTATE, QG_EUNSUPPORTED = -4, -5, -6
+SCHEMES = {"cnab2": 0, "bpr353": 1}
+STATUS_NAMES = {0: "QG_OK", -1: "QG_EINVAL", -2: "QG_ENOMEM",
+                -3: "QG_EDEVICE", -4: "QG_ENONFINITE", -5: "QG_ESTATE",
+                -6: "QG_EUNSUPPORTED"}
+
+
+class qg_params(ctypes.Structure):
+    _fields_ = [("E", ctypes.c_double), ("Ra", ctypes.c_double),
+                ("Pr", ctypes.c_double), ("eta", ctypes.c_double),
+                ("n_phi", ctypes.c_int), ("n_r", ctypes.c_int),
+                ("n_c", ctypes.c_int), ("precision", ctypes.c_int)]
+
+
+class qg_diag(ctypes.Structure):
+    _fields_ = [("t", ctypes.c_double), ("E_kin", ctypes.c_double),
+                ("E_zon", ctypes.c_double), ("E_therm", ctypes.c_double),
+                ("enstrophy", ctypes.c_double), ("Re", ctypes.c_double),
+                ("Ro", ctypes.c_double), ("dt_cfl", ctypes.c_double),
+                ("step", ctypes.c_longlong), ("nonfinite", ctypes.c_int)]
+
+
+class QGError(RuntimeError):
+    def __init__(self, status, msg=""):
+        self.status = status
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
+
+
+_lib = None
+
+
+def load():
+    """Load libqg.so; fails loudly when the HIP library is not built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(
+            f"HIP library {LIB_PATH} is missing; run __graft_entry__.build() "
+            "(or python -m paper_1902_07092_amd.build)")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, i, d = ctypes.c_void_p, ctypes.c_int, ctypes.c_double
+    sig = {
+        "qg_workspace_size": (i, [ctypes.POINTER(qg_params),
+                                  ctypes.POINTER(ctypes.c_size_t)]),
+        "qg_create": (i, [ctypes.POINTER(vp), ctypes.POINTER(qg_params), vp,
+                          ctypes.c_size_t, vp]),
+        "qg_set_state": (i, [vp, vp, vp, vp, i]),
+        "qg_get_state": (i, [vp, vp, vp, vp, i]),
+        "qg_step": (i, [vp, d, i, i]),
+        "qg_diagnostics": (i, [vp, ctypes.POINTER(qg_diag)]),
+        "qg_last_error": (ctypes.c_char_p, [vp]),
+        "qg_destroy": (None, [vp]),
+        "qg_operator_band": (i, [d, i, i, vp]),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(L, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = L
+    return L
+
+
+# ---------------------------------------------------------------- C ABI names
+def qg_workspace_size(params: qg_params) -> int:
+    n = ctypes.c_size_t(0)
+    st = load().qg_workspace_size(ctypes.byref(params), ctypes.byref(n))
+    if st != QG_OK:
+        raise QGError(st, "invalid parameters")
+    return n.value
+
+
+def qg_operator_band(eta: float, n_c: int, which: int) -> np.ndarray:
+    out = np.zeros((n_c, 17), np.float64)
+    st = load().qg_operator_band(eta, n_c, which,
+                                 out.ctypes.data_as(ctypes.c_void_p))
+    if st != QG_OK:
+        raise QGError(st, "qg_operator_band")
+    return out
+
+
+def _check(ctx, st):
+    if st != QG_OK:
+        msg = load().qg_last_error(ctx)
+        raise QGError(st, msg.decode() if msg else "")
+
+
+def qg_create(params, workspace_ptr, nbytes, stream_ptr):
+    ctx = ctypes.c_void_p()
+    st = load().qg_create(ctypes.byref(ctx), ctypes.byref(params),
+                          ctypes.c_void_p(workspace_ptr), nbytes,
+                          ctypes.c_void_p(stream_ptr))
+    if st != QG_OK:
+        raise QGError(st, "qg_create")
+    return ctx
+
+
+def qg_set_state(ctx, psi_ptr, theta_ptr, uphi_ptr, on_device):
+    _check(ctx, load().qg_set_state(ctx, psi_ptr, theta_ptr, uphi_ptr,
+                                    int(on_device)))
+
+
+def qg_get_state(ctx, psi_ptr, theta_ptr, uphi_ptr, on_device):
+    _check(ctx, load().qg_get_state(ctx, psi_ptr, theta_ptr, uphi_ptr,
+                                    int(on_device)))
+
+
+def qg_step(ctx, dt, scheme, nsteps):
+    _check(ctx, load().qg_step(ctx, float(dt), int(scheme), int(nsteps)))
+
+
+def qg_diagnostics(ctx) -> dict:
+    d = qg_diag()
+    _check(ctx, load().qg_diagnostics(ctx, ctypes.byref(d)))
+    return {name: getattr(d, name) for name, _ in qg_diag._fields_}
+
+
+def qg_last_error(ctx) -> str:
+    msg = load().qg_last_error(ctx)
+    return msg.decode() if msg else ""
+
+
+def qg_destroy(ctx):
+    load().qg_destroy(ctx)
+
+
+# ---------------------------------------------------------------- wrapper
+class QGSolver:
+    """One solver context on a HIP device, workspace allocated by torch."""
+
+    def __init__(self, E, Ra, Pr, eta, n_phi, n_r, n_c=0, device="cuda:0",
+                 stream=None):
+        import torch
+        self.torch = torch
+        self.device = torch.device(device)
+        self.params = qg_params(E, Ra, Pr, eta, n_phi, n_r, n_c, 0)
+        self.M = n_phi // 3 + 1
+        self.K = n_c if n_c else (2 * (n_r - 1)) // 3
+        nbytes = qg_workspace_size(self.params)
+        with torch.cuda.device(self.device):
+            self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8,
+                                         device=self.device)
+            base = self.workspace.data_ptr()
+            aligned = (base + 255) // 256 * 256
+            self.stream = stream or torch.cuda.current_stream(self.device)
+            self.ctx = qg_create(self.params, aligned, nbytes,
+                                 self.stream.cuda_stream)
+        self.nbytes = nbytes
+
+    def __del__(self):
+        ctx = getattr(self, "ctx", None)
+        if ctx:
+            qg_destroy(ctx)
+            self.ctx = None
+
+    def _arrays(self, psi, theta, uphi):
+        torch = self.torch
+        if isinstance(psi, torch.Tensor):
+            ps = psi.to(self.device, torch.complex128).contiguous()
+            th = theta.to(self.device, torch.complex128).contiguous()
+            up = uphi.to(self.device, torch.float64).contiguous()
+            return (ps, th, up), (ps.data_ptr(), th.data_ptr(),
+                                  up.data_ptr()), 1
+        ps = np.ascontiguousarray(psi, np.complex128)
+        th = np.ascontiguousarray(theta, np.complex128)
+        up = np.ascontiguousarray(uphi, np.float64)
+        return (ps, th, up), (ps.ctypes.data, th.ctypes.data,
+                              up.ctypes.data), 0
+
+    def set_state(self, psi, theta, uphi):
+        keep, ptrs, dev = self._arrays(psi, theta, uphi)
+        if keep[0].shape != (self.M, self.K) or keep[1].shape != (
+                self.M, self.K) or keep[2].shape != (self.K,):
+            raise ValueError("state arrays must be (M, K), (M, K), (K,)")
+        qg_set_state(self.ctx, *[ctypes.c_void_p(p) for p in ptrs], dev)
+
+    def get_state(self, on_device=False):
+        torch = self.torch
+        if on_device:
+            ps = torch.empty((self.M, self.K), dtype=torch.complex128,
+                             device=self.device)
+            th = torch.empty_like(ps)
+            up = torch.empty(self.K, dtype=torch.float64, device=self.device)
+            ptrs = (ps.data_ptr(), th.data_ptr(), up.data_ptr())
+        else:
+            ps = np.empty((self.M, self.K), np.complex128)
+            th = np.empty_like(ps)
+            up = np.empty(self.K)
+            ptrs = (ps.ctypes.data, th.ctypes.data, up.ctypes.data)
+        qg_get_state(self.ctx, *[ctypes.c_void_p(p) for p in ptrs],
+                     int(on_device))
+        return ps, th, up
+
+    def step(self, dt, scheme="cnab2", n=1):
+        qg_step(self.ctx, dt, SCHEMES[scheme], n)
+
+    def diagnostics(self):
+        return qg_diagnostics(self.ctx)
