@@ -1,0 +1,171 @@
+#!/usr/bin/env python
+"""Benchmark of the FP64 IMEX step of spherical QG convection on one GPU.
+
+Workload (default): 3072 x 1025 grid (N_m = 1024, N_c = 682), E = 1e-8,
+Pr = 1, Ra = 20 Ra_c, CNAB2, dt = 3e-9, seeded turbulent-like initial
+state (k^-5/3 spectrum, random phases).  A step is one CNAB2 step of the
+whole hot path: Chebyshev synthesis, azimuthal FFTs and products, radial
+analysis, explicit terms, right-hand sides and the bordered solves of every
+m.  The state is resident in HBM before the timed region; the time-step
+factorisation is done once before it (as in the paper's timings).
+
+Prints one JSON line (metric, value = grid-point-steps/s, roofline of the
+dominant kernel measured with HIP events on the solver's stream, CPU
+baseline of the oracle on the host cores).
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "grid-point-steps/s FP64 vs mixed/batched; adjoint/forward time ratio"
+HBM_PEAK_GBS = 8000.0
+
+
+def alg_bytes(kernel, M, R, K, nterm=2):
+    """Compulsory HBM bytes of one launch (FP64 complex = 16 B): the
+    kernel's own inputs and outputs, factor re-reads excluded."""
+    c = 16
+    return {
+        "synth": 2 * M * K * c + 6 * R * M * c,
+        "ring": 8 * R * M * c + 8 * R,
+        "analysis": 2 * R * M * c + 8 * R + 3 * M * K * c,
+        "solve_psi": (2 + nterm) * (M - 1) * K * c,
+        "solve_real": (2 + nterm) * (M + 1) * K * c,
+    }[kernel]
+
+
+def factor_bytes(kernel, M, K):
+    """Bytes of the stored LU/Schur factors one solve launch streams."""
+    if kernel == "solve_psi":
+        n = K - 4
+        return (M - 1) * (n * 4 + n * (8 + 17 + 4) * 16 + (32 + 16) * 16)
+    if kernel == "solve_real":
+        n = K - 2
+        return (M + 1) * (n * 4 + n * (4 + 9 + 2) * 8 + (8 + 4) * 8)
+    return 0
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for f in ("kernels.hip", "kernels.h"):
+        with open(os.path.join(ROOT, "paper_1902_07092_amd", "csrc", f),
+                  "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_for(kernel, workload):
+    """Counter-measured HBM bytes per launch from profiles/, if they were
+    taken on the current kernel sources."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    try:
+        data = json.load(open(path))
+        rec = data[workload][kernel]
+        if rec.get("source_hash") != kernel_source_hash():
+            return None
+        return rec["bytes_per_launch"]
+    except (KeyError, ValueError, TypeError):
+        return None
+
+
+def cpu_baseline(w, state, steps):
+    """The oracle, as it stands, on the host cores: init (operators and
+    factorisation) untimed, then `steps` full steps timed."""
+    from oracle.step import QGOracle
+    o = QGOracle(w.E, w.Ra, w.Pr, w.eta, w.n_phi, w.n_r, w.n_c)
+    o.set_state(state.psi, state.theta, state.uphi0)
+    o.factor(0.5 * w.dt)
+    t0 = time.perf_counter()
+    o.step(w.dt, w.scheme, steps)
+    dt = time.perf_counter() - t0
+    return {"value": w.grid_points * steps / dt, "unit": "grid-point-steps/s",
+            "cores": os.cpu_count(), "kind": "oracle",
+            "sample": f"{steps} full {w.scheme.upper()} step(s) of "
+                      f"{w.name}, oracle init untimed, {dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--workload", default="large_3072x1025_E1e-8_cnab2")
+    ap.add_argument("--cpu-steps", type=int, default=1)
+    ap.add_argument("--no-cpu", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: the step's per-m and per-ring "
+              "kernels run on a single device; --gpus must be 1",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_1902_07092_amd import inputs, qg
+    w = inputs.WORKLOADS[args.workload]
+    state = inputs.workload_state(w)
+    solver = qg.QGSolver(w.E, w.Ra, w.Pr, w.eta, w.n_phi, w.n_r, w.n_c,
+                         device="cuda:0")
+    solver.set_state(state.psi, state.theta, state.uphi0)
+    solver.step(w.dt, w.scheme, 0)            # factorise (untimed)
+    solver.step(w.dt, w.scheme, args.warmup)
+    stream = solver.stream
+    torch.cuda.synchronize()
+    start = torch.cuda.Event(enable_timing=True)
+    stop = torch.cuda.Event(enable_timing=True)
+    start.record(stream)
+    solver.step(w.dt, w.scheme, args.steps)
+    stop.record(stream)
+    torch.cuda.synchronize()
+    total_ms = start.elapsed_time(stop)
+    ms_per_step = total_ms / args.steps
+    value = w.grid_points * args.steps / (total_ms * 1e-3)
+
+    # per-kernel durations over the same number of steps, HIP events on
+    # the solver's stream around every launch
+    kern = solver.step_timed(w.dt, w.scheme, args.steps)
+    M, R, K = w.M, w.n_r, w.n_c
+    dominant = max(kern, key=lambda k: kern[k][0])
+    ms_tot, launches = kern[dominant]
+    avg_s = ms_tot / launches * 1e-3
+    ab = alg_bytes(dominant, M, R, K)
+    achieved = ab / avg_s / 1e9
+    traffic = traffic_for(dominant, w.name)
+    roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                "traffic": traffic, "kernel": dominant,
+                "alg_bytes_per_launch": ab,
+                "avg_launch_us": avg_s * 1e6}
+    kernels = {k: {"avg_launch_us": v[0] / max(1, v[1]) * 1e3,
+                   "launches": v[1],
+                   "alg_GBps": alg_bytes(k, M, R, K) / (v[0] / max(1, v[1])
+                                                        * 1e-3) / 1e9,
+                   "factor_bytes_per_launch": factor_bytes(k, M, K)}
+               for k, v in kern.items()}
+    out = {"metric": METRIC, "value": value, "unit": "grid-point-steps/s",
+           "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+           "ms_per_step": ms_per_step, "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+           "data": "synthetic",
+           "config": {"workload": w.name, "n_phi": w.n_phi, "n_r": w.n_r,
+                      "n_c": w.n_c, "E": w.E, "Ra": w.Ra, "Pr": w.Pr,
+                      "eta": w.eta, "scheme": w.scheme, "dt": w.dt,
+                      "parallelism": "single GPU"},
+           "roofline": roofline, "kernels": kernels}
+    print(f"[bench] gpu done: {ms_per_step:.4f} ms/step", file=sys.stderr,
+          flush=True)
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(w, state, args.cpu_steps)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

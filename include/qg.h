@@ -115,6 +115,17 @@ qg_status qg_get_state(qg_ctx *ctx, double *psi, double *theta, double *uphi,
  * qg_set_state. */
 qg_status qg_step(qg_ctx *ctx, double dt, int scheme, int nsteps);
 
+/* qg_step with per-kernel timing, for benchmarks: HIP events are recorded
+ * on the context's stream around every kernel launch.  On return (stream
+ * synchronised) kernel_ms[c] holds the summed duration in milliseconds and
+ * launches[c] the number of launches of kernel class c:
+ *   0 synthesis (inverse DCT + fields, per m)   1 azimuthal transforms and
+ *   products (per radial level)   2 analysis (forward DCT + explicit terms,
+ *   per m)   3 Psi bordered solves   4 theta / zonal-flow bordered solves.
+ * A dt change refactorises before the timed steps. */
+qg_status qg_step_timed(qg_ctx *ctx, double dt, int scheme, int nsteps,
+                        double *kernel_ms, int *launches);
+
 /* Diagnostics of the current state (synchronises the stream). */
 qg_status qg_diagnostics(qg_ctx *ctx, qg_diag *out);
 

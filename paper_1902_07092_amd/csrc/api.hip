@@ -166,6 +166,11 @@ struct qg_ctx {
   double t = 0.0;
   long long step = 0;
   std::string err;
+  // per-kernel timing (qg_step_timed): events recorded around each launch
+  bool prof = false;
+  std::vector<hipEvent_t> ev_pool;
+  size_t ev_used = 0;
+  std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> ev_marks;
   double2* ptr2(size_t off) { return reinterpret_cast<double2*>(ws + off); }
   double* ptrd(size_t off) { return reinterpret_cast<double*>(ws + off); }
   double2* psi() { return ptr2(w.state); }
@@ -329,20 +334,48 @@ qg_status refactor(qg_ctx* ctx, double adt) {
   return QG_OK;
 }
 
+// Kernel classes timed by qg_step_timed.
+enum { K_SYNTH = 0, K_RING = 1, K_ANALYSIS = 2, K_SOLVE_PSI = 3, K_SOLVE_REAL = 4, K_COUNT = 5 };
+
+hipEvent_t next_event(qg_ctx* ctx) {
+  if (ctx->ev_used == ctx->ev_pool.size()) {
+    hipEvent_t e;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    ctx->ev_pool.push_back(e);
+  }
+  return ctx->ev_pool[ctx->ev_used++];
+}
+
+template <typename F>
+void timed(qg_ctx* ctx, int cls, F launch) {
+  if (!ctx->prof) { launch(); return; }
+  hipEvent_t a = next_event(ctx), b = next_event(ctx);
+  if (a) hipEventRecord(a, ctx->st);
+  launch();
+  if (b) hipEventRecord(b, ctx->st);
+  if (a && b) ctx->ev_marks.push_back({cls, {a, b}});
+}
+
 qg_status explicit_terms(qg_ctx* ctx, const double2* psi, const double2* th, double2* Ep,
                          double2* Et) {
-  launch_synth(ctx->g, psi, th, ctx->ptr2(ctx->w.X), nullptr, ctx->t_synth, ctx->st);
-  launch_ring(ctx->g, ctx->ptr2(ctx->w.X), ctx->ptr2(ctx->w.NL), ctx->ptrd(ctx->w.zonal), nullptr,
-              ctx->t_ring, ctx->st);
-  launch_analysis(ctx->g, ctx->b, ctx->ptr2(ctx->w.NL), ctx->ptrd(ctx->w.zonal), th, Ep, Et,
-                  ctx->t_ana, ctx->st);
+  timed(ctx, K_SYNTH, [&] {
+    launch_synth(ctx->g, psi, th, ctx->ptr2(ctx->w.X), nullptr, ctx->t_synth, ctx->st);
+  });
+  timed(ctx, K_RING, [&] {
+    launch_ring(ctx->g, ctx->ptr2(ctx->w.X), ctx->ptr2(ctx->w.NL), ctx->ptrd(ctx->w.zonal),
+                nullptr, ctx->t_ring, ctx->st);
+  });
+  timed(ctx, K_ANALYSIS, [&] {
+    launch_analysis(ctx->g, ctx->b, ctx->ptr2(ctx->w.NL), ctx->ptrd(ctx->w.zonal), th, Ep, Et,
+                    ctx->t_ana, ctx->st);
+  });
   HIPCHK(hipGetLastError());
   return QG_OK;
 }
 
 qg_status implicit_solve(qg_ctx* ctx, const RhsSpec& rs) {
-  launch_solve_psi(ctx->g, ctx->b, ctx->Fp, rs, ctx->st);
-  launch_solve_real(ctx->g, ctx->b, ctx->Fr, rs, ctx->st);
+  timed(ctx, K_SOLVE_PSI, [&] { launch_solve_psi(ctx->g, ctx->b, ctx->Fp, rs, ctx->st); });
+  timed(ctx, K_SOLVE_REAL, [&] { launch_solve_real(ctx->g, ctx->b, ctx->Fr, rs, ctx->st); });
   HIPCHK(hipGetLastError());
   return QG_OK;
 }
@@ -447,9 +480,9 @@ qg_status qg_create(qg_ctx** out, const qg_params* p, void* workspace, size_t wo
   Sizes z;
   std::string why;
   if (!sizes_of(p, z, why)) return QG_EINVAL;
-  Plan pd, pp;
+  Plan pd, pp, ph;
   if (!is_pow2(z.R - 1) || !make_plan(2 * (z.R - 1), pd) || !make_plan(z.nphi, pp) ||
-      z.nphi % 3)
+      z.nphi % 6 || !make_plan(z.nphi / 2, ph))
     return QG_EUNSUPPORTED;
   if (!workspace || ((uintptr_t)workspace & 255)) return QG_EINVAL;
   WsMap w = map_workspace(z);
@@ -467,7 +500,8 @@ qg_status qg_create(qg_ctx** out, const qg_params* p, void* workspace, size_t wo
   const int MAXB = 4, MAXP = 5, MAXJ = 16;
   ctx->t_synth = round64(std::max({64, (z.R + MAXP - 1) / MAXP, (pd.max_nb + MAXB - 1) / MAXB}));
   ctx->t_ana = ctx->t_synth;
-  ctx->t_ring = round64(std::max({64, (z.nphi + MAXJ - 1) / MAXJ, (pp.max_nb + MAXB - 1) / MAXB}));
+  ctx->t_ring = round64(std::max({64, (z.nphi + MAXJ - 1) / MAXJ, (pp.max_nb + MAXB - 1) / MAXB,
+                                  (ph.max_nb + MAXB - 1) / MAXB}));
   int dev = 0;
   hipDeviceProp_t prop;
   if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess) {
@@ -538,9 +572,15 @@ qg_status qg_create(qg_ctx** out, const qg_params* p, void* workspace, size_t wo
   g.dct.n = pd.n; g.dct.npass = pd.npass;
   std::copy(pd.radix, pd.radix + 24, g.dct.radix);
   g.dct.tw = ctx->ptr2(w.twd);
+  g.dct.tw_stride = 1;
   g.phi.n = pp.n; g.phi.npass = pp.npass;
   std::copy(pp.radix, pp.radix + 24, g.phi.radix);
   g.phi.tw = ctx->ptr2(w.twp);
+  g.phi.tw_stride = 1;
+  g.phi_half.n = ph.n; g.phi_half.npass = ph.npass;
+  std::copy(ph.radix, ph.radix + 24, g.phi_half.radix);
+  g.phi_half.tw = ctx->ptr2(w.twp);
+  g.phi_half.tw_stride = 2;
   const double* bd = ctx->ptrd(w.bands);
   const size_t bs = (size_t)z.K * BANDW;
   ctx->b = Bands{bd, bd + bs, bd + 2 * bs, bd + 3 * bs, bd + 4 * bs,
@@ -694,9 +734,40 @@ qg_status qg_diagnostics(qg_ctx* ctx, qg_diag* out) {
   return QG_OK;
 }
 
+qg_status qg_step_timed(qg_ctx* ctx, double dt, int scheme, int nsteps, double* kernel_ms,
+                        int* launches) {
+  if (!ctx || !kernel_ms || !launches) return QG_EINVAL;
+  // factorise first so that the refactorisation is outside the timing
+  if (0.5 * dt != ctx->factored_adt && dt > 0 && std::isfinite(dt)) {
+    qg_status s = refactor(ctx, 0.5 * dt);
+    if (s != QG_OK) return s;
+    ctx->have_prev = 0;
+  }
+  ctx->prof = true;
+  ctx->ev_used = 0;
+  ctx->ev_marks.clear();
+  qg_status s = qg_step(ctx, dt, scheme, nsteps);
+  ctx->prof = false;
+  if (s != QG_OK) return s;
+  HIPCHK(hipStreamSynchronize(ctx->st));
+  for (int c = 0; c < K_COUNT; ++c) { kernel_ms[c] = 0.0; launches[c] = 0; }
+  for (auto& mk : ctx->ev_marks) {
+    float ms = 0.f;
+    HIPCHK(hipEventElapsedTime(&ms, mk.second.first, mk.second.second));
+    kernel_ms[mk.first] += ms;
+    launches[mk.first] += 1;
+  }
+  ctx->ev_marks.clear();
+  return QG_OK;
+}
+
 const char* qg_last_error(const qg_ctx* ctx) { return ctx ? ctx->err.c_str() : "null context"; }
 
-void qg_destroy(qg_ctx* ctx) { delete ctx; }
+void qg_destroy(qg_ctx* ctx) {
+  if (!ctx) return;
+  for (hipEvent_t e : ctx->ev_pool) hipEventDestroy(e);
+  delete ctx;
+}
 
 qg_status qg_operator_band(double eta, int n_c, int which, double* out) {
   if (!(eta > 0 && eta < 1) || n_c < 8 || which < 0 || which > 8 || !out) return QG_EINVAL;

@@ -10,7 +10,8 @@ struct FftPlan {
   int n;
   int npass;
   int radix[24];
-  const double2* tw;
+  const double2* tw;   // tw[k * tw_stride] = exp(-2 pi i k / n)
+  int tw_stride;
 };
 
 struct Geom {
@@ -23,6 +24,7 @@ struct Geom {
   const double* dsk;            // local radial spacing (CFL)
   FftPlan dct;                  // length 2 (R - 1)
   FftPlan phi;                  // length nphi
+  FftPlan phi_half;             // length nphi / 2 (real transforms)
 };
 
 struct Bands {  // [K][17] each, see host_ops.h

@@ -72,7 +72,7 @@ __device__ void fft_lds(double2* buf, const FftPlan& P, int sgn) {
 #pragma unroll
       for (int r = 1; r < 4; ++r) {
         if (r < R) {
-          double2 w = P.tw[k * r * tws];
+          double2 w = P.tw[k * r * tws * P.tw_stride];
           if (sgn > 0) w.y = -w.y;
           v[i][r] = cmul(v[i][r], w);
         }
@@ -335,24 +335,28 @@ __global__ void synth_kernel(Geom g, const double2* __restrict__ psi,
 
 // ---------------------------------------------------------------- ring
 // Per radial level: three complex inverse FFTs of length N_phi (each
-// carries two real fields), the products
+// carries two real fields of similar size), the products
 //   N_omega = dPsi/dphi c_w + v d omega/dphi,
 //   N_theta = dPsi/dphi c_t + v d theta/dphi,
-// one forward FFT of N_omega + i N_theta scaled by 1/N_phi and truncated to
-// m <= N_m, and the zonal forcing mean(u_s omega) = 2 sum_{m>=1}
-// Re(u_s,m conj(omega_m)).
+// then one real forward FFT per product (eq. ifft; N_omega can exceed
+// N_theta by many orders of magnitude, so the two never share a complex
+// transform), scaled by 1/N_phi and truncated to m <= N_m, and the zonal
+// forcing mean(u_s omega) = 2 sum_{m>=1} Re(u_s,m conj(omega_m)).
+// A real sequence x of length N goes through a complex FFT of length N/2 of
+// z_j = x_2j + i x_2j+1:  X_k = (Z_k + Z*_{N/2-k})/2 - (i/2) w^k (Z_k - Z*_{N/2-k}),
+// w = exp(-2 pi i / N).
 template <int MAXB, int MAXJ>
 __global__ void ring_kernel(Geom g, const double2* __restrict__ X, double2* __restrict__ NL,
                             double* __restrict__ zonal, double* __restrict__ rate) {
   extern __shared__ double2 fb[];
   __shared__ double red[16];
-  const int R = g.R, M = g.M, nphi = g.nphi;
+  const int R = g.R, M = g.M, nphi = g.nphi, nh = nphi / 2;
   const int T = blockDim.x, t = threadIdx.x;
   const int k = blockIdx.x;
   const double s = g.half * g.xk[k] + g.mid;
   const double h2s = (g.s_o * g.s_o - s * s) / s;
   double2 z1[MAXJ];
-  double nw[MAXJ];
+  double nw[MAXJ], nt[MAXJ];
   double rmax = 0.0;
   for (int q = 0; q < 3; ++q) {
     const double2* A = X + ((size_t)(2 * q) * R + k) * M;
@@ -381,28 +385,39 @@ __global__ void ring_kernel(Geom g, const double2* __restrict__ X, double2* __re
       } else if (q == 1) {
         nw[i] = z1[i].x * z.x + z1[i].y * z.y;
       } else {
-        fb[j] = make_double2(nw[i], z1[i].x * z.x + z1[i].y * z.y);
+        nt[i] = z1[i].x * z.x + z1[i].y * z.y;
       }
     }
     __syncthreads();
   }
-  fft_lds<MAXB>(fb, g.phi, -1);
+  // real products, N_omega in doubles [0, nphi), N_theta in [nphi, 2 nphi)
+  double* fr = reinterpret_cast<double*>(fb);
+#pragma unroll
+  for (int i = 0; i < MAXJ; ++i) {
+    int j = t + i * T;
+    if (j >= nphi) continue;
+    fr[j] = nw[i];
+    fr[nphi + j] = nt[i];
+  }
+  __syncthreads();
+  fft_lds<MAXB>(fb, g.phi_half, -1);
+  fft_lds<MAXB>(fb + nh, g.phi_half, -1);
   const double inv = 1.0 / nphi;
   for (int m = t; m < M; m += T) {
-    double2 Wm = fb[m];
-    double2 nw_m, nt_m;
-    if (m == 0) {
-      nw_m = make_double2(Wm.x * inv, 0.0);
-      nt_m = make_double2(Wm.y * inv, 0.0);
-    } else {
-      double2 Wn = fb[nphi - m];
-      double2 sum = make_double2(Wm.x + Wn.x, Wm.y - Wn.y);   // W_m + conj(W_-m)
-      double2 dif = make_double2(Wm.x - Wn.x, Wm.y + Wn.y);   // W_m - conj(W_-m)
-      nw_m = (0.5 * inv) * sum;
-      nt_m = make_double2(0.5 * inv * dif.y, -0.5 * inv * dif.x);
+    const double2 w = g.phi.tw[m];
+#pragma unroll
+    for (int f = 0; f < 2; ++f) {
+      const double2* Z = fb + f * nh;
+      double2 zk = Z[m % nh];
+      double2 zc = Z[(nh - m % nh) % nh];
+      zc.y = -zc.y;
+      double2 e = 0.5 * (zk + zc);
+      double2 d = zk - zc;
+      double2 o = make_double2(0.5 * d.y, -0.5 * d.x);   // (Z_k - Z*)/(2i)
+      double2 xm = e + cmul(w, o);
+      if (m == 0) xm.y = 0.0;
+      NL[((size_t)f * R + k) * M + m] = inv * xm;
     }
-    NL[((size_t)0 * R + k) * M + m] = nw_m;
-    NL[((size_t)1 * R + k) * M + m] = nt_m;
   }
   // zonal forcing from the spectral fields: u_s,m = (h^2/s) X0_m,
   // omega_m = X3_m / (i m)  =>  Re(u_s,m conj(omega_m)) = -(h^2/s) Im(X0 conj X3)/m

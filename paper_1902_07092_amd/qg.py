@@ -69,6 +69,7 @@ def load():
         "qg_last_error": (ctypes.c_char_p, [vp]),
         "qg_destroy": (None, [vp]),
         "qg_operator_band": (i, [d, i, i, vp]),
+        "qg_step_timed": (i, [vp, d, i, i, vp, vp]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(L, name)
@@ -124,6 +125,18 @@ def qg_get_state(ctx, psi_ptr, theta_ptr, uphi_ptr, on_device):
 
 def qg_step(ctx, dt, scheme, nsteps):
     _check(ctx, load().qg_step(ctx, float(dt), int(scheme), int(nsteps)))
+
+
+KERNEL_CLASSES = ("synth", "ring", "analysis", "solve_psi", "solve_real")
+
+
+def qg_step_timed(ctx, dt, scheme, nsteps):
+    ms = (ctypes.c_double * 5)()
+    n = (ctypes.c_int * 5)()
+    _check(ctx, load().qg_step_timed(ctx, float(dt), int(scheme), int(nsteps),
+                                     ctypes.cast(ms, ctypes.c_void_p),
+                                     ctypes.cast(n, ctypes.c_void_p)))
+    return {k: (ms[i], n[i]) for i, k in enumerate(KERNEL_CLASSES)}
 
 
 def qg_diagnostics(ctx) -> dict:
@@ -210,6 +223,10 @@ class QGSolver:
 
     def step(self, dt, scheme="cnab2", n=1):
         qg_step(self.ctx, dt, SCHEMES[scheme], n)
+
+    def step_timed(self, dt, scheme="cnab2", n=1):
+        """Returns {kernel class: (total ms, launches)}."""
+        return qg_step_timed(self.ctx, dt, SCHEMES[scheme], n)
 
     def diagnostics(self):
         return qg_diagnostics(self.ctx)

@@ -1,0 +1,92 @@
+"""Write tests/golden/parity_tolerances.json: the FP64 rounding floor of
+the oracle for each GPU parity case, measured by re-running the oracle with
+rounding-level noise injected into every transform and derivative.
+
+A backward-stable transform (FFT, DCT, coefficient recurrence) returns y
+with |y - y_exact| <= c u ||y||, u = 2^-53.  Two correct FP64
+implementations therefore differ by noise of that size at each transform;
+the step then propagates it.  The floor of a field is
+max over seeds of max|y_noisy - y| / max|y| after the case's steps.  The
+parity tolerance is max(1e-11, 10 x floor).
+
+Calls only the oracle and the seeded input generators.
+"""
+import json
+import os
+import sys
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(os.path.dirname(HERE))
+sys.path.insert(0, ROOT)
+
+from oracle import transforms as tr  # noqa: E402
+from oracle.step import QGOracle  # noqa: E402
+from paper_1902_07092_amd import inputs  # noqa: E402
+
+U = 2.0 ** -53
+CASES = {
+    "small_cnab2_1": ("SMALL", "cnab2", 1),
+    "small_cnab2_20": ("SMALL", "cnab2", 20),
+    "small_bpr353_5": ("SMALL", "bpr353", 5),
+    "small_cnab2_100": ("SMALL", "cnab2", 100),
+    "medium_bpr353_2": ("MEDIUM", "bpr353", 2),
+    "large_cnab2_2": ("LARGE", "cnab2", 2),
+}
+WRAPPED = ("cheb_to_grid", "grid_to_cheb", "phi_to_grid", "grid_to_phi",
+           "cheb_ds")
+
+
+def _noisy(fn, rng):
+    def wrapped(*a, **k):
+        y = fn(*a, **k)
+        scale = np.abs(y).max(axis=-1, keepdims=True)
+        noise = rng.standard_normal(y.shape)
+        if np.iscomplexobj(y):
+            noise = noise + 1j * rng.standard_normal(y.shape)
+        return y + U * scale * noise
+    return wrapped
+
+
+def run(name, scheme, steps, seed):
+    w = getattr(inputs, name)
+    st = inputs.workload_state(w)
+    orig = {f: getattr(tr, f) for f in WRAPPED}
+    if seed is not None:
+        rng = np.random.default_rng(seed)
+        for f in WRAPPED:
+            setattr(tr, f, _noisy(orig[f], rng))
+    try:
+        o = QGOracle(w.E, w.Ra, w.Pr, w.eta, w.n_phi, w.n_r, w.n_c)
+        o.set_state(st.psi, st.theta, st.uphi0)
+        o.step(w.dt, scheme, steps)
+    finally:
+        for f in WRAPPED:
+            setattr(tr, f, orig[f])
+    return o
+
+
+def main(only=None):
+    path = os.path.join(HERE, "parity_tolerances.json")
+    out = json.load(open(path)) if os.path.exists(path) else {}
+    for case, (name, scheme, steps) in CASES.items():
+        if only and case not in only:
+            continue
+        ref = run(name, scheme, steps, None)
+        floor = {"psi": 0.0, "theta": 0.0, "uphi": 0.0}
+        for seed in (1, 2):
+            o = run(name, scheme, steps, seed)
+            for f in floor:
+                a, b = getattr(o, f), getattr(ref, f)
+                sc = np.abs(b).max()
+                if sc > 0:
+                    floor[f] = max(floor[f], float(np.abs(a - b).max() / sc))
+        tol = {f: max(1e-11, 10.0 * v) for f, v in floor.items()}
+        out[case] = {"floor": floor, "tol": tol}
+        print(case, out[case], flush=True)
+        json.dump(out, open(path, "w"), indent=1, sort_keys=True)
+
+
+if __name__ == "__main__":
+    main(sys.argv[1:] or None)
