@@ -35,20 +35,20 @@ def alg_bytes(kernel, M, R, K, nterm=2):
         "synth": 2 * M * K * c + 6 * R * M * c,
         "ring": 8 * R * M * c + 8 * R,
         "analysis": 2 * R * M * c + 8 * R + 3 * M * K * c,
-        "solve_psi": (2 + nterm) * (M - 1) * K * c,
-        "solve_real": (2 + nterm) * (M + 1) * K * c,
+        "solve": 2 * 2 * M * K * c,
+        "rhs": (2 + nterm) * 2 * M * K * c,
     }[kernel]
 
 
 def factor_bytes(kernel, M, K):
     """Bytes of the stored LU/Schur factors one solve launch streams."""
-    if kernel == "solve_psi":
-        n = K - 4
-        return (M - 1) * (n * 4 + n * (8 + 17 + 4) * 16 + (32 + 16) * 16)
-    if kernel == "solve_real":
-        n = K - 2
-        return (M + 1) * (n * 4 + n * (4 + 9 + 2) * 8 + (8 + 4) * 8)
-    return 0
+    if kernel != "solve":
+        return 0
+    n4, n2 = K - 4, K - 2
+    p4, p2 = (n4 + 15) // 16 * 16, (n2 + 15) // 16 * 16
+    psi = (M - 1) * (p4 * 4 + p4 * (8 + 13) * 16 + 4 * n4 * 16 + (32 + 16) * 16)
+    real = (M + 1) * (p2 * 4 + p2 * (4 + 5) * 8 + 2 * n2 * 8 + (8 + 4) * 8)
+    return psi + real
 
 
 def kernel_source_hash():

@@ -121,7 +121,8 @@ qg_status qg_step(qg_ctx *ctx, double dt, int scheme, int nsteps);
  * launches[c] the number of launches of kernel class c:
  *   0 synthesis (inverse DCT + fields, per m)   1 azimuthal transforms and
  *   products (per radial level)   2 analysis (forward DCT + explicit terms,
- *   per m)   3 Psi bordered solves   4 theta / zonal-flow bordered solves.
+ *   per m)   3 bordered solves of every system (one launch)   4 right-hand
+ *   sides of every system (one launch).
  * A dt change refactorises before the timed steps. */
 qg_status qg_step_timed(qg_ctx *ctx, double dt, int scheme, int nsteps,
                         double *kernel_ms, int *launches);

@@ -22,10 +22,13 @@ void launch_ring(const Geom& g, const double2* X, double2* NL, double* zonal, do
 void launch_analysis(const Geom& g, const Bands& b, const double2* NL, const double* zonal,
                      const double2* th_state, double2* Epsi, double2* Eth, int threads,
                      hipStream_t st);
-void launch_solve_psi(const Geom& g, const Bands& b, const FactorSet<double2>& F,
-                      const RhsSpec& rs, hipStream_t st);
-void launch_solve_real(const Geom& g, const Bands& b, const FactorSet<double>& F,
-                       const RhsSpec& rs, hipStream_t st);
+size_t solve_lds_bytes(const Geom& g, int kutp, int kutr);
+void launch_rhs(const Geom& g, const Bands& b, const RhsSpec& rs, double2* rhs, hipStream_t st);
+void launch_lin(const Geom& g, const Bands& b, const double2* ypsi, const double2* yth,
+                double2* lpsi, double2* lth, hipStream_t st);
+bool launch_solve(const Geom& g, const FactorSet<double2>& Fp, const FactorSet<double>& Fr,
+                  double2* rhs, const RhsSpec& rs, int kutp, int kutr, hipStream_t st);
+int solve_batch();
 }  // namespace qg
 
 using namespace qg;
@@ -81,6 +84,7 @@ struct Layout {
 
 struct Sizes {
   int M, K, R, nphi, n4, n2, Sr;
+  int p4, p2;   // n4, n2 padded to whole 32-step batches
 };
 
 bool sizes_of(const qg_params* p, Sizes& z, std::string& why) {
@@ -98,12 +102,14 @@ bool sizes_of(const qg_params* p, Sizes& z, std::string& why) {
   z.nphi = p->n_phi;
   z.n4 = K - 4;
   z.n2 = K - 2;
+  z.p4 = (z.n4 + 15) / 16 * 16;   // whole solve batches (16 steps)
+  z.p2 = (z.n2 + 15) / 16 * 16;
   z.Sr = z.M + 1;
   return true;
 }
 
 struct WsMap {
-  size_t state, ybuf, eslot, lslot, X, NL, zonal, rate, diag, xk, wq, dsk, twd, twp, bands;
+  size_t state, ybuf, eslot, lslot, X, NL, zonal, rate, diag, xk, wq, dsk, twd, twp, bands, rhs;
   size_t p_piv, p_L, p_U, p_W, p_C, p_Mi;
   size_t r_piv, r_L, r_U, r_W, r_C, r_Mi;
   size_t total;
@@ -130,16 +136,17 @@ WsMap map_workspace(const Sizes& z) {
   w.twd = L.take((size_t)2 * (z.R - 1) * sizeof(double2));
   w.twp = L.take((size_t)z.nphi * sizeof(double2));
   w.bands = L.take((size_t)9 * z.K * BANDW * sizeof(double));
-  w.p_piv = L.take(Sp * z.n4 * sizeof(int));
-  w.p_L = L.take(Sp * z.n4 * 8 * sizeof(double2));
-  w.p_U = L.take(Sp * z.n4 * 17 * sizeof(double2));
+  w.rhs = L.take((size_t)2 * z.M * z.K * sizeof(double2));
+  w.p_piv = L.take(Sp * z.p4 * sizeof(int));
+  w.p_L = L.take(Sp * z.p4 * 8 * sizeof(double2));
+  w.p_U = L.take(Sp * z.p4 * 17 * sizeof(double2));
   w.p_W = L.take(Sp * 4 * z.n4 * sizeof(double2));
   w.p_C = L.take(Sp * 8 * 4 * sizeof(double2));
   w.p_Mi = L.take(Sp * 16 * sizeof(double2));
   const size_t Sr = z.Sr;
-  w.r_piv = L.take(Sr * z.n2 * sizeof(int));
-  w.r_L = L.take(Sr * z.n2 * 4 * sizeof(double));
-  w.r_U = L.take(Sr * z.n2 * 9 * sizeof(double));
+  w.r_piv = L.take(Sr * z.p2 * sizeof(int));
+  w.r_L = L.take(Sr * z.p2 * 4 * sizeof(double));
+  w.r_U = L.take(Sr * z.p2 * 9 * sizeof(double));
   w.r_W = L.take(Sr * 2 * z.n2 * sizeof(double));
   w.r_C = L.take(Sr * 4 * 2 * sizeof(double));
   w.r_Mi = L.take(Sr * 4 * sizeof(double));
@@ -161,6 +168,7 @@ struct qg_ctx {
   FactorSet<double2> Fp;
   FactorSet<double> Fr;
   int t_synth = 64, t_ring = 64, t_ana = 64;
+  int kutp = 16, kutr = 8;   // stored U super-diagonals (Psi, real systems)
   double factored_adt = -1.0;
   int have_prev = 0, cur = 0;
   double t = 0.0;
@@ -255,20 +263,40 @@ void assemble(const qg_ctx* ctx, int kind, int m, double adt, std::vector<T>& fu
     }
 }
 
+// Largest row-interchange offset of a factorisation.
+template <typename T>
+int max_pivot(const BorderedFactor<T>& f) {
+  int mx = 0;
+  for (int v : f.piv) mx = std::max(mx, v);
+  return mx;
+}
+
+// Device layout of one system: steps padded to npad with identity steps
+// (no interchange, zero multipliers, U = 1), U truncated to wu columns
+// (the dropped fill is checked to be exactly zero).
 template <typename T, typename D2>
-void pack(const BorderedFactor<T>& f, size_t s, int kl, int wu, int p, int* piv, D2* L, D2* U,
-          D2* W, D2* C, D2* Mi) {
-  const int n = f.n;
+bool pack(const BorderedFactor<T>& f, size_t s, int kl, int wu, int p, int npad, int* piv, D2* L,
+          D2* U, D2* W, D2* C, D2* Mi) {
+  const int n = f.n, wfull = f.kl + f.ku + 1;
   auto cvt = [](const T& v) -> D2 {
     if constexpr (std::is_same<T, cplx>::value) return make_double2(v.real(), v.imag());
     else return v;
   };
-  for (int j = 0; j < n; ++j) piv[s * n + j] = f.piv[j];
-  for (size_t i = 0; i < (size_t)n * kl; ++i) L[s * n * kl + i] = cvt(f.Lc[i]);
-  for (size_t i = 0; i < (size_t)n * wu; ++i) U[s * n * wu + i] = cvt(f.Uc[i]);
+  const T one(1.0);
+  for (int j = 0; j < npad; ++j) {
+    piv[s * npad + j] = (j < n) ? f.piv[j] : 0;
+    for (int d = 0; d < kl; ++d)
+      L[(s * npad + j) * kl + d] = cvt(j < n ? f.Lc[(size_t)j * kl + d] : T(0));
+    for (int e = 0; e < wu; ++e)
+      U[(s * npad + j) * wu + e] = cvt(j < n ? f.Uc[(size_t)j * wfull + e] : (e == 0 ? one : T(0)));
+    if (j < n)
+      for (int e = wu; e < wfull; ++e)
+        if (f.Uc[(size_t)j * wfull + e] != T(0)) return false;
+  }
   for (size_t i = 0; i < (size_t)p * n; ++i) W[s * p * n + i] = cvt(f.W[i]);
   for (size_t i = 0; i < (size_t)kl * p; ++i) C[s * kl * p + i] = cvt(f.Cb[i]);
   for (size_t i = 0; i < (size_t)p * p; ++i) Mi[s * p * p + i] = cvt(f.Minv[i]);
+  return true;
 }
 
 template <typename F>
@@ -285,34 +313,44 @@ void parallel_for(int count, F fn) {
 qg_status refactor(qg_ctx* ctx, double adt) {
   const Sizes& z = ctx->z;
   const size_t Sp = z.M - 1, Sr = z.Sr;
-  std::vector<int> ppiv(Sp * z.n4), rpiv(Sr * z.n2);
-  std::vector<double2> pL(Sp * z.n4 * 8), pU(Sp * z.n4 * 17), pW(Sp * 4 * z.n4), pC(Sp * 32),
-      pM(Sp * 16);
-  std::vector<double> rL(Sr * z.n2 * 4), rU(Sr * z.n2 * 9), rW(Sr * 2 * z.n2), rC(Sr * 8),
-      rM(Sr * 4);
+  std::vector<BorderedFactor<cplx>> fp(Sp);
+  std::vector<BorderedFactor<double>> fr(Sr);
   std::vector<int> ok(Sp + Sr, 1);
   parallel_for((int)(Sp + Sr), [&](int idx) {
+    int p;
     if (idx < (int)Sp) {
-      int m = idx + 1, p;
       std::vector<cplx> full;
-      assemble<cplx>(ctx, 0, m, adt, full, p);
-      BorderedFactor<cplx> f;
-      if (!factor_bordered<cplx>(full, z.K, 4, 8, 8, f)) { ok[idx] = 0; return; }
-      pack<cplx, double2>(f, idx, 8, 17, 4, ppiv.data(), pL.data(), pU.data(), pW.data(),
-                          pC.data(), pM.data());
+      assemble<cplx>(ctx, 0, idx + 1, adt, full, p);
+      ok[idx] = factor_bordered<cplx>(full, z.K, 4, 8, 8, fp[idx]);
     } else {
-      int s = idx - (int)Sp, p;
-      int kind = (s == 0) ? 1 : 2, m = (s == 0) ? 0 : s - 1;
+      const int s = idx - (int)Sp;
       std::vector<double> full;
-      assemble<double>(ctx, kind, m, adt, full, p);
-      BorderedFactor<double> f;
-      if (!factor_bordered<double>(full, z.K, 2, 4, 4, f)) { ok[idx] = 0; return; }
-      pack<double, double>(f, s, 4, 9, 2, rpiv.data(), rL.data(), rU.data(), rW.data(), rC.data(),
-                           rM.data());
+      assemble<double>(ctx, s == 0 ? 1 : 2, s == 0 ? 0 : s - 1, adt, full, p);
+      ok[idx] = factor_bordered<double>(full, z.K, 2, 4, 4, fr[s]);
     }
   });
   for (int v : ok)
     if (!v) return fail(ctx, QG_EINVAL, "singular tau matrix (dt too large or bad parameters)");
+  int mp = 0, mr = 0;
+  for (auto& f : fp) mp = std::max(mp, max_pivot(f));
+  for (auto& f : fr) mr = std::max(mr, max_pivot(f));
+  int kutp = (8 + mp <= 12) ? 12 : 16;
+  int kutr = (4 + mr <= 4) ? 4 : 8;
+  std::vector<int> ppiv(Sp * z.p4), rpiv(Sr * z.p2);
+  std::vector<double2> pL(Sp * z.p4 * 8), pU(Sp * z.p4 * (kutp + 1)), pW(Sp * 4 * z.n4),
+      pC(Sp * 32), pM(Sp * 16);
+  std::vector<double> rL(Sr * z.p2 * 4), rU(Sr * z.p2 * (kutr + 1)), rW(Sr * 2 * z.n2),
+      rC(Sr * 8), rM(Sr * 4);
+  parallel_for((int)(Sp + Sr), [&](int idx) {
+    if (idx < (int)Sp)
+      ok[idx] = pack<cplx, double2>(fp[idx], idx, 8, kutp + 1, 4, z.p4, ppiv.data(), pL.data(),
+                                    pU.data(), pW.data(), pC.data(), pM.data());
+    else
+      ok[idx] = pack<double, double>(fr[idx - Sp], idx - Sp, 4, kutr + 1, 2, z.p2, rpiv.data(),
+                                     rL.data(), rU.data(), rW.data(), rC.data(), rM.data());
+  });
+  for (int v : ok)
+    if (!v) return fail(ctx, QG_EINVAL, "internal: band fill beyond the stored width");
   const WsMap& w = ctx->w;
   auto up = [&](size_t off, const void* src, size_t bytes) {
     return hipMemcpyAsync(ctx->ws + off, src, bytes, hipMemcpyHostToDevice, ctx->st);
@@ -330,12 +368,14 @@ qg_status refactor(qg_ctx* ctx, double adt) {
   HIPCHK(up(w.r_C, rC.data(), rC.size() * sizeof(double)));
   HIPCHK(up(w.r_Mi, rM.data(), rM.size() * sizeof(double)));
   HIPCHK(hipStreamSynchronize(ctx->st));
+  ctx->kutp = kutp;
+  ctx->kutr = kutr;
   ctx->factored_adt = adt;
   return QG_OK;
 }
 
 // Kernel classes timed by qg_step_timed.
-enum { K_SYNTH = 0, K_RING = 1, K_ANALYSIS = 2, K_SOLVE_PSI = 3, K_SOLVE_REAL = 4, K_COUNT = 5 };
+enum { K_SYNTH = 0, K_RING = 1, K_ANALYSIS = 2, K_SOLVE = 3, K_RHS = 4, K_COUNT = 5 };
 
 hipEvent_t next_event(qg_ctx* ctx) {
   if (ctx->ev_used == ctx->ev_pool.size()) {
@@ -350,9 +390,9 @@ template <typename F>
 void timed(qg_ctx* ctx, int cls, F launch) {
   if (!ctx->prof) { launch(); return; }
   hipEvent_t a = next_event(ctx), b = next_event(ctx);
-  if (a) hipEventRecord(a, ctx->st);
+  if (a) (void)hipEventRecord(a, ctx->st);
   launch();
-  if (b) hipEventRecord(b, ctx->st);
+  if (b) (void)hipEventRecord(b, ctx->st);
   if (a && b) ctx->ev_marks.push_back({cls, {a, b}});
 }
 
@@ -374,8 +414,15 @@ qg_status explicit_terms(qg_ctx* ctx, const double2* psi, const double2* th, dou
 }
 
 qg_status implicit_solve(qg_ctx* ctx, const RhsSpec& rs) {
-  timed(ctx, K_SOLVE_PSI, [&] { launch_solve_psi(ctx->g, ctx->b, ctx->Fp, rs, ctx->st); });
-  timed(ctx, K_SOLVE_REAL, [&] { launch_solve_real(ctx->g, ctx->b, ctx->Fr, rs, ctx->st); });
+  double2* rhs = ctx->ptr2(ctx->w.rhs);
+  timed(ctx, K_RHS, [&] { launch_rhs(ctx->g, ctx->b, rs, rhs, ctx->st); });
+  bool ok = true;
+  timed(ctx, K_SOLVE, [&] {
+    ok = launch_solve(ctx->g, ctx->Fp, ctx->Fr, rhs, rs, ctx->kutp, ctx->kutr, ctx->st);
+  });
+  if (!ok) return fail(ctx, QG_EUNSUPPORTED, "no solve kernel for this band width");
+  if (rs.lin_psi)
+    launch_lin(ctx->g, ctx->b, rs.out_psi, rs.out_th, rs.lin_psi, rs.lin_th, ctx->st);
   HIPCHK(hipGetLastError());
   return QG_OK;
 }
@@ -510,7 +557,8 @@ qg_status qg_create(qg_ctx** out, const qg_params* p, void* workspace, size_t wo
   }
   const size_t lds_synth = sizeof(double2) * (2 * z.K + 2 * (z.R - 1) + 2 * ctx->t_synth);
   const size_t lds_ring = sizeof(double2) * z.nphi;
-  const size_t lds_solve = sizeof(double2) * (2 * z.K) + sizeof(double2) * 32 * 25 + 128;
+  ctx->g.K = z.K;
+  const size_t lds_solve = solve_lds_bytes(ctx->g, 16, 8);
   if (ctx->t_synth > 1024 || ctx->t_ring > 1024 ||
       std::max({lds_synth, lds_ring, lds_solve}) > (size_t)prop.sharedMemPerBlock) {
     delete ctx;
@@ -539,8 +587,10 @@ qg_status qg_create(qg_ctx** out, const qg_params* p, void* workspace, size_t wo
   const std::vector<double>* bl[9] = {&ctx->ops.A0, &ctx->ops.A2, &ctx->ops.B0,
                                       &ctx->ops.B2, &ctx->ops.B4, &ctx->ops.C,
                                       &ctx->ops.D,  &ctx->ops.F0, &ctx->ops.F2};
-  for (int i = 0; i < 9; ++i)
-    std::copy(bl[i]->begin(), bl[i]->end(), bandbuf.begin() + (size_t)i * z.K * BANDW);
+  for (int i = 0; i < 9; ++i)   // device layout: offset-major [17][K]
+    for (int k = 0; k < z.K; ++k)
+      for (int o = 0; o < BANDW; ++o)
+        bandbuf[(size_t)i * z.K * BANDW + (size_t)o * z.K + k] = (*bl[i])[(size_t)k * BANDW + o];
   auto up = [&](size_t off, const void* src, size_t bytes) {
     return hipMemcpyAsync(ctx->ws + off, src, bytes, hipMemcpyHostToDevice, ctx->st);
   };
@@ -765,7 +815,7 @@ const char* qg_last_error(const qg_ctx* ctx) { return ctx ? ctx->err.c_str() : "
 
 void qg_destroy(qg_ctx* ctx) {
   if (!ctx) return;
-  for (hipEvent_t e : ctx->ev_pool) hipEventDestroy(e);
+  for (hipEvent_t e : ctx->ev_pool) (void)hipEventDestroy(e);
   delete ctx;
 }
 

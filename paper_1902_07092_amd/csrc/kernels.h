@@ -27,7 +27,7 @@ struct Geom {
   FftPlan phi_half;             // length nphi / 2 (real transforms)
 };
 
-struct Bands {  // [K][17] each, see host_ops.h
+struct Bands {  // [17][K] each (offset-major): entry (k, n) at [(n - k + 8) * K + k]
   const double *A0, *A2, *B0, *B2, *B4, *C, *D, *F0, *F2;
 };
 

@@ -466,92 +466,121 @@ __global__ void analysis_kernel(Geom g, Bands b, const double2* __restrict__ NL,
     if (m > 0) {
       if (k >= 4)
         for (int n = lo; n <= hi; ++n) {
-          double c = b.C[k * 17 + (n - k + 8)];
+          double c = b.C[(size_t)(n - k + 8) * K + k];
           double2 v = ca[n] + bcoef * times_i(thm[n]);
           ep += c * v;
         }
     } else if (k >= 2) {
-      for (int n = lo; n <= hi; ++n) ep -= b.D[k * 17 + (n - k + 8)] * ca[n];
+      for (int n = lo; n <= hi; ++n) ep -= b.D[(size_t)(n - k + 8) * K + k] * ca[n];
     }
     if (k >= 2)
-      for (int n = lo; n <= hi; ++n) et -= b.D[k * 17 + (n - k + 8)] * cb[n];
+      for (int n = lo; n <= hi; ++n) et -= b.D[(size_t)(n - k + 8) * K + k] * cb[n];
     Epsi[(size_t)m * K + k] = ep;
     Eth[(size_t)m * K + k] = et;
   }
 }
 
-// --------------------------------------------------------------- solve
-// One wavefront per bordered system.  kind 0: Psi of m = blockIdx.x + 1
-// (complex matrix A_m - a dt B_m, p = 4, band 8/8).  kind 1: blockIdx.x = 0
-// is the zonal flow (D - a dt E), blockIdx.x = 1 + m is theta of m
-// (D - a dt F_m / Pr); real matrices, p = 2, band 4/4.
-template <typename TF, int P, int KL, int KU>
-__global__ __launch_bounds__(64) void solve_kernel(Geom g, Bands b, FactorSet<TF> F,
-                                                   RhsSpec rs, int kind) {
-  constexpr int KUT = KL + KU;
-  constexpr int WU = KUT + 1;
-  constexpr int BATCH = 32;
-  extern __shared__ double2 sm[];
-  const int K = g.K, n = K - P;
-  const int t = threadIdx.x;
-  const int sys = blockIdx.x;
-  int m;
-  bool is_psi_row;   // state row lives in the psi array (Psi or zonal flow)
-  if (kind == 0) { m = sys + 1; is_psi_row = true; }
-  else if (sys == 0) { m = 0; is_psi_row = true; }
-  else { m = sys - 1; is_psi_row = false; }
-  const bool zonal = (kind == 1 && sys == 0);
-  double2* yb = sm;                 // K: base state, later the new state
-  double2* hb = sm + K;             // n: right-hand side / solution
-  TF* Lst = reinterpret_cast<TF*>(hb + n);
-  TF* Ust = Lst + BATCH * KL;
-  int* pst = reinterpret_cast<int*>(Ust + BATCH * WU);
-
-  const double2* ybase = (is_psi_row ? rs.base_psi : rs.base_th) + (size_t)m * K;
-  for (int k = t; k < K; k += 64) yb[k] = ybase[k];
-  __syncthreads();
-
-  const double dm = (double)m, m2 = dm * dm;
-  // banded coefficient of (Mass + c Lin) at (k, n); Psi has an imaginary
-  // Coriolis part (2 m / E) C in Lin.
-  auto coef = [&](int k, int off, double c, double& re, double& im) {
-    const int idx = k * 17 + off + 8;
-    if (kind == 0) {
-      re = b.A0[idx] + m2 * b.A2[idx] + c * (b.B0[idx] + m2 * b.B2[idx] + m2 * m2 * b.B4[idx]);
-      im = c * g.two_over_E * dm * b.C[idx];
-    } else if (zonal) {
-      re = b.D[idx] + c * (b.F0[idx] + b.F2[idx]);
-      im = 0.0;
-    } else {
-      re = b.D[idx] + c * g.inv_Pr * (b.F0[idx] + m2 * b.F2[idx]);
-      im = 0.0;
-    }
-  };
-  // right-hand side, rows k >= P
-  for (int k = P + t; k < K; k += 64) {
-    double2 acc = zero2();
-    const int lo = max(0, k - 8), hi = min(K - 1, k + 8);
-    for (int nn = lo; nn <= hi; ++nn) {
-      double re, im;
-      coef(k, nn - k, rs.cL, re, im);
+// ----------------------------------------------------------------- rhs
+// Right-hand side of one implicit solve, rows k >= p of every system:
+//   rhs = (Mass + cL Lin) y_base + sum_q coef_q slot_q.
+// Thread per (system, row); bands are offset-major ([17][K]).  System
+// index: s < M - 1 is Psi of m = s + 1, s = M - 1 the zonal flow, s > M - 1
+// theta of m = s - M.  Output rhs[s][K] (rows < p left zero).
+__global__ void rhs_kernel(Geom g, Bands b, RhsSpec rs, double2* __restrict__ rhs) {
+  const int K = g.K, M = g.M;
+  const int s = blockIdx.y;
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= K) return;
+  const int kind = (s < M - 1) ? 0 : (s == M - 1 ? 1 : 2);
+  const int m = (kind == 0) ? s + 1 : (kind == 1 ? 0 : s - M);
+  const int P = (kind == 0) ? 4 : 2;
+  double2 acc = zero2();
+  if (k >= P) {
+    const double2* yb = (kind == 2 ? rs.base_th : rs.base_psi) + (size_t)m * K;
+    const double dm = (double)m, m2 = dm * dm, cL = rs.cL;
+#pragma unroll
+    for (int o = 0; o < 17; ++o) {
+      const int nn = k + o - 8;
+      if (nn < 0 || nn >= K) continue;
+      const size_t idx = (size_t)o * K + k;
+      double re, im = 0.0;
+      if (kind == 0) {
+        re = b.A0[idx] + m2 * b.A2[idx] + cL * (b.B0[idx] + m2 * b.B2[idx] + m2 * m2 * b.B4[idx]);
+        im = cL * g.two_over_E * dm * b.C[idx];
+      } else if (kind == 1) {
+        re = b.D[idx] + cL * (b.F0[idx] + b.F2[idx]);
+      } else {
+        re = b.D[idx] + cL * g.inv_Pr * (b.F0[idx] + m2 * b.F2[idx]);
+      }
       acc += cmul(make_double2(re, im), yb[nn]);
     }
-    for (int q = 0; q < rs.nterm; ++q) {
-      const double2* src = (is_psi_row ? rs.term_psi[q] : rs.term_th[q]) + (size_t)m * K;
-      acc += rs.coef[q] * src[k];
+#pragma unroll
+    for (int q = 0; q < MAX_TERMS; ++q) {
+      if (q < rs.nterm) {
+        const double2* src = (kind == 2 ? rs.term_th[q] : rs.term_psi[q]) + (size_t)m * K;
+        acc += rs.coef[q] * src[k];
+      }
     }
-    hb[k - P] = acc;
   }
-  __syncthreads();
+  rhs[(size_t)s * K + k] = acc;
+}
 
-  const size_t so = (size_t)sys;
-  // Schur complement for the p boundary unknowns: psi_1 = -Minv (w . h)
+// --------------------------------------------------------------- solve
+// One wavefront per bordered system (same system index as rhs_kernel):
+// psi_1 = -Minv (w . h), h <- h - C psi_1, then the band LU solve with row
+// interchanges (forward, LAPACK gbtrs order) and back substitution.
+//
+// Lane t holds position q = t (mod 64) of a 64-wide window of the
+// right-hand side.  Each step reads the pivot row with readlane, swaps with
+// writelane, and updates the lanes below (above) it with one FMA.  Factor
+// columns are staged in LDS in double-buffered batches of B steps (factor
+// arrays padded to whole batches with identity steps), and the window is
+// refilled from global memory with loads issued a batch ahead.  KUT is the
+// number of stored U super-diagonals (ku plus the largest pivot offset).
+constexpr int SOLVE_BATCH = 16;
+
+template <typename TF, int N>
+struct Regs { TF v[N]; };
+
+// The AMDGPU writelane intrinsic (lane `lane` of v takes the uniform value
+// x), reached through its LLVM name since this clang has no builtin for it.
+__device__ int llvm_amdgcn_writelane(int x, int lane, int v) __asm("llvm.amdgcn.writelane.i32");
+__device__ __forceinline__ int writelane_i(int v, int x, int lane) {
+  return llvm_amdgcn_writelane(x, lane, v);
+}
+__device__ __forceinline__ double writelane_d(double v, double x, int lane) {
+  long long bv = __double_as_longlong(v), bx = __double_as_longlong(x);
+  int lo = writelane_i((int)(bv & 0xffffffffLL), (int)(bx & 0xffffffffLL), lane);
+  int hi = writelane_i((int)(bv >> 32), (int)(bx >> 32), lane);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+__device__ __forceinline__ double2 writelane2(double2 v, double2 x, int lane) {
+  return make_double2(writelane_d(v.x, x.x, lane), writelane_d(v.y, x.y, lane));
+}
+
+template <typename TF, int P, int KL, int KUT>
+__device__ void solve_system(const Geom& g, const FactorSet<TF>& F, double2* rhs,
+                             const RhsSpec& rs, int kind, int sys, int so, double2* sm) {
+  constexpr int WU = KUT + 1;
+  constexpr int B = SOLVE_BATCH;
+  constexpr int LPL = (B * KL + 63) / 64;
+  constexpr int UPL = (B * WU + 63) / 64;
+  const int K = g.K, M = g.M, n = K - P;
+  const int npad = (n + B - 1) / B * B;
+  const int t = threadIdx.x;
+  const int m = (kind == 0) ? sys + 1 : (kind == 1 ? 0 : sys - M);
+  TF* Lst = reinterpret_cast<TF*>(sm);            // [2][B*KL]
+  TF* Ust = Lst + 2 * B * KL;                     // [2][B*WU]
+  double2* hg = rhs + (size_t)sys * K + P;        // h, then y, then x (n entries)
+  auto hat = [&](int q) { return (q >= 0 && q < n) ? hg[q] : zero2(); };
+
+  // Schur complement for the p boundary unknowns
   double2 wh[P];
 #pragma unroll
   for (int i = 0; i < P; ++i) {
     double2 acc = zero2();
-    const TF* wr = F.W + (so * P + i) * n;
-    for (int j = t; j < n; j += 64) acc += mulf(wr[j], hb[j]);
+    const TF* wr = F.W + ((size_t)so * P + i) * n;
+    for (int j = t; j < n; j += 64) acc += mulf(wr[j], hg[j]);
     for (int off = 32; off > 0; off >>= 1) {
       acc.x += __shfl_xor(acc.x, off);
       acc.y += __shfl_xor(acc.y, off);
@@ -563,110 +592,194 @@ __global__ __launch_bounds__(64) void solve_kernel(Geom g, Bands b, FactorSet<TF
   for (int i = 0; i < P; ++i) {
     double2 acc = zero2();
 #pragma unroll
-    for (int i2 = 0; i2 < P; ++i2) acc -= mulf(F.Minv[(so * P + i) * P + i2], wh[i2]);
+    for (int i2 = 0; i2 < P; ++i2) acc -= mulf(F.Minv[((size_t)so * P + i) * P + i2], wh[i2]);
     psi1[i] = acc;
   }
-  if (t < KL && t < n) {
-    double2 acc = hb[t];
+  double2 bw = hat(t);
+  if (t < KL) {
 #pragma unroll
-    for (int i = 0; i < P; ++i) acc -= mulf(F.Cb[(so * KL + t) * P + i], psi1[i]);
-    hb[t] = acc;
+    for (int i = 0; i < P; ++i) bw -= mulf(F.Cb[((size_t)so * KL + t) * P + i], psi1[i]);
+  }
+
+  const int* piv = F.piv + (size_t)so * npad;
+  const TF* Lc = F.Lc + (size_t)so * npad * KL;
+  const TF* Uc = F.Uc + (size_t)so * npad * WU;
+  const int nb = npad / B;
+
+  // ---- forward elimination
+  Regs<TF, LPL> lr;
+#pragma unroll
+  for (int i = 0; i < LPL; ++i) {
+    const int idx = t + 64 * i;
+    if (idx < B * KL) Lst[idx] = Lc[idx];
+  }
+  int pv_cur = (t < B) ? piv[t] : 0;
+  // window refill prefetch: the lane retiring at the end of batch bi
+  // holds position q = j0 + ((t - j0) & 63) < j0 + B and takes q + 64
+  double2 hn = hat(t + 64);   // used by the lanes retiring after batch 0
+  __syncthreads();
+  for (int bi = 0; bi < nb; ++bi) {
+    const int j0 = bi * B;
+    const TF* Lcur = Lst + (bi & 1) * B * KL;
+    int pv_next = 0;
+    if (bi + 1 < nb) {
+#pragma unroll
+      for (int i = 0; i < LPL; ++i) {
+        const int idx = t + 64 * i;
+        lr.v[i] = (idx < B * KL) ? Lc[(size_t)(j0 + B) * KL + idx] : tzero<TF>();
+      }
+      pv_next = (t < B) ? piv[j0 + B + t] : 0;
+    }
+#pragma unroll
+    for (int jj = 0; jj < B; ++jj) {
+      const int j = j0 + jj;
+      const int p = __builtin_amdgcn_readlane(pv_cur, jj);
+      const int src = j & 63;
+      const int dst = (j + p) & 63;
+      const int d = ((t - j) & 63) - 1;
+      const bool act = (d >= 0 && d < KL);
+      const TF l = Lcur[jj * KL + (act ? d : 0)];
+      const double2 a = readlane2(bw, src);
+      const double2 bj = readlane2(bw, dst);
+      bw = writelane2(bw, a, dst);
+      bw = writelane2(bw, bj, src);
+      if (act) bw -= mulf(l, bj);
+    }
+    // positions j0..j0+B-1 are final
+    const int q = j0 + ((t - j0) & 63);
+    const bool retire = (q < j0 + B);
+    if (retire && q < n) hg[q] = bw;
+    if (retire) bw = hn;
+    // the lanes retiring after the next batch prefetch their new position
+    const int q2 = j0 + B + ((t - j0 - B) & 63);
+    if (q2 < j0 + 2 * B) hn = hat(q2 + 64);
+    if (bi + 1 < nb) {
+      TF* Lnext = Lst + ((bi + 1) & 1) * B * KL;
+#pragma unroll
+      for (int i = 0; i < LPL; ++i) {
+        const int idx = t + 64 * i;
+        if (idx < B * KL) Lnext[idx] = lr.v[i];
+      }
+    }
+    pv_cur = pv_next;
+    __syncthreads();
+  }
+
+  // ---- back substitution (column oriented), batches from the bottom
+  Regs<TF, UPL> ur;
+#pragma unroll
+  for (int i = 0; i < UPL; ++i) {
+    const int idx = t + 64 * i;
+    if (idx < B * WU) Ust[idx] = Uc[(size_t)(npad - B) * WU + idx];
+  }
+  // y was written to global memory by other lanes: make it visible
+  __threadfence();
+  {
+    const int top = npad - 1;
+    const int q0 = top - ((top - t) & 63);
+    bw = hat(q0);
+    hn = hat(q0 - 64);   // used by the lanes retiring after batch 0
   }
   __syncthreads();
-
-  // ---- forward elimination with row interchanges (LAPACK gbtrs order)
-  const int* piv = F.piv + so * n;
-  const TF* Lc = F.Lc + so * n * KL;
-  const TF* Uc = F.Uc + so * n * WU;
-  double2 bw = (t < n) ? hb[t] : zero2();
-  for (int j0 = 0; j0 < n; j0 += BATCH) {
-    const int jend = min(BATCH, n - j0);
-    for (int idx = t; idx < BATCH * KL; idx += 64) {
-      int jj = idx / KL;
-      Lst[idx] = (jj < jend) ? Lc[(size_t)(j0 + jj) * KL + (idx % KL)] : tzero<TF>();
-    }
-    if (t < BATCH) pst[t] = (t < jend) ? piv[j0 + t] : 0;
-    __syncthreads();
-    for (int jj = 0; jj < jend; ++jj) {
-      const int j = j0 + jj;
-      const int p = __builtin_amdgcn_readfirstlane(pst[jj]);
-      const int src = j & 63;
-      if (p != 0) {
-        const int dst = (j + p) & 63;
-        double2 a = readlane2(bw, src), c = readlane2(bw, dst);
-        if (t == src) bw = c;
-        else if (t == dst) bw = a;
+  for (int bi = 0; bi < nb; ++bi) {
+    const int c0 = npad - (bi + 1) * B;   // first column of this batch
+    const TF* Ucur = Ust + (bi & 1) * B * WU;
+    if (bi + 1 < nb) {
+#pragma unroll
+      for (int i = 0; i < UPL; ++i) {
+        const int idx = t + 64 * i;
+        ur.v[i] = (idx < B * WU) ? Uc[(size_t)(c0 - B) * WU + idx] : tzero<TF>();
       }
-      const double2 bj = readlane2(bw, src);
-      const int d = ((t - j) & 63) - 1;
-      if (d >= 0 && d < KL && j + 1 + d < n) bw -= mulf(Lst[jj * KL + d], bj);
     }
-    const int q = j0 + ((t - j0) & 63);
-    if (q < j0 + BATCH && q < n) {
-      hb[q] = bw;
-      const int q2 = q + 64;
-      bw = (q2 < n) ? hb[q2] : zero2();
-    }
-    __syncthreads();
-  }
-
-  // ---- back substitution with U (column oriented)
-  {
-    const int top = n - 1;
-    const int q0 = top - ((top - t) & 63);
-    bw = (q0 >= 0) ? hb[q0] : zero2();
-  }
-  for (int j1 = n - 1; j1 >= 0; j1 -= BATCH) {
-    const int jend = min(BATCH, j1 + 1);
-    for (int idx = t; idx < BATCH * WU; idx += 64) {
-      int jj = idx / WU;
-      Ust[idx] = (jj < jend) ? Uc[(size_t)(j1 - jj) * WU + (idx % WU)] : tzero<TF>();
-    }
-    __syncthreads();
-    for (int jj = 0; jj < jend; ++jj) {
-      const int j = j1 - jj;
+#pragma unroll
+    for (int jj = B - 1; jj >= 0; --jj) {
+      const int j = c0 + jj;
       const int src = j & 63;
-      const double2 xj = mulf(Ust[jj * WU], readlane2(bw, src));
-      if (t == src) bw = xj;
       const int e = (j - t) & 63;
-      if (e >= 1 && e <= KUT && j - e >= 0) bw -= mulf(Ust[jj * WU + e], xj);
+      const bool act = (e >= 1 && e <= KUT);
+      const TF* urow = Ucur + jj * WU;
+      const TF uj = urow[act ? e : 0];
+      const double2 xj = mulf(urow[0], readlane2(bw, src));
+      bw = writelane2(bw, xj, src);
+      if (act) bw -= mulf(uj, xj);
     }
+    const int j1 = c0 + B - 1;
     const int q = j1 - ((j1 - t) & 63);
-    if (q > j1 - BATCH && q >= 0) {
-      hb[q] = bw;
-      const int q2 = q - 64;
-      bw = (q2 >= 0) ? hb[q2] : zero2();
+    const bool retire = (q >= c0);
+    if (retire && q < n) hg[q] = bw;
+    if (retire) bw = hn;
+    const int q2 = (c0 - 1) - ((c0 - 1 - t) & 63);   // retiring after the next batch
+    if (q2 >= c0 - B) hn = hat(q2 - 64);
+    if (bi + 1 < nb) {
+      TF* Unext = Ust + ((bi + 1) & 1) * B * WU;
+#pragma unroll
+      for (int i = 0; i < UPL; ++i) {
+        const int idx = t + 64 * i;
+        if (idx < B * WU) Unext[idx] = ur.v[i];
+      }
     }
     __syncthreads();
   }
 
   // ---- new state
-  double2* out = (is_psi_row ? rs.out_psi : rs.out_th) + (size_t)m * K;
-  const bool real_row = (kind == 1 && m == 0);   // zonal flow and theta_0
+  __threadfence();
+  double2* out = (kind == 2 ? rs.out_th : rs.out_psi) + (size_t)m * K;
+  const bool real_row = (kind != 0 && m == 0);   // zonal flow and theta_0
   for (int k = t; k < K; k += 64) {
-    double2 v = (k < P) ? psi1[k] : hb[k - P];
+    double2 v = zero2();
+#pragma unroll
+    for (int i = 0; i < P; ++i)
+      if (k == i) v = psi1[i];
+    if (k >= P) v = hg[k - P];
     if (real_row) v.y = 0.0;
-    yb[k] = v;
     out[k] = v;
   }
-  double2* lin = is_psi_row ? rs.lin_psi : rs.lin_th;
-  if (lin) {
-    __syncthreads();
-    lin += (size_t)m * K;
-    for (int k = t; k < K; k += 64) {
-      double2 acc = zero2();
-      if (k >= P) {
-        const int lo = max(0, k - 8), hi = min(K - 1, k + 8);
-        for (int nn = lo; nn <= hi; ++nn) {
-          double re0, im0, re1, im1;
-          coef(k, nn - k, 0.0, re0, im0);
-          coef(k, nn - k, 1.0, re1, im1);
-          acc += cmul(make_double2(re1 - re0, im1 - im0), yb[nn]);
-        }
+}
+
+template <int KUTP, int KUTR>
+__global__ __launch_bounds__(64) void solve_all_kernel(Geom g, FactorSet<double2> Fp,
+                                                       FactorSet<double> Fr, double2* rhs,
+                                                       RhsSpec rs) {
+  extern __shared__ double2 sm[];
+  const int blk = blockIdx.x, M = g.M;
+  if (blk < M - 1) solve_system<double2, 4, 8, KUTP>(g, Fp, rhs, rs, 0, blk, blk, sm);
+  else solve_system<double, 2, 4, KUTR>(g, Fr, rhs, rs, blk == M - 1 ? 1 : 2, blk,
+                                        blk - (M - 1), sm);
+}
+
+// Lin y_new for BPR353 stages (rows >= p), thread per (system, row).
+__global__ void lin_kernel(Geom g, Bands b, const double2* __restrict__ ypsi,
+                           const double2* __restrict__ yth, double2* __restrict__ lpsi,
+                           double2* __restrict__ lth) {
+  const int K = g.K, M = g.M;
+  const int s = blockIdx.y;
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= K) return;
+  const int kind = (s < M - 1) ? 0 : (s == M - 1 ? 1 : 2);
+  const int m = (kind == 0) ? s + 1 : (kind == 1 ? 0 : s - M);
+  const int P = (kind == 0) ? 4 : 2;
+  const double2* y = (kind == 2 ? yth : ypsi) + (size_t)m * K;
+  double2 acc = zero2();
+  if (k >= P) {
+    const double dm = (double)m, m2 = dm * dm;
+#pragma unroll
+    for (int o = 0; o < 17; ++o) {
+      const int nn = k + o - 8;
+      if (nn < 0 || nn >= K) continue;
+      const size_t idx = (size_t)o * K + k;
+      double re, im = 0.0;
+      if (kind == 0) {
+        re = b.B0[idx] + m2 * b.B2[idx] + m2 * m2 * b.B4[idx];
+        im = g.two_over_E * dm * b.C[idx];
+      } else if (kind == 1) {
+        re = b.F0[idx] + b.F2[idx];
+      } else {
+        re = g.inv_Pr * (b.F0[idx] + m2 * b.F2[idx]);
       }
-      lin[k] = acc;
+      acc += cmul(make_double2(re, im), y[nn]);
     }
   }
+  (kind == 2 ? lth : lpsi)[(size_t)m * K + k] = acc;
 }
 
 // ------------------------------------------------------------ launchers
@@ -698,20 +811,37 @@ void launch_analysis(const Geom& g, const Bands& b, const double2* NL, const dou
                      th_state, Epsi, Eth);
 }
 
-void launch_solve_psi(const Geom& g, const Bands& b, const FactorSet<double2>& F,
-                      const RhsSpec& rs, hipStream_t st) {
-  const int n = g.K - 4;
-  size_t shm = sizeof(double2) * (g.K + n) + sizeof(double2) * 32 * (8 + 17) + sizeof(int) * 32;
-  hipLaunchKernelGGL((solve_kernel<double2, 4, 8, 8>), dim3(g.M - 1), dim3(64), shm, st, g, b, F, rs,
-                     0);
+size_t solve_lds_bytes(const Geom& g, int kutp, int kutr) {
+  const int B = SOLVE_BATCH;
+  const size_t psi = sizeof(double2) * 2 * B * (8 + kutp + 1);
+  const size_t real = sizeof(double) * 2 * B * (4 + kutr + 1);
+  return psi > real ? psi : real;
 }
 
-void launch_solve_real(const Geom& g, const Bands& b, const FactorSet<double>& F,
-                       const RhsSpec& rs, hipStream_t st) {
-  const int n = g.K - 2;
-  size_t shm = sizeof(double2) * (g.K + n) + sizeof(double) * 32 * (4 + 9) + sizeof(int) * 32;
-  hipLaunchKernelGGL((solve_kernel<double, 2, 4, 4>), dim3(g.M + 1), dim3(64), shm, st, g, b, F, rs,
-                     1);
+int solve_batch() { return SOLVE_BATCH; }
+
+void launch_rhs(const Geom& g, const Bands& b, const RhsSpec& rs, double2* rhs, hipStream_t st) {
+  dim3 grid((g.K + 255) / 256, 2 * g.M);
+  hipLaunchKernelGGL(rhs_kernel, grid, dim3(256), 0, st, g, b, rs, rhs);
+}
+
+void launch_lin(const Geom& g, const Bands& b, const double2* ypsi, const double2* yth,
+                double2* lpsi, double2* lth, hipStream_t st) {
+  dim3 grid((g.K + 255) / 256, 2 * g.M);
+  hipLaunchKernelGGL(lin_kernel, grid, dim3(256), 0, st, g, b, ypsi, yth, lpsi, lth);
+}
+
+bool launch_solve(const Geom& g, const FactorSet<double2>& Fp, const FactorSet<double>& Fr,
+                  double2* rhs, const RhsSpec& rs, int kutp, int kutr, hipStream_t st) {
+  const size_t shm = solve_lds_bytes(g, kutp, kutr);
+  const dim3 grid(2 * g.M), block(64);
+  if (kutp == 12 && kutr == 4)
+    hipLaunchKernelGGL((solve_all_kernel<12, 4>), grid, block, shm, st, g, Fp, Fr, rhs, rs);
+  else if (kutp == 16 && kutr == 8)
+    hipLaunchKernelGGL((solve_all_kernel<16, 8>), grid, block, shm, st, g, Fp, Fr, rhs, rs);
+  else
+    return false;
+  return true;
 }
 
 }  // namespace qg

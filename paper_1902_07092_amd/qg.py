@@ -127,7 +127,7 @@ def qg_step(ctx, dt, scheme, nsteps):
     _check(ctx, load().qg_step(ctx, float(dt), int(scheme), int(nsteps)))
 
 
-KERNEL_CLASSES = ("synth", "ring", "analysis", "solve_psi", "solve_real")
+KERNEL_CLASSES = ("synth", "ring", "analysis", "solve", "rhs")
 
 
 def qg_step_timed(ctx, dt, scheme, nsteps):
@@ -136,7 +136,7 @@ def qg_step_timed(ctx, dt, scheme, nsteps):
     _check(ctx, load().qg_step_timed(ctx, float(dt), int(scheme), int(nsteps),
                                      ctypes.cast(ms, ctypes.c_void_p),
                                      ctypes.cast(n, ctypes.c_void_p)))
-    return {k: (ms[i], n[i]) for i, k in enumerate(KERNEL_CLASSES)}
+    return {k: (ms[i], n[i]) for i, k in enumerate(KERNEL_CLASSES) if n[i]}
 
 
 def qg_diagnostics(ctx) -> dict:
