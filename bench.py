@@ -92,6 +92,27 @@ def cpu_baseline(w, state, steps):
                       f"{w.name}, oracle init untimed, {dt:.1f} s"}
 
 
+def copy_calibration(torch, mb, steps):
+    """A plain copy of known size: FETCH_SIZE and WRITE_SIZE of its
+    dispatches, against the bytes it must move, give the factor that turns
+    the counters of the step's kernels into HBM bytes."""
+    n = mb * (1 << 20)
+    src = torch.empty(n, dtype=torch.uint8, device="cuda:0").fill_(1)
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    start = torch.cuda.Event(enable_timing=True)
+    stop = torch.cuda.Event(enable_timing=True)
+    start.record()
+    for _ in range(steps):
+        dst.copy_(src)
+    stop.record()
+    torch.cuda.synchronize()
+    ms = start.elapsed_time(stop) / steps
+    print(json.dumps({"copy_bytes_read": n, "copy_bytes_written": n,
+                      "ms_per_copy": ms, "GBps": 2 * n / ms / 1e6}),
+          flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -100,6 +121,9 @@ def main():
     ap.add_argument("--workload", default="large_3072x1025_E1e-8_cnab2")
     ap.add_argument("--cpu-steps", type=int, default=1)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MB",
+                    help="only run a plain device-to-device copy of MB MiB "
+                         "(steps times), the reference for HBM counters")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: the step's per-m and per-ring "
@@ -108,6 +132,10 @@ def main():
         sys.exit(2)
 
     import torch
+
+    if args.copy_calibration:
+        copy_calibration(torch, args.copy_calibration, args.steps)
+        return
 
     from paper_1902_07092_amd import inputs, qg
     w = inputs.WORKLOADS[args.workload]

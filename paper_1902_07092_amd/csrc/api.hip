@@ -15,13 +15,6 @@
 #include "kernels.h"
 
 namespace qg {
-void launch_synth(const Geom& g, const double2* psi, const double2* th, double2* X, double* diag,
-                  int threads, hipStream_t st);
-void launch_ring(const Geom& g, const double2* X, double2* NL, double* zonal, double* rate,
-                 int threads, hipStream_t st);
-void launch_analysis(const Geom& g, const Bands& b, const double2* NL, const double* zonal,
-                     const double2* th_state, double2* Epsi, double2* Eth, int threads,
-                     hipStream_t st);
 size_t solve_lds_bytes(const Geom& g, int kutp, int kutr);
 void launch_rhs(const Geom& g, const Bands& b, const RhsSpec& rs, double2* rhs, hipStream_t st);
 void launch_lin(const Geom& g, const Bands& b, const double2* ypsi, const double2* yth,
@@ -50,28 +43,6 @@ const double BPR_AI[5][5] = {{0, 0, 0, 0, 0},
                              {0.25, 0, 0.75, -0.5, 0.5}};
 
 bool is_pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
-
-struct Plan {
-  int n = 0, npass = 0, radix[24] = {0};
-  int max_nb = 0;
-};
-
-bool make_plan(int n, Plan& p) {
-  p.n = n;
-  p.npass = 0;
-  int rest = n;
-  if (rest % 3 == 0) { p.radix[p.npass++] = 3; rest /= 3; }
-  if (!is_pow2(rest)) return false;
-  int L = 0;
-  while ((1 << L) < rest) ++L;
-  if (L % 2) p.radix[p.npass++] = 2;
-  for (int i = 0; i < L / 2; ++i) p.radix[p.npass++] = 4;
-  p.max_nb = 0;
-  for (int i = 0; i < p.npass; ++i) p.max_nb = std::max(p.max_nb, n / p.radix[i]);
-  return true;
-}
-
-int round64(int v) { return ((v + 63) / 64) * 64; }
 
 struct Layout {
   size_t total = 0;
@@ -109,7 +80,8 @@ bool sizes_of(const qg_params* p, Sizes& z, std::string& why) {
 }
 
 struct WsMap {
-  size_t state, ybuf, eslot, lslot, X, NL, zonal, rate, diag, xk, wq, dsk, twd, twp, bands, rhs;
+  size_t state, ybuf, eslot, lslot, X, NL, zonal, rate, diag, xk, wq, dsk, twd, twp, twh, wphi,
+      bands, rhs;
   size_t p_piv, p_L, p_U, p_W, p_C, p_Mi;
   size_t r_piv, r_L, r_U, r_W, r_C, r_Mi;
   size_t total;
@@ -135,6 +107,8 @@ WsMap map_workspace(const Sizes& z) {
   w.dsk = L.take(z.R * sizeof(double));
   w.twd = L.take((size_t)2 * (z.R - 1) * sizeof(double2));
   w.twp = L.take((size_t)z.nphi * sizeof(double2));
+  w.twh = L.take((size_t)z.nphi / 2 * sizeof(double2));
+  w.wphi = L.take((size_t)(z.nphi / 2 + 1) * sizeof(double2));
   w.bands = L.take((size_t)9 * z.K * BANDW * sizeof(double));
   w.rhs = L.take((size_t)2 * z.M * z.K * sizeof(double2));
   w.p_piv = L.take(Sp * z.p4 * sizeof(int));
@@ -167,7 +141,6 @@ struct qg_ctx {
   Bands b;
   FactorSet<double2> Fp;
   FactorSet<double> Fr;
-  int t_synth = 64, t_ring = 64, t_ana = 64;
   int kutp = 16, kutr = 8;   // stored U super-diagonals (Psi, real systems)
   double factored_adt = -1.0;
   int have_prev = 0, cur = 0;
@@ -398,17 +371,19 @@ void timed(qg_ctx* ctx, int cls, F launch) {
 
 qg_status explicit_terms(qg_ctx* ctx, const double2* psi, const double2* th, double2* Ep,
                          double2* Et) {
+  bool ok = true;
   timed(ctx, K_SYNTH, [&] {
-    launch_synth(ctx->g, psi, th, ctx->ptr2(ctx->w.X), nullptr, ctx->t_synth, ctx->st);
+    ok = launch_synth(ctx->g, psi, th, ctx->ptr2(ctx->w.X), nullptr, ctx->st) && ok;
   });
   timed(ctx, K_RING, [&] {
-    launch_ring(ctx->g, ctx->ptr2(ctx->w.X), ctx->ptr2(ctx->w.NL), ctx->ptrd(ctx->w.zonal),
-                nullptr, ctx->t_ring, ctx->st);
+    ok = launch_ring(ctx->g, ctx->ptr2(ctx->w.X), ctx->ptr2(ctx->w.NL), ctx->ptrd(ctx->w.zonal),
+                     nullptr, ctx->st) && ok;
   });
   timed(ctx, K_ANALYSIS, [&] {
-    launch_analysis(ctx->g, ctx->b, ctx->ptr2(ctx->w.NL), ctx->ptrd(ctx->w.zonal), th, Ep, Et,
-                    ctx->t_ana, ctx->st);
+    ok = launch_analysis(ctx->g, ctx->b, ctx->ptr2(ctx->w.NL), ctx->ptrd(ctx->w.zonal), th, Ep,
+                         Et, ctx->st) && ok;
   });
+  if (!ok) return fail(ctx, QG_EUNSUPPORTED, "no transform kernel for these sizes");
   HIPCHK(hipGetLastError());
   return QG_OK;
 }
@@ -527,9 +502,7 @@ qg_status qg_create(qg_ctx** out, const qg_params* p, void* workspace, size_t wo
   Sizes z;
   std::string why;
   if (!sizes_of(p, z, why)) return QG_EINVAL;
-  Plan pd, pp, ph;
-  if (!is_pow2(z.R - 1) || !make_plan(2 * (z.R - 1), pd) || !make_plan(z.nphi, pp) ||
-      z.nphi % 6 || !make_plan(z.nphi / 2, ph))
+  if (!is_pow2(z.R - 1) || z.nphi % 6 || !transform_sizes_ok(2 * (z.R - 1), z.nphi))
     return QG_EUNSUPPORTED;
   if (!workspace || ((uintptr_t)workspace & 255)) return QG_EINVAL;
   WsMap w = map_workspace(z);
@@ -543,24 +516,16 @@ qg_status qg_create(qg_ctx** out, const qg_params* p, void* workspace, size_t wo
   ctx->ws = static_cast<char*>(workspace);
   ctx->st = static_cast<hipStream_t>(stream);
 
-  // launch shapes: FFT passes need MAXB (4) butterflies per thread at most
-  const int MAXB = 4, MAXP = 5, MAXJ = 16;
-  ctx->t_synth = round64(std::max({64, (z.R + MAXP - 1) / MAXP, (pd.max_nb + MAXB - 1) / MAXB}));
-  ctx->t_ana = ctx->t_synth;
-  ctx->t_ring = round64(std::max({64, (z.nphi + MAXJ - 1) / MAXJ, (pp.max_nb + MAXB - 1) / MAXB,
-                                  (ph.max_nb + MAXB - 1) / MAXB}));
   int dev = 0;
   hipDeviceProp_t prop;
   if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess) {
     delete ctx;
     return QG_EDEVICE;
   }
-  const size_t lds_synth = sizeof(double2) * (2 * z.K + 2 * (z.R - 1) + 2 * ctx->t_synth);
-  const size_t lds_ring = sizeof(double2) * z.nphi;
+  const size_t lds_fft = transform_lds_bytes(2 * (z.R - 1), z.nphi, z.K) + 1024;
   ctx->g.K = z.K;
   const size_t lds_solve = solve_lds_bytes(ctx->g, 16, 8);
-  if (ctx->t_synth > 1024 || ctx->t_ring > 1024 ||
-      std::max({lds_synth, lds_ring, lds_solve}) > (size_t)prop.sharedMemPerBlock) {
+  if (std::max(lds_fft, lds_solve) > (size_t)prop.sharedMemPerBlock) {
     delete ctx;
     return QG_EUNSUPPORTED;
   }
@@ -582,7 +547,9 @@ qg_status qg_create(qg_ctx** out, const qg_params* p, void* workspace, size_t wo
     double b = (k + 1 < z.R) ? std::fabs(sk(k) - sk(k + 1)) : 1e300;
     dsk[k] = std::min(a, b);
   }
-  std::vector<double2> twd = twiddles(2 * (z.R - 1)), twp = twiddles(z.nphi);
+  std::vector<double2> twd = plan_twiddles(2 * (z.R - 1)), twp = plan_twiddles(z.nphi),
+                       twh = plan_twiddles(z.nphi / 2), wphi = twiddles(z.nphi);
+  wphi.resize(z.nphi / 2 + 1);
   std::vector<double> bandbuf((size_t)9 * z.K * BANDW);
   const std::vector<double>* bl[9] = {&ctx->ops.A0, &ctx->ops.A2, &ctx->ops.B0,
                                       &ctx->ops.B2, &ctx->ops.B4, &ctx->ops.C,
@@ -599,6 +566,8 @@ qg_status qg_create(qg_ctx** out, const qg_params* p, void* workspace, size_t wo
       up(w.dsk, dsk.data(), dsk.size() * 8) != hipSuccess ||
       up(w.twd, twd.data(), twd.size() * 16) != hipSuccess ||
       up(w.twp, twp.data(), twp.size() * 16) != hipSuccess ||
+      up(w.twh, twh.data(), twh.size() * 16) != hipSuccess ||
+      up(w.wphi, wphi.data(), wphi.size() * 16) != hipSuccess ||
       up(w.bands, bandbuf.data(), bandbuf.size() * 8) != hipSuccess ||
       hipMemsetAsync(ctx->ws + w.state, 0, 2 * (size_t)z.M * z.K * sizeof(double2), ctx->st) !=
           hipSuccess ||
@@ -619,18 +588,10 @@ qg_status qg_create(qg_ctx** out, const qg_params* p, void* workspace, size_t wo
   g.xk = ctx->ptrd(w.xk);
   g.wq = ctx->ptrd(w.wq);
   g.dsk = ctx->ptrd(w.dsk);
-  g.dct.n = pd.n; g.dct.npass = pd.npass;
-  std::copy(pd.radix, pd.radix + 24, g.dct.radix);
-  g.dct.tw = ctx->ptr2(w.twd);
-  g.dct.tw_stride = 1;
-  g.phi.n = pp.n; g.phi.npass = pp.npass;
-  std::copy(pp.radix, pp.radix + 24, g.phi.radix);
-  g.phi.tw = ctx->ptr2(w.twp);
-  g.phi.tw_stride = 1;
-  g.phi_half.n = ph.n; g.phi_half.npass = ph.npass;
-  std::copy(ph.radix, ph.radix + 24, g.phi_half.radix);
-  g.phi_half.tw = ctx->ptr2(w.twp);
-  g.phi_half.tw_stride = 2;
+  g.tw_dct = ctx->ptr2(w.twd);
+  g.tw_phi = ctx->ptr2(w.twp);
+  g.tw_half = ctx->ptr2(w.twh);
+  g.w_phi = ctx->ptr2(w.wphi);
   const double* bd = ctx->ptrd(w.bands);
   const size_t bs = (size_t)z.K * BANDW;
   ctx->b = Bands{bd, bd + bs, bd + 2 * bs, bd + 3 * bs, bd + 4 * bs,
@@ -750,10 +711,11 @@ qg_status qg_step(qg_ctx* ctx, double dt, int scheme, int nsteps) {
 qg_status qg_diagnostics(qg_ctx* ctx, qg_diag* out) {
   if (!ctx || !out) return QG_EINVAL;
   const Sizes& z = ctx->z;
-  launch_synth(ctx->g, ctx->psi(), ctx->th(), ctx->ptr2(ctx->w.X), ctx->ptrd(ctx->w.diag),
-               ctx->t_synth, ctx->st);
-  launch_ring(ctx->g, ctx->ptr2(ctx->w.X), ctx->ptr2(ctx->w.NL), ctx->ptrd(ctx->w.zonal),
-              ctx->ptrd(ctx->w.rate), ctx->t_ring, ctx->st);
+  if (!launch_synth(ctx->g, ctx->psi(), ctx->th(), ctx->ptr2(ctx->w.X), ctx->ptrd(ctx->w.diag),
+                    ctx->st) ||
+      !launch_ring(ctx->g, ctx->ptr2(ctx->w.X), ctx->ptr2(ctx->w.NL), ctx->ptrd(ctx->w.zonal),
+                   ctx->ptrd(ctx->w.rate), ctx->st))
+    return fail(ctx, QG_EUNSUPPORTED, "no transform kernel for these sizes");
   HIPCHK(hipGetLastError());
   std::vector<double> d((size_t)z.M * 8), rate(z.R);
   HIPCHK(hipMemcpyAsync(d.data(), ctx->ptrd(ctx->w.diag), d.size() * 8, hipMemcpyDeviceToHost,

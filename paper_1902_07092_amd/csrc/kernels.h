@@ -2,17 +2,9 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
-namespace qg {
+#include <vector>
 
-// In-LDS Stockham FFT plan: n = product of radices (2, 3 or 4), twiddles
-// tw[k] = exp(-2 pi i k / n), k < n.
-struct FftPlan {
-  int n;
-  int npass;
-  int radix[24];
-  const double2* tw;   // tw[k * tw_stride] = exp(-2 pi i k / n)
-  int tw_stride;
-};
+namespace qg {
 
 struct Geom {
   int M, K, R, nphi;
@@ -22,9 +14,10 @@ struct Geom {
   const double* xk;             // Gauss-Lobatto nodes, x_0 = +1
   const double* wq;             // Clenshaw-Curtis weight * half * s_k
   const double* dsk;            // local radial spacing (CFL)
-  FftPlan dct;                  // length 2 (R - 1)
-  FftPlan phi;                  // length nphi
-  FftPlan phi_half;             // length nphi / 2 (real transforms)
+  const double2* tw_dct;        // plan twiddles, length 2 (R - 1) (fft.h layout)
+  const double2* tw_phi;        // plan twiddles, length nphi
+  const double2* tw_half;       // plan twiddles, length nphi / 2
+  const double2* w_phi;         // exp(-2 pi i m / nphi), m <= nphi / 2
 };
 
 struct Bands {  // [17][K] each (offset-major): entry (k, n) at [(n - k + 8) * K + k]
@@ -59,5 +52,17 @@ struct RhsSpec {
   double2* lin_psi;          // optional: Lin y_new (nullptr: not needed)
   double2* lin_th;
 };
+
+// Transform kernels (transforms.hip).  The launchers return false for a
+// size without a compiled plan.
+bool transform_sizes_ok(int n2, int nphi);
+size_t transform_lds_bytes(int n2, int nphi, int K);
+std::vector<double2> plan_twiddles(int n);
+bool launch_synth(const Geom& g, const double2* psi, const double2* th, double2* X, double* diag,
+                  hipStream_t st);
+bool launch_ring(const Geom& g, const double2* X, double2* NL, double* zonal, double* rate,
+                 hipStream_t st);
+bool launch_analysis(const Geom& g, const Bands& b, const double2* NL, const double* zonal,
+                     const double2* th_state, double2* Epsi, double2* Eth, hipStream_t st);
 
 }  // namespace qg

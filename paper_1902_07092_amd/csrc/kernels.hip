@@ -1,14 +1,11 @@
-// HIP kernels of one IMEX step of spherical quasi-geostrophic convection
-// (Chebyshev-integration / tau radial scheme, Fourier in azimuth), FP64.
+// Implicit-stage kernels of one IMEX step of spherical quasi-geostrophic
+// convection (Chebyshev-integration / tau radial scheme), FP64:
 //
-//   synth_kernel     per m:    Chebyshev derivatives, inverse DCT-I
-//                              (eq. cheb), six spectral-in-phi fields
-//   ring_kernel      per s_k:  c2r FFTs (eq. fft), advection products,
-//                              r2c FFT (eq. ifft), zonal forcing
-//   analysis_kernel  per m:    forward DCT-I (eq. icheb), radial dealiasing,
-//                              explicit right-hand sides C[..], -D[..]
-//   solve_kernel     per system: IMEX right-hand side and bordered band
-//                              solve (Appendix A), one wavefront each
+//   rhs_kernel        per (system, row): IMEX right-hand side
+//   solve_all_kernel  per system: bordered band solve (Appendix A), one
+//                     wavefront each
+//   lin_kernel        per (system, row): implicit operator applied to a new
+//                     stage value (BPR353)
 #include <hip/hip_runtime.h>
 
 #include "kernels.h"
@@ -40,444 +37,6 @@ __device__ __forceinline__ double readlane_d(double v, int lane) {
 }
 __device__ __forceinline__ double2 readlane2(double2 v, int lane) {
   return make_double2(readlane_d(v.x, lane), readlane_d(v.y, lane));
-}
-
-// ------------------------------------------------------------------ FFT
-// In-place Stockham FFT in LDS: every pass loads its butterfly inputs into
-// registers, synchronises, and writes the outputs back to the same buffer.
-// sgn = -1: X_k = sum_j x_j e^{-2 pi i jk/n}; sgn = +1: the e^{+} sum.
-template <int MAXB>
-__device__ void fft_lds(double2* buf, const FftPlan& P, int sgn) {
-  const int n = P.n;
-  const int T = blockDim.x, t = threadIdx.x;
-  int Ns = 1;
-  for (int s = 0; s < P.npass; ++s) {
-    const int R = P.radix[s];
-    const int nb = n / R;
-    const int tws = n / (Ns * R);
-    double2 v[MAXB][4];
-#pragma unroll
-    for (int i = 0; i < MAXB; ++i) {
-      int j = t + i * T;
-#pragma unroll
-      for (int r = 0; r < 4; ++r)
-        v[i][r] = (j < nb && r < R) ? buf[j + r * nb] : zero2();
-    }
-    __syncthreads();
-#pragma unroll
-    for (int i = 0; i < MAXB; ++i) {
-      int j = t + i * T;
-      if (j >= nb) continue;
-      int k = j % Ns;
-#pragma unroll
-      for (int r = 1; r < 4; ++r) {
-        if (r < R) {
-          double2 w = P.tw[k * r * tws * P.tw_stride];
-          if (sgn > 0) w.y = -w.y;
-          v[i][r] = cmul(v[i][r], w);
-        }
-      }
-      double2 y0, y1, y2, y3;
-      if (R == 2) {
-        y0 = v[i][0] + v[i][1];
-        y1 = v[i][0] - v[i][1];
-        y2 = y3 = zero2();
-      } else if (R == 4) {
-        double2 a = v[i][0] + v[i][2], b = v[i][0] - v[i][2];
-        double2 c = v[i][1] + v[i][3], d = v[i][1] - v[i][3];
-        double2 id = times_i(d);
-        if (sgn < 0) id = make_double2(-id.x, -id.y);   // (sgn i) d
-        y0 = a + c;
-        y1 = b + id;
-        y2 = a - c;
-        y3 = b - id;
-      } else {  // R == 3
-        const double h3 = 0.86602540378443864676;   // sqrt(3)/2
-        double2 t1 = v[i][1] + v[i][2], t2 = v[i][1] - v[i][2];
-        double2 base = v[i][0] - 0.5 * t1;
-        double2 rot = (sgn * h3) * times_i(t2);
-        y0 = v[i][0] + t1;
-        y1 = base + rot;
-        y2 = base - rot;
-        y3 = zero2();
-      }
-      int o = (j / Ns) * Ns * R + k;
-      buf[o] = y0;
-      buf[o + Ns] = y1;
-      if (R > 2) buf[o + 2 * Ns] = y2;
-      if (R > 3) buf[o + 3 * Ns] = y3;
-    }
-    __syncthreads();
-    Ns *= R;
-  }
-}
-
-// ------------------------------------------------------------ reductions
-__device__ double block_sum(double v, double* red) {
-  const int t = threadIdx.x, T = blockDim.x;
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
-  if ((t & 63) == 0) red[t >> 6] = v;
-  __syncthreads();
-  double s = 0.0;
-  if (t == 0)
-    for (int w = 0; w < (T + 63) / 64; ++w) s += red[w];
-  __syncthreads();
-  return s;  // valid on thread 0
-}
-
-__device__ double block_max(double v, double* red) {
-  const int t = threadIdx.x, T = blockDim.x;
-  for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off));
-  if ((t & 63) == 0) red[t >> 6] = v;
-  __syncthreads();
-  double s = 0.0;
-  if (t == 0)
-    for (int w = 0; w < (T + 63) / 64; ++w) s = fmax(s, red[w]);
-  __syncthreads();
-  return s;
-}
-
-// ------------------------------------------------- Chebyshev derivative
-// dst_n = (4/c_n) sum_{j > n, j - n odd} j src_j (c_0 = 2, else 1): the
-// coefficients of d/ds on the unit gap (ds = dx/2).  Parallel suffix sums
-// of j src_j over each parity class.
-__device__ void cheb_deriv(const double2* src, double2* dst, int K, double2* scan) {
-  const int T = blockDim.x, t = threadIdx.x;
-  const int npair = (K + 1) / 2;
-  const int ch = (npair + T - 1) / T;
-  const int p0 = min(npair, t * ch), p1 = min(npair, p0 + ch);
-  double2 se = zero2(), so = zero2();
-  for (int pp = p0; pp < p1; ++pp) {
-    int je = 2 * pp, jo = je + 1;
-    se += (double)je * src[je];
-    if (jo < K) so += (double)jo * src[jo];
-  }
-  scan[t] = se;
-  scan[T + t] = so;
-  __syncthreads();
-  for (int off = 1; off < T; off <<= 1) {
-    double2 ae = zero2(), ao = zero2();
-    if (t + off < T) { ae = scan[t + off]; ao = scan[T + t + off]; }
-    __syncthreads();
-    scan[t] += ae;
-    scan[T + t] += ao;
-    __syncthreads();
-  }
-  double2 re = (t + 1 < T) ? scan[t + 1] : zero2();
-  double2 ro = (t + 1 < T) ? scan[T + t + 1] : zero2();
-  for (int pp = p1 - 1; pp >= p0; --pp) {
-    int je = 2 * pp, jo = je + 1;
-    if (jo < K) {
-      dst[jo] = 4.0 * re;            // S_{jo+1} = S_{je+2}
-      ro += (double)jo * src[jo];    // S_{jo}
-    }
-    dst[je] = (je == 0 ? 2.0 : 4.0) * ro;
-    re += (double)je * src[je];      // S_{je}
-  }
-  __syncthreads();
-}
-
-// Inverse DCT-I (eq. cheb, standard coefficients): f_k = sum_{n<K} a_n
-// cos(pi n k / N), N = R - 1, through the FFT of the even extension
-// e_0 = 2 a_0, e_n = e_{2N-n} = a_n; f_k = FFT(e)_k / 2.  Each thread keeps
-// the values at k = t + i T.
-template <int MAXB, int MAXP>
-__device__ void dct_inverse(const double2* coef, int K, double2* fb, const Geom& g,
-                            double2 (&out)[MAXP]) {
-  const int N = g.R - 1, T = blockDim.x, t = threadIdx.x;
-  for (int i = t; i < 2 * N; i += T) {
-    int n = (i <= N) ? i : 2 * N - i;
-    double2 v = (n < K) ? coef[n] : zero2();
-    if (i == 0) v = 2.0 * v;
-    fb[i] = v;
-  }
-  __syncthreads();
-  fft_lds<MAXB>(fb, g.dct, -1);
-#pragma unroll
-  for (int i = 0; i < MAXP; ++i) {
-    int k = t + i * T;
-    out[i] = (k < g.R) ? 0.5 * fb[k] : zero2();
-  }
-  __syncthreads();
-}
-
-// Forward DCT-I (eq. icheb, standard coefficients), keeping n < K (radial
-// dealiasing): a_n = (h_n / N) [f_0 + (-1)^n f_N + 2 sum f_k cos(pi nk/N)],
-// h_0 = h_N = 1/2.  Values are read through get(k).
-template <int MAXB, typename Get>
-__device__ void dct_forward(Get get, double2* coef, int K, double2* fb, const Geom& g) {
-  const int N = g.R - 1, T = blockDim.x, t = threadIdx.x;
-  for (int i = t; i < 2 * N; i += T) fb[i] = get((i <= N) ? i : 2 * N - i);
-  __syncthreads();
-  fft_lds<MAXB>(fb, g.dct, -1);
-  const double invN = 1.0 / N;
-  for (int n = t; n < K; n += T) coef[n] = ((n == 0) ? 0.5 * invN : invN) * fb[n];
-  __syncthreads();
-}
-
-// -------------------------------------------------------------- synth
-// Fields (Fourier coefficient m at s_k), written X[f][k][m]:
-//   0: dPsi/dphi = i m Psi          1: v = u_phi / s
-//   2: c_w = omega + (h^2/s) d_s omega   3: d omega/dphi = i m omega
-//   4: c_t = (h^2/s)(d_s theta + dTc/ds [m=0])   5: d theta/dphi
-// with u_phi = -h^2 Psi' + 3 s Psi (+ zonal flow at m = 0), omega = -L_I Psi
-// (m >= 1) and omega_0 = u' + u/s (Sect. 3.2.1).
-template <int MAXB, int MAXP>
-__global__ void synth_kernel(Geom g, const double2* __restrict__ psi,
-                             const double2* __restrict__ th, double2* __restrict__ X,
-                             double* __restrict__ diag) {
-  extern __shared__ double2 sm[];
-  __shared__ double red[16];
-  const int K = g.K, R = g.R, M = g.M, N = R - 1;
-  const int T = blockDim.x, t = threadIdx.x;
-  const int m = blockIdx.x;
-  double2* ca = sm;
-  double2* cb = sm + K;
-  double2* fb = sm + 2 * K;
-  double2* scan = fb + 2 * N;
-
-  for (int n = t; n < K; n += T) ca[n] = psi[(size_t)m * K + n];
-  __syncthreads();
-  double2 P0[MAXP], P1[MAXP], P2[MAXP], P3[MAXP], T0[MAXP], T1[MAXP];
-  dct_inverse<MAXB, MAXP>(ca, K, fb, g, P0);
-  cheb_deriv(ca, cb, K, scan);
-  dct_inverse<MAXB, MAXP>(cb, K, fb, g, P1);
-  cheb_deriv(cb, ca, K, scan);
-  dct_inverse<MAXB, MAXP>(ca, K, fb, g, P2);
-  if (m > 0) {
-    cheb_deriv(ca, cb, K, scan);
-    dct_inverse<MAXB, MAXP>(cb, K, fb, g, P3);
-  } else {
-#pragma unroll
-    for (int i = 0; i < MAXP; ++i) P3[i] = zero2();
-  }
-  for (int n = t; n < K; n += T) ca[n] = th[(size_t)m * K + n];
-  __syncthreads();
-  dct_inverse<MAXB, MAXP>(ca, K, fb, g, T0);
-  cheb_deriv(ca, cb, K, scan);
-  dct_inverse<MAXB, MAXP>(cb, K, fb, g, T1);
-
-  const double dm = (double)m, m2 = dm * dm, so2 = g.s_o * g.s_o;
-  double ek = 0.0, et = 0.0, ens = 0.0, ez = 0.0;
-#pragma unroll
-  for (int i = 0; i < MAXP; ++i) {
-    const int k = t + i * T;
-    if (k >= R) continue;
-    const double s = g.half * g.xk[k] + g.mid;
-    const double is = 1.0 / s;
-    const double h2 = so2 - s * s;
-    const double h2s = h2 * is;
-    double2 F[6];
-    double2 om;
-    if (m > 0) {
-      double2 LI = h2 * P2[i] + (h2s - 5.0 * s) * P1[i] - (6.0 + m2 * h2 * is * is) * P0[i];
-      double2 dLI = h2 * P3[i] + (h2s - 7.0 * s) * P2[i]
-                  - (so2 * is * is + 12.0 + m2 * h2 * is * is) * P1[i]
-                  + (2.0 * m2 * so2 * is * is * is) * P0[i];
-      om = make_double2(-LI.x, -LI.y);
-      double2 dom = make_double2(-dLI.x, -dLI.y);
-      double2 uph = (3.0 * s) * P0[i] - h2 * P1[i];
-      F[0] = dm * times_i(P0[i]);
-      F[1] = is * uph;
-      F[2] = om + h2s * dom;
-      F[3] = dm * times_i(om);
-      F[4] = h2s * T1[i];
-      F[5] = dm * times_i(T0[i]);
-      if (diag) {
-        const double w = g.wq[k];
-        double us2 = h2s * h2s * m2 * (P0[i].x * P0[i].x + P0[i].y * P0[i].y);
-        ek += 2.0 * w * (us2 + uph.x * uph.x + uph.y * uph.y);
-        et += 2.0 * w * (T0[i].x * T0[i].x + T0[i].y * T0[i].y);
-        ens += 2.0 * w * (om.x * om.x + om.y * om.y);
-      }
-    } else {
-      // zonal flow u = P0, u' = P1, u'' = P2 (real)
-      om = P1[i] + is * P0[i];
-      double2 dom = P2[i] + is * P1[i] - (is * is) * P0[i];
-      F[0] = zero2();
-      F[1] = is * P0[i];
-      F[2] = om + h2s * dom;
-      F[3] = zero2();
-      F[4] = h2s * (T1[i] + make_double2(g.dtc_coef * is, 0.0));
-      F[5] = zero2();
-      if (diag) {
-        const double w = g.wq[k];
-        ek += w * P0[i].x * P0[i].x;
-        ez += w * P0[i].x * P0[i].x;
-        et += w * T0[i].x * T0[i].x;
-        ens += w * om.x * om.x;
-      }
-    }
-#pragma unroll
-    for (int f = 0; f < 6; ++f) X[((size_t)f * R + k) * M + m] = F[f];
-  }
-  if (diag) {
-    const double pi = 3.14159265358979323846;
-    double bad = 0.0;
-    for (int n = t; n < K; n += T) {
-      double2 a = psi[(size_t)m * K + n], b = th[(size_t)m * K + n];
-      if (!isfinite(a.x) || !isfinite(a.y) || !isfinite(b.x) || !isfinite(b.y)) bad = 1.0;
-    }
-    double s0 = block_sum(ek, red);
-    double s1 = block_sum(ez, red);
-    double s2 = block_sum(et, red);
-    double s3 = block_sum(ens, red);
-    double s4 = block_max(bad, red);
-    if (t == 0) {
-      diag[m * 8 + 0] = pi * s0;
-      diag[m * 8 + 1] = pi * s1;
-      diag[m * 8 + 2] = pi * s2;
-      diag[m * 8 + 3] = 2.0 * pi * s3;
-      diag[m * 8 + 4] = s4;
-    }
-  }
-}
-
-// ---------------------------------------------------------------- ring
-// Per radial level: three complex inverse FFTs of length N_phi (each
-// carries two real fields of similar size), the products
-//   N_omega = dPsi/dphi c_w + v d omega/dphi,
-//   N_theta = dPsi/dphi c_t + v d theta/dphi,
-// then one real forward FFT per product (eq. ifft; N_omega can exceed
-// N_theta by many orders of magnitude, so the two never share a complex
-// transform), scaled by 1/N_phi and truncated to m <= N_m, and the zonal
-// forcing mean(u_s omega) = 2 sum_{m>=1} Re(u_s,m conj(omega_m)).
-// A real sequence x of length N goes through a complex FFT of length N/2 of
-// z_j = x_2j + i x_2j+1:  X_k = (Z_k + Z*_{N/2-k})/2 - (i/2) w^k (Z_k - Z*_{N/2-k}),
-// w = exp(-2 pi i / N).
-template <int MAXB, int MAXJ>
-__global__ void ring_kernel(Geom g, const double2* __restrict__ X, double2* __restrict__ NL,
-                            double* __restrict__ zonal, double* __restrict__ rate) {
-  extern __shared__ double2 fb[];
-  __shared__ double red[16];
-  const int R = g.R, M = g.M, nphi = g.nphi, nh = nphi / 2;
-  const int T = blockDim.x, t = threadIdx.x;
-  const int k = blockIdx.x;
-  const double s = g.half * g.xk[k] + g.mid;
-  const double h2s = (g.s_o * g.s_o - s * s) / s;
-  double2 z1[MAXJ];
-  double nw[MAXJ], nt[MAXJ];
-  double rmax = 0.0;
-  for (int q = 0; q < 3; ++q) {
-    const double2* A = X + ((size_t)(2 * q) * R + k) * M;
-    const double2* B = X + ((size_t)(2 * q + 1) * R + k) * M;
-    for (int i = t; i < nphi; i += T) {
-      double2 z = zero2();
-      if (i < M) {
-        double2 a = A[i], b = B[i];
-        z = (i == 0) ? make_double2(a.x, b.x) : make_double2(a.x - b.y, a.y + b.x);
-      } else if (i > nphi - M) {
-        double2 a = A[nphi - i], b = B[nphi - i];
-        z = make_double2(a.x + b.y, b.x - a.y);
-      }
-      fb[i] = z;
-    }
-    __syncthreads();
-    fft_lds<MAXB>(fb, g.phi, +1);
-#pragma unroll
-    for (int i = 0; i < MAXJ; ++i) {
-      int j = t + i * T;
-      if (j >= nphi) continue;
-      double2 z = fb[j];
-      if (q == 0) {
-        z1[i] = z;
-        if (rate) rmax = fmax(rmax, fmax(h2s * fabs(z.x) / g.dsk[k], fabs(z.y) * nphi / (2.0 * 3.14159265358979323846)));
-      } else if (q == 1) {
-        nw[i] = z1[i].x * z.x + z1[i].y * z.y;
-      } else {
-        nt[i] = z1[i].x * z.x + z1[i].y * z.y;
-      }
-    }
-    __syncthreads();
-  }
-  // real products, N_omega in doubles [0, nphi), N_theta in [nphi, 2 nphi)
-  double* fr = reinterpret_cast<double*>(fb);
-#pragma unroll
-  for (int i = 0; i < MAXJ; ++i) {
-    int j = t + i * T;
-    if (j >= nphi) continue;
-    fr[j] = nw[i];
-    fr[nphi + j] = nt[i];
-  }
-  __syncthreads();
-  fft_lds<MAXB>(fb, g.phi_half, -1);
-  fft_lds<MAXB>(fb + nh, g.phi_half, -1);
-  const double inv = 1.0 / nphi;
-  for (int m = t; m < M; m += T) {
-    const double2 w = g.phi.tw[m];
-#pragma unroll
-    for (int f = 0; f < 2; ++f) {
-      const double2* Z = fb + f * nh;
-      double2 zk = Z[m % nh];
-      double2 zc = Z[(nh - m % nh) % nh];
-      zc.y = -zc.y;
-      double2 e = 0.5 * (zk + zc);
-      double2 d = zk - zc;
-      double2 o = make_double2(0.5 * d.y, -0.5 * d.x);   // (Z_k - Z*)/(2i)
-      double2 xm = e + cmul(w, o);
-      if (m == 0) xm.y = 0.0;
-      NL[((size_t)f * R + k) * M + m] = inv * xm;
-    }
-  }
-  // zonal forcing from the spectral fields: u_s,m = (h^2/s) X0_m,
-  // omega_m = X3_m / (i m)  =>  Re(u_s,m conj(omega_m)) = -(h^2/s) Im(X0 conj X3)/m
-  const double2* A0 = X + ((size_t)0 * R + k) * M;
-  const double2* A3 = X + ((size_t)3 * R + k) * M;
-  double zs = 0.0;
-  for (int m = 1 + t; m < M; m += T) {
-    double2 a = A0[m], b = A3[m];
-    zs += (a.y * b.x - a.x * b.y) / (double)m;
-  }
-  double tot = block_sum(zs, red);
-  if (t == 0) zonal[k] = -2.0 * h2s * tot;
-  if (rate) {
-    double rm = block_max(rmax, red);
-    if (t == 0) rate[k] = rm;
-  }
-}
-
-// ------------------------------------------------------------ analysis
-// Explicit right-hand sides at a stage state:
-//   m >= 1: E_psi = C [ (Ra/Pr)(i m/s_o) theta + N_omega ]   (eq. psi_int)
-//   m = 0:  E_u   = -D [ mean(u_s omega) ]                   (eq. uphi_int)
-//   all m:  E_th  = -D [ N_theta ]                           (eq. temp_int)
-template <int MAXB>
-__global__ void analysis_kernel(Geom g, Bands b, const double2* __restrict__ NL,
-                                const double* __restrict__ zonal,
-                                const double2* __restrict__ th_state,
-                                double2* __restrict__ Epsi, double2* __restrict__ Eth) {
-  extern __shared__ double2 sm[];
-  const int K = g.K, R = g.R, M = g.M, N = R - 1;
-  const int T = blockDim.x, t = threadIdx.x;
-  const int m = blockIdx.x;
-  double2* ca = sm;
-  double2* cb = sm + K;
-  double2* fb = sm + 2 * K;
-  if (m == 0)
-    dct_forward<MAXB>([&](int kk) { return make_double2(zonal[kk], 0.0); }, ca, K, fb, g);
-  else
-    dct_forward<MAXB>([&](int kk) { return NL[((size_t)0 * R + kk) * M + m]; }, ca, K, fb, g);
-  dct_forward<MAXB>([&](int kk) { return NL[((size_t)1 * R + kk) * M + m]; }, cb, K, fb, g);
-  const double2* thm = th_state + (size_t)m * K;
-  const double bcoef = g.Ra_Pr * (double)m / g.s_o;   // (Ra/Pr)(m/s_o), times i
-  for (int k = t; k < K; k += T) {
-    double2 ep = zero2(), et = zero2();
-    const int lo = max(0, k - 8), hi = min(K - 1, k + 8);
-    if (m > 0) {
-      if (k >= 4)
-        for (int n = lo; n <= hi; ++n) {
-          double c = b.C[(size_t)(n - k + 8) * K + k];
-          double2 v = ca[n] + bcoef * times_i(thm[n]);
-          ep += c * v;
-        }
-    } else if (k >= 2) {
-      for (int n = lo; n <= hi; ++n) ep -= b.D[(size_t)(n - k + 8) * K + k] * ca[n];
-    }
-    if (k >= 2)
-      for (int n = lo; n <= hi; ++n) et -= b.D[(size_t)(n - k + 8) * K + k] * cb[n];
-    Epsi[(size_t)m * K + k] = ep;
-    Eth[(size_t)m * K + k] = et;
-  }
 }
 
 // ----------------------------------------------------------------- rhs
@@ -783,34 +342,6 @@ __global__ void lin_kernel(Geom g, Bands b, const double2* __restrict__ ypsi,
 }
 
 // ------------------------------------------------------------ launchers
-template <int MAXB, int MAXP>
-void launch_synth_t(const Geom& g, const double2* psi, const double2* th, double2* X,
-                    double* diag, int threads, hipStream_t st) {
-  size_t shm = sizeof(double2) * (2 * g.K + 2 * (g.R - 1) + 2 * threads);
-  hipLaunchKernelGGL((synth_kernel<MAXB, MAXP>), dim3(g.M), dim3(threads), shm, st, g, psi, th, X,
-                     diag);
-}
-
-void launch_synth(const Geom& g, const double2* psi, const double2* th, double2* X, double* diag,
-                  int threads, hipStream_t st) {
-  if (threads <= 256) launch_synth_t<4, 5>(g, psi, th, X, diag, threads, st);
-  else launch_synth_t<4, 5>(g, psi, th, X, diag, threads, st);
-}
-
-void launch_ring(const Geom& g, const double2* X, double2* NL, double* zonal, double* rate,
-                 int threads, hipStream_t st) {
-  size_t shm = sizeof(double2) * g.nphi;
-  hipLaunchKernelGGL((ring_kernel<4, 16>), dim3(g.R), dim3(threads), shm, st, g, X, NL, zonal, rate);
-}
-
-void launch_analysis(const Geom& g, const Bands& b, const double2* NL, const double* zonal,
-                     const double2* th_state, double2* Epsi, double2* Eth, int threads,
-                     hipStream_t st) {
-  size_t shm = sizeof(double2) * (2 * g.K + 2 * (g.R - 1));
-  hipLaunchKernelGGL((analysis_kernel<4>), dim3(g.M), dim3(threads), shm, st, g, b, NL, zonal,
-                     th_state, Epsi, Eth);
-}
-
 size_t solve_lds_bytes(const Geom& g, int kutp, int kutr) {
   const int B = SOLVE_BATCH;
   const size_t psi = sizeof(double2) * 2 * B * (8 + kutp + 1);

@@ -1,0 +1,579 @@
+// Transform kernels of one IMEX step of spherical quasi-geostrophic
+// convection (FP64, gfx950):
+//
+//   synth_kernel     per m:    Chebyshev derivative recurrences and inverse
+//                              DCT-I (eq. cheb) of Psi, Psi', Psi'', Psi''',
+//                              theta, theta'; the six products' factors in
+//                              physical s and spectral phi
+//   ring_kernel      per s_k:  c2r FFTs (eq. fft), advection products,
+//                              r2c FFTs (eq. ifft), zonal forcing
+//   analysis_kernel  per m:    forward DCT-I (eq. icheb) with radial
+//                              dealiasing, explicit terms C[..], -D[..]
+//
+// Layout: X[f][k][m] and NL[f][k][m] (m fastest).  The per-m kernels map
+// consecutive m to the same XCD (blocks go to the eight XCDs round robin),
+// so that the 16-byte strided stores and loads of neighbouring m share L2
+// lines.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <vector>
+
+#include "fft.h"
+#include "kernels.h"
+
+namespace qg {
+
+namespace {
+
+__device__ __forceinline__ double2 add2(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ double2 sub2(double2 a, double2 b) { return make_double2(a.x - b.x, a.y - b.y); }
+__device__ __forceinline__ double2 scl2(double s, double2 a) { return make_double2(s * a.x, s * a.y); }
+__device__ __forceinline__ double2 ix(double m, double2 a) { return make_double2(-m * a.y, m * a.x); }  // i m a
+__device__ __forceinline__ double2 z2() { return make_double2(0.0, 0.0); }
+__device__ __forceinline__ double abs2(double2 a) { return a.x * a.x + a.y * a.y; }
+
+constexpr int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
+constexpr int threads_dct(int n2) { return clampi(n2 / 8, 64, 256); }
+constexpr int threads_phi(int nphi) { return clampi(nphi / 12, 64, 256); }
+
+// Block -> m: XCD x = block mod 8 takes the contiguous range [x per, (x+1) per).
+__device__ __forceinline__ int xcd_index(int count) {
+  const int per = (count + 7) >> 3;
+  return (blockIdx.x & 7) * per + (blockIdx.x >> 3);
+}
+int xcd_grid(int count) { return 8 * ((count + 7) / 8); }
+
+// Hides a value from the optimiser for one use: the per-point factors of
+// the derivative loops would otherwise be hoisted out of those loops for all
+// points at once and held in registers for the whole kernel.
+__device__ __forceinline__ void opaque(double& s, int& k) {
+  asm volatile("" : "+v"(s), "+v"(k));
+}
+
+__device__ __forceinline__ double2 shfl_down2(double2 v, int off) {
+  return make_double2(__shfl_down(v.x, off), __shfl_down(v.y, off));
+}
+
+// Transform with outputs in registers, out[i] = X_{t + i T} (zero past n).
+template <int n, int T>
+constexpr int out_count() { return (n + T - 1) / T; }
+
+template <int n, int T, int SGN, typename Get>
+__device__ __forceinline__ void fft_out(Get get, double2* buf, const double2* __restrict__ tw,
+                                        double2 (&out)[out_count<n, T>()]) {
+  if constexpr (reg_out_ok<n, T>()) {
+    fft_to_regs<n, T, SGN>(get, buf, tw, out);
+  } else {
+    fft_to_lds<n, T, SGN>(get, buf, tw);
+#pragma unroll
+    for (int i = 0; i < out_count<n, T>(); ++i) {
+      const int k = threadIdx.x + i * T;
+      out[i] = (k < n) ? buf[lds_pad(k)] : z2();
+    }
+  }
+}
+
+// In-place Chebyshev derivative d/ds on the unit gap (ds = dx / 2):
+// c'_n = (4 / c_n) sum_{j > n, j - n odd} j c_j, c_0 = 2, else 1.  Each
+// thread takes a run of (even, odd) index pairs; the suffix sums over the
+// runs of later threads come from a wavefront scan and one LDS exchange.
+// Ends with a barrier.
+template <int T>
+__device__ void cheb_deriv_inplace(double2* c, int K, double2* wred) {
+  constexpr int NW = T / 64;
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  const int npair = (K + 1) / 2;
+  const int ch = (npair + T - 1) / T;
+  const int p0 = min(npair, t * ch), p1 = min(npair, p0 + ch);
+  double2 se = z2(), so = z2();
+  for (int p = p0; p < p1; ++p) {
+    const int je = 2 * p, jo = je + 1;
+    se = add2(se, scl2((double)je, c[je]));
+    if (jo < K) so = add2(so, scl2((double)jo, c[jo]));
+  }
+  // exclusive suffix sums over the lanes above this one
+  double2 xe = shfl_down2(se, 1), xo = shfl_down2(so, 1);
+  if (lane == 63) xe = xo = z2();
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    const double2 ue = shfl_down2(xe, off), uo = shfl_down2(xo, off);
+    if (lane + off < 64) {
+      xe = add2(xe, ue);
+      xo = add2(xo, uo);
+    }
+  }
+  if (lane == 0) {
+    wred[2 * w] = add2(xe, se);
+    wred[2 * w + 1] = add2(xo, so);
+  }
+  __syncthreads();
+  double2 re = xe, ro = xo;
+  for (int w2 = w + 1; w2 < NW; ++w2) {
+    re = add2(re, wred[2 * w2]);
+    ro = add2(ro, wred[2 * w2 + 1]);
+  }
+  for (int p = p1 - 1; p >= p0; --p) {
+    const int je = 2 * p, jo = je + 1;
+    const double2 ae = c[je];
+    const double2 ao = (jo < K) ? c[jo] : z2();
+    if (jo < K) c[jo] = scl2(4.0, re);       // S_even(p + 1)
+    ro = add2(ro, scl2((double)jo, ao));     // S_odd(p)
+    c[je] = scl2(je == 0 ? 2.0 : 4.0, ro);
+    re = add2(re, scl2((double)je, ae));     // S_even(p)
+  }
+  __syncthreads();
+}
+
+__device__ double block_sum(double v, double* red) {
+  const int t = threadIdx.x, T = blockDim.x;
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+  __syncthreads();
+  if ((t & 63) == 0) red[t >> 6] = v;
+  __syncthreads();
+  double s = 0.0;
+  for (int w = 0; w < (T + 63) / 64; ++w) s += red[w];
+  return s;
+}
+
+__device__ double block_max(double v, double* red) {
+  const int t = threadIdx.x, T = blockDim.x;
+  for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off));
+  __syncthreads();
+  if ((t & 63) == 0) red[t >> 6] = v;
+  __syncthreads();
+  double s = 0.0;
+  for (int w = 0; w < (T + 63) / 64; ++w) s = fmax(s, red[w]);
+  return s;
+}
+
+}  // namespace
+
+// -------------------------------------------------------------- synth
+// Fields (Fourier coefficient m at s_k), written X[f][k][m]:
+//   0: dPsi/dphi = i m Psi          1: v = u_phi / s
+//   2: c_w = omega + (h^2/s) d_s omega   3: d omega/dphi = i m omega
+//   4: c_t = (h^2/s)(d_s theta + dTc/ds [m=0])   5: d theta/dphi
+// with u_phi = -h^2 Psi' + 3 s Psi (+ zonal flow at m = 0), omega = -L_I Psi
+// (m >= 1) and omega_0 = u' + u/s (Sect. 3.2.1).  The inverse DCT-I of a
+// coefficient row a_n (n < K) is the FFT of the even extension e_0 = a_0,
+// e_n = e_{2N-n} = a_n / 2 (eq. cheb).  Thread t owns the radial points
+// k = t + i T, and the fields are accumulated derivative by derivative.
+template <int N2, int T>
+__global__ __launch_bounds__(T) void synth_kernel(Geom g, const double2* __restrict__ psi,
+                                                  const double2* __restrict__ th,
+                                                  double2* __restrict__ X,
+                                                  double* __restrict__ diag) {
+  extern __shared__ double2 sm[];
+  __shared__ double2 wred[2 * (T / 64)];
+  __shared__ double red[T / 64];
+  constexpr int N = N2 / 2;
+  constexpr int E = out_count<N2, T>();
+  constexpr int NP = (N / T + 1) < E ? (N / T + 1) : E;   // registers holding k <= N
+  const int K = g.K, R = g.R, M = g.M;
+  const int t = threadIdx.x;
+  const int m = xcd_index(M);
+  if (m >= M) return;
+  double2* fb = sm;
+  double2* c = sm + lds_slots(N2);
+  auto ext = [&](int i) -> double2 {
+    const int nn = (i <= N) ? i : N2 - i;
+    if (nn >= K) return z2();
+    const double2 v = c[nn];
+    return nn == 0 ? v : scl2(0.5, v);
+  };
+  auto store = [&](int f, int k, double2 v) { X[((size_t)f * R + k) * M + m] = v; };
+
+  const double dm = (double)m, m2 = dm * dm, so2 = g.s_o * g.s_o;
+  double sk[NP];
+#pragma unroll
+  for (int i = 0; i < NP; ++i) {
+    const int k = t + i * T;
+    sk[i] = (k <= N) ? g.half * g.xk[k] + g.mid : 1.0;
+  }
+  double2 a1[NP], a2[NP], a3[NP];   // m > 0: u_phi, omega, c_w accumulators
+  double ek = 0.0, et = 0.0, ens = 0.0, ez = 0.0;
+
+  for (int nn = t; nn < K; nn += T) c[nn] = psi[(size_t)m * K + nn];
+  __syncthreads();
+  const int nder = (m > 0) ? 4 : 3;
+#pragma unroll 1
+  for (int d = 0; d < nder; ++d) {
+    if (d > 0) cheb_deriv_inplace<T>(c, K, wred);
+    double2 P[E];
+    fft_out<N2, T, -1>(ext, fb, g.tw_dct, P);
+#pragma unroll
+    for (int i = 0; i < NP; ++i) {
+      int k = t + i * T;
+      if (k > N) continue;
+      double s = sk[i];
+      opaque(s, k);
+      const double is = 1.0 / s, h2 = so2 - s * s, h2s = h2 * is;
+      const double2 p = P[i];
+      if (m > 0) {
+        const double mh = m2 * h2 * is * is;
+        if (d == 0) {
+          store(0, k, ix(dm, p));
+          a1[i] = scl2(3.0 * s, p);
+          a2[i] = scl2(6.0 + mh, p);
+          a3[i] = scl2(6.0 + mh - h2s * 2.0 * m2 * so2 * is * is * is, p);
+          if (diag) ek += 2.0 * g.wq[k] * h2s * h2s * m2 * abs2(p);
+        } else if (d == 1) {
+          const double2 uph = sub2(a1[i], scl2(h2, p));
+          store(1, k, scl2(is, uph));
+          if (diag) ek += 2.0 * g.wq[k] * abs2(uph);
+          a2[i] = sub2(a2[i], scl2(h2s - 5.0 * s, p));
+          a3[i] = add2(a3[i], scl2(-(h2s - 5.0 * s) + h2s * (so2 * is * is + 12.0 + mh), p));
+        } else if (d == 2) {
+          const double2 om = sub2(a2[i], scl2(h2, p));
+          store(3, k, ix(dm, om));
+          if (diag) ens += 2.0 * g.wq[k] * abs2(om);
+          a3[i] = sub2(a3[i], scl2(h2 + h2s * (h2s - 7.0 * s), p));
+        } else {
+          store(2, k, sub2(a3[i], scl2(h2s * h2, p)));
+        }
+      } else {
+        // zonal flow u = P0, u' = P1, u'' = P2 (real)
+        if (d == 0) {
+          store(0, k, z2());
+          store(1, k, scl2(is, p));
+          store(3, k, z2());
+          a1[i] = p;
+          a2[i] = scl2(is, p);                                   // omega
+          a3[i] = sub2(scl2(is, p), scl2(h2s * is * is, p));     // c_w
+          if (diag) {
+            ek += g.wq[k] * p.x * p.x;
+            ez += g.wq[k] * p.x * p.x;
+          }
+        } else if (d == 1) {
+          a2[i] = add2(a2[i], p);
+          a3[i] = add2(a3[i], scl2(1.0 + h2s * is, p));
+          if (diag) ens += g.wq[k] * a2[i].x * a2[i].x;
+        } else {
+          store(2, k, add2(a3[i], scl2(h2s, p)));
+        }
+      }
+    }
+  }
+  // theta, theta'
+  __syncthreads();
+  for (int nn = t; nn < K; nn += T) c[nn] = th[(size_t)m * K + nn];
+  __syncthreads();
+#pragma unroll 1
+  for (int d = 0; d < 2; ++d) {
+    if (d > 0) cheb_deriv_inplace<T>(c, K, wred);
+    double2 P[E];
+    fft_out<N2, T, -1>(ext, fb, g.tw_dct, P);
+#pragma unroll
+    for (int i = 0; i < NP; ++i) {
+      int k = t + i * T;
+      if (k > N) continue;
+      double s = sk[i];
+      opaque(s, k);
+      const double is = 1.0 / s, h2s = (so2 - s * s) * is;
+      const double2 p = P[i];
+      if (d == 0) {
+        store(5, k, ix(dm, p));
+        if (diag) et += (m > 0 ? 2.0 : 1.0) * g.wq[k] * (m > 0 ? abs2(p) : p.x * p.x);
+      } else {
+        double2 v = p;
+        if (m == 0) v.x += g.dtc_coef * is;
+        store(4, k, scl2(h2s, v));
+      }
+    }
+  }
+  if (diag) {
+    const double pi = 3.14159265358979323846;
+    double bad = 0.0;
+    for (int nn = t; nn < K; nn += T) {
+      const double2 a = psi[(size_t)m * K + nn], b = th[(size_t)m * K + nn];
+      if (!isfinite(a.x) || !isfinite(a.y) || !isfinite(b.x) || !isfinite(b.y)) bad = 1.0;
+    }
+    const double s0 = block_sum(ek, red);
+    const double s1 = block_sum(ez, red);
+    const double s2 = block_sum(et, red);
+    const double s3 = block_sum(ens, red);
+    const double s4 = block_max(bad, red);
+    if (t == 0) {
+      diag[m * 8 + 0] = pi * s0;
+      diag[m * 8 + 1] = pi * s1;
+      diag[m * 8 + 2] = pi * s2;
+      diag[m * 8 + 3] = 2.0 * pi * s3;
+      diag[m * 8 + 4] = s4;
+    }
+  }
+}
+
+// ---------------------------------------------------------------- ring
+// Per radial level: three complex inverse FFTs of length N_phi (each
+// carries two real fields of similar size: z = A + i B from the half
+// spectra), the products
+//   N_omega = dPsi/dphi c_w + v d omega/dphi,
+//   N_theta = dPsi/dphi c_t + v d theta/dphi,
+// then the two real forward FFTs (eq. ifft) as one batch of two complex
+// FFTs of length N_phi/2 of z_j = x_2j + i x_2j+1:
+//   X_m = (Z_m + Z*_{N/2-m})/2 - (i/2) w^m (Z_m - Z*_{N/2-m}),  w = e^{-2 pi i/N},
+// scaled by 1/N_phi and truncated to m <= N_m (N_omega can exceed N_theta by
+// many orders of magnitude, so the two never share one complex transform).
+// Zonal forcing: mean(u_s omega) = 2 sum_{m>=1} Re(u_s,m conj(omega_m)) with
+// u_s,m = (h^2/s) X0_m and omega_m = X3_m / (i m).
+template <int NPHI, int T>
+__global__ __launch_bounds__(T) void ring_kernel(Geom g, const double2* __restrict__ X,
+                                                 double2* __restrict__ NL,
+                                                 double* __restrict__ zonal,
+                                                 double* __restrict__ rate) {
+  extern __shared__ double2 fb[];
+  __shared__ double red[T / 64];
+  constexpr int E = out_count<NPHI, T>();
+  constexpr int NH = NPHI / 2;
+  const int R = g.R, M = g.M;
+  const int t = threadIdx.x;
+  const int k = blockIdx.x;
+  const double s = g.half * g.xk[k] + g.mid;
+  const double h2s = (g.s_o * g.s_o - s * s) / s;
+  const double2* X0 = X + (size_t)k * M;
+  double2 z1[E];
+  double nw[E], nt[E];
+  double zs = 0.0, rmax = 0.0;
+#pragma unroll
+  for (int q = 0; q < 3; ++q) {
+    const double2* A = X + ((size_t)(2 * q) * R + k) * M;
+    const double2* B = X + ((size_t)(2 * q + 1) * R + k) * M;
+    auto get = [&](int i) -> double2 {
+      if (i < M) {
+        const double2 a = A[i], b = B[i];
+        if (q == 1 && i > 0) {
+          const double2 x0 = X0[i];
+          zs += (x0.y * b.x - x0.x * b.y) / (double)i;
+        }
+        return (i == 0) ? make_double2(a.x, b.x) : make_double2(a.x - b.y, a.y + b.x);
+      }
+      if (i > NPHI - M) {
+        const double2 a = A[NPHI - i], b = B[NPHI - i];
+        return make_double2(a.x + b.y, b.x - a.y);
+      }
+      return z2();
+    };
+    double2 z[E];
+    fft_out<NPHI, T, +1>(get, fb, g.tw_phi, z);
+#pragma unroll
+    for (int i = 0; i < E; ++i) {
+      if (q == 0) {
+        z1[i] = z[i];
+        if (rate)
+          rmax = fmax(rmax, fmax(h2s * fabs(z[i].x) / g.dsk[k],
+                                 fabs(z[i].y) * NPHI / (2.0 * 3.14159265358979323846)));
+      } else if (q == 1) {
+        nw[i] = z1[i].x * z[i].x + z1[i].y * z[i].y;
+      } else {
+        nt[i] = z1[i].x * z[i].x + z1[i].y * z[i].y;
+      }
+    }
+  }
+  // real products: N_omega at doubles [0, NPHI), N_theta at [NPHI, 2 NPHI)
+  __syncthreads();
+  double* fr = reinterpret_cast<double*>(fb);
+#pragma unroll
+  for (int i = 0; i < E; ++i) {
+    const int j = t + i * T;
+    if (j < NPHI) {
+      fr[j] = nw[i];
+      fr[NPHI + j] = nt[i];
+    }
+  }
+  __syncthreads();
+  const double2* zin = fb;
+  fft_to_lds<NH, T, -1, 2>([&](int ii) { return zin[ii]; }, fb, g.tw_half);
+  const double inv = 1.0 / NPHI;
+  for (int m = t; m < M; m += T) {
+    const double2 w = g.w_phi[m];
+#pragma unroll
+    for (int f = 0; f < 2; ++f) {
+      double2 zk = fb[lds_pad(f * NH + m)];
+      double2 zc = fb[lds_pad(f * NH + (NH - m) % NH)];
+      zc.y = -zc.y;
+      const double2 e = scl2(0.5, add2(zk, zc));
+      const double2 dd = sub2(zk, zc);
+      const double2 o = make_double2(0.5 * dd.y, -0.5 * dd.x);   // (Z_m - Z*)/(2i)
+      double2 xm = add2(e, make_double2(w.x * o.x - w.y * o.y, w.x * o.y + w.y * o.x));
+      if (m == 0) xm.y = 0.0;
+      NL[((size_t)f * R + k) * M + m] = scl2(inv, xm);
+    }
+  }
+  const double tot = block_sum(zs, red);
+  if (t == 0) zonal[k] = -2.0 * h2s * tot;
+  if (rate) {
+    const double rm = block_max(rmax, red);
+    if (t == 0) rate[k] = rm;
+  }
+}
+
+// ------------------------------------------------------------ analysis
+// Explicit right-hand sides at a stage state:
+//   m >= 1: E_psi = C [ (Ra/Pr)(i m/s_o) theta + N_omega ]   (eq. psi_int)
+//   m = 0:  E_u   = -D [ mean(u_s omega) ]                   (eq. uphi_int)
+//   all m:  E_th  = -D [ N_theta ]                           (eq. temp_int)
+// Forward DCT-I (eq. icheb): a_n = (h_n / N) FFT(e)_n with the even
+// extension e_i = f_{|i|}, h_0 = 1/2, else 1, kept for n < K.
+template <int N2, int T>
+__global__ __launch_bounds__(T) void analysis_kernel(Geom g, Bands b,
+                                                     const double2* __restrict__ NL,
+                                                     const double* __restrict__ zonal,
+                                                     const double2* __restrict__ th_state,
+                                                     double2* __restrict__ Epsi,
+                                                     double2* __restrict__ Eth) {
+  extern __shared__ double2 sm[];
+  constexpr int N = N2 / 2;
+  constexpr int E = out_count<N2, T>();
+  const int K = g.K, R = g.R, M = g.M;
+  const int t = threadIdx.x;
+  const int m = xcd_index(M);
+  if (m >= M) return;
+  double2* fb = sm;
+  double2* c = sm + lds_slots(N2);
+  const double invN = 1.0 / N;
+  const double2* thm = th_state + (size_t)m * K;
+  const double bcoef = g.Ra_Pr * (double)m / g.s_o;   // (Ra/Pr)(m/s_o), times i
+#pragma unroll
+  for (int f = 0; f < 2; ++f) {
+    auto get = [&](int i) -> double2 {
+      const int kk = (i <= N) ? i : N2 - i;
+      if (f == 0 && m == 0) return make_double2(zonal[kk], 0.0);
+      return NL[((size_t)f * R + kk) * M + m];
+    };
+    double2 o[E];
+    fft_out<N2, T, -1>(get, fb, g.tw_dct, o);
+#pragma unroll
+    for (int i = 0; i < E; ++i) {
+      const int nn = t + i * T;
+      if (nn < K) c[nn] = scl2(nn == 0 ? 0.5 * invN : invN, o[i]);
+    }
+    __syncthreads();
+    for (int k = t; k < K; k += T) {
+      double2 acc = z2();
+      const int lo = max(0, k - 8), hi = min(K - 1, k + 8);
+      if (f == 0 && m > 0) {
+        if (k >= 4)
+          for (int nn = lo; nn <= hi; ++nn) {
+            const double cc = b.C[(size_t)(nn - k + 8) * K + k];
+            acc = add2(acc, scl2(cc, add2(c[nn], ix(bcoef, thm[nn]))));
+          }
+        Epsi[(size_t)m * K + k] = acc;
+      } else {
+        if (k >= 2)
+          for (int nn = lo; nn <= hi; ++nn)
+            acc = sub2(acc, scl2(b.D[(size_t)(nn - k + 8) * K + k], c[nn]));
+        (f == 0 ? Epsi : Eth)[(size_t)m * K + k] = acc;
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// ------------------------------------------------------------ launchers
+namespace {
+
+template <typename Kern>
+void allow_lds(Kern k, size_t bytes) {
+  if (bytes > 65536)
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(k),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+}
+
+template <int N2>
+void synth_n(const Geom& g, const double2* psi, const double2* th, double2* X, double* diag,
+             hipStream_t st) {
+  constexpr int T = threads_dct(N2);
+  const size_t shm = sizeof(double2) * (lds_slots(N2) + g.K);
+  allow_lds(synth_kernel<N2, T>, shm);
+  hipLaunchKernelGGL((synth_kernel<N2, T>), dim3(xcd_grid(g.M)), dim3(T), shm, st, g, psi, th, X,
+                     diag);
+}
+
+template <int NPHI>
+void ring_n(const Geom& g, const double2* X, double2* NL, double* zonal, double* rate,
+            hipStream_t st) {
+  constexpr int T = threads_phi(NPHI);
+  const size_t shm = sizeof(double2) * lds_slots(NPHI);
+  allow_lds(ring_kernel<NPHI, T>, shm);
+  hipLaunchKernelGGL((ring_kernel<NPHI, T>), dim3(g.R), dim3(T), shm, st, g, X, NL, zonal, rate);
+}
+
+template <int N2>
+void analysis_n(const Geom& g, const Bands& b, const double2* NL, const double* zonal,
+                const double2* th, double2* Ep, double2* Et, hipStream_t st) {
+  constexpr int T = threads_dct(N2);
+  const size_t shm = sizeof(double2) * (lds_slots(N2) + g.K);
+  allow_lds(analysis_kernel<N2, T>, shm);
+  hipLaunchKernelGGL((analysis_kernel<N2, T>), dim3(xcd_grid(g.M)), dim3(T), shm, st, g, b, NL,
+                     zonal, th, Ep, Et);
+}
+
+#define QG_DCT_SIZES(X) X(32) X(64) X(128) X(256) X(512) X(1024) X(2048) X(4096)
+#define QG_PHI_SIZES(X) X(24) X(48) X(96) X(192) X(384) X(768) X(1536) X(3072) X(6144)
+
+}  // namespace
+
+bool transform_sizes_ok(int n2, int nphi) {
+  bool a = false, b = false;
+#define QG_CASE(n) a = a || (n2 == n);
+  QG_DCT_SIZES(QG_CASE)
+#undef QG_CASE
+#define QG_CASE(n) b = b || (nphi == n);
+  QG_PHI_SIZES(QG_CASE)
+#undef QG_CASE
+  return a && b;
+}
+
+size_t transform_lds_bytes(int n2, int nphi, int K) {
+  const size_t d = sizeof(double2) * (lds_slots(n2) + K);
+  const size_t p = sizeof(double2) * lds_slots(nphi);
+  return d > p ? d : p;
+}
+
+std::vector<double2> plan_twiddles(int n) {
+  const RadixPlan pl = radix_plan(n);
+  std::vector<double2> tw(n > 1 ? n - 1 : 1, make_double2(1.0, 0.0));
+  const long double pi = 3.14159265358979323846264338327950288L;
+  for (int s = 0; s < pl.np; ++s) {
+    const int R = pl.r[s], Ns = plan_ns(pl, s);
+    for (int r = 1; r < R; ++r)
+      for (int k = 0; k < Ns; ++k) {
+        const long double a = -2.0L * pi * (long double)(k * r) / (long double)(Ns * R);
+        tw[(Ns - 1) + (r - 1) * Ns + k] = make_double2((double)cosl(a), (double)sinl(a));
+      }
+  }
+  return tw;
+}
+
+bool launch_synth(const Geom& g, const double2* psi, const double2* th, double2* X, double* diag,
+                  hipStream_t st) {
+  switch (2 * (g.R - 1)) {
+#define QG_CASE(n) case n: synth_n<n>(g, psi, th, X, diag, st); return true;
+    QG_DCT_SIZES(QG_CASE)
+#undef QG_CASE
+    default: return false;
+  }
+}
+
+bool launch_ring(const Geom& g, const double2* X, double2* NL, double* zonal, double* rate,
+                 hipStream_t st) {
+  switch (g.nphi) {
+#define QG_CASE(n) case n: ring_n<n>(g, X, NL, zonal, rate, st); return true;
+    QG_PHI_SIZES(QG_CASE)
+#undef QG_CASE
+    default: return false;
+  }
+}
+
+bool launch_analysis(const Geom& g, const Bands& b, const double2* NL, const double* zonal,
+                     const double2* th_state, double2* Epsi, double2* Eth, hipStream_t st) {
+  switch (2 * (g.R - 1)) {
+#define QG_CASE(n) case n: analysis_n<n>(g, b, NL, zonal, th_state, Epsi, Eth, st); return true;
+    QG_DCT_SIZES(QG_CASE)
+#undef QG_CASE
+    default: return false;
+  }
+}
+
+}  // namespace qg
