@@ -70,6 +70,12 @@ typedef struct {
   int n_c;       /* Chebyshev modes kept, 8 <= n_c < n_r; 0 selects
                     floor(2 (n_r - 1) / 3) (radial dealiasing, Sect. 3.2.1) */
   int precision; /* 0 = FP64 (the only value accepted by this build) */
+  int pivoting;  /* band LU of the bordered systems (Appendix A):
+                    0 = without row interchanges when every system's growth
+                        factor max|U| / max|D| stays <= 1e4, else with
+                        partial pivoting (the choice is made at each
+                        factorisation and reported in qg_diag);
+                    1 = always with partial pivoting */
 } qg_params;
 
 typedef struct {
@@ -83,6 +89,9 @@ typedef struct {
   double dt_cfl;    /* right side of eq. (cfl) with alpha = 1 */
   long long step;   /* steps taken since the last qg_set_state */
   int nonfinite;    /* 1 if the state holds NaN or Inf */
+  int pivoted;      /* 1 if the band LUs in use have row interchanges */
+  double growth;    /* largest growth factor max|U| / max|D| of those LUs
+                       (0 before the first factorisation) */
 } qg_diag;
 
 /* Device bytes the caller must provide to qg_create for these parameters.

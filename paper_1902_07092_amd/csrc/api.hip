@@ -20,8 +20,12 @@ void launch_rhs(const Geom& g, const Bands& b, const RhsSpec& rs, double2* rhs, 
 void launch_lin(const Geom& g, const Bands& b, const double2* ypsi, const double2* yth,
                 double2* lpsi, double2* lth, hipStream_t st);
 bool launch_solve(const Geom& g, const FactorSet<double2>& Fp, const FactorSet<double>& Fr,
-                  double2* rhs, const RhsSpec& rs, int kutp, int kutr, hipStream_t st);
+                  double2* rhs, const RhsSpec& rs, int kutp, int kutr, bool pivoted,
+                  hipStream_t st);
 int solve_batch();
+bool launch_solve_np(const Geom& g, const FactorSet<double2>& Fp, const FactorSet<double>& Fr,
+                     double2* rhs, const RhsSpec& rs, int qp, int qr, hipStream_t st);
+int solve_np_pad();
 }  // namespace qg
 
 using namespace qg;
@@ -55,7 +59,8 @@ struct Layout {
 
 struct Sizes {
   int M, K, R, nphi, n4, n2, Sr;
-  int p4, p2;   // n4, n2 padded to whole 32-step batches
+  int p4, p2;   // n4, n2 padded to whole 16-step batches (pivoted solve)
+  int q4, q2;   // n4, n2 padded to a multiple of 48 (unpivoted solve)
 };
 
 bool sizes_of(const qg_params* p, Sizes& z, std::string& why) {
@@ -67,6 +72,7 @@ bool sizes_of(const qg_params* p, Sizes& z, std::string& why) {
   int K = p->n_c ? p->n_c : (2 * (p->n_r - 1)) / 3;
   if (K < 8 || K >= p->n_r) { why = "n_c must satisfy 8 <= n_c < n_r"; return false; }
   if (p->precision != 0) { why = "only precision = 0 (FP64) is supported"; return false; }
+  if (p->pivoting != 0 && p->pivoting != 1) { why = "pivoting must be 0 or 1"; return false; }
   z.M = p->n_phi / 3 + 1;
   z.K = K;
   z.R = p->n_r;
@@ -75,6 +81,8 @@ bool sizes_of(const qg_params* p, Sizes& z, std::string& why) {
   z.n2 = K - 2;
   z.p4 = (z.n4 + 15) / 16 * 16;   // whole solve batches (16 steps)
   z.p2 = (z.n2 + 15) / 16 * 16;
+  z.q4 = (z.n4 + 47) / 48 * 48;
+  z.q2 = (z.n2 + 47) / 48 * 48;
   z.Sr = z.M + 1;
   return true;
 }
@@ -82,8 +90,8 @@ bool sizes_of(const qg_params* p, Sizes& z, std::string& why) {
 struct WsMap {
   size_t state, ybuf, eslot, lslot, X, NL, zonal, rate, diag, xk, wq, dsk, twd, twp, twh, wphi,
       bands, rhs;
-  size_t p_piv, p_L, p_U, p_W, p_C, p_Mi;
-  size_t r_piv, r_L, r_U, r_W, r_C, r_Mi;
+  size_t p_piv, p_L, p_U, p_W, p_C, p_Mi, p_ui;
+  size_t r_piv, r_L, r_U, r_W, r_C, r_Mi, r_ui;
   size_t total;
 };
 
@@ -112,15 +120,17 @@ WsMap map_workspace(const Sizes& z) {
   w.bands = L.take((size_t)9 * z.K * BANDW * sizeof(double));
   w.rhs = L.take((size_t)2 * z.M * z.K * sizeof(double2));
   w.p_piv = L.take(Sp * z.p4 * sizeof(int));
-  w.p_L = L.take(Sp * z.p4 * 8 * sizeof(double2));
-  w.p_U = L.take(Sp * z.p4 * 17 * sizeof(double2));
+  w.p_L = L.take(Sp * std::max(z.p4, z.q4) * 8 * sizeof(double2));
+  w.p_U = L.take(Sp * std::max(z.p4 * 17, z.q4 * 8) * sizeof(double2));
+  w.p_ui = L.take(Sp * z.q4 * sizeof(double2));
   w.p_W = L.take(Sp * 4 * z.n4 * sizeof(double2));
   w.p_C = L.take(Sp * 8 * 4 * sizeof(double2));
   w.p_Mi = L.take(Sp * 16 * sizeof(double2));
   const size_t Sr = z.Sr;
   w.r_piv = L.take(Sr * z.p2 * sizeof(int));
-  w.r_L = L.take(Sr * z.p2 * 4 * sizeof(double));
-  w.r_U = L.take(Sr * z.p2 * 9 * sizeof(double));
+  w.r_L = L.take(Sr * std::max(z.p2, z.q2) * 4 * sizeof(double));
+  w.r_U = L.take(Sr * std::max(z.p2 * 9, z.q2 * 4) * sizeof(double));
+  w.r_ui = L.take(Sr * z.q2 * sizeof(double));
   w.r_W = L.take(Sr * 2 * z.n2 * sizeof(double));
   w.r_C = L.take(Sr * 4 * 2 * sizeof(double));
   w.r_Mi = L.take(Sr * 4 * sizeof(double));
@@ -142,6 +152,8 @@ struct qg_ctx {
   FactorSet<double2> Fp;
   FactorSet<double> Fr;
   int kutp = 16, kutr = 8;   // stored U super-diagonals (Psi, real systems)
+  bool pivoted = true;       // band LU with row interchanges in use
+  double growth = 0.0;       // largest growth factor of the band LUs in use
   double factored_adt = -1.0;
   int have_prev = 0, cur = 0;
   double t = 0.0;
@@ -250,7 +262,7 @@ int max_pivot(const BorderedFactor<T>& f) {
 template <typename T, typename D2>
 bool pack(const BorderedFactor<T>& f, size_t s, int kl, int wu, int p, int npad, int* piv, D2* L,
           D2* U, D2* W, D2* C, D2* Mi) {
-  const int n = f.n, wfull = f.kl + f.ku + 1;
+  const int n = f.n, wfull = f.kut + 1;
   auto cvt = [](const T& v) -> D2 {
     if constexpr (std::is_same<T, cplx>::value) return make_double2(v.real(), v.imag());
     else return v;
@@ -272,6 +284,32 @@ bool pack(const BorderedFactor<T>& f, size_t s, int kl, int wu, int p, int npad,
   return true;
 }
 
+// Unpivoted layout of one system: multipliers L [q][kl], U scaled to a
+// unit diagonal by rows, column-wise [q][ku], and 1/U(j,j) [q]; steps past
+// n are identity steps (zero multipliers, unit diagonal).
+template <typename T, typename D2>
+void pack_np(const BorderedFactor<T>& f, size_t s, int kl, int ku, int p, int q, D2* L, D2* U,
+             D2* ui, D2* W, D2* C, D2* Mi) {
+  const int n = f.n, wf = f.kut + 1;
+  auto cvt = [](const T& v) -> D2 {
+    if constexpr (std::is_same<T, cplx>::value) return make_double2(v.real(), v.imag());
+    else return v;
+  };
+  for (int j = 0; j < q; ++j) {
+    for (int d = 0; d < kl; ++d)
+      L[(s * q + j) * kl + d] = cvt(j < n ? f.Lc[(size_t)j * kl + d] : T(0));
+    for (int e = 1; e <= ku; ++e) {
+      T v(0);
+      if (j < n && j - e >= 0) v = f.Uc[(size_t)j * wf + e] * f.Uc[(size_t)(j - e) * wf];
+      U[(s * q + j) * ku + (e - 1)] = cvt(v);
+    }
+    ui[s * q + j] = cvt(j < n ? f.Uc[(size_t)j * wf] : T(1));
+  }
+  for (size_t i = 0; i < (size_t)p * n; ++i) W[s * p * n + i] = cvt(f.W[i]);
+  for (size_t i = 0; i < (size_t)kl * p; ++i) C[s * kl * p + i] = cvt(f.Cb[i]);
+  for (size_t i = 0; i < (size_t)p * p; ++i) Mi[s * p * p + i] = cvt(f.Minv[i]);
+}
+
 template <typename F>
 void parallel_for(int count, F fn) {
   unsigned hw = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
@@ -283,66 +321,105 @@ void parallel_for(int count, F fn) {
   for (auto& x : th) x.join();
 }
 
+// Unpivoted band LUs are used when every system's growth factor stays
+// below this bound (their solve then needs no row interchanges); otherwise
+// all systems are refactored with partial pivoting.
+constexpr double MAX_UNPIVOTED_GROWTH = 1e4;
+
 qg_status refactor(qg_ctx* ctx, double adt) {
   const Sizes& z = ctx->z;
   const size_t Sp = z.M - 1, Sr = z.Sr;
   std::vector<BorderedFactor<cplx>> fp(Sp);
   std::vector<BorderedFactor<double>> fr(Sr);
   std::vector<int> ok(Sp + Sr, 1);
-  parallel_for((int)(Sp + Sr), [&](int idx) {
-    int p;
-    if (idx < (int)Sp) {
-      std::vector<cplx> full;
-      assemble<cplx>(ctx, 0, idx + 1, adt, full, p);
-      ok[idx] = factor_bordered<cplx>(full, z.K, 4, 8, 8, fp[idx]);
-    } else {
-      const int s = idx - (int)Sp;
-      std::vector<double> full;
-      assemble<double>(ctx, s == 0 ? 1 : 2, s == 0 ? 0 : s - 1, adt, full, p);
-      ok[idx] = factor_bordered<double>(full, z.K, 2, 4, 4, fr[s]);
-    }
-  });
+  bool pivot = ctx->p.pivoting != 0;
+  for (int attempt = 0; attempt < 2; ++attempt) {
+    parallel_for((int)(Sp + Sr), [&](int idx) {
+      int p;
+      if (idx < (int)Sp) {
+        std::vector<cplx> full;
+        assemble<cplx>(ctx, 0, idx + 1, adt, full, p);
+        ok[idx] = factor_bordered<cplx>(full, z.K, 4, 8, 8, pivot, fp[idx]);
+      } else {
+        const int s = idx - (int)Sp;
+        std::vector<double> full;
+        assemble<double>(ctx, s == 0 ? 1 : 2, s == 0 ? 0 : s - 1, adt, full, p);
+        ok[idx] = factor_bordered<double>(full, z.K, 2, 4, 4, pivot, fr[s]);
+      }
+    });
+    double growth = 0.0;
+    bool good = true;
+    for (int v : ok) good = good && v;
+    for (auto& f : fp) growth = std::max(growth, f.growth);
+    for (auto& f : fr) growth = std::max(growth, f.growth);
+    ctx->growth = growth;
+    if (pivot || (good && growth <= MAX_UNPIVOTED_GROWTH)) break;
+    pivot = true;   // unpivoted elimination broke down or grew: pivot everywhere
+    std::fill(ok.begin(), ok.end(), 1);
+  }
   for (int v : ok)
     if (!v) return fail(ctx, QG_EINVAL, "singular tau matrix (dt too large or bad parameters)");
   int mp = 0, mr = 0;
   for (auto& f : fp) mp = std::max(mp, max_pivot(f));
   for (auto& f : fr) mr = std::max(mr, max_pivot(f));
-  int kutp = (8 + mp <= 12) ? 12 : 16;
-  int kutr = (4 + mr <= 4) ? 4 : 8;
-  std::vector<int> ppiv(Sp * z.p4), rpiv(Sr * z.p2);
-  std::vector<double2> pL(Sp * z.p4 * 8), pU(Sp * z.p4 * (kutp + 1)), pW(Sp * 4 * z.n4),
-      pC(Sp * 32), pM(Sp * 16);
-  std::vector<double> rL(Sr * z.p2 * 4), rU(Sr * z.p2 * (kutr + 1)), rW(Sr * 2 * z.n2),
-      rC(Sr * 8), rM(Sr * 4);
-  parallel_for((int)(Sp + Sr), [&](int idx) {
-    if (idx < (int)Sp)
-      ok[idx] = pack<cplx, double2>(fp[idx], idx, 8, kutp + 1, 4, z.p4, ppiv.data(), pL.data(),
-                                    pU.data(), pW.data(), pC.data(), pM.data());
-    else
-      ok[idx] = pack<double, double>(fr[idx - Sp], idx - Sp, 4, kutr + 1, 2, z.p2, rpiv.data(),
-                                     rL.data(), rU.data(), rW.data(), rC.data(), rM.data());
-  });
-  for (int v : ok)
-    if (!v) return fail(ctx, QG_EINVAL, "internal: band fill beyond the stored width");
+  const int kutp = !pivot ? 8 : ((8 + mp <= 12) ? 12 : 16);
+  const int kutr = !pivot ? 4 : ((4 + mr <= 4) ? 4 : 8);
   const WsMap& w = ctx->w;
   auto up = [&](size_t off, const void* src, size_t bytes) {
     return hipMemcpyAsync(ctx->ws + off, src, bytes, hipMemcpyHostToDevice, ctx->st);
   };
-  HIPCHK(up(w.p_piv, ppiv.data(), ppiv.size() * sizeof(int)));
-  HIPCHK(up(w.p_L, pL.data(), pL.size() * sizeof(double2)));
-  HIPCHK(up(w.p_U, pU.data(), pU.size() * sizeof(double2)));
+  std::vector<double2> pW(Sp * 4 * z.n4), pC(Sp * 32), pM(Sp * 16);
+  std::vector<double> rW(Sr * 2 * z.n2), rC(Sr * 8), rM(Sr * 4);
+  if (pivot) {
+    std::vector<int> ppiv(Sp * z.p4), rpiv(Sr * z.p2);
+    std::vector<double2> pL(Sp * z.p4 * 8), pU(Sp * z.p4 * (kutp + 1));
+    std::vector<double> rL(Sr * z.p2 * 4), rU(Sr * z.p2 * (kutr + 1));
+    parallel_for((int)(Sp + Sr), [&](int idx) {
+      if (idx < (int)Sp)
+        ok[idx] = pack<cplx, double2>(fp[idx], idx, 8, kutp + 1, 4, z.p4, ppiv.data(), pL.data(),
+                                      pU.data(), pW.data(), pC.data(), pM.data());
+      else
+        ok[idx] = pack<double, double>(fr[idx - Sp], idx - Sp, 4, kutr + 1, 2, z.p2, rpiv.data(),
+                                       rL.data(), rU.data(), rW.data(), rC.data(), rM.data());
+    });
+    for (int v : ok)
+      if (!v) return fail(ctx, QG_EINVAL, "internal: band fill beyond the stored width");
+    HIPCHK(up(w.p_piv, ppiv.data(), ppiv.size() * sizeof(int)));
+    HIPCHK(up(w.p_L, pL.data(), pL.size() * sizeof(double2)));
+    HIPCHK(up(w.p_U, pU.data(), pU.size() * sizeof(double2)));
+    HIPCHK(up(w.r_piv, rpiv.data(), rpiv.size() * sizeof(int)));
+    HIPCHK(up(w.r_L, rL.data(), rL.size() * sizeof(double)));
+    HIPCHK(up(w.r_U, rU.data(), rU.size() * sizeof(double)));
+    HIPCHK(hipStreamSynchronize(ctx->st));
+  } else {
+    std::vector<double2> pL(Sp * z.q4 * 8), pU(Sp * z.q4 * 8), pui(Sp * z.q4);
+    std::vector<double> rL(Sr * z.q2 * 4), rU(Sr * z.q2 * 4), rui(Sr * z.q2);
+    parallel_for((int)(Sp + Sr), [&](int idx) {
+      if (idx < (int)Sp)
+        pack_np<cplx, double2>(fp[idx], idx, 8, 8, 4, z.q4, pL.data(), pU.data(), pui.data(),
+                               pW.data(), pC.data(), pM.data());
+      else
+        pack_np<double, double>(fr[idx - Sp], idx - Sp, 4, 4, 2, z.q2, rL.data(), rU.data(),
+                                rui.data(), rW.data(), rC.data(), rM.data());
+    });
+    HIPCHK(up(w.p_L, pL.data(), pL.size() * sizeof(double2)));
+    HIPCHK(up(w.p_U, pU.data(), pU.size() * sizeof(double2)));
+    HIPCHK(up(w.p_ui, pui.data(), pui.size() * sizeof(double2)));
+    HIPCHK(up(w.r_L, rL.data(), rL.size() * sizeof(double)));
+    HIPCHK(up(w.r_U, rU.data(), rU.size() * sizeof(double)));
+    HIPCHK(up(w.r_ui, rui.data(), rui.size() * sizeof(double)));
+    HIPCHK(hipStreamSynchronize(ctx->st));
+  }
   HIPCHK(up(w.p_W, pW.data(), pW.size() * sizeof(double2)));
   HIPCHK(up(w.p_C, pC.data(), pC.size() * sizeof(double2)));
   HIPCHK(up(w.p_Mi, pM.data(), pM.size() * sizeof(double2)));
-  HIPCHK(up(w.r_piv, rpiv.data(), rpiv.size() * sizeof(int)));
-  HIPCHK(up(w.r_L, rL.data(), rL.size() * sizeof(double)));
-  HIPCHK(up(w.r_U, rU.data(), rU.size() * sizeof(double)));
   HIPCHK(up(w.r_W, rW.data(), rW.size() * sizeof(double)));
   HIPCHK(up(w.r_C, rC.data(), rC.size() * sizeof(double)));
   HIPCHK(up(w.r_Mi, rM.data(), rM.size() * sizeof(double)));
   HIPCHK(hipStreamSynchronize(ctx->st));
   ctx->kutp = kutp;
   ctx->kutr = kutr;
+  ctx->pivoted = pivot;
   ctx->factored_adt = adt;
   return QG_OK;
 }
@@ -393,7 +470,11 @@ qg_status implicit_solve(qg_ctx* ctx, const RhsSpec& rs) {
   timed(ctx, K_RHS, [&] { launch_rhs(ctx->g, ctx->b, rs, rhs, ctx->st); });
   bool ok = true;
   timed(ctx, K_SOLVE, [&] {
-    ok = launch_solve(ctx->g, ctx->Fp, ctx->Fr, rhs, rs, ctx->kutp, ctx->kutr, ctx->st);
+    ok = ctx->pivoted
+             ? launch_solve(ctx->g, ctx->Fp, ctx->Fr, rhs, rs, ctx->kutp, ctx->kutr, true,
+                            ctx->st)
+             : launch_solve_np(ctx->g, ctx->Fp, ctx->Fr, rhs, rs, ctx->z.q4, ctx->z.q2,
+                               ctx->st);
   });
   if (!ok) return fail(ctx, QG_EUNSUPPORTED, "no solve kernel for this band width");
   if (rs.lin_psi)
@@ -598,10 +679,12 @@ qg_status qg_create(qg_ctx** out, const qg_params* p, void* workspace, size_t wo
                  bd + 5 * bs, bd + 6 * bs, bd + 7 * bs, bd + 8 * bs};
   ctx->Fp = FactorSet<double2>{reinterpret_cast<const int*>(ctx->ws + w.p_piv), ctx->ptr2(w.p_L),
                                ctx->ptr2(w.p_U), ctx->ptr2(w.p_W), ctx->ptr2(w.p_C),
-                               ctx->ptr2(w.p_Mi)};
+                               ctx->ptr2(w.p_Mi), ctx->ptr2(w.p_L), ctx->ptr2(w.p_U),
+                               ctx->ptr2(w.p_ui)};
   ctx->Fr = FactorSet<double>{reinterpret_cast<const int*>(ctx->ws + w.r_piv), ctx->ptrd(w.r_L),
                               ctx->ptrd(w.r_U), ctx->ptrd(w.r_W), ctx->ptrd(w.r_C),
-                              ctx->ptrd(w.r_Mi)};
+                              ctx->ptrd(w.r_Mi), ctx->ptrd(w.r_L), ctx->ptrd(w.r_U),
+                              ctx->ptrd(w.r_ui)};
   *out = ctx;
   return QG_OK;
 }
@@ -743,6 +826,8 @@ qg_status qg_diagnostics(qg_ctx* ctx, qg_diag* out) {
   out->dt_cfl = rmax > 0 ? 1.0 / rmax : INFINITY;
   out->step = ctx->step;
   out->nonfinite = bad > 0 ? 1 : 0;
+  out->pivoted = (ctx->factored_adt >= 0.0 && ctx->pivoted) ? 1 : 0;
+  out->growth = ctx->factored_adt >= 0.0 ? ctx->growth : 0.0;
   return QG_OK;
 }
 

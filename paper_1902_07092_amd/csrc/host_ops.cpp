@@ -175,24 +175,30 @@ template <typename T> double mag(const T& v) { return std::abs(v); }
 }  // namespace
 
 template <typename T>
-bool factor_bordered(const std::vector<T>& full, int K, int p, int kl, int ku,
+bool factor_bordered(const std::vector<T>& full, int K, int p, int kl, int ku, bool pivot,
                      BorderedFactor<T>& f) {
   const int n = K - p;
   f.p = p; f.n = n; f.kl = kl; f.ku = ku;
-  const int kut = kl + ku;             // U bandwidth after pivoting fill
+  const int kut = pivot ? kl + ku : ku;   // U bandwidth (with the pivoting fill)
+  f.kut = kut;
   const int ld = 2 * kl + ku + 1;      // LAPACK band storage
   std::vector<T> ab((size_t)ld * n, T(0));
   auto A = [&](int i, int j) -> T& { return ab[(size_t)j * ld + (kl + ku + i - j)]; };
   auto Dfull = [&](int i, int j) { return full[(size_t)(p + i) * K + (p + j)]; };
+  double dmax = 0.0;
   for (int j = 0; j < n; ++j)
-    for (int i = std::max(0, j - ku); i <= std::min(n - 1, j + kl); ++i) A(i, j) = Dfull(i, j);
+    for (int i = std::max(0, j - ku); i <= std::min(n - 1, j + kl); ++i) {
+      A(i, j) = Dfull(i, j);
+      dmax = std::max(dmax, mag(A(i, j)));
+    }
   std::vector<int> ipiv(n);
   for (int j = 0; j < n; ++j) {
     int last = std::min(n - 1, j + kl);
     int jp = j;
     double best = mag(A(j, j));
-    for (int i = j + 1; i <= last; ++i)
-      if (mag(A(i, j)) > best) { best = mag(A(i, j)); jp = i; }
+    if (pivot)
+      for (int i = j + 1; i <= last; ++i)
+        if (mag(A(i, j)) > best) { best = mag(A(i, j)); jp = i; }
     ipiv[j] = jp;
     if (best == 0.0) return false;
     int cend = std::min(n - 1, j + kut);
@@ -206,6 +212,10 @@ bool factor_bordered(const std::vector<T>& full, int K, int p, int kl, int ku,
       for (int i = j + 1; i <= last; ++i) A(i, cc) -= A(i, j) * u;
     }
   }
+  double umax = 0.0;
+  for (int j = 0; j < n; ++j)
+    for (int e = 0; e <= kut && j - e >= 0; ++e) umax = std::max(umax, mag(A(j - e, j)));
+  f.growth = dmax > 0.0 ? umax / dmax : 0.0;
   f.piv.assign(n, 0);
   f.Lc.assign((size_t)n * kl, T(0));
   f.Uc.assign((size_t)n * (kut + 1), T(0));
@@ -274,9 +284,9 @@ bool factor_bordered(const std::vector<T>& full, int K, int p, int kl, int ku,
   return true;
 }
 
-template bool factor_bordered<double>(const std::vector<double>&, int, int, int, int,
+template bool factor_bordered<double>(const std::vector<double>&, int, int, int, int, bool,
                                       BorderedFactor<double>&);
-template bool factor_bordered<cplx>(const std::vector<cplx>&, int, int, int, int,
+template bool factor_bordered<cplx>(const std::vector<cplx>&, int, int, int, int, bool,
                                     BorderedFactor<cplx>&);
 
 }  // namespace qg

@@ -27,14 +27,17 @@ struct Operators {
 Operators build_operators(double eta, int K);
 
 // Factorisation of one bordered system (p tau rows on top of a band with
-// kl sub- and ku super-diagonals).  Band LU with partial pivoting of the
-// band block D (positions 0..n-1, n = K - p), Schur data for the border.
+// kl sub- and ku super-diagonals).  Band LU of the band block D (positions
+// 0..n-1, n = K - p), with partial pivoting or without row interchanges,
+// and the Schur data for the border.
 template <typename T>
 struct BorderedFactor {
   int p = 0, n = 0, kl = 0, ku = 0;
+  int kut = 0;                // stored U super-diagonals: kl + ku pivoted, ku unpivoted
+  double growth = 0.0;        // max |U| / max |D| over the band
   std::vector<int32_t> piv;   // [n] pivot offset (row swapped with j at step j)
   std::vector<T> Lc;          // [n][kl] multipliers of column j, rows j+1..j+kl
-  std::vector<T> Uc;          // [n][kl+ku+1] e=0: 1/U(j,j); e>=1: U(j-e, j)
+  std::vector<T> Uc;          // [n][kut+1] e=0: 1/U(j,j); e>=1: U(j-e, j)
   std::vector<T> W;           // [p][n]  w = B D^-1
   std::vector<T> Cb;          // [kl][p] first kl rows of the border column C
   std::vector<T> Minv;        // [p][p]  (A - w C)^-1
@@ -42,7 +45,7 @@ struct BorderedFactor {
 
 // Full bordered K x K matrix given as dense rows; builds the factor.
 template <typename T>
-bool factor_bordered(const std::vector<T>& full, int K, int p, int kl, int ku,
+bool factor_bordered(const std::vector<T>& full, int K, int p, int kl, int ku, bool pivot,
                      BorderedFactor<T>& out);
 
 // Tau rows: Dirichlet at s_o, Dirichlet at s_i, third derivative at s_o,

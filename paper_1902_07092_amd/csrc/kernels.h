@@ -24,15 +24,21 @@ struct Bands {  // [17][K] each (offset-major): entry (k, n) at [(n - k + 8) * K
   const double *A0, *A2, *B0, *B2, *B4, *C, *D, *F0, *F2;
 };
 
-// Factors of all bordered systems of one kind (see host_ops.h layout).
+// Factors of all bordered systems of one kind.  With row interchanges
+// (pivoted solve): piv, Lc, Uc in the host_ops.h layout, steps padded to
+// whole 16-step batches.  Without (unpivoted solve): L, U, ui, steps padded
+// to q rows (a multiple of 48).  W, Cb and Minv serve both.
 template <typename TF>
 struct FactorSet {
-  const int* piv;     // [S][n]
-  const TF* Lc;       // [S][n][kl]
-  const TF* Uc;       // [S][n][kl+ku+1]
+  const int* piv;     // [S][npad] row-interchange offsets
+  const TF* Lc;       // [S][npad][kl]
+  const TF* Uc;       // [S][npad][kut+1]  e=0: 1/U(j,j); e>=1: U(j-e, j)
   const TF* W;        // [S][p][n]
   const TF* Cb;       // [S][kl][p]
   const TF* Minv;     // [S][p][p]
+  const TF* L;        // [S][q][kl]  multipliers of column j, rows j+1..j+kl
+  const TF* U;        // [S][q][ku]  U(j-e, j) / U(j-e, j-e), e = 1..ku
+  const TF* ui;       // [S][q]      1 / U(j, j)
 };
 
 constexpr int MAX_TERMS = 8;

@@ -90,8 +90,9 @@ __global__ void rhs_kernel(Geom g, Bands b, RhsSpec rs, double2* __restrict__ rh
 // interchanges (forward, LAPACK gbtrs order) and back substitution.
 //
 // Lane t holds position q = t (mod 64) of a 64-wide window of the
-// right-hand side.  Each step reads the pivot row with readlane, swaps with
-// writelane, and updates the lanes below (above) it with one FMA.  Factor
+// right-hand side.  Each step reads the pivot row with readlane (and, with
+// row interchanges, swaps it in with writelane), and updates the lanes below
+// (above) it with one FMA.  Factor
 // columns are staged in LDS in double-buffered batches of B steps (factor
 // arrays padded to whole batches with identity steps), and the window is
 // refilled from global memory with loads issued a batch ahead.  KUT is the
@@ -117,7 +118,7 @@ __device__ __forceinline__ double2 writelane2(double2 v, double2 x, int lane) {
   return make_double2(writelane_d(v.x, x.x, lane), writelane_d(v.y, x.y, lane));
 }
 
-template <typename TF, int P, int KL, int KUT>
+template <typename TF, int P, int KL, int KUT, bool PIV>
 __device__ void solve_system(const Geom& g, const FactorSet<TF>& F, double2* rhs,
                              const RhsSpec& rs, int kind, int sys, int so, double2* sm) {
   constexpr int WU = KUT + 1;
@@ -172,7 +173,7 @@ __device__ void solve_system(const Geom& g, const FactorSet<TF>& F, double2* rhs
     const int idx = t + 64 * i;
     if (idx < B * KL) Lst[idx] = Lc[idx];
   }
-  int pv_cur = (t < B) ? piv[t] : 0;
+  int pv_cur = (PIV && t < B) ? piv[t] : 0;
   // window refill prefetch: the lane retiring at the end of batch bi
   // holds position q = j0 + ((t - j0) & 63) < j0 + B and takes q + 64
   double2 hn = hat(t + 64);   // used by the lanes retiring after batch 0
@@ -187,22 +188,28 @@ __device__ void solve_system(const Geom& g, const FactorSet<TF>& F, double2* rhs
         const int idx = t + 64 * i;
         lr.v[i] = (idx < B * KL) ? Lc[(size_t)(j0 + B) * KL + idx] : tzero<TF>();
       }
-      pv_next = (t < B) ? piv[j0 + B + t] : 0;
+      if (PIV) pv_next = (t < B) ? piv[j0 + B + t] : 0;
     }
 #pragma unroll
     for (int jj = 0; jj < B; ++jj) {
       const int j = j0 + jj;
-      const int p = __builtin_amdgcn_readlane(pv_cur, jj);
       const int src = j & 63;
-      const int dst = (j + p) & 63;
       const int d = ((t - j) & 63) - 1;
       const bool act = (d >= 0 && d < KL);
       const TF l = Lcur[jj * KL + (act ? d : 0)];
-      const double2 a = readlane2(bw, src);
-      const double2 bj = readlane2(bw, dst);
-      bw = writelane2(bw, a, dst);
-      bw = writelane2(bw, bj, src);
-      if (act) bw -= mulf(l, bj);
+      if constexpr (PIV) {
+        const int p = __builtin_amdgcn_readlane(pv_cur, jj);
+        const int dst = (j + p) & 63;
+        const double2 a = readlane2(bw, src);
+        const double2 bj = readlane2(bw, dst);
+        bw = writelane2(bw, a, dst);
+        bw = writelane2(bw, bj, src);
+        if (act) bw -= mulf(l, bj);
+      } else {
+        // no interchanges: row j is final, the KL rows below take it
+        const double2 bj = readlane2(bw, src);
+        if (act) bw -= mulf(l, bj);
+      }
     }
     // positions j0..j0+B-1 are final
     const int q = j0 + ((t - j0) & 63);
@@ -295,15 +302,15 @@ __device__ void solve_system(const Geom& g, const FactorSet<TF>& F, double2* rhs
   }
 }
 
-template <int KUTP, int KUTR>
+template <int KUTP, int KUTR, bool PIV>
 __global__ __launch_bounds__(64) void solve_all_kernel(Geom g, FactorSet<double2> Fp,
                                                        FactorSet<double> Fr, double2* rhs,
                                                        RhsSpec rs) {
   extern __shared__ double2 sm[];
   const int blk = blockIdx.x, M = g.M;
-  if (blk < M - 1) solve_system<double2, 4, 8, KUTP>(g, Fp, rhs, rs, 0, blk, blk, sm);
-  else solve_system<double, 2, 4, KUTR>(g, Fr, rhs, rs, blk == M - 1 ? 1 : 2, blk,
-                                        blk - (M - 1), sm);
+  if (blk < M - 1) solve_system<double2, 4, 8, KUTP, PIV>(g, Fp, rhs, rs, 0, blk, blk, sm);
+  else solve_system<double, 2, 4, KUTR, PIV>(g, Fr, rhs, rs, blk == M - 1 ? 1 : 2, blk,
+                                             blk - (M - 1), sm);
 }
 
 // Lin y_new for BPR353 stages (rows >= p), thread per (system, row).
@@ -363,13 +370,16 @@ void launch_lin(const Geom& g, const Bands& b, const double2* ypsi, const double
 }
 
 bool launch_solve(const Geom& g, const FactorSet<double2>& Fp, const FactorSet<double>& Fr,
-                  double2* rhs, const RhsSpec& rs, int kutp, int kutr, hipStream_t st) {
+                  double2* rhs, const RhsSpec& rs, int kutp, int kutr, bool pivoted,
+                  hipStream_t st) {
   const size_t shm = solve_lds_bytes(g, kutp, kutr);
   const dim3 grid(2 * g.M), block(64);
-  if (kutp == 12 && kutr == 4)
-    hipLaunchKernelGGL((solve_all_kernel<12, 4>), grid, block, shm, st, g, Fp, Fr, rhs, rs);
-  else if (kutp == 16 && kutr == 8)
-    hipLaunchKernelGGL((solve_all_kernel<16, 8>), grid, block, shm, st, g, Fp, Fr, rhs, rs);
+  if (!pivoted && kutp == 8 && kutr == 4)
+    hipLaunchKernelGGL((solve_all_kernel<8, 4, false>), grid, block, shm, st, g, Fp, Fr, rhs, rs);
+  else if (pivoted && kutp == 12 && kutr == 4)
+    hipLaunchKernelGGL((solve_all_kernel<12, 4, true>), grid, block, shm, st, g, Fp, Fr, rhs, rs);
+  else if (pivoted && kutp == 16 && kutr == 8)
+    hipLaunchKernelGGL((solve_all_kernel<16, 8, true>), grid, block, shm, st, g, Fp, Fr, rhs, rs);
   else
     return false;
   return true;

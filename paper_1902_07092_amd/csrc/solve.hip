@@ -1,0 +1,362 @@
+// Bordered band solves of every system (Appendix A) with band LUs that have
+// no row interchanges, FP64, gfx950.
+//
+// A wavefront carries four systems, sixteen lanes each.  Lane l of a
+// system holds rows q = l (mod 16) of a sixteen-row window.  Elimination
+// step j broadcasts the final row j inside each 16-lane row with DPP
+// (row_newbcast), and the rows below it (forward, multipliers of L) or above
+// it (backward, U scaled to a unit diagonal) take one complex FMA each.
+// Every eight steps the eight finished lanes store their row and take the
+// row sixteen further on, loaded three batches ahead.  The factor columns
+// of a batch of sixteen steps are loaded three batches ahead into
+// registers and staged through a two-slot LDS ring.
+//
+// Per system: h = rhs rows p.. ; Schur part psi_1 = -Minv (w . h),
+// h <- h - C psi_1 (first kl rows); forward L y = h with y' = y / U_jj
+// stored over h; backward U' x = y'; the new state [psi_1, x] is written.
+#include <hip/hip_runtime.h>
+
+#include <utility>
+
+#include "kernels.h"
+
+namespace qg {
+
+namespace {
+
+constexpr int SB = 16;     // steps per batch = lanes per system
+constexpr int NSET = 3;    // factor batches in flight (the batch loop is unrolled by NSET)
+
+__device__ __forceinline__ double2 z2() { return make_double2(0.0, 0.0); }
+
+// Value of lane LANE of each 16-lane row.
+template <int LANE>
+__device__ __forceinline__ double bcast(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffffLL), 0x150 + LANE, 0xF, 0xF,
+                                             false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), 0x150 + LANE, 0xF, 0xF, false);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+template <int LANE>
+__device__ __forceinline__ double2 bcast2(double2 v) {
+  return make_double2(bcast<LANE>(v.x), bcast<LANE>(v.y));
+}
+
+// bw -= l a
+__device__ __forceinline__ void fms(double2& bw, double l, double2 a) {
+  bw.x = fma(-l, a.x, bw.x);
+  bw.y = fma(-l, a.y, bw.y);
+}
+__device__ __forceinline__ void fms(double2& bw, double2 l, double2 a) {
+  bw.x = fma(-l.x, a.x, bw.x);
+  bw.x = fma(l.y, a.y, bw.x);
+  bw.y = fma(-l.x, a.y, bw.y);
+  bw.y = fma(-l.y, a.x, bw.y);
+}
+__device__ __forceinline__ double2 mul(double l, double2 a) { return make_double2(l * a.x, l * a.y); }
+__device__ __forceinline__ double2 mul(double2 l, double2 a) {
+  return make_double2(l.x * a.x - l.y * a.y, l.x * a.y + l.y * a.x);
+}
+
+template <typename TF> __device__ __forceinline__ TF tz();
+template <> __device__ __forceinline__ double tz<double>() { return 0.0; }
+template <> __device__ __forceinline__ double2 tz<double2>() { return z2(); }
+
+// One kind of system (P border rows, KW band width, factor type TF) for the
+// four systems of this wavefront.
+template <typename TF, int P, int KW>
+struct Solver4 {
+  static constexpr int CPS = SB * KW * (int)sizeof(TF) / 16;   // 16-byte chunks per system batch
+  static constexpr int NCH = 4 * CPS / 64;                     // chunks per lane per batch
+  static_assert(NCH * 64 == 4 * CPS, "batch does not divide over the wavefront");
+
+  // (plain copies: references to the kernel's by-value arguments would
+  // place those structures in scratch memory)
+  FactorSet<TF> F;
+  double2* out_psi;
+  double2* out_th;
+  int M, K;
+  int kind, nsys, sys0, so0;   // kind of system; valid count; first global / factor index
+  int n, q, nb;                // band rows, padded rows (multiple of NSET * SB), batches
+  TF* ring;                    // LDS [2][4][SB][KW]
+  int t, lane, grp;
+  bool valid;
+  int so;                      // factor index of this lane's system (clamped)
+  double2* hg;                 // this system's h / y' (rhs rows p..)
+
+  struct Batch {
+    double2 v[NCH];
+  };
+  // chunk I of this lane: wave chunk c = t + 64 I, system c / CPS
+  template <int I>
+  __device__ __forceinline__ double2 load_chunk(const TF* base, int b) const {
+    const int c = t + 64 * I;
+    const int gs = c / CPS, e = c - gs * CPS;
+    const int s = min(so0 + gs, so0 + nsys - 1);
+    return reinterpret_cast<const double2*>(base + ((size_t)s * q + (size_t)b * SB) * KW)[e];
+  }
+  template <int... I>
+  __device__ __forceinline__ Batch load_batch(const TF* base, int b,
+                                              std::integer_sequence<int, I...>) const {
+    return Batch{{load_chunk<I>(base, b)...}};
+  }
+  __device__ __forceinline__ Batch load_batch(const TF* base, int b) const {
+    return load_batch(base, b, std::make_integer_sequence<int, NCH>{});
+  }
+  template <int... I>
+  __device__ __forceinline__ void stage(int slot, const Batch& r,
+                                        std::integer_sequence<int, I...>) const {
+    double2* dst = reinterpret_cast<double2*>(ring + (size_t)slot * 4 * SB * KW);
+    ((dst[t + 64 * I] = r.v[I]), ...);
+  }
+  __device__ __forceinline__ void stage(int slot, const Batch& r) const {
+    stage(slot, r, std::make_integer_sequence<int, NCH>{});
+  }
+  __device__ __forceinline__ TF coef(int slot, int jj, int d) const {   // d in [1, KW]
+    return ring[(((size_t)slot * 4 + grp) * SB + jj) * KW + (d - 1)];
+  }
+  __device__ __forceinline__ double2 hrow(int r) const { return (r < n) ? hg[r] : z2(); }
+  __device__ __forceinline__ TF uirow(int r) const {
+    return F.ui[(size_t)so * q + min(r, q - 1)];
+  }
+
+  // ---------------------------------------------------------- forward
+  template <int JJ>
+  __device__ __forceinline__ void fstep(double2& bw, int slot) const {
+    const int d = (lane - JJ) & 15;
+    const bool act = (d >= 1 && d <= KW);
+    TF l = coef(slot, JJ, act ? d : 1);
+    if (!act) l = tz<TF>();
+    const double2 a = bcast2<JJ>(bw);
+    fms(bw, l, a);
+  }
+  template <int... J>
+  __device__ __forceinline__ void fhalf(double2& bw, int slot, std::integer_sequence<int, J...>)
+      const {
+    (fstep<J>(bw, slot), ...);
+  }
+  // backward step: column j = b SB + JJ
+  template <int JJ>
+  __device__ __forceinline__ void bstep(double2& bw, int slot) const {
+    const int e = (JJ - lane) & 15;
+    const bool act = (e >= 1 && e <= KW);
+    TF u = coef(slot, JJ, act ? e : 1);
+    if (!act) u = tz<TF>();
+    const double2 x = bcast2<JJ>(bw);
+    fms(bw, u, x);
+  }
+  template <int... J>
+  __device__ __forceinline__ void bhalf(double2& bw, int slot, std::integer_sequence<int, J...>)
+      const {
+    (bstep<15 - J>(bw, slot), ...);
+  }
+
+  __device__ __forceinline__ void run(double2* out_state) {
+    // ---- Schur part for the p border unknowns
+    double2 wh[P];
+#pragma unroll
+    for (int i = 0; i < P; ++i) wh[i] = z2();
+    const TF* Wr = F.W + (size_t)so * P * n;
+    for (int j = lane; j < n; j += SB) {
+      const double2 h = hg[j];
+#pragma unroll
+      for (int i = 0; i < P; ++i) {
+        const double2 v = mul(Wr[(size_t)i * n + j], h);
+        wh[i].x += v.x;
+        wh[i].y += v.y;
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < P; ++i)
+#pragma unroll
+      for (int off = 8; off > 0; off >>= 1) {
+        wh[i].x += __shfl_xor(wh[i].x, off, 16);
+        wh[i].y += __shfl_xor(wh[i].y, off, 16);
+      }
+    double2 psi1[P];
+#pragma unroll
+    for (int i = 0; i < P; ++i) {
+      double2 acc = z2();
+#pragma unroll
+      for (int i2 = 0; i2 < P; ++i2) fms(acc, F.Minv[((size_t)so * P + i) * P + i2], wh[i2]);
+      psi1[i] = acc;
+    }
+
+    // ---- forward: L y = h, y' = y / U_jj over h
+    double2 bw = hrow(lane);
+    if (lane < KW) {
+#pragma unroll
+      for (int i = 0; i < P; ++i) fms(bw, F.Cb[((size_t)so * KW + lane) * P + i], psi1[i]);
+    }
+    sweep<true>(bw);
+    __threadfence();
+
+    // ---- backward: U' x = y'
+    bw = hrow((nb - 1) * SB + lane);
+    sweep<false>(bw);
+
+    // ---- border unknowns
+    if (valid && lane < P) {
+      double2 v = psi1[0];
+#pragma unroll
+      for (int i = 1; i < P; ++i)
+        if (lane == i) v = psi1[i];
+      if (kind != 0 && (kind == 1 || sys0 + grp == M)) v.y = 0.0;
+      out_state[lane] = v;
+    }
+  }
+
+  // One full sweep; FWD: batches 0..nb-1, else nb-1..0.
+  template <bool FWD>
+  __device__ __forceinline__ void sweep(double2& bw) {
+    const TF* base = FWD ? F.L : F.U;
+    const bool real_row = (kind == 1) || (kind == 2 && sys0 + grp == M);
+    double2* xo = out_ptr() + P;
+    auto bidx = [&](int i) { return FWD ? i : nb - 1 - i; };
+    Batch s0, s1, s2;           // batch i + NSET of the sweep sits in s[(i + NSET) mod NSET]
+    double2 h0, h1, h2;         // refill rows of batches 0, 1, 2 (mod NSET)
+    TF u0, u1, u2;              // 1 / U(j, j) of the rows retiring in those batches
+    {   // batch 0 to the ring, batches 1..NSET in flight (loads past the
+        // last batch re-read it)
+      stage(0, load_batch(base, bidx(0)));
+      s1 = load_batch(base, bidx(min(1, nb - 1)));
+      s2 = load_batch(base, bidx(min(2, nb - 1)));
+      s0 = load_batch(base, bidx(min(3, nb - 1)));
+      auto refill = [&](int k) {   // next (FWD) / previous block of 16 rows
+        const int rr = FWD ? (k + 1) * SB + lane : (nb - 2 - k) * SB + lane;
+        return (rr >= 0 && rr < q) ? hrow(rr) : z2();
+      };
+      h0 = refill(0); h1 = refill(1); h2 = refill(2);
+      if (FWD) {
+        u0 = uirow(lane); u1 = uirow(SB + lane); u2 = uirow(2 * SB + lane);
+      }
+    }
+    for (int i0 = 0; i0 < nb; i0 += NSET) {   // nb is a multiple of NSET
+      batch<FWD>(bw, i0, base, real_row, xo, s1, h0, u0);
+      batch<FWD>(bw, i0 + 1, base, real_row, xo, s2, h1, u1);
+      batch<FWD>(bw, i0 + 2, base, real_row, xo, s0, h2, u2);
+    }
+  }
+
+  // Batch i of a sweep.  nxt holds batch i + 1 (staged to the ring now)
+  // and is reloaded with batch i + 1 + NSET; hr / ur are this batch's
+  // refill rows and scalings, reloaded for batch i + NSET.
+  template <bool FWD>
+  __device__ __forceinline__ void batch(double2& bw, int i, const TF* base, bool real_row,
+                                        double2* xo, Batch& nxt, double2& hr, TF& ur) {
+    const int b = FWD ? i : nb - 1 - i;
+    const int slot = i & 1;
+    // next batch to the ring, and the batch NSET after it in flight
+    if (i + 1 < nb) stage((i + 1) & 1, nxt);
+    {
+      const int inext = min(i + 1 + NSET, nb - 1);
+      nxt = load_batch(base, FWD ? inext : nb - 1 - inext);
+    }
+    const int row = b * SB + lane;          // this lane's row in batch b
+    if (FWD) {
+      fhalf(bw, slot, std::make_integer_sequence<int, 8>{});
+      if (lane < 8) {                        // rows b SB + 0..7 are final
+        if (valid && row < n) hg[row] = mul(ur, bw);
+        bw = hr;
+      }
+      fhalf8(bw, slot);
+      if (lane >= 8) {
+        if (valid && row < n) hg[row] = mul(ur, bw);
+        bw = hr;
+      }
+      // refills and scalings of batch i + NSET
+      const int rn = (b + NSET + 1) * SB + lane;
+      hr = (rn < q) ? hrow(rn) : z2();
+      ur = uirow((b + NSET) * SB + lane);
+    } else {
+      bhalf(bw, slot, std::make_integer_sequence<int, 8>{});   // columns 15..8
+      if (lane >= 8) {                       // rows b SB + 8..15 are final
+        if (valid && row < n) {
+          double2 v = bw;
+          if (real_row) v.y = 0.0;
+          xo[row] = v;
+        }
+        bw = hr;
+      }
+      bhalf8(bw, slot);                      // columns 7..0
+      if (lane < 8) {
+        if (valid && row < n) {
+          double2 v = bw;
+          if (real_row) v.y = 0.0;
+          xo[row] = v;
+        }
+        bw = hr;
+      }
+      const int rn = (b - NSET - 1) * SB + lane;
+      hr = (rn >= 0) ? hrow(rn) : z2();
+    }
+  }
+  __device__ __forceinline__ void fhalf8(double2& bw, int slot) const {
+    fstep<8>(bw, slot); fstep<9>(bw, slot); fstep<10>(bw, slot); fstep<11>(bw, slot);
+    fstep<12>(bw, slot); fstep<13>(bw, slot); fstep<14>(bw, slot); fstep<15>(bw, slot);
+  }
+  __device__ __forceinline__ void bhalf8(double2& bw, int slot) const {
+    bstep<7>(bw, slot); bstep<6>(bw, slot); bstep<5>(bw, slot); bstep<4>(bw, slot);
+    bstep<3>(bw, slot); bstep<2>(bw, slot); bstep<1>(bw, slot); bstep<0>(bw, slot);
+  }
+  __device__ __forceinline__ double2* out_ptr() const {
+    const int m = (kind == 0) ? sys0 + grp + 1 : (kind == 1 ? 0 : sys0 + grp - M);
+    return (kind == 2 ? out_th : out_psi) + (size_t)max(m, 0) * K;
+  }
+};
+
+}  // namespace
+
+// Block: one wavefront, four systems.  Blocks [0, nbp) take the Psi systems
+// (m = 1..M-1), the rest the real systems (zonal flow, theta of every m).
+__global__ __launch_bounds__(64) void solve_np_kernel(Geom g, FactorSet<double2> Fp,
+                                                      FactorSet<double> Fr, double2* rhs,
+                                                      RhsSpec rs, int qp, int qr) {
+  __shared__ double2 ring_mem[2 * 4 * SB * 8];
+  const int M = g.M, K = g.K;
+  const int nbp = (M - 1 + 3) / 4;
+  const int t = threadIdx.x, lane = t & 15, grp = t >> 4;
+  if ((int)blockIdx.x < nbp) {
+    Solver4<double2, 4, 8> s{Fp, rs.out_psi, rs.out_th, M, K};
+    s.kind = 0;
+    s.sys0 = 4 * blockIdx.x;
+    s.so0 = s.sys0;
+    s.nsys = min(4, M - 1 - s.sys0);
+    s.n = K - 4; s.q = qp; s.nb = qp / SB;
+    s.ring = ring_mem;
+    s.t = t; s.lane = lane; s.grp = grp;
+    s.valid = grp < s.nsys;
+    s.so = s.so0 + min(grp, s.nsys - 1);
+    s.hg = rhs + (size_t)(s.sys0 + min(grp, s.nsys - 1)) * K + 4;
+    s.run(s.out_ptr());
+  } else {
+    Solver4<double, 2, 4> s{Fr, rs.out_psi, rs.out_th, M, K};
+    const int r0 = 4 * (blockIdx.x - nbp);     // first real-system index
+    s.kind = (r0 == 0) ? 1 : 2;                // the zonal flow leads the first block
+    s.sys0 = (M - 1) + r0;
+    s.so0 = r0;
+    s.nsys = min(4, M + 1 - r0);
+    s.n = K - 2; s.q = qr; s.nb = qr / SB;
+    s.ring = reinterpret_cast<double*>(ring_mem);
+    s.t = t; s.lane = lane; s.grp = grp;
+    s.valid = grp < s.nsys;
+    s.so = s.so0 + min(grp, s.nsys - 1);
+    s.hg = rhs + (size_t)(s.sys0 + min(grp, s.nsys - 1)) * K + 2;
+    // system kind per group: only group 0 of block 0 is the zonal flow
+    if (r0 == 0 && grp > 0) s.kind = 2;
+    s.run(s.out_ptr());
+  }
+}
+
+bool launch_solve_np(const Geom& g, const FactorSet<double2>& Fp, const FactorSet<double>& Fr,
+                     double2* rhs, const RhsSpec& rs, int qp, int qr, hipStream_t st) {
+  if (qp % (NSET * SB) || qr % (NSET * SB)) return false;
+  const int blocks = (g.M - 1 + 3) / 4 + (g.M + 1 + 3) / 4;
+  hipLaunchKernelGGL(solve_np_kernel, dim3(blocks), dim3(64), 0, st, g, Fp, Fr, rhs, rs, qp, qr);
+  return true;
+}
+
+int solve_np_pad() { return NSET * SB; }
+
+}  // namespace qg

@@ -26,7 +26,8 @@ class qg_params(ctypes.Structure):
     _fields_ = [("E", ctypes.c_double), ("Ra", ctypes.c_double),
                 ("Pr", ctypes.c_double), ("eta", ctypes.c_double),
                 ("n_phi", ctypes.c_int), ("n_r", ctypes.c_int),
-                ("n_c", ctypes.c_int), ("precision", ctypes.c_int)]
+                ("n_c", ctypes.c_int), ("precision", ctypes.c_int),
+                ("pivoting", ctypes.c_int)]
 
 
 class qg_diag(ctypes.Structure):
@@ -34,7 +35,8 @@ class qg_diag(ctypes.Structure):
                 ("E_zon", ctypes.c_double), ("E_therm", ctypes.c_double),
                 ("enstrophy", ctypes.c_double), ("Re", ctypes.c_double),
                 ("Ro", ctypes.c_double), ("dt_cfl", ctypes.c_double),
-                ("step", ctypes.c_longlong), ("nonfinite", ctypes.c_int)]
+                ("step", ctypes.c_longlong), ("nonfinite", ctypes.c_int),
+                ("pivoted", ctypes.c_int), ("growth", ctypes.c_double)]
 
 
 class QGError(RuntimeError):
@@ -159,11 +161,11 @@ class QGSolver:
     """One solver context on a HIP device, workspace allocated by torch."""
 
     def __init__(self, E, Ra, Pr, eta, n_phi, n_r, n_c=0, device="cuda:0",
-                 stream=None):
+                 stream=None, pivoting=0):
         import torch
         self.torch = torch
         self.device = torch.device(device)
-        self.params = qg_params(E, Ra, Pr, eta, n_phi, n_r, n_c, 0)
+        self.params = qg_params(E, Ra, Pr, eta, n_phi, n_r, n_c, 0, pivoting)
         self.M = n_phi // 3 + 1
         self.K = n_c if n_c else (2 * (n_r - 1)) // 3
         nbytes = qg_workspace_size(self.params)

@@ -50,9 +50,10 @@ def _rel(a, b):
         np.abs(a).max())
 
 
-def _pair(qg, w, state, n_c=None):
+def _pair(qg, w, state, n_c=None, pivoting=0):
     K = w.n_c if n_c is None else n_c
-    s = qg.QGSolver(w.E, w.Ra, w.Pr, w.eta, w.n_phi, w.n_r, K)
+    s = qg.QGSolver(w.E, w.Ra, w.Pr, w.eta, w.n_phi, w.n_r, K,
+                    pivoting=pivoting)
     s.set_state(state.psi, state.theta, state.uphi0)
     o = QGOracle(w.E, w.Ra, w.Pr, w.eta, w.n_phi, w.n_r, K)
     o.set_state(state.psi, state.theta, state.uphi0)
@@ -153,6 +154,27 @@ def test_large_cnab2_parity(qg):
     ok, tol = _within(err, "large_cnab2_2")
     assert ok, (err, tol)
     assert err["theta"] < TOL     # theta's own floor is far below 1e-11
+    d = s.diagnostics()
+    _say(f"  band LU pivoted={d['pivoted']} growth={d['growth']:.3g}")
+    assert d["pivoted"] == 0 and 1.0 <= d["growth"] <= 1e4
+
+
+@pytest.mark.parametrize("wname,scheme,nsteps", [("SMALL", "cnab2", 5),
+                                                 ("MEDIUM", "bpr353", 1)])
+def test_pivoted_band_lu_parity(qg, wname, scheme, nsteps):
+    """The partial-pivoting factorisation and its solve (the fallback when
+    an unpivoted band LU would grow) against the oracle."""
+    w = getattr(inputs, wname)
+    _say(f"[parity] pivoted band LU {w.n_phi}x{w.n_r} {scheme} x{nsteps}")
+    s, o = _pair(qg, w, inputs.workload_state(w), pivoting=1)
+    s.step(w.dt, scheme, nsteps)
+    o.step(w.dt, scheme, nsteps)
+    err = _compare(s, o)
+    _say(f"  rel err {err}")
+    case = "small_cnab2_1" if wname == "SMALL" else "medium_bpr353_2"
+    ok, tol = _within(err, case)
+    assert ok, (err, tol)
+    assert s.diagnostics()["pivoted"] == 1
 
 
 def test_deterministic_reruns(qg):
