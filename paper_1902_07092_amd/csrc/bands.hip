@@ -1,0 +1,142 @@
+// Banded products of the implicit stage, FP64, gfx950:
+//   out = (alpha Mass + cL Lin) y + sum_q coef_q slot_q     (rows k >= p)
+// for every system: Psi (m >= 1, eq. psi_int: Mass = A_m, Lin = B_m), the
+// zonal flow (eq. uphi_int: Mass = D, Lin = E) and theta (eq. temp_int:
+// Mass = D, Lin = F_m / Pr).  alpha = 1 gives the right-hand side of an
+// implicit solve (CNAB2, BPR353 stages); alpha = 0, cL = 1 the product
+// Lin y of a new stage value (BPR353).
+//
+// The operators split in powers of m (A_m = A0 + m^2 A2, B_m = B0 + m^2 B2
+// + m^4 B4 + (2/E) i m C, F_m = F0 + m^2 F2), so a thread keeps the
+// m-independent combinations of its row's 17 band entries in registers and
+// runs over a chunk of m: the bands are read once per (row, chunk) instead
+// of once per system.
+#include <hip/hip_runtime.h>
+
+#include "kernels.h"
+
+namespace qg {
+
+namespace {
+
+constexpr int BW = 17;    // band entries per row (offsets -8..8)
+constexpr int MCH = 16;   // systems per thread
+constexpr int RB = 64;    // rows per block
+
+__device__ __forceinline__ double2 ld(const double2* p, int i, int K) {
+  return (i >= 0 && i < K) ? p[i] : make_double2(0.0, 0.0);
+}
+
+}  // namespace
+
+// blockIdx.x: rows [RB x, RB x + RB); blockIdx.y: chunk of MCH systems;
+// blockIdx.z: 0 = Psi (m = 1 + MCH y + i), 1 = zonal flow and theta
+// (u = MCH y + i: u = 0 the zonal flow, u >= 1 theta of m = u - 1).
+// sys_out: out rows are system indices (Psi m -> m - 1, zonal -> M - 1,
+// theta m -> M + m) in out_psi; else out_psi[m] (Psi, zonal at m = 0) and
+// out_th[m].
+__global__ __launch_bounds__(64) void band_kernel(Geom g, Bands b, RhsSpec rs, double alpha,
+                                                  double2* __restrict__ out_psi,
+                                                  double2* __restrict__ out_th, int sys_out) {
+  const int K = g.K, M = g.M;
+  const int k = blockIdx.x * RB + threadIdx.x;
+  const int kind = blockIdx.z;
+  const int u0 = blockIdx.y * MCH;
+  if (k >= K) return;
+  const double cL = rs.cL;
+  if (kind == 0) {
+    double P0[BW], P1[BW], P2[BW], P3[BW];
+#pragma unroll
+    for (int o = 0; o < BW; ++o) {
+      const size_t i = (size_t)o * K + k;
+      P0[o] = alpha * b.A0[i] + cL * b.B0[i];
+      P1[o] = alpha * b.A2[i] + cL * b.B2[i];
+      P2[o] = cL * b.B4[i];
+      P3[o] = cL * g.two_over_E * b.C[i];
+    }
+    for (int i = 0; i < MCH; ++i) {
+      const int m = 1 + u0 + i;
+      if (m >= M) break;
+      double2 acc = make_double2(0.0, 0.0);
+      if (k >= 4) {
+        const double dm = (double)m, m2 = dm * dm;
+        const double2* y = rs.base_psi + (size_t)m * K;
+#pragma unroll
+        for (int o = 0; o < BW; ++o) {
+          const double re = P0[o] + m2 * (P1[o] + m2 * P2[o]);
+          const double im = dm * P3[o];
+          const double2 v = ld(y, k + o - 8, K);
+          acc.x += re * v.x - im * v.y;
+          acc.y += re * v.y + im * v.x;
+        }
+        for (int q = 0; q < rs.nterm; ++q) {
+          const double2 v = rs.term_psi[q][(size_t)m * K + k];
+          acc.x += rs.coef[q] * v.x;
+          acc.y += rs.coef[q] * v.y;
+        }
+      }
+      double2* o = sys_out ? out_psi + (size_t)(m - 1) * K : out_psi + (size_t)m * K;
+      o[k] = acc;
+    }
+  } else {
+    double D[BW], F0[BW], F2[BW];
+#pragma unroll
+    for (int o = 0; o < BW; ++o) {
+      const size_t i = (size_t)o * K + k;
+      D[o] = alpha * b.D[i];
+      F0[o] = b.F0[i];
+      F2[o] = b.F2[i];
+    }
+    for (int i = 0; i < MCH; ++i) {
+      const int u = u0 + i;
+      if (u > M) break;
+      const bool zonal = (u == 0);
+      const int m = zonal ? 0 : u - 1;
+      const double s1 = zonal ? cL : cL * g.inv_Pr;
+      const double s2 = zonal ? cL : cL * g.inv_Pr * (double)m * (double)m;
+      double2 acc = make_double2(0.0, 0.0);
+      if (k >= 2) {
+        const double2* y = (zonal ? rs.base_psi : rs.base_th) + (size_t)m * K;
+#pragma unroll
+        for (int o = 0; o < BW; ++o) {
+          const double re = D[o] + s1 * F0[o] + s2 * F2[o];
+          const double2 v = ld(y, k + o - 8, K);
+          acc.x += re * v.x;
+          acc.y += re * v.y;
+        }
+        for (int q = 0; q < rs.nterm; ++q) {
+          const double2 v = (zonal ? rs.term_psi[q] : rs.term_th[q])[(size_t)m * K + k];
+          acc.x += rs.coef[q] * v.x;
+          acc.y += rs.coef[q] * v.y;
+        }
+      }
+      double2* o = sys_out ? out_psi + (size_t)(zonal ? M - 1 : M + m) * K
+                           : (zonal ? out_psi : out_th) + (size_t)m * K;
+      o[k] = acc;
+    }
+  }
+}
+
+namespace {
+dim3 band_grid(const Geom& g) {
+  const int chunks = (g.M + 1 + MCH - 1) / MCH;   // covers M - 1 Psi and M + 1 real systems
+  return dim3((g.K + RB - 1) / RB, chunks, 2);
+}
+}  // namespace
+
+void launch_rhs(const Geom& g, const Bands& b, const RhsSpec& rs, double2* rhs, hipStream_t st) {
+  hipLaunchKernelGGL(band_kernel, band_grid(g), dim3(RB), 0, st, g, b, rs, 1.0, rhs,
+                     (double2*)nullptr, 1);
+}
+
+void launch_lin(const Geom& g, const Bands& b, const double2* ypsi, const double2* yth,
+                double2* lpsi, double2* lth, hipStream_t st) {
+  RhsSpec rs{};
+  rs.base_psi = ypsi;
+  rs.base_th = yth;
+  rs.cL = 1.0;
+  rs.nterm = 0;
+  hipLaunchKernelGGL(band_kernel, band_grid(g), dim3(RB), 0, st, g, b, rs, 0.0, lpsi, lth, 0);
+}
+
+}  // namespace qg

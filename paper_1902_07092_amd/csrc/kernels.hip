@@ -1,11 +1,6 @@
-// Implicit-stage kernels of one IMEX step of spherical quasi-geostrophic
-// convection (Chebyshev-integration / tau radial scheme), FP64:
-//
-//   rhs_kernel        per (system, row): IMEX right-hand side
-//   solve_all_kernel  per system: bordered band solve (Appendix A), one
-//                     wavefront each
-//   lin_kernel        per (system, row): implicit operator applied to a new
-//                     stage value (BPR353)
+// Bordered band solve with row interchanges (Appendix A), FP64: the
+// fallback used when an unpivoted band LU would grow (see solve.hip for the
+// unpivoted solve).  One wavefront per system.
 #include <hip/hip_runtime.h>
 
 #include "kernels.h"
@@ -39,53 +34,9 @@ __device__ __forceinline__ double2 readlane2(double2 v, int lane) {
   return make_double2(readlane_d(v.x, lane), readlane_d(v.y, lane));
 }
 
-// ----------------------------------------------------------------- rhs
-// Right-hand side of one implicit solve, rows k >= p of every system:
-//   rhs = (Mass + cL Lin) y_base + sum_q coef_q slot_q.
-// Thread per (system, row); bands are offset-major ([17][K]).  System
-// index: s < M - 1 is Psi of m = s + 1, s = M - 1 the zonal flow, s > M - 1
-// theta of m = s - M.  Output rhs[s][K] (rows < p left zero).
-__global__ void rhs_kernel(Geom g, Bands b, RhsSpec rs, double2* __restrict__ rhs) {
-  const int K = g.K, M = g.M;
-  const int s = blockIdx.y;
-  const int k = blockIdx.x * blockDim.x + threadIdx.x;
-  if (k >= K) return;
-  const int kind = (s < M - 1) ? 0 : (s == M - 1 ? 1 : 2);
-  const int m = (kind == 0) ? s + 1 : (kind == 1 ? 0 : s - M);
-  const int P = (kind == 0) ? 4 : 2;
-  double2 acc = zero2();
-  if (k >= P) {
-    const double2* yb = (kind == 2 ? rs.base_th : rs.base_psi) + (size_t)m * K;
-    const double dm = (double)m, m2 = dm * dm, cL = rs.cL;
-#pragma unroll
-    for (int o = 0; o < 17; ++o) {
-      const int nn = k + o - 8;
-      if (nn < 0 || nn >= K) continue;
-      const size_t idx = (size_t)o * K + k;
-      double re, im = 0.0;
-      if (kind == 0) {
-        re = b.A0[idx] + m2 * b.A2[idx] + cL * (b.B0[idx] + m2 * b.B2[idx] + m2 * m2 * b.B4[idx]);
-        im = cL * g.two_over_E * dm * b.C[idx];
-      } else if (kind == 1) {
-        re = b.D[idx] + cL * (b.F0[idx] + b.F2[idx]);
-      } else {
-        re = b.D[idx] + cL * g.inv_Pr * (b.F0[idx] + m2 * b.F2[idx]);
-      }
-      acc += cmul(make_double2(re, im), yb[nn]);
-    }
-#pragma unroll
-    for (int q = 0; q < MAX_TERMS; ++q) {
-      if (q < rs.nterm) {
-        const double2* src = (kind == 2 ? rs.term_th[q] : rs.term_psi[q]) + (size_t)m * K;
-        acc += rs.coef[q] * src[k];
-      }
-    }
-  }
-  rhs[(size_t)s * K + k] = acc;
-}
-
 // --------------------------------------------------------------- solve
-// One wavefront per bordered system (same system index as rhs_kernel):
+// One wavefront per bordered system (system index: s < M - 1 is Psi of
+// m = s + 1, s = M - 1 the zonal flow, s > M - 1 theta of m = s - M):
 // psi_1 = -Minv (w . h), h <- h - C psi_1, then the band LU solve with row
 // interchanges (forward, LAPACK gbtrs order) and back substitution.
 //
@@ -313,41 +264,6 @@ __global__ __launch_bounds__(64) void solve_all_kernel(Geom g, FactorSet<double2
                                              blk - (M - 1), sm);
 }
 
-// Lin y_new for BPR353 stages (rows >= p), thread per (system, row).
-__global__ void lin_kernel(Geom g, Bands b, const double2* __restrict__ ypsi,
-                           const double2* __restrict__ yth, double2* __restrict__ lpsi,
-                           double2* __restrict__ lth) {
-  const int K = g.K, M = g.M;
-  const int s = blockIdx.y;
-  const int k = blockIdx.x * blockDim.x + threadIdx.x;
-  if (k >= K) return;
-  const int kind = (s < M - 1) ? 0 : (s == M - 1 ? 1 : 2);
-  const int m = (kind == 0) ? s + 1 : (kind == 1 ? 0 : s - M);
-  const int P = (kind == 0) ? 4 : 2;
-  const double2* y = (kind == 2 ? yth : ypsi) + (size_t)m * K;
-  double2 acc = zero2();
-  if (k >= P) {
-    const double dm = (double)m, m2 = dm * dm;
-#pragma unroll
-    for (int o = 0; o < 17; ++o) {
-      const int nn = k + o - 8;
-      if (nn < 0 || nn >= K) continue;
-      const size_t idx = (size_t)o * K + k;
-      double re, im = 0.0;
-      if (kind == 0) {
-        re = b.B0[idx] + m2 * b.B2[idx] + m2 * m2 * b.B4[idx];
-        im = g.two_over_E * dm * b.C[idx];
-      } else if (kind == 1) {
-        re = b.F0[idx] + b.F2[idx];
-      } else {
-        re = g.inv_Pr * (b.F0[idx] + m2 * b.F2[idx]);
-      }
-      acc += cmul(make_double2(re, im), y[nn]);
-    }
-  }
-  (kind == 2 ? lth : lpsi)[(size_t)m * K + k] = acc;
-}
-
 // ------------------------------------------------------------ launchers
 size_t solve_lds_bytes(const Geom& g, int kutp, int kutr) {
   const int B = SOLVE_BATCH;
@@ -357,17 +273,6 @@ size_t solve_lds_bytes(const Geom& g, int kutp, int kutr) {
 }
 
 int solve_batch() { return SOLVE_BATCH; }
-
-void launch_rhs(const Geom& g, const Bands& b, const RhsSpec& rs, double2* rhs, hipStream_t st) {
-  dim3 grid((g.K + 255) / 256, 2 * g.M);
-  hipLaunchKernelGGL(rhs_kernel, grid, dim3(256), 0, st, g, b, rs, rhs);
-}
-
-void launch_lin(const Geom& g, const Bands& b, const double2* ypsi, const double2* yth,
-                double2* lpsi, double2* lth, hipStream_t st) {
-  dim3 grid((g.K + 255) / 256, 2 * g.M);
-  hipLaunchKernelGGL(lin_kernel, grid, dim3(256), 0, st, g, b, ypsi, yth, lpsi, lth);
-}
 
 bool launch_solve(const Geom& g, const FactorSet<double2>& Fp, const FactorSet<double>& Fr,
                   double2* rhs, const RhsSpec& rs, int kutp, int kutr, bool pivoted,
