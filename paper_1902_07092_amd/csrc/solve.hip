@@ -79,7 +79,7 @@ struct Solver4 {
   int M, K;
   int kind, nsys, sys0, so0;   // kind of system; valid count; first global / factor index
   int n, q, nb;                // band rows, padded rows (multiple of NSET * SB), batches
-  TF* ring;                    // LDS [2][4][SB][KW]
+  TF* ring;                    // LDS [2][4][SB KW + pad]
   int t, lane, grp;
   bool valid;
   int so;                      // factor index of this lane's system (clamped)
@@ -104,17 +104,22 @@ struct Solver4 {
   __device__ __forceinline__ Batch load_batch(const TF* base, int b) const {
     return load_batch(base, b, std::make_integer_sequence<int, NCH>{});
   }
+  // LDS ring slot: [4 systems][SB][KW], each system's block followed by a
+  // 16-byte pad so that the four systems' reads fall in different banks
+  static constexpr int SYS_CH = CPS + 1;   // 16-byte chunks per system block
   template <int... I>
   __device__ __forceinline__ void stage(int slot, const Batch& r,
                                         std::integer_sequence<int, I...>) const {
-    double2* dst = reinterpret_cast<double2*>(ring + (size_t)slot * 4 * SB * KW);
-    ((dst[t + 64 * I] = r.v[I]), ...);
+    double2* dst = reinterpret_cast<double2*>(ring) + (size_t)slot * 4 * SYS_CH;
+    ((dst[(t + 64 * I) + (t + 64 * I) / CPS] = r.v[I]), ...);
   }
   __device__ __forceinline__ void stage(int slot, const Batch& r) const {
     stage(slot, r, std::make_integer_sequence<int, NCH>{});
   }
   __device__ __forceinline__ TF coef(int slot, int jj, int d) const {   // d in [1, KW]
-    return ring[(((size_t)slot * 4 + grp) * SB + jj) * KW + (d - 1)];
+    const TF* blk = reinterpret_cast<const TF*>(reinterpret_cast<const double2*>(ring) +
+                                                (size_t)(slot * 4 + grp) * SYS_CH);
+    return blk[jj * KW + (d - 1)];
   }
   __device__ __forceinline__ double2 hrow(int r) const { return (r < n) ? hg[r] : z2(); }
   __device__ __forceinline__ TF uirow(int r) const {
@@ -313,7 +318,7 @@ struct Solver4 {
 __global__ __launch_bounds__(64) void solve_np_kernel(Geom g, FactorSet<double2> Fp,
                                                       FactorSet<double> Fr, double2* rhs,
                                                       RhsSpec rs, int qp, int qr) {
-  __shared__ double2 ring_mem[2 * 4 * SB * 8];
+  __shared__ double2 ring_mem[2 * 4 * (SB * 8 + 1)];
   const int M = g.M, K = g.K;
   const int nbp = (M - 1 + 3) / 4;
   const int t = threadIdx.x, lane = t & 15, grp = t >> 4;

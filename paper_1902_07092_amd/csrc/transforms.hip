@@ -10,9 +10,11 @@
 //   analysis_kernel  per m:    forward DCT-I (eq. icheb) with radial
 //                              dealiasing, explicit terms C[..], -D[..]
 //
-// Layout: X[f][k][m] and NL[f][k][m] (m fastest).  The per-m kernels map
-// consecutive m to the same XCD (blocks go to the eight XCDs round robin),
-// so that the 16-byte strided stores and loads of neighbouring m share L2
+// Layout: X[f][k][m] (m fastest, written per m, read per ring) and
+// NL[f][m][k] (k fastest, written per ring, read per m): every kernel
+// reads contiguous rows and scatters only its stores.  Blocks go to the
+// eight XCDs round robin; the kernels map consecutive m (or k) to the same
+// XCD so that the 16-byte scattered stores of neighbouring blocks share L2
 // lines.
 #include <hip/hip_runtime.h>
 
@@ -328,7 +330,8 @@ __global__ __launch_bounds__(T) void ring_kernel(Geom g, const double2* __restri
   constexpr int NH = NPHI / 2;
   const int R = g.R, M = g.M;
   const int t = threadIdx.x;
-  const int k = blockIdx.x;
+  const int k = xcd_index(R);
+  if (k >= R) return;
   const double s = g.half * g.xk[k] + g.mid;
   const double h2s = (g.s_o * g.s_o - s * s) / s;
   const double2* X0 = X + (size_t)k * M;
@@ -397,7 +400,7 @@ __global__ __launch_bounds__(T) void ring_kernel(Geom g, const double2* __restri
       const double2 o = make_double2(0.5 * dd.y, -0.5 * dd.x);   // (Z_m - Z*)/(2i)
       double2 xm = add2(e, make_double2(w.x * o.x - w.y * o.y, w.x * o.y + w.y * o.x));
       if (m == 0) xm.y = 0.0;
-      NL[((size_t)f * R + k) * M + m] = scl2(inv, xm);
+      NL[((size_t)f * M + m) * R + k] = scl2(inv, xm);
     }
   }
   const double tot = block_sum(zs, red);
@@ -439,7 +442,7 @@ __global__ __launch_bounds__(T) void analysis_kernel(Geom g, Bands b,
     auto get = [&](int i) -> double2 {
       const int kk = (i <= N) ? i : N2 - i;
       if (f == 0 && m == 0) return make_double2(zonal[kk], 0.0);
-      return NL[((size_t)f * R + kk) * M + m];
+      return NL[((size_t)f * M + m) * R + kk];
     };
     double2 o[E];
     fft_out<N2, T, -1>(get, fb, g.tw_dct, o);
@@ -449,20 +452,28 @@ __global__ __launch_bounds__(T) void analysis_kernel(Geom g, Bands b,
       if (nn < K) c[nn] = scl2(nn == 0 ? 0.5 * invN : invN, o[i]);
     }
     __syncthreads();
+    // band rows: fixed 17 terms (entries outside the matrix are stored as
+    // zeros), so that every load of a row is issued at once
     for (int k = t; k < K; k += T) {
       double2 acc = z2();
-      const int lo = max(0, k - 8), hi = min(K - 1, k + 8);
       if (f == 0 && m > 0) {
-        if (k >= 4)
-          for (int nn = lo; nn <= hi; ++nn) {
-            const double cc = b.C[(size_t)(nn - k + 8) * K + k];
+        if (k >= 4) {
+#pragma unroll
+          for (int o = 0; o < 17; ++o) {
+            const int nn = min(max(k + o - 8, 0), K - 1);
+            const double cc = b.C[(size_t)o * K + k];
             acc = add2(acc, scl2(cc, add2(c[nn], ix(bcoef, thm[nn]))));
           }
+        }
         Epsi[(size_t)m * K + k] = acc;
       } else {
-        if (k >= 2)
-          for (int nn = lo; nn <= hi; ++nn)
-            acc = sub2(acc, scl2(b.D[(size_t)(nn - k + 8) * K + k], c[nn]));
+        if (k >= 2) {
+#pragma unroll
+          for (int o = 0; o < 17; ++o) {
+            const int nn = min(max(k + o - 8, 0), K - 1);
+            acc = sub2(acc, scl2(b.D[(size_t)o * K + k], c[nn]));
+          }
+        }
         (f == 0 ? Epsi : Eth)[(size_t)m * K + k] = acc;
       }
     }
@@ -496,7 +507,8 @@ void ring_n(const Geom& g, const double2* X, double2* NL, double* zonal, double*
   constexpr int T = threads_phi(NPHI);
   const size_t shm = sizeof(double2) * lds_slots(NPHI);
   allow_lds(ring_kernel<NPHI, T>, shm);
-  hipLaunchKernelGGL((ring_kernel<NPHI, T>), dim3(g.R), dim3(T), shm, st, g, X, NL, zonal, rate);
+  hipLaunchKernelGGL((ring_kernel<NPHI, T>), dim3(xcd_grid(g.R)), dim3(T), shm, st, g, X, NL,
+                     zonal, rate);
 }
 
 template <int N2>
