@@ -40,23 +40,28 @@ def alg_bytes(kernel, M, R, K, nterm=2):
     }[kernel]
 
 
-def factor_bytes(kernel, M, K):
-    """Bytes of the stored LU/Schur factors one solve launch streams."""
+def factor_bytes(kernel, M, K, pad=48):
+    """Bytes of the stored band-LU factors one solve launch streams
+    (unpivoted layout: L, U scaled, 1/U_jj padded to whole batches of
+    `pad` steps; W, C, Minv)."""
     if kernel != "solve":
         return 0
     n4, n2 = K - 4, K - 2
-    p4, p2 = (n4 + 15) // 16 * 16, (n2 + 15) // 16 * 16
-    psi = (M - 1) * (p4 * 4 + p4 * (8 + 13) * 16 + 4 * n4 * 16 + (32 + 16) * 16)
-    real = (M + 1) * (p2 * 4 + p2 * (4 + 5) * 8 + 2 * n2 * 8 + (8 + 4) * 8)
+    q4, q2 = (n4 + pad - 1) // pad * pad, (n2 + pad - 1) // pad * pad
+    psi = (M - 1) * (q4 * (8 + 8 + 1) * 16 + 4 * n4 * 16 + (32 + 16) * 16)
+    real = (M + 1) * (q2 * (4 + 4 + 1) * 8 + 2 * n2 * 8 + (8 + 4) * 8)
     return psi + real
 
 
 def kernel_source_hash():
+    """Hash of every device source: counter-measured traffic is reported
+    only for the kernels it was measured on."""
     h = hashlib.sha256()
-    for f in ("kernels.hip", "kernels.h"):
-        with open(os.path.join(ROOT, "paper_1902_07092_amd", "csrc", f),
-                  "rb") as fh:
-            h.update(fh.read())
+    csrc = os.path.join(ROOT, "paper_1902_07092_amd", "csrc")
+    for f in sorted(os.listdir(csrc)):
+        if f.endswith((".hip", ".h")):
+            with open(os.path.join(csrc, f), "rb") as fh:
+                h.update(fh.read())
     return h.hexdigest()[:16]
 
 
