@@ -60,7 +60,7 @@ struct Layout {
 struct Sizes {
   int M, K, R, nphi, n4, n2, Sr;
   int p4, p2;   // n4, n2 padded to whole 16-step batches (pivoted solve)
-  int q4, q2;   // n4, n2 padded to a multiple of 48 (unpivoted solve)
+  int q4, q2;   // n4, n2 padded to whole groups of solve batches (unpivoted solve)
 };
 
 bool sizes_of(const qg_params* p, Sizes& z, std::string& why) {
@@ -81,8 +81,9 @@ bool sizes_of(const qg_params* p, Sizes& z, std::string& why) {
   z.n2 = K - 2;
   z.p4 = (z.n4 + 15) / 16 * 16;   // whole solve batches (16 steps)
   z.p2 = (z.n2 + 15) / 16 * 16;
-  z.q4 = (z.n4 + 47) / 48 * 48;
-  z.q2 = (z.n2 + 47) / 48 * 48;
+  const int qpad = solve_np_pad();   // unpivoted solve: whole groups of prefetched batches
+  z.q4 = (z.n4 + qpad - 1) / qpad * qpad;
+  z.q2 = (z.n2 + qpad - 1) / qpad * qpad;
   z.Sr = z.M + 1;
   return true;
 }

@@ -27,7 +27,7 @@ struct Bands {  // [17][K] each (offset-major): entry (k, n) at [(n - k + 8) * K
 // Factors of all bordered systems of one kind.  With row interchanges
 // (pivoted solve): piv, Lc, Uc in the host_ops.h layout, steps padded to
 // whole 16-step batches.  Without (unpivoted solve): L, U, ui, steps padded
-// to q rows (a multiple of 48).  W, Cb and Minv serve both.
+// to q rows (a multiple of solve_np_pad()).  W, Cb and Minv serve both.
 template <typename TF>
 struct FactorSet {
   const int* piv;     // [S][npad] row-interchange offsets

@@ -24,8 +24,11 @@ namespace qg {
 
 namespace {
 
+#ifndef QG_SOLVE_NSET
+#define QG_SOLVE_NSET 3
+#endif
 constexpr int SB = 16;     // steps per batch = lanes per system
-constexpr int NSET = 3;    // factor batches in flight (the batch loop is unrolled by NSET)
+constexpr int NSET = QG_SOLVE_NSET;   // factor batches in flight (the batch loop is unrolled by NSET)
 
 __device__ __forceinline__ double2 z2() { return make_double2(0.0, 0.0); }
 
@@ -33,9 +36,9 @@ __device__ __forceinline__ double2 z2() { return make_double2(0.0, 0.0); }
 template <int LANE>
 __device__ __forceinline__ double bcast(double v) {
   const long long b = __double_as_longlong(v);
-  const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffffLL), 0x150 + LANE, 0xF, 0xF,
-                                             false);
-  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), 0x150 + LANE, 0xF, 0xF, false);
+  // every lane has a source under row_newbcast, so no "old" value is needed
+  const int lo = __builtin_amdgcn_mov_dpp((int)(b & 0xffffffffLL), 0x150 + LANE, 0xF, 0xF, true);
+  const int hi = __builtin_amdgcn_mov_dpp((int)(b >> 32), 0x150 + LANE, 0xF, 0xF, true);
   return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 template <int LANE>
@@ -127,34 +130,37 @@ struct Solver4 {
   }
 
   // ---------------------------------------------------------- forward
+  // The eight coefficients of a half batch are read from LDS before its
+  // first step (the compiler barrier keeps the reads together), so that the
+  // elimination chain never waits on LDS.
   template <int JJ>
-  __device__ __forceinline__ void fstep(double2& bw, int slot) const {
+  __device__ __forceinline__ TF fcoef(int slot) const {   // this lane's L entry at step JJ
     const int d = (lane - JJ) & 15;
     const bool act = (d >= 1 && d <= KW);
-    TF l = coef(slot, JJ, act ? d : 1);
-    if (!act) l = tz<TF>();
-    const double2 a = bcast2<JJ>(bw);
-    fms(bw, l, a);
+    const TF l = coef(slot, JJ, act ? d : 1);
+    return act ? l : tz<TF>();
   }
-  template <int... J>
-  __device__ __forceinline__ void fhalf(double2& bw, int slot, std::integer_sequence<int, J...>)
-      const {
-    (fstep<J>(bw, slot), ...);
-  }
-  // backward step: column j = b SB + JJ
   template <int JJ>
-  __device__ __forceinline__ void bstep(double2& bw, int slot) const {
+  __device__ __forceinline__ TF bcoef(int slot) const {   // this lane's U' entry at column JJ
     const int e = (JJ - lane) & 15;
     const bool act = (e >= 1 && e <= KW);
-    TF u = coef(slot, JJ, act ? e : 1);
-    if (!act) u = tz<TF>();
-    const double2 x = bcast2<JJ>(bw);
-    fms(bw, u, x);
+    const TF u = coef(slot, JJ, act ? e : 1);
+    return act ? u : tz<TF>();
   }
-  template <int... J>
+  template <int J0, int... J>
+  __device__ __forceinline__ void fhalf(double2& bw, int slot, std::integer_sequence<int, J...>)
+      const {
+    TF c[sizeof...(J)] = {fcoef<J0 + J>(slot)...};
+    asm volatile("" ::: "memory");
+    ((fms(bw, c[J], bcast2<J0 + J>(bw))), ...);
+  }
+  // backward: columns J0 + 7 - J, J = 0..7
+  template <int J0, int... J>
   __device__ __forceinline__ void bhalf(double2& bw, int slot, std::integer_sequence<int, J...>)
       const {
-    (bstep<15 - J>(bw, slot), ...);
+    TF c[sizeof...(J)] = {bcoef<J0 + 7 - J>(slot)...};
+    asm volatile("" ::: "memory");
+    ((fms(bw, c[J], bcast2<J0 + 7 - J>(bw))), ...);
   }
 
   __device__ __forceinline__ void run(double2* out_state) {
@@ -163,13 +169,27 @@ struct Solver4 {
 #pragma unroll
     for (int i = 0; i < P; ++i) wh[i] = z2();
     const TF* Wr = F.W + (size_t)so * P * n;
-    for (int j = lane; j < n; j += SB) {
-      const double2 h = hg[j];
+    // eight rows per lane in flight: the loads of a chunk issue together
+    for (int j0 = 0; j0 < n; j0 += 8 * SB) {
+      double2 h[8];
+      TF w[8][P];
 #pragma unroll
-      for (int i = 0; i < P; ++i) {
-        const double2 v = mul(Wr[(size_t)i * n + j], h);
-        wh[i].x += v.x;
-        wh[i].y += v.y;
+      for (int u = 0; u < 8; ++u) {
+        const int j = min(j0 + u * SB + lane, n - 1);
+        h[u] = hg[j];
+#pragma unroll
+        for (int i = 0; i < P; ++i) w[u][i] = Wr[(size_t)i * n + j];
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        if (j0 + u * SB + lane < n) {
+#pragma unroll
+          for (int i = 0; i < P; ++i) {
+            const double2 v = mul(w[u][i], h[u]);
+            wh[i].x += v.x;
+            wh[i].y += v.y;
+          }
+        }
       }
     }
 #pragma unroll
@@ -219,29 +239,43 @@ struct Solver4 {
     const bool real_row = (kind == 1) || (kind == 2 && sys0 + grp == M);
     double2* xo = out_ptr() + P;
     auto bidx = [&](int i) { return FWD ? i : nb - 1 - i; };
-    Batch s0, s1, s2;           // batch i + NSET of the sweep sits in s[(i + NSET) mod NSET]
-    double2 h0, h1, h2;         // refill rows of batches 0, 1, 2 (mod NSET)
-    TF u0, u1, u2;              // 1 / U(j, j) of the rows retiring in those batches
+    // sets[k] holds a batch i = k (mod NSET) ahead of its use; hs / us
+    // the refill rows and 1 / U(j, j) of batches k (mod NSET)
+    Batch sets[NSET];
+    double2 hs[NSET];
+    TF us[NSET];
     {   // batch 0 to the ring, batches 1..NSET in flight (loads past the
         // last batch re-read it)
       stage(0, load_batch(base, bidx(0)));
-      s1 = load_batch(base, bidx(min(1, nb - 1)));
-      s2 = load_batch(base, bidx(min(2, nb - 1)));
-      s0 = load_batch(base, bidx(min(3, nb - 1)));
-      auto refill = [&](int k) {   // next (FWD) / previous block of 16 rows
-        const int rr = FWD ? (k + 1) * SB + lane : (nb - 2 - k) * SB + lane;
-        return (rr >= 0 && rr < q) ? hrow(rr) : z2();
-      };
-      h0 = refill(0); h1 = refill(1); h2 = refill(2);
-      if (FWD) {
-        u0 = uirow(lane); u1 = uirow(SB + lane); u2 = uirow(2 * SB + lane);
-      }
+      prologue<FWD>(sets, hs, us, std::make_integer_sequence<int, NSET>{});
     }
-    for (int i0 = 0; i0 < nb; i0 += NSET) {   // nb is a multiple of NSET
-      batch<FWD>(bw, i0, base, real_row, xo, s1, h0, u0);
-      batch<FWD>(bw, i0 + 1, base, real_row, xo, s2, h1, u1);
-      batch<FWD>(bw, i0 + 2, base, real_row, xo, s0, h2, u2);
-    }
+    for (int i0 = 0; i0 < nb; i0 += NSET)   // nb is a multiple of NSET
+      batches<FWD>(bw, i0, base, real_row, xo, sets, hs, us,
+                   std::make_integer_sequence<int, NSET>{});
+  }
+
+  template <bool FWD, int... KK>
+  __device__ __forceinline__ void prologue(Batch (&sets)[NSET], double2 (&hs)[NSET],
+                                           TF (&us)[NSET], std::integer_sequence<int, KK...>) {
+    // batch k + 1 goes to sets[(k + 1) mod NSET]
+    ((sets[(KK + 1) % NSET] =
+          load_batch(base_of<FWD>(), FWD ? min(KK + 1, nb - 1) : nb - 1 - min(KK + 1, nb - 1))),
+     ...);
+    ((hs[KK] = refill_row<FWD>(KK)), ...);
+    if (FWD) ((us[KK] = uirow(KK * SB + lane)), ...);
+  }
+  template <bool FWD>
+  __device__ __forceinline__ const TF* base_of() const { return FWD ? F.L : F.U; }
+  template <bool FWD>
+  __device__ __forceinline__ double2 refill_row(int k) const {   // used in batch k
+    const int rr = FWD ? (k + 1) * SB + lane : (nb - 2 - k) * SB + lane;
+    return (rr >= 0 && rr < q) ? hrow(rr) : z2();
+  }
+  template <bool FWD, int... KK>
+  __device__ __forceinline__ void batches(double2& bw, int i0, const TF* base, bool real_row,
+                                          double2* xo, Batch (&sets)[NSET], double2 (&hs)[NSET],
+                                          TF (&us)[NSET], std::integer_sequence<int, KK...>) {
+    (batch<FWD>(bw, i0 + KK, base, real_row, xo, sets[(KK + 1) % NSET], hs[KK], us[KK]), ...);
   }
 
   // Batch i of a sweep.  nxt holds batch i + 1 (staged to the ring now)
@@ -260,12 +294,12 @@ struct Solver4 {
     }
     const int row = b * SB + lane;          // this lane's row in batch b
     if (FWD) {
-      fhalf(bw, slot, std::make_integer_sequence<int, 8>{});
+      fhalf<0>(bw, slot, std::make_integer_sequence<int, 8>{});
       if (lane < 8) {                        // rows b SB + 0..7 are final
         if (valid && row < n) hg[row] = mul(ur, bw);
         bw = hr;
       }
-      fhalf8(bw, slot);
+      fhalf<8>(bw, slot, std::make_integer_sequence<int, 8>{});
       if (lane >= 8) {
         if (valid && row < n) hg[row] = mul(ur, bw);
         bw = hr;
@@ -275,7 +309,7 @@ struct Solver4 {
       hr = (rn < q) ? hrow(rn) : z2();
       ur = uirow((b + NSET) * SB + lane);
     } else {
-      bhalf(bw, slot, std::make_integer_sequence<int, 8>{});   // columns 15..8
+      bhalf<8>(bw, slot, std::make_integer_sequence<int, 8>{});   // columns 15..8
       if (lane >= 8) {                       // rows b SB + 8..15 are final
         if (valid && row < n) {
           double2 v = bw;
@@ -284,7 +318,7 @@ struct Solver4 {
         }
         bw = hr;
       }
-      bhalf8(bw, slot);                      // columns 7..0
+      bhalf<0>(bw, slot, std::make_integer_sequence<int, 8>{});   // columns 7..0
       if (lane < 8) {
         if (valid && row < n) {
           double2 v = bw;
@@ -296,14 +330,6 @@ struct Solver4 {
       const int rn = (b - NSET - 1) * SB + lane;
       hr = (rn >= 0) ? hrow(rn) : z2();
     }
-  }
-  __device__ __forceinline__ void fhalf8(double2& bw, int slot) const {
-    fstep<8>(bw, slot); fstep<9>(bw, slot); fstep<10>(bw, slot); fstep<11>(bw, slot);
-    fstep<12>(bw, slot); fstep<13>(bw, slot); fstep<14>(bw, slot); fstep<15>(bw, slot);
-  }
-  __device__ __forceinline__ void bhalf8(double2& bw, int slot) const {
-    bstep<7>(bw, slot); bstep<6>(bw, slot); bstep<5>(bw, slot); bstep<4>(bw, slot);
-    bstep<3>(bw, slot); bstep<2>(bw, slot); bstep<1>(bw, slot); bstep<0>(bw, slot);
   }
   __device__ __forceinline__ double2* out_ptr() const {
     const int m = (kind == 0) ? sys0 + grp + 1 : (kind == 1 ? 0 : sys0 + grp - M);
