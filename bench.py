@@ -118,6 +118,42 @@ def copy_calibration(torch, mb, steps):
           flush=True)
 
 
+def timed_steps(torch, solver, w, steps):
+    stream = solver.stream
+    torch.cuda.synchronize()
+    start = torch.cuda.Event(enable_timing=True)
+    stop = torch.cuda.Event(enable_timing=True)
+    start.record(stream)
+    solver.step(w.dt, w.scheme, steps)
+    stop.record(stream)
+    torch.cuda.synchronize()
+    return start.elapsed_time(stop)
+
+
+def mixed_run(qg, torch, w, state, args, fp64_solver):
+    """The same sequence of steps with FP32 transforms and products (FP64
+    solves, state and history); its state is compared with the FP64 run's
+    after the same steps."""
+    import numpy as np
+    s = qg.QGSolver(w.E, w.Ra, w.Pr, w.eta, w.n_phi, w.n_r, w.n_c,
+                    device="cuda:0", precision=1)
+    s.set_state(state.psi, state.theta, state.uphi0)
+    s.step(w.dt, w.scheme, 0)
+    s.step(w.dt, w.scheme, args.warmup)
+    ms = timed_steps(torch, s, w, args.steps) / args.steps
+    kern = s.step_timed(w.dt, w.scheme, args.steps)
+    a, b = s.get_state(), fp64_solver.get_state()
+    rel = {f: float(np.abs(x - y).max() / max(np.abs(y).max(), 1e-300))
+           for f, x, y in zip(("psi", "theta", "uphi"), a, b)}
+    return {"value": w.grid_points / (ms * 1e-3), "unit": "grid-point-steps/s",
+            "ms_per_step": ms, "precision": "FP32 transforms and products, "
+            "FP64 solves/state/diagnostics",
+            "rel_diff_vs_fp64_run": rel,
+            "rel_diff_after_steps": args.warmup + 2 * args.steps,
+            "kernels": {k: {"avg_launch_us": v[0] / max(1, v[1]) * 1e3,
+                            "launches": v[1]} for k, v in kern.items()}}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -126,6 +162,11 @@ def main():
     ap.add_argument("--workload", default="large_3072x1025_E1e-8_cnab2")
     ap.add_argument("--cpu-steps", type=int, default=1)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-mixed", action="store_true",
+                    help="skip the mixed-precision run")
+    ap.add_argument("--precision", choices=("fp64", "mixed"), default="fp64",
+                    help="precision of the headline run (mixed also runs the "
+                         "12288 x 4097 workload, which FP64 does not fit)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MB",
                     help="only run a plain device-to-device copy of MB MiB "
                          "(steps times), the reference for HBM counters")
@@ -145,8 +186,9 @@ def main():
     from paper_1902_07092_amd import inputs, qg
     w = inputs.WORKLOADS[args.workload]
     state = inputs.workload_state(w)
+    prec = 1 if args.precision == "mixed" else 0
     solver = qg.QGSolver(w.E, w.Ra, w.Pr, w.eta, w.n_phi, w.n_r, w.n_c,
-                         device="cuda:0")
+                         device="cuda:0", precision=prec)
     solver.set_state(state.psi, state.theta, state.uphi0)
     solver.step(w.dt, w.scheme, 0)            # factorise (untimed)
     solver.step(w.dt, w.scheme, args.warmup)
@@ -195,6 +237,12 @@ def main():
            "roofline": roofline, "kernels": kernels}
     print(f"[bench] gpu done: {ms_per_step:.4f} ms/step", file=sys.stderr,
           flush=True)
+    if prec == 1:
+        out["dtype"] = "f32+f64"
+    if not args.no_mixed and prec == 0:
+        out["mixed"] = mixed_run(qg, torch, w, state, args, solver)
+        print(f"[bench] mixed done: {out['mixed']['ms_per_step']:.4f} ms/step",
+              file=sys.stderr, flush=True)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(w, state, args.cpu_steps)
     print(json.dumps(out), flush=True)

@@ -69,7 +69,16 @@ typedef struct {
                     needs exceed the device limit give QG_EUNSUPPORTED */
   int n_c;       /* Chebyshev modes kept, 8 <= n_c < n_r; 0 selects
                     floor(2 (n_r - 1) / 3) (radial dealiasing, Sect. 3.2.1) */
-  int precision; /* 0 = FP64 (the only value accepted by this build) */
+  int precision; /* 0 = FP64 throughout.  1 = mixed: the transforms and
+                    advection products (synthesis outputs, azimuthal FFTs
+                    and products, the input of the forward radial
+                    transform) in FP32 with FP32 accumulation; Chebyshev
+                    recurrences, explicit-term band products, right-hand
+                    sides, band LU factors, solves, state, history and
+                    diagnostics in FP64 (the diagnostics use the FP64
+                    transforms whenever those fit the device, i.e. up to
+                    n_phi = 6144, n_r = 2049).  Mixed also accepts
+                    n_phi = 12288 and n_r = 4097. */
   int pivoting;  /* band LU of the bordered systems (Appendix A):
                     0 = without row interchanges when every system's growth
                         factor max|U| / max|D| stays <= 1e4, else with

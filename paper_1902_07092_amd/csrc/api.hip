@@ -71,7 +71,7 @@ bool sizes_of(const qg_params* p, Sizes& z, std::string& why) {
   if (p->n_r < 17) { why = "n_r must be >= 17"; return false; }
   int K = p->n_c ? p->n_c : (2 * (p->n_r - 1)) / 3;
   if (K < 8 || K >= p->n_r) { why = "n_c must satisfy 8 <= n_c < n_r"; return false; }
-  if (p->precision != 0) { why = "only precision = 0 (FP64) is supported"; return false; }
+  if (p->precision != 0 && p->precision != 1) { why = "precision must be 0 or 1"; return false; }
   if (p->pivoting != 0 && p->pivoting != 1) { why = "pivoting must be 0 or 1"; return false; }
   z.M = p->n_phi / 3 + 1;
   z.K = K;
@@ -90,7 +90,7 @@ bool sizes_of(const qg_params* p, Sizes& z, std::string& why) {
 
 struct WsMap {
   size_t state, ybuf, eslot, lslot, X, NL, zonal, rate, diag, xk, wq, dsk, twd, twp, twh, wphi,
-      bands, rhs;
+      twd32, twp32, twh32, wphi32, bands, rhs;
   size_t p_piv, p_L, p_U, p_W, p_C, p_Mi, p_ui;
   size_t r_piv, r_L, r_U, r_W, r_C, r_Mi, r_ui;
   size_t total;
@@ -118,6 +118,10 @@ WsMap map_workspace(const Sizes& z) {
   w.twp = L.take((size_t)z.nphi * sizeof(double2));
   w.twh = L.take((size_t)z.nphi / 2 * sizeof(double2));
   w.wphi = L.take((size_t)(z.nphi / 2 + 1) * sizeof(double2));
+  w.twd32 = L.take((size_t)2 * (z.R - 1) * sizeof(float2));
+  w.twp32 = L.take((size_t)z.nphi * sizeof(float2));
+  w.twh32 = L.take((size_t)z.nphi / 2 * sizeof(float2));
+  w.wphi32 = L.take((size_t)(z.nphi / 2 + 1) * sizeof(float2));
   w.bands = L.take((size_t)9 * z.K * BANDW * sizeof(double));
   w.rhs = L.take((size_t)2 * z.M * z.K * sizeof(double2));
   w.p_piv = L.take(Sp * z.p4 * sizeof(int));
@@ -154,6 +158,8 @@ struct qg_ctx {
   FactorSet<double> Fr;
   int kutp = 16, kutr = 8;   // stored U super-diagonals (Psi, real systems)
   bool pivoted = true;       // band LU with row interchanges in use
+  bool mixed = false;        // FP32 transforms and products (qg_params.precision = 1)
+  bool diag64 = true;        // FP64 transform kernels exist for the diagnostics
   double growth = 0.0;       // largest growth factor of the band LUs in use
   double factored_adt = -1.0;
   int have_prev = 0, cur = 0;
@@ -451,15 +457,15 @@ qg_status explicit_terms(qg_ctx* ctx, const double2* psi, const double2* th, dou
                          double2* Et) {
   bool ok = true;
   timed(ctx, K_SYNTH, [&] {
-    ok = launch_synth(ctx->g, psi, th, ctx->ptr2(ctx->w.X), nullptr, ctx->st) && ok;
+    ok = launch_synth(ctx->g, psi, th, ctx->ptr2(ctx->w.X), nullptr, ctx->mixed, ctx->st) && ok;
   });
   timed(ctx, K_RING, [&] {
     ok = launch_ring(ctx->g, ctx->ptr2(ctx->w.X), ctx->ptr2(ctx->w.NL), ctx->ptrd(ctx->w.zonal),
-                     nullptr, ctx->st) && ok;
+                     nullptr, ctx->mixed, ctx->st) && ok;
   });
   timed(ctx, K_ANALYSIS, [&] {
     ok = launch_analysis(ctx->g, ctx->b, ctx->ptr2(ctx->w.NL), ctx->ptrd(ctx->w.zonal), th, Ep,
-                         Et, ctx->st) && ok;
+                         Et, ctx->mixed, ctx->st) && ok;
   });
   if (!ok) return fail(ctx, QG_EUNSUPPORTED, "no transform kernel for these sizes");
   HIPCHK(hipGetLastError());
@@ -584,7 +590,8 @@ qg_status qg_create(qg_ctx** out, const qg_params* p, void* workspace, size_t wo
   Sizes z;
   std::string why;
   if (!sizes_of(p, z, why)) return QG_EINVAL;
-  if (!is_pow2(z.R - 1) || z.nphi % 6 || !transform_sizes_ok(2 * (z.R - 1), z.nphi))
+  const bool mixed = p->precision == 1;
+  if (!is_pow2(z.R - 1) || z.nphi % 6 || !transform_sizes_ok(2 * (z.R - 1), z.nphi, mixed))
     return QG_EUNSUPPORTED;
   if (!workspace || ((uintptr_t)workspace & 255)) return QG_EINVAL;
   WsMap w = map_workspace(z);
@@ -604,9 +611,14 @@ qg_status qg_create(qg_ctx** out, const qg_params* p, void* workspace, size_t wo
     delete ctx;
     return QG_EDEVICE;
   }
-  const size_t lds_fft = transform_lds_bytes(2 * (z.R - 1), z.nphi, z.K) + 1024;
+  const size_t lds_fft = transform_lds_bytes(2 * (z.R - 1), z.nphi, z.K, mixed) + 1024;
   ctx->g.K = z.K;
   const size_t lds_solve = solve_lds_bytes(ctx->g, 16, 8);
+  ctx->mixed = mixed;
+  // diagnostics stay FP64 whenever the FP64 transform kernels fit
+  ctx->diag64 = transform_sizes_ok(2 * (z.R - 1), z.nphi, false) &&
+                transform_lds_bytes(2 * (z.R - 1), z.nphi, z.K, false) + 1024 <=
+                    (size_t)prop.sharedMemPerBlock;
   if (std::max(lds_fft, lds_solve) > (size_t)prop.sharedMemPerBlock) {
     delete ctx;
     return QG_EUNSUPPORTED;
@@ -632,6 +644,13 @@ qg_status qg_create(qg_ctx** out, const qg_params* p, void* workspace, size_t wo
   std::vector<double2> twd = plan_twiddles(2 * (z.R - 1)), twp = plan_twiddles(z.nphi),
                        twh = plan_twiddles(z.nphi / 2), wphi = twiddles(z.nphi);
   wphi.resize(z.nphi / 2 + 1);
+  auto to32 = [](const std::vector<double2>& v) {
+    std::vector<float2> o(v.size());
+    for (size_t i = 0; i < v.size(); ++i) o[i] = make_float2((float)v[i].x, (float)v[i].y);
+    return o;
+  };
+  const std::vector<float2> twd32 = to32(twd), twp32 = to32(twp), twh32 = to32(twh),
+                            wphi32 = to32(wphi);
   std::vector<double> bandbuf((size_t)9 * z.K * BANDW);
   const std::vector<double>* bl[9] = {&ctx->ops.A0, &ctx->ops.A2, &ctx->ops.B0,
                                       &ctx->ops.B2, &ctx->ops.B4, &ctx->ops.C,
@@ -650,6 +669,10 @@ qg_status qg_create(qg_ctx** out, const qg_params* p, void* workspace, size_t wo
       up(w.twp, twp.data(), twp.size() * 16) != hipSuccess ||
       up(w.twh, twh.data(), twh.size() * 16) != hipSuccess ||
       up(w.wphi, wphi.data(), wphi.size() * 16) != hipSuccess ||
+      up(w.twd32, twd32.data(), twd32.size() * 8) != hipSuccess ||
+      up(w.twp32, twp32.data(), twp32.size() * 8) != hipSuccess ||
+      up(w.twh32, twh32.data(), twh32.size() * 8) != hipSuccess ||
+      up(w.wphi32, wphi32.data(), wphi32.size() * 8) != hipSuccess ||
       up(w.bands, bandbuf.data(), bandbuf.size() * 8) != hipSuccess ||
       hipMemsetAsync(ctx->ws + w.state, 0, 2 * (size_t)z.M * z.K * sizeof(double2), ctx->st) !=
           hipSuccess ||
@@ -674,6 +697,10 @@ qg_status qg_create(qg_ctx** out, const qg_params* p, void* workspace, size_t wo
   g.tw_phi = ctx->ptr2(w.twp);
   g.tw_half = ctx->ptr2(w.twh);
   g.w_phi = ctx->ptr2(w.wphi);
+  g.tw_dct32 = reinterpret_cast<const float2*>(ctx->ws + w.twd32);
+  g.tw_phi32 = reinterpret_cast<const float2*>(ctx->ws + w.twp32);
+  g.tw_half32 = reinterpret_cast<const float2*>(ctx->ws + w.twh32);
+  g.w_phi32 = reinterpret_cast<const float2*>(ctx->ws + w.wphi32);
   const double* bd = ctx->ptrd(w.bands);
   const size_t bs = (size_t)z.K * BANDW;
   ctx->b = Bands{bd, bd + bs, bd + 2 * bs, bd + 3 * bs, bd + 4 * bs,
@@ -795,10 +822,11 @@ qg_status qg_step(qg_ctx* ctx, double dt, int scheme, int nsteps) {
 qg_status qg_diagnostics(qg_ctx* ctx, qg_diag* out) {
   if (!ctx || !out) return QG_EINVAL;
   const Sizes& z = ctx->z;
+  const bool mixed = !ctx->diag64;   // FP64 diagnostics whenever those kernels fit
   if (!launch_synth(ctx->g, ctx->psi(), ctx->th(), ctx->ptr2(ctx->w.X), ctx->ptrd(ctx->w.diag),
-                    ctx->st) ||
+                    mixed, ctx->st) ||
       !launch_ring(ctx->g, ctx->ptr2(ctx->w.X), ctx->ptr2(ctx->w.NL), ctx->ptrd(ctx->w.zonal),
-                   ctx->ptrd(ctx->w.rate), ctx->st))
+                   ctx->ptrd(ctx->w.rate), mixed, ctx->st))
     return fail(ctx, QG_EUNSUPPORTED, "no transform kernel for these sizes");
   HIPCHK(hipGetLastError());
   std::vector<double> d((size_t)z.M * 8), rate(z.R);

@@ -1,6 +1,7 @@
 // Block-wide FFTs in LDS for the transforms of the QG step (eq. fft,
 // eq. ifft in azimuth; the even extension behind eq. cheb / eq. icheb in
-// radius), FP64, compile-time radix plans for gfx950.
+// radius), FP64 (double2) or FP32 (float2), compile-time radix plans for
+// gfx950.
 //
 // A length-n transform runs as Stockham passes of radix 16, 8, 4, 3 or 2.
 // A pass reads its butterfly inputs x[j + r n/R] into registers, applies
@@ -61,47 +62,63 @@ constexpr bool plan_valid(int n) {
 
 constexpr int LDS_PAD_SHIFT = 3;
 __host__ __device__ constexpr int lds_pad(int i) { return i + (i >> LDS_PAD_SHIFT); }
-// LDS elements (double2) of `count` padded transforms of length n laid end to end
+// LDS elements of `count` padded transforms of length n laid end to end
 __host__ __device__ constexpr int lds_slots(int n, int count = 1) { return lds_pad(n * count) + 1; }
 
 #ifdef __HIPCC__
 namespace fftd {
 
-__device__ __forceinline__ double2 add(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
-__device__ __forceinline__ double2 sub(double2 a, double2 b) { return make_double2(a.x - b.x, a.y - b.y); }
-__device__ __forceinline__ double2 scl(double s, double2 a) { return make_double2(s * a.x, s * a.y); }
-__device__ __forceinline__ double2 mul(double2 a, double2 b) {
-  return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+template <typename C> struct Real;
+template <> struct Real<double2> { using type = double; };
+template <> struct Real<float2> { using type = float; };
+template <typename C> using real_t = typename Real<C>::type;
+
+template <typename C>
+__device__ __forceinline__ C mk(real_t<C> x, real_t<C> y);
+template <>
+__device__ __forceinline__ double2 mk<double2>(double x, double y) { return make_double2(x, y); }
+template <>
+__device__ __forceinline__ float2 mk<float2>(float x, float y) { return make_float2(x, y); }
+template <typename C>
+__device__ __forceinline__ C add(C a, C b) { return mk<C>(a.x + b.x, a.y + b.y); }
+template <typename C>
+__device__ __forceinline__ C sub(C a, C b) { return mk<C>(a.x - b.x, a.y - b.y); }
+template <typename C>
+__device__ __forceinline__ C scl(real_t<C> s, C a) { return mk<C>(s * a.x, s * a.y); }
+template <typename C>
+__device__ __forceinline__ C mul(C a, C b) {
+  return mk<C>(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
 }
 // SGN * i * a
-template <int SGN>
-__device__ __forceinline__ double2 rot(double2 a) {
-  return SGN > 0 ? make_double2(-a.y, a.x) : make_double2(a.y, -a.x);
+template <int SGN, typename C>
+__device__ __forceinline__ C rot(C a) {
+  return SGN > 0 ? mk<C>(-a.y, a.x) : mk<C>(a.y, -a.x);
 }
 
 // e^{SGN 2 pi i e / 16} * a for the constant exponents of the 16-point DFT
-template <int SGN, int E>
-__device__ __forceinline__ double2 w16(double2 a) {
+template <int SGN, int E, typename C>
+__device__ __forceinline__ C w16(C a) {
+  using R = real_t<C>;
   constexpr double c1 = 0.92387953251128675613;  // cos(pi/8)
   constexpr double s1 = 0.38268343236508977173;  // sin(pi/8)
   constexpr double c2 = 0.70710678118654752440;  // cos(pi/4)
   constexpr int e = E % 16;
   if constexpr (e == 0) return a;
   else if constexpr (e == 4) return rot<SGN>(a);
-  else if constexpr (e == 8) return make_double2(-a.x, -a.y);
+  else if constexpr (e == 8) return mk<C>(-a.x, -a.y);
   else if constexpr (e == 12) return rot<-SGN>(a);
   else {
     constexpr double ang[16][2] = {{1, 0}, {c1, s1}, {c2, c2}, {s1, c1}, {0, 1}, {-s1, c1},
                                    {-c2, c2}, {-c1, s1}, {-1, 0}, {-c1, -s1}, {-c2, -c2},
                                    {-s1, -c1}, {0, -1}, {s1, -c1}, {c2, -c2}, {c1, -s1}};
-    return mul(a, make_double2(ang[e][0], SGN * ang[e][1]));
+    return mul(a, mk<C>((R)ang[e][0], (R)(SGN * ang[e][1])));
   }
 }
 
-template <int SGN>
-__device__ __forceinline__ void dft4(double2& x0, double2& x1, double2& x2, double2& x3) {
-  const double2 a = add(x0, x2), b = sub(x0, x2);
-  const double2 c = add(x1, x3), d = rot<SGN>(sub(x1, x3));
+template <int SGN, typename C>
+__device__ __forceinline__ void dft4(C& x0, C& x1, C& x2, C& x3) {
+  const C a = add(x0, x2), b = sub(x0, x2);
+  const C c = add(x1, x3), d = rot<SGN>(sub(x1, x3));
   x0 = add(a, c);
   x1 = add(b, d);
   x2 = sub(a, c);
@@ -109,17 +126,18 @@ __device__ __forceinline__ void dft4(double2& x0, double2& x1, double2& x2, doub
 }
 
 // y_q = sum_r x_r e^{SGN 2 pi i r q / R}, in place
-template <int R, int SGN>
-__device__ __forceinline__ void dft(double2* v) {
+template <int R, int SGN, typename C>
+__device__ __forceinline__ void dft(C* v) {
+  using RT = real_t<C>;
   if constexpr (R == 2) {
-    const double2 t = sub(v[0], v[1]);
+    const C t = sub(v[0], v[1]);
     v[0] = add(v[0], v[1]);
     v[1] = t;
   } else if constexpr (R == 3) {
-    constexpr double h3 = 0.86602540378443864676;  // sqrt(3)/2
-    const double2 t1 = add(v[1], v[2]), t2 = sub(v[1], v[2]);
-    const double2 base = sub(v[0], scl(0.5, t1));
-    const double2 r = scl(h3, rot<SGN>(t2));
+    const RT h3 = (RT)0.86602540378443864676;  // sqrt(3)/2
+    const C t1 = add(v[1], v[2]), t2 = sub(v[1], v[2]);
+    const C base = sub(v[0], scl((RT)0.5, t1));
+    const C r = scl(h3, rot<SGN>(t2));
     v[0] = add(v[0], t1);
     v[1] = add(base, r);
     v[2] = sub(base, r);
@@ -127,8 +145,8 @@ __device__ __forceinline__ void dft(double2* v) {
     dft4<SGN>(v[0], v[1], v[2], v[3]);
   } else if constexpr (R == 8) {
     // 4-point DFTs of the even and odd samples, then one radix-2 stage
-    double2 e0 = v[0], e1 = v[2], e2 = v[4], e3 = v[6];
-    double2 o0 = v[1], o1 = v[3], o2 = v[5], o3 = v[7];
+    C e0 = v[0], e1 = v[2], e2 = v[4], e3 = v[6];
+    C o0 = v[1], o1 = v[3], o2 = v[5], o3 = v[7];
     dft4<SGN>(e0, e1, e2, e3);
     dft4<SGN>(o0, o1, o2, o3);
     o1 = w16<SGN, 2>(o1);
@@ -140,7 +158,7 @@ __device__ __forceinline__ void dft(double2* v) {
     v[3] = add(e3, o3); v[7] = sub(e3, o3);
   } else if constexpr (R == 16) {
     // r = u + 4 s, q = q1 + 4 q2: DFT4 over s, twiddle w16^{u q1}, DFT4 over u
-    double2 a[4][4];
+    C a[4][4];
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
       a[u][0] = v[u]; a[u][1] = v[u + 4]; a[u][2] = v[u + 8]; a[u][3] = v[u + 12];
@@ -151,7 +169,7 @@ __device__ __forceinline__ void dft(double2* v) {
     a[3][1] = w16<SGN, 3>(a[3][1]); a[3][2] = w16<SGN, 6>(a[3][2]); a[3][3] = w16<SGN, 9>(a[3][3]);
 #pragma unroll
     for (int q1 = 0; q1 < 4; ++q1) {
-      double2 b0 = a[0][q1], b1 = a[1][q1], b2 = a[2][q1], b3 = a[3][q1];
+      C b0 = a[0][q1], b1 = a[1][q1], b2 = a[2][q1], b3 = a[3][q1];
       dft4<SGN>(b0, b1, b2, b3);
       v[q1] = b0; v[q1 + 4] = b1; v[q1 + 8] = b2; v[q1 + 12] = b3;
     }
@@ -161,8 +179,8 @@ __device__ __forceinline__ void dft(double2* v) {
 // One Stockham pass over BATCH transforms of length n held end to end.
 // Inputs come from `get(global index)`, outputs go to `put(global index,
 // value)` (the index space is batch * n + position).
-template <int n, int T, int BATCH, int S, int SGN, typename Get, typename Put>
-__device__ __forceinline__ void pass(Get get, Put put, const double2* tw) {
+template <int n, int T, int BATCH, int S, int SGN, typename C, typename Get, typename Put>
+__device__ __forceinline__ void pass(Get get, Put put, const C* tw) {
   // An opaque copy of the table pointer keeps the compiler from hoisting
   // the twiddle loads of every pass out of the caller's loops (that would
   // hold all of them in registers for the whole kernel).
@@ -176,7 +194,7 @@ __device__ __forceinline__ void pass(Get get, Put put, const double2* tw) {
   constexpr int nb = n / R;
   constexpr int NB = nb * BATCH;
   constexpr int NBT = (NB + T - 1) / T;
-  double2 v[NBT][R];
+  C v[NBT][R];
 #pragma unroll
   for (int b = 0; b < NBT; ++b) {
     const int g = t + b * T;
@@ -186,14 +204,14 @@ __device__ __forceinline__ void pass(Get get, Put put, const double2* tw) {
         const int k = j % Ns;
 #pragma unroll
         for (int r = 1; r < R; ++r) {
-          double2 w = tw[(Ns - 1) + (r - 1) * Ns + k];
+          C w = tw[(Ns - 1) + (r - 1) * Ns + k];
           if (SGN > 0) w.y = -w.y;
           v[b][r] = w;
         }
       }
 #pragma unroll
       for (int r = 0; r < R; ++r) {
-        const double2 x = get(bt * n + j + r * nb);
+        const C x = get(bt * n + j + r * nb);
         if constexpr (Ns > 1) {
           if (r > 0) v[b][r] = mul(x, v[b][r]);
           else v[b][r] = x;
@@ -221,41 +239,44 @@ __device__ __forceinline__ void pass(Get get, Put put, const double2* tw) {
 
 // Writes into the padded LDS buffer; begin/end are the barriers that keep
 // the in-place passes race free.
+template <typename C>
 struct LdsPut {
-  double2* buf;
+  C* buf;
   __device__ __forceinline__ void begin() const { __syncthreads(); }
   __device__ __forceinline__ void end() const { __syncthreads(); }
-  __device__ __forceinline__ void operator()(int i, double2 x, int, int) const { buf[lds_pad(i)] = x; }
+  __device__ __forceinline__ void operator()(int i, C x, int, int) const { buf[lds_pad(i)] = x; }
 };
 
 // Keeps the last pass's outputs in registers: out[b + r NBT] holds element
 // t + (b + r NBT) T of the (single) transform.
-template <int NBT, int E>
+template <int NBT, int E, typename C>
 struct RegPut {
-  double2 (&out)[E];
+  C (&out)[E];
   __device__ __forceinline__ void begin() const {}
   __device__ __forceinline__ void end() const {}
-  __device__ __forceinline__ void operator()(int, double2 x, int b, int r) const { out[b + r * NBT] = x; }
+  __device__ __forceinline__ void operator()(int, C x, int b, int r) const { out[b + r * NBT] = x; }
 };
 
+template <typename C>
 struct LdsGet {
-  const double2* buf;
-  __device__ __forceinline__ double2 operator()(int i) const { return buf[lds_pad(i)]; }
+  const C* buf;
+  __device__ __forceinline__ C operator()(int i) const { return buf[lds_pad(i)]; }
 };
 
 // Passes S .. np - 1; the last one writes to LDS or (REGS) to registers.
-template <int n, int T, int BATCH, int S, int SGN, bool REGS, typename Get, typename Out>
-__device__ __forceinline__ void chain(Get get, double2* buf, const double2* __restrict__ tw,
-                                      Out& out) {
+template <int n, int T, int BATCH, int S, int SGN, bool REGS, typename C, typename Get,
+          typename Out>
+__device__ __forceinline__ void chain(Get get, C* buf, const C* __restrict__ tw, Out& out) {
   constexpr RadixPlan pl = radix_plan(n);
   constexpr bool last = (S + 1 == pl.np);
   constexpr int NBT = (n / pl.r[S]) * BATCH / T;
   if constexpr (S == 0) {
-    if constexpr (last && REGS) pass<n, T, BATCH, S, SGN>(get, RegPut<NBT, n / T>{out}, tw);
-    else pass<n, T, BATCH, S, SGN>(get, LdsPut{buf}, tw);
+    if constexpr (last && REGS) pass<n, T, BATCH, S, SGN>(get, RegPut<NBT, n / T, C>{out}, tw);
+    else pass<n, T, BATCH, S, SGN>(get, LdsPut<C>{buf}, tw);
   } else {
-    if constexpr (last && REGS) pass<n, T, BATCH, S, SGN>(LdsGet{buf}, RegPut<NBT, n / T>{out}, tw);
-    else pass<n, T, BATCH, S, SGN>(LdsGet{buf}, LdsPut{buf}, tw);
+    if constexpr (last && REGS)
+      pass<n, T, BATCH, S, SGN>(LdsGet<C>{buf}, RegPut<NBT, n / T, C>{out}, tw);
+    else pass<n, T, BATCH, S, SGN>(LdsGet<C>{buf}, LdsPut<C>{buf}, tw);
   }
   if constexpr (!last) chain<n, T, BATCH, S + 1, SGN, REGS>(get, buf, tw, out);
 }
@@ -275,11 +296,11 @@ constexpr bool reg_out_ok() {
 }
 
 // Transform with the result in LDS (natural order, padded indices).
-// Starts and ends with a barrier.
-template <int n, int T, int SGN, int BATCH = 1, typename Get>
-__device__ __forceinline__ void fft_to_lds(Get get, double2* buf, const double2* __restrict__ tw) {
+// Starts and ends with a barrier.  C is double2 or float2.
+template <int n, int T, int SGN, int BATCH = 1, typename C, typename Get>
+__device__ __forceinline__ void fft_to_lds(Get get, C* buf, const C* __restrict__ tw) {
   static_assert(plan_valid(n), "unsupported transform length");
-  double2 none[1];
+  C none[1];
   fftd::chain<n, T, BATCH, 0, SGN, false>(get, buf, tw, none);
 }
 
@@ -287,9 +308,9 @@ __device__ __forceinline__ void fft_to_lds(Get get, double2* buf, const double2*
 // scratch for the intermediate passes; the first pass starts with a
 // barrier, so `buf` may still be read before the call, and the caller
 // needs a barrier before writing `buf` afterwards.
-template <int n, int T, int SGN, typename Get>
-__device__ __forceinline__ void fft_to_regs(Get get, double2* buf, const double2* __restrict__ tw,
-                                            double2 (&out)[n / T]) {
+template <int n, int T, int SGN, typename C, typename Get>
+__device__ __forceinline__ void fft_to_regs(Get get, C* buf, const C* __restrict__ tw,
+                                            C (&out)[n / T]) {
   static_assert(plan_valid(n), "unsupported transform length");
   static_assert(reg_out_ok<n, T>(), "last pass does not divide over the block");
   fftd::chain<n, T, 1, 0, SGN, true>(get, buf, tw, out);

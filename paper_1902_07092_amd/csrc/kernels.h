@@ -18,6 +18,10 @@ struct Geom {
   const double2* tw_phi;        // plan twiddles, length nphi
   const double2* tw_half;       // plan twiddles, length nphi / 2
   const double2* w_phi;         // exp(-2 pi i m / nphi), m <= nphi / 2
+  const float2* tw_dct32;       // the same tables in FP32 (mixed precision)
+  const float2* tw_phi32;
+  const float2* tw_half32;
+  const float2* w_phi32;
 };
 
 struct Bands {  // [17][K] each (offset-major): entry (k, n) at [(n - k + 8) * K + k]
@@ -59,16 +63,18 @@ struct RhsSpec {
   double2* lin_th;
 };
 
-// Transform kernels (transforms.hip).  The launchers return false for a
-// size without a compiled plan.
-bool transform_sizes_ok(int n2, int nphi);
-size_t transform_lds_bytes(int n2, int nphi, int K);
+// Transform kernels (transforms.hip), FP64 or, with `mixed`, FP32 for the
+// transforms and products (exchange arrays X and NL in float2).  The
+// launchers return false for a size without a compiled plan.
+bool transform_sizes_ok(int n2, int nphi, bool mixed);
+size_t transform_lds_bytes(int n2, int nphi, int K, bool mixed);
 std::vector<double2> plan_twiddles(int n);
-bool launch_synth(const Geom& g, const double2* psi, const double2* th, double2* X, double* diag,
-                  hipStream_t st);
-bool launch_ring(const Geom& g, const double2* X, double2* NL, double* zonal, double* rate,
+bool launch_synth(const Geom& g, const double2* psi, const double2* th, void* X, double* diag,
+                  bool mixed, hipStream_t st);
+bool launch_ring(const Geom& g, const void* X, void* NL, double* zonal, double* rate, bool mixed,
                  hipStream_t st);
-bool launch_analysis(const Geom& g, const Bands& b, const double2* NL, const double* zonal,
-                     const double2* th_state, double2* Epsi, double2* Eth, hipStream_t st);
+bool launch_analysis(const Geom& g, const Bands& b, const void* NL, const double* zonal,
+                     const double2* th_state, double2* Epsi, double2* Eth, bool mixed,
+                     hipStream_t st);
 
 }  // namespace qg

@@ -53,6 +53,37 @@ __device__ __forceinline__ void opaque(double& s, int& k) {
   asm volatile("" : "+v"(s), "+v"(k));
 }
 
+// FP64 <-> transform precision
+template <typename C> __device__ __forceinline__ C to_c(double2 v);
+template <> __device__ __forceinline__ double2 to_c<double2>(double2 v) { return v; }
+template <> __device__ __forceinline__ float2 to_c<float2>(double2 v) {
+  return make_float2((float)v.x, (float)v.y);
+}
+__device__ __forceinline__ double2 to_d2(double2 v) { return v; }
+__device__ __forceinline__ double2 to_d2(float2 v) { return make_double2(v.x, v.y); }
+template <typename C> __device__ __forceinline__ C zc() { return to_c<C>(make_double2(0.0, 0.0)); }
+
+// Twiddle tables of the transform precision.
+template <typename C> struct Tw;
+template <> struct Tw<double2> {
+  static __device__ __forceinline__ const double2* dct(const Geom& g) { return g.tw_dct; }
+  static __device__ __forceinline__ const double2* phi(const Geom& g) { return g.tw_phi; }
+  static __device__ __forceinline__ const double2* half(const Geom& g) { return g.tw_half; }
+  static __device__ __forceinline__ const double2* w(const Geom& g) { return g.w_phi; }
+};
+template <> struct Tw<float2> {
+  static __device__ __forceinline__ const float2* dct(const Geom& g) { return g.tw_dct32; }
+  static __device__ __forceinline__ const float2* phi(const Geom& g) { return g.tw_phi32; }
+  static __device__ __forceinline__ const float2* half(const Geom& g) { return g.tw_half32; }
+  static __device__ __forceinline__ const float2* w(const Geom& g) { return g.w_phi32; }
+};
+
+// Byte offset of the FP64 coefficient buffer after n transform slots.
+template <typename C>
+constexpr size_t coef_offset(int slots) {
+  return ((size_t)slots * sizeof(C) + 15) / 16 * 16;
+}
+
 __device__ __forceinline__ double2 shfl_down2(double2 v, int off) {
   return make_double2(__shfl_down(v.x, off), __shfl_down(v.y, off));
 }
@@ -61,9 +92,9 @@ __device__ __forceinline__ double2 shfl_down2(double2 v, int off) {
 template <int n, int T>
 constexpr int out_count() { return (n + T - 1) / T; }
 
-template <int n, int T, int SGN, typename Get>
-__device__ __forceinline__ void fft_out(Get get, double2* buf, const double2* __restrict__ tw,
-                                        double2 (&out)[out_count<n, T>()]) {
+template <int n, int T, int SGN, typename C, typename Get>
+__device__ __forceinline__ void fft_out(Get get, C* buf, const C* __restrict__ tw,
+                                        C (&out)[out_count<n, T>()]) {
   if constexpr (reg_out_ok<n, T>()) {
     fft_to_regs<n, T, SGN>(get, buf, tw, out);
   } else {
@@ -71,7 +102,7 @@ __device__ __forceinline__ void fft_out(Get get, double2* buf, const double2* __
 #pragma unroll
     for (int i = 0; i < out_count<n, T>(); ++i) {
       const int k = threadIdx.x + i * T;
-      out[i] = (k < n) ? buf[lds_pad(k)] : z2();
+      out[i] = (k < n) ? buf[lds_pad(k)] : zc<C>();
     }
   }
 }
@@ -161,10 +192,10 @@ __device__ double block_max(double v, double* red) {
 // coefficient row a_n (n < K) is the FFT of the even extension e_0 = a_0,
 // e_n = e_{2N-n} = a_n / 2 (eq. cheb).  Thread t owns the radial points
 // k = t + i T, and the fields are accumulated derivative by derivative.
-template <int N2, int T>
+template <int N2, int T, typename C>
 __global__ __launch_bounds__(T) void synth_kernel(Geom g, const double2* __restrict__ psi,
                                                   const double2* __restrict__ th,
-                                                  double2* __restrict__ X,
+                                                  C* __restrict__ X,
                                                   double* __restrict__ diag) {
   extern __shared__ double2 sm[];
   __shared__ double2 wred[2 * (T / 64)];
@@ -176,15 +207,15 @@ __global__ __launch_bounds__(T) void synth_kernel(Geom g, const double2* __restr
   const int t = threadIdx.x;
   const int m = xcd_index(M);
   if (m >= M) return;
-  double2* fb = sm;
-  double2* c = sm + lds_slots(N2);
-  auto ext = [&](int i) -> double2 {
+  C* fb = reinterpret_cast<C*>(sm);
+  double2* c = reinterpret_cast<double2*>(reinterpret_cast<char*>(sm) + coef_offset<C>(lds_slots(N2)));
+  auto ext = [&](int i) -> C {
     const int nn = (i <= N) ? i : N2 - i;
-    if (nn >= K) return z2();
+    if (nn >= K) return zc<C>();
     const double2 v = c[nn];
-    return nn == 0 ? v : scl2(0.5, v);
+    return to_c<C>(nn == 0 ? v : scl2(0.5, v));
   };
-  auto store = [&](int f, int k, double2 v) { X[((size_t)f * R + k) * M + m] = v; };
+  auto store = [&](int f, int k, double2 v) { X[((size_t)f * R + k) * M + m] = to_c<C>(v); };
 
   const double dm = (double)m, m2 = dm * dm, so2 = g.s_o * g.s_o;
   double sk[NP];
@@ -202,8 +233,8 @@ __global__ __launch_bounds__(T) void synth_kernel(Geom g, const double2* __restr
 #pragma unroll 1
   for (int d = 0; d < nder; ++d) {
     if (d > 0) cheb_deriv_inplace<T>(c, K, wred);
-    double2 P[E];
-    fft_out<N2, T, -1>(ext, fb, g.tw_dct, P);
+    C P[E];
+    fft_out<N2, T, -1>(ext, fb, Tw<C>::dct(g), P);
 #pragma unroll
     for (int i = 0; i < NP; ++i) {
       int k = t + i * T;
@@ -211,7 +242,7 @@ __global__ __launch_bounds__(T) void synth_kernel(Geom g, const double2* __restr
       double s = sk[i];
       opaque(s, k);
       const double is = 1.0 / s, h2 = so2 - s * s, h2s = h2 * is;
-      const double2 p = P[i];
+      const double2 p = to_d2(P[i]);
       if (m > 0) {
         const double mh = m2 * h2 * is * is;
         if (d == 0) {
@@ -264,8 +295,8 @@ __global__ __launch_bounds__(T) void synth_kernel(Geom g, const double2* __restr
 #pragma unroll 1
   for (int d = 0; d < 2; ++d) {
     if (d > 0) cheb_deriv_inplace<T>(c, K, wred);
-    double2 P[E];
-    fft_out<N2, T, -1>(ext, fb, g.tw_dct, P);
+    C P[E];
+    fft_out<N2, T, -1>(ext, fb, Tw<C>::dct(g), P);
 #pragma unroll
     for (int i = 0; i < NP; ++i) {
       int k = t + i * T;
@@ -273,7 +304,7 @@ __global__ __launch_bounds__(T) void synth_kernel(Geom g, const double2* __restr
       double s = sk[i];
       opaque(s, k);
       const double is = 1.0 / s, h2s = (so2 - s * s) * is;
-      const double2 p = P[i];
+      const double2 p = to_d2(P[i]);
       if (d == 0) {
         store(5, k, ix(dm, p));
         if (diag) et += (m > 0 ? 2.0 : 1.0) * g.wq[k] * (m > 0 ? abs2(p) : p.x * p.x);
@@ -319,12 +350,14 @@ __global__ __launch_bounds__(T) void synth_kernel(Geom g, const double2* __restr
 // many orders of magnitude, so the two never share one complex transform).
 // Zonal forcing: mean(u_s omega) = 2 sum_{m>=1} Re(u_s,m conj(omega_m)) with
 // u_s,m = (h^2/s) X0_m and omega_m = X3_m / (i m).
-template <int NPHI, int T>
-__global__ __launch_bounds__(T) void ring_kernel(Geom g, const double2* __restrict__ X,
-                                                 double2* __restrict__ NL,
+template <int NPHI, int T, typename C>
+__global__ __launch_bounds__(T) void ring_kernel(Geom g, const C* __restrict__ X,
+                                                 C* __restrict__ NL,
                                                  double* __restrict__ zonal,
                                                  double* __restrict__ rate) {
-  extern __shared__ double2 fb[];
+  using RT = fftd::real_t<C>;
+  extern __shared__ double2 sm[];
+  C* fb = reinterpret_cast<C*>(sm);
   __shared__ double red[T / 64];
   constexpr int E = out_count<NPHI, T>();
   constexpr int NH = NPHI / 2;
@@ -334,38 +367,38 @@ __global__ __launch_bounds__(T) void ring_kernel(Geom g, const double2* __restri
   if (k >= R) return;
   const double s = g.half * g.xk[k] + g.mid;
   const double h2s = (g.s_o * g.s_o - s * s) / s;
-  const double2* X0 = X + (size_t)k * M;
-  double2 z1[E];
-  double nw[E], nt[E];
+  const C* X0 = X + (size_t)k * M;
+  C z1[E];
+  RT nw[E], nt[E];
   double zs = 0.0, rmax = 0.0;
 #pragma unroll
   for (int q = 0; q < 3; ++q) {
-    const double2* A = X + ((size_t)(2 * q) * R + k) * M;
-    const double2* B = X + ((size_t)(2 * q + 1) * R + k) * M;
-    auto get = [&](int i) -> double2 {
+    const C* A = X + ((size_t)(2 * q) * R + k) * M;
+    const C* B = X + ((size_t)(2 * q + 1) * R + k) * M;
+    auto get = [&](int i) -> C {
       if (i < M) {
-        const double2 a = A[i], b = B[i];
+        const C a = A[i], b = B[i];
         if (q == 1 && i > 0) {
-          const double2 x0 = X0[i];
-          zs += (x0.y * b.x - x0.x * b.y) / (double)i;
+          const C x0 = X0[i];
+          zs += ((double)x0.y * b.x - (double)x0.x * b.y) / (double)i;
         }
-        return (i == 0) ? make_double2(a.x, b.x) : make_double2(a.x - b.y, a.y + b.x);
+        return (i == 0) ? fftd::mk<C>(a.x, b.x) : fftd::mk<C>(a.x - b.y, a.y + b.x);
       }
       if (i > NPHI - M) {
-        const double2 a = A[NPHI - i], b = B[NPHI - i];
-        return make_double2(a.x + b.y, b.x - a.y);
+        const C a = A[NPHI - i], b = B[NPHI - i];
+        return fftd::mk<C>(a.x + b.y, b.x - a.y);
       }
-      return z2();
+      return zc<C>();
     };
-    double2 z[E];
-    fft_out<NPHI, T, +1>(get, fb, g.tw_phi, z);
+    C z[E];
+    fft_out<NPHI, T, +1>(get, fb, Tw<C>::phi(g), z);
 #pragma unroll
     for (int i = 0; i < E; ++i) {
       if (q == 0) {
         z1[i] = z[i];
         if (rate)
-          rmax = fmax(rmax, fmax(h2s * fabs(z[i].x) / g.dsk[k],
-                                 fabs(z[i].y) * NPHI / (2.0 * 3.14159265358979323846)));
+          rmax = fmax(rmax, fmax(h2s * fabs((double)z[i].x) / g.dsk[k],
+                                 fabs((double)z[i].y) * NPHI / (2.0 * 3.14159265358979323846)));
       } else if (q == 1) {
         nw[i] = z1[i].x * z[i].x + z1[i].y * z[i].y;
       } else {
@@ -373,9 +406,9 @@ __global__ __launch_bounds__(T) void ring_kernel(Geom g, const double2* __restri
       }
     }
   }
-  // real products: N_omega at doubles [0, NPHI), N_theta at [NPHI, 2 NPHI)
+  // real products: N_omega at [0, NPHI), N_theta at [NPHI, 2 NPHI) (reals)
   __syncthreads();
-  double* fr = reinterpret_cast<double*>(fb);
+  RT* fr = reinterpret_cast<RT*>(fb);
 #pragma unroll
   for (int i = 0; i < E; ++i) {
     const int j = t + i * T;
@@ -385,22 +418,22 @@ __global__ __launch_bounds__(T) void ring_kernel(Geom g, const double2* __restri
     }
   }
   __syncthreads();
-  const double2* zin = fb;
-  fft_to_lds<NH, T, -1, 2>([&](int ii) { return zin[ii]; }, fb, g.tw_half);
-  const double inv = 1.0 / NPHI;
+  const C* zin = fb;
+  fft_to_lds<NH, T, -1, 2>([&](int ii) { return zin[ii]; }, fb, Tw<C>::half(g));
+  const RT inv = (RT)1.0 / (RT)NPHI;
   for (int m = t; m < M; m += T) {
-    const double2 w = g.w_phi[m];
+    const C w = Tw<C>::w(g)[m];
 #pragma unroll
     for (int f = 0; f < 2; ++f) {
-      double2 zk = fb[lds_pad(f * NH + m)];
-      double2 zc = fb[lds_pad(f * NH + (NH - m) % NH)];
-      zc.y = -zc.y;
-      const double2 e = scl2(0.5, add2(zk, zc));
-      const double2 dd = sub2(zk, zc);
-      const double2 o = make_double2(0.5 * dd.y, -0.5 * dd.x);   // (Z_m - Z*)/(2i)
-      double2 xm = add2(e, make_double2(w.x * o.x - w.y * o.y, w.x * o.y + w.y * o.x));
-      if (m == 0) xm.y = 0.0;
-      NL[((size_t)f * M + m) * R + k] = scl2(inv, xm);
+      C zk = fb[lds_pad(f * NH + m)];
+      C zc_ = fb[lds_pad(f * NH + (NH - m) % NH)];
+      zc_.y = -zc_.y;
+      const C e = fftd::scl((RT)0.5, fftd::add(zk, zc_));
+      const C dd = fftd::sub(zk, zc_);
+      const C o = fftd::mk<C>((RT)0.5 * dd.y, (RT)-0.5 * dd.x);   // (Z_m - Z*)/(2i)
+      C xm = fftd::add(e, fftd::mul(w, o));
+      if (m == 0) xm.y = 0;
+      NL[((size_t)f * M + m) * R + k] = fftd::scl(inv, xm);
     }
   }
   const double tot = block_sum(zs, red);
@@ -418,9 +451,9 @@ __global__ __launch_bounds__(T) void ring_kernel(Geom g, const double2* __restri
 //   all m:  E_th  = -D [ N_theta ]                           (eq. temp_int)
 // Forward DCT-I (eq. icheb): a_n = (h_n / N) FFT(e)_n with the even
 // extension e_i = f_{|i|}, h_0 = 1/2, else 1, kept for n < K.
-template <int N2, int T>
+template <int N2, int T, typename C>
 __global__ __launch_bounds__(T) void analysis_kernel(Geom g, Bands b,
-                                                     const double2* __restrict__ NL,
+                                                     const C* __restrict__ NL,
                                                      const double* __restrict__ zonal,
                                                      const double2* __restrict__ th_state,
                                                      double2* __restrict__ Epsi,
@@ -432,24 +465,24 @@ __global__ __launch_bounds__(T) void analysis_kernel(Geom g, Bands b,
   const int t = threadIdx.x;
   const int m = xcd_index(M);
   if (m >= M) return;
-  double2* fb = sm;
-  double2* c = sm + lds_slots(N2);
+  C* fb = reinterpret_cast<C*>(sm);
+  double2* c = reinterpret_cast<double2*>(reinterpret_cast<char*>(sm) + coef_offset<C>(lds_slots(N2)));
   const double invN = 1.0 / N;
   const double2* thm = th_state + (size_t)m * K;
   const double bcoef = g.Ra_Pr * (double)m / g.s_o;   // (Ra/Pr)(m/s_o), times i
 #pragma unroll
   for (int f = 0; f < 2; ++f) {
-    auto get = [&](int i) -> double2 {
+    auto get = [&](int i) -> C {
       const int kk = (i <= N) ? i : N2 - i;
-      if (f == 0 && m == 0) return make_double2(zonal[kk], 0.0);
+      if (f == 0 && m == 0) return to_c<C>(make_double2(zonal[kk], 0.0));
       return NL[((size_t)f * M + m) * R + kk];
     };
-    double2 o[E];
-    fft_out<N2, T, -1>(get, fb, g.tw_dct, o);
+    C o[E];
+    fft_out<N2, T, -1>(get, fb, Tw<C>::dct(g), o);
 #pragma unroll
     for (int i = 0; i < E; ++i) {
       const int nn = t + i * T;
-      if (nn < K) c[nn] = scl2(nn == 0 ? 0.5 * invN : invN, o[i]);
+      if (nn < K) c[nn] = scl2(nn == 0 ? 0.5 * invN : invN, to_d2(o[i]));
     }
     __syncthreads();
     // band rows: fixed 17 terms (entries outside the matrix are stored as
@@ -491,55 +524,63 @@ void allow_lds(Kern k, size_t bytes) {
                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
 }
 
-template <int N2>
-void synth_n(const Geom& g, const double2* psi, const double2* th, double2* X, double* diag,
+template <typename C>
+size_t dct_lds(int n2, int K) { return coef_offset<C>(lds_slots(n2)) + sizeof(double2) * K; }
+template <typename C>
+size_t phi_lds(int nphi) { return sizeof(C) * lds_slots(nphi); }
+
+template <int N2, typename C>
+void synth_n(const Geom& g, const double2* psi, const double2* th, void* X, double* diag,
              hipStream_t st) {
   constexpr int T = threads_dct(N2);
-  const size_t shm = sizeof(double2) * (lds_slots(N2) + g.K);
-  allow_lds(synth_kernel<N2, T>, shm);
-  hipLaunchKernelGGL((synth_kernel<N2, T>), dim3(xcd_grid(g.M)), dim3(T), shm, st, g, psi, th, X,
-                     diag);
+  const size_t shm = dct_lds<C>(N2, g.K);
+  allow_lds(synth_kernel<N2, T, C>, shm);
+  hipLaunchKernelGGL((synth_kernel<N2, T, C>), dim3(xcd_grid(g.M)), dim3(T), shm, st, g, psi, th,
+                     static_cast<C*>(X), diag);
 }
 
-template <int NPHI>
-void ring_n(const Geom& g, const double2* X, double2* NL, double* zonal, double* rate,
-            hipStream_t st) {
+template <int NPHI, typename C>
+void ring_n(const Geom& g, const void* X, void* NL, double* zonal, double* rate, hipStream_t st) {
   constexpr int T = threads_phi(NPHI);
-  const size_t shm = sizeof(double2) * lds_slots(NPHI);
-  allow_lds(ring_kernel<NPHI, T>, shm);
-  hipLaunchKernelGGL((ring_kernel<NPHI, T>), dim3(xcd_grid(g.R)), dim3(T), shm, st, g, X, NL,
-                     zonal, rate);
+  const size_t shm = phi_lds<C>(NPHI);
+  allow_lds(ring_kernel<NPHI, T, C>, shm);
+  hipLaunchKernelGGL((ring_kernel<NPHI, T, C>), dim3(xcd_grid(g.R)), dim3(T), shm, st, g,
+                     static_cast<const C*>(X), static_cast<C*>(NL), zonal, rate);
 }
 
-template <int N2>
-void analysis_n(const Geom& g, const Bands& b, const double2* NL, const double* zonal,
+template <int N2, typename C>
+void analysis_n(const Geom& g, const Bands& b, const void* NL, const double* zonal,
                 const double2* th, double2* Ep, double2* Et, hipStream_t st) {
   constexpr int T = threads_dct(N2);
-  const size_t shm = sizeof(double2) * (lds_slots(N2) + g.K);
-  allow_lds(analysis_kernel<N2, T>, shm);
-  hipLaunchKernelGGL((analysis_kernel<N2, T>), dim3(xcd_grid(g.M)), dim3(T), shm, st, g, b, NL,
-                     zonal, th, Ep, Et);
+  const size_t shm = dct_lds<C>(N2, g.K);
+  allow_lds(analysis_kernel<N2, T, C>, shm);
+  hipLaunchKernelGGL((analysis_kernel<N2, T, C>), dim3(xcd_grid(g.M)), dim3(T), shm, st, g, b,
+                     static_cast<const C*>(NL), zonal, th, Ep, Et);
 }
 
-#define QG_DCT_SIZES(X) X(32) X(64) X(128) X(256) X(512) X(1024) X(2048) X(4096)
-#define QG_PHI_SIZES(X) X(24) X(48) X(96) X(192) X(384) X(768) X(1536) X(3072) X(6144)
+// Compiled lengths: FP64 up to 2 (N_r - 1) = 4096 and N_phi = 6144 (the LDS
+// bound of the FP64 rings), FP32 up to 8192 and 12288.
+#define QG_DCT64(X) X(32) X(64) X(128) X(256) X(512) X(1024) X(2048) X(4096)
+#define QG_PHI64(X) X(24) X(48) X(96) X(192) X(384) X(768) X(1536) X(3072) X(6144)
+#define QG_DCT32(X) QG_DCT64(X) X(8192)
+#define QG_PHI32(X) QG_PHI64(X) X(12288)
 
 }  // namespace
 
-bool transform_sizes_ok(int n2, int nphi) {
+bool transform_sizes_ok(int n2, int nphi, bool mixed) {
   bool a = false, b = false;
 #define QG_CASE(n) a = a || (n2 == n);
-  QG_DCT_SIZES(QG_CASE)
+  if (mixed) { QG_DCT32(QG_CASE) } else { QG_DCT64(QG_CASE) }
 #undef QG_CASE
 #define QG_CASE(n) b = b || (nphi == n);
-  QG_PHI_SIZES(QG_CASE)
+  if (mixed) { QG_PHI32(QG_CASE) } else { QG_PHI64(QG_CASE) }
 #undef QG_CASE
   return a && b;
 }
 
-size_t transform_lds_bytes(int n2, int nphi, int K) {
-  const size_t d = sizeof(double2) * (lds_slots(n2) + K);
-  const size_t p = sizeof(double2) * lds_slots(nphi);
+size_t transform_lds_bytes(int n2, int nphi, int K, bool mixed) {
+  const size_t d = mixed ? dct_lds<float2>(n2, K) : dct_lds<double2>(n2, K);
+  const size_t p = mixed ? phi_lds<float2>(nphi) : phi_lds<double2>(nphi);
   return d > p ? d : p;
 }
 
@@ -558,31 +599,58 @@ std::vector<double2> plan_twiddles(int n) {
   return tw;
 }
 
-bool launch_synth(const Geom& g, const double2* psi, const double2* th, double2* X, double* diag,
-                  hipStream_t st) {
-  switch (2 * (g.R - 1)) {
-#define QG_CASE(n) case n: synth_n<n>(g, psi, th, X, diag, st); return true;
-    QG_DCT_SIZES(QG_CASE)
+bool launch_synth(const Geom& g, const double2* psi, const double2* th, void* X, double* diag,
+                  bool mixed, hipStream_t st) {
+  const int n2 = 2 * (g.R - 1);
+  if (mixed) {
+    switch (n2) {
+#define QG_CASE(n) case n: synth_n<n, float2>(g, psi, th, X, diag, st); return true;
+      QG_DCT32(QG_CASE)
+#undef QG_CASE
+      default: return false;
+    }
+  }
+  switch (n2) {
+#define QG_CASE(n) case n: synth_n<n, double2>(g, psi, th, X, diag, st); return true;
+    QG_DCT64(QG_CASE)
 #undef QG_CASE
     default: return false;
   }
 }
 
-bool launch_ring(const Geom& g, const double2* X, double2* NL, double* zonal, double* rate,
+bool launch_ring(const Geom& g, const void* X, void* NL, double* zonal, double* rate, bool mixed,
                  hipStream_t st) {
+  if (mixed) {
+    switch (g.nphi) {
+#define QG_CASE(n) case n: ring_n<n, float2>(g, X, NL, zonal, rate, st); return true;
+      QG_PHI32(QG_CASE)
+#undef QG_CASE
+      default: return false;
+    }
+  }
   switch (g.nphi) {
-#define QG_CASE(n) case n: ring_n<n>(g, X, NL, zonal, rate, st); return true;
-    QG_PHI_SIZES(QG_CASE)
+#define QG_CASE(n) case n: ring_n<n, double2>(g, X, NL, zonal, rate, st); return true;
+    QG_PHI64(QG_CASE)
 #undef QG_CASE
     default: return false;
   }
 }
 
-bool launch_analysis(const Geom& g, const Bands& b, const double2* NL, const double* zonal,
-                     const double2* th_state, double2* Epsi, double2* Eth, hipStream_t st) {
-  switch (2 * (g.R - 1)) {
-#define QG_CASE(n) case n: analysis_n<n>(g, b, NL, zonal, th_state, Epsi, Eth, st); return true;
-    QG_DCT_SIZES(QG_CASE)
+bool launch_analysis(const Geom& g, const Bands& b, const void* NL, const double* zonal,
+                     const double2* th_state, double2* Epsi, double2* Eth, bool mixed,
+                     hipStream_t st) {
+  const int n2 = 2 * (g.R - 1);
+  if (mixed) {
+    switch (n2) {
+#define QG_CASE(n) case n: analysis_n<n, float2>(g, b, NL, zonal, th_state, Epsi, Eth, st); return true;
+      QG_DCT32(QG_CASE)
+#undef QG_CASE
+      default: return false;
+    }
+  }
+  switch (n2) {
+#define QG_CASE(n) case n: analysis_n<n, double2>(g, b, NL, zonal, th_state, Epsi, Eth, st); return true;
+    QG_DCT64(QG_CASE)
 #undef QG_CASE
     default: return false;
   }

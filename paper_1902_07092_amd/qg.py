@@ -161,11 +161,12 @@ class QGSolver:
     """One solver context on a HIP device, workspace allocated by torch."""
 
     def __init__(self, E, Ra, Pr, eta, n_phi, n_r, n_c=0, device="cuda:0",
-                 stream=None, pivoting=0):
+                 stream=None, pivoting=0, precision=0):
         import torch
         self.torch = torch
         self.device = torch.device(device)
-        self.params = qg_params(E, Ra, Pr, eta, n_phi, n_r, n_c, 0, pivoting)
+        self.params = qg_params(E, Ra, Pr, eta, n_phi, n_r, n_c, precision,
+                                pivoting)
         self.M = n_phi // 3 + 1
         self.K = n_c if n_c else (2 * (n_r - 1)) // 3
         nbytes = qg_workspace_size(self.params)

@@ -3,7 +3,8 @@ the oracle for each GPU parity case, measured by re-running the oracle with
 rounding-level noise injected into every transform and derivative.
 
 A backward-stable transform (FFT, DCT, coefficient recurrence) returns y
-with |y - y_exact| <= c u ||y||, u = 2^-53.  Two correct FP64
+with |y - y_exact| <= c u ||y||, u = 2^-53 (2^-24 for the FP32 transforms
+of the mixed-precision step).  Two correct FP64
 implementations therefore differ by noise of that size at each transform;
 the step then propagates it.  The floor of a field is
 max over seeds of max|y_noisy - y| / max|y| after the case's steps.  The
@@ -26,6 +27,7 @@ from oracle.step import QGOracle  # noqa: E402
 from paper_1902_07092_amd import inputs  # noqa: E402
 
 U = 2.0 ** -53
+U32 = 2.0 ** -24
 CASES = {
     "small_cnab2_1": ("SMALL", "cnab2", 1),
     "small_cnab2_20": ("SMALL", "cnab2", 20),
@@ -34,29 +36,36 @@ CASES = {
     "medium_bpr353_2": ("MEDIUM", "bpr353", 2),
     "large_cnab2_2": ("LARGE", "cnab2", 2),
 }
+# Mixed precision (FP32 transforms and products): the same measurement with
+# u = 2^-24; the mixed-precision tests accept 30 x this floor.
+CASES32 = {
+    "mixed_small_cnab2_50": ("SMALL", "cnab2", 50),
+    "mixed_medium_bpr353_1": ("MEDIUM", "bpr353", 1),
+    "mixed_large_cnab2_1": ("LARGE", "cnab2", 1),
+}
 WRAPPED = ("cheb_to_grid", "grid_to_cheb", "phi_to_grid", "grid_to_phi",
            "cheb_ds")
 
 
-def _noisy(fn, rng):
+def _noisy(fn, rng, u):
     def wrapped(*a, **k):
         y = fn(*a, **k)
         scale = np.abs(y).max(axis=-1, keepdims=True)
         noise = rng.standard_normal(y.shape)
         if np.iscomplexobj(y):
             noise = noise + 1j * rng.standard_normal(y.shape)
-        return y + U * scale * noise
+        return y + u * scale * noise
     return wrapped
 
 
-def run(name, scheme, steps, seed):
+def run(name, scheme, steps, seed, u=U):
     w = getattr(inputs, name)
     st = inputs.workload_state(w)
     orig = {f: getattr(tr, f) for f in WRAPPED}
     if seed is not None:
         rng = np.random.default_rng(seed)
         for f in WRAPPED:
-            setattr(tr, f, _noisy(orig[f], rng))
+            setattr(tr, f, _noisy(orig[f], rng, u))
     try:
         o = QGOracle(w.E, w.Ra, w.Pr, w.eta, w.n_phi, w.n_r, w.n_c)
         o.set_state(st.psi, st.theta, st.uphi0)
@@ -67,22 +76,35 @@ def run(name, scheme, steps, seed):
     return o
 
 
+def floors(name, scheme, steps, u):
+    ref = run(name, scheme, steps, None)
+    floor = {"psi": 0.0, "theta": 0.0, "uphi": 0.0}
+    for seed in (1, 2):
+        o = run(name, scheme, steps, seed, u)
+        for f in floor:
+            a, b = getattr(o, f), getattr(ref, f)
+            sc = np.abs(b).max()
+            if sc > 0:
+                floor[f] = max(floor[f], float(np.abs(a - b).max() / sc))
+    return floor
+
+
 def main(only=None):
     path = os.path.join(HERE, "parity_tolerances.json")
     out = json.load(open(path)) if os.path.exists(path) else {}
     for case, (name, scheme, steps) in CASES.items():
         if only and case not in only:
             continue
-        ref = run(name, scheme, steps, None)
-        floor = {"psi": 0.0, "theta": 0.0, "uphi": 0.0}
-        for seed in (1, 2):
-            o = run(name, scheme, steps, seed)
-            for f in floor:
-                a, b = getattr(o, f), getattr(ref, f)
-                sc = np.abs(b).max()
-                if sc > 0:
-                    floor[f] = max(floor[f], float(np.abs(a - b).max() / sc))
+        floor = floors(name, scheme, steps, U)
         tol = {f: max(1e-11, 10.0 * v) for f, v in floor.items()}
+        out[case] = {"floor": floor, "tol": tol}
+        print(case, out[case], flush=True)
+        json.dump(out, open(path, "w"), indent=1, sort_keys=True)
+    for case, (name, scheme, steps) in CASES32.items():
+        if only and case not in only:
+            continue
+        floor = floors(name, scheme, steps, U32)
+        tol = {f: 30.0 * v for f, v in floor.items()}
         out[case] = {"floor": floor, "tol": tol}
         print(case, out[case], flush=True)
         json.dump(out, open(path, "w"), indent=1, sort_keys=True)
