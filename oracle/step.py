@@ -157,12 +157,13 @@ class QGOracle:
         return dict(us=us, uphi=uph, om=om, dom=dom, th=T[0], dth=T[1],
                     dphi_psi=im * P[0])
 
-    def explicit(self, psi, theta, uphi):
-        """Explicit right-hand sides (K-vectors, rows >= q meaningful):
-        E_psi = C[(Ra/Pr)(i m/s_o) theta + N_omega], E_theta = -D[N_theta],
-        E_u = -D[N_uphi]."""
+    def advection_grid(self, psi, theta, uphi):
+        """Advection terms on the (N_r, N_phi) grid, eqs. vort, uphi, temp:
+        N_omega = div(u omega), N_theta = u.grad(theta) + u_s dT_c/ds
+        (div(u theta) + beta u_s theta = u.grad(theta) by eq. cont) and the
+        zonal forcing mean_phi(u_s omega); also u_s and theta on the grid."""
         f = self.spectral_fields(psi, theta, uphi)
-        M, K, n_phi = self.M, self.K, self.n_phi
+        n_phi = self.n_phi
         im = 1j * self.mvec[:, None]
 
         def to_grid(c):          # (M, R) -> (R, N_phi), eq. (fft)
@@ -177,6 +178,16 @@ class QGOracle:
         n_om = us * dom + uph / s * dpom + om * divu
         n_th = us * (dth + self.dtc[:, None]) + uph / s * dpth
         n_u = np.mean(us * om, axis=1)
+        return dict(n_om=n_om, n_th=n_th, n_u=n_u, us=us, th=th)
+
+    def explicit(self, psi, theta, uphi):
+        """Explicit right-hand sides (K-vectors, rows >= q meaningful):
+        E_psi = C[(Ra/Pr)(i m/s_o) theta + N_omega], E_theta = -D[N_theta],
+        E_u = -D[N_uphi]."""
+        a = self.advection_grid(psi, theta, uphi)
+        n_om, n_th, n_u = a["n_om"], a["n_th"], a["n_u"]
+        M, K = self.M, self.K
+        im = 1j * self.mvec[:, None]
 
         def to_spec(g):          # (R, N_phi) -> (M, K), eq. (ifft), (icheb)
             return tr.grid_to_cheb(tr.grid_to_phi(g, M).T, K)

@@ -181,3 +181,53 @@ def test_inputs_satisfy_boundary_conditions():
             scale = np.abs(rows) @ np.abs(a).T
             assert np.all(np.abs(rows @ a.T) <= 1e-14 * scale + 1e-300)
         assert np.all(st.psi[0] == 0) and np.all(st.theta[0].imag == 0)
+
+
+def _smooth_state(o, seed):
+    """Random Psi, theta on the App. B bases with coefficients decaying like
+    exp(-(m + n)/4), so that grid quadrature is converged."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    m = np.arange(o.M)[:, None]
+    n = np.arange(o.K)[None, :]
+    env = np.exp(-(m + n) / 4.0)
+    cp = env * (rng.standard_normal((o.M, o.K))
+                + 1j * rng.standard_normal((o.M, o.K)))
+    ct = env * (rng.standard_normal((o.M, o.K))
+                + 1j * rng.standard_normal((o.M, o.K)))
+    cp[0] = 0
+    ct[0] = ct[0].real
+    return (inputs.psi_from_basis(cp, o.K),
+            inputs.dirichlet_from_basis(ct, o.K))
+
+
+def test_advection_conserves_height_weighted_invariants():
+    """Sect. 2: h u is solenoidal (eq. cont), h u = curl(chi e_z) with
+    chi = h psi = h^3 Psi, and the kinetic energy (1/2) int h |u|^2 changes
+    under the flux-form advection of eq. vort by -int chi div(u omega),
+    which vanishes because u . grad(chi) = 0 pointwise; likewise
+    int h theta u.grad(theta) = 0 for eq. temp.  Both integrals of the
+    oracle's grid advection terms must vanish to quadrature accuracy; a
+    dropped or mis-signed term (e.g. omega div u, whose own integral is
+    ~1e-3 of the scale) breaks them by orders of magnitude."""
+    o = QGOracle(1e-3, 1.0, 1.0, 0.35, 96, 97)
+    psi, theta = _smooth_state(o, 11)
+    a = o.advection_grid(psi, theta, np.zeros(o.K))
+    h2 = (o.s_o**2 - o.s**2)[:, None]
+    h = np.sqrt(h2)
+    chi = h2 * h * tr.phi_to_grid(tr.cheb_to_grid(psi, o.n_r).T, o.n_phi)
+    w = (grid.clenshaw_curtis(o.n_r) * 0.5 * (o.s_o - o.s_i) * o.s)[:, None]
+    e_rate = np.sum(w * chi * a["n_om"])
+    e_scale = np.sum(w * np.abs(chi * a["n_om"]))
+    assert abs(e_rate) <= 1e-8 * e_scale, e_rate / e_scale
+    adv = a["n_th"] - a["us"] * o.dtc[:, None]
+    t_rate = np.sum(w * h * a["th"] * adv)
+    t_scale = np.sum(w * np.abs(h * a["th"] * adv))
+    assert abs(t_rate) <= 1e-8 * t_scale, t_rate / t_scale
+    # the test has teeth: without the compressible term omega div u
+    # (= omega dPsi/dphi) the energy integral is far from zero
+    om = tr.phi_to_grid(o.spectral_fields(psi, theta, np.zeros(o.K))["om"].T,
+                        o.n_phi)
+    divu = tr.phi_to_grid((1j * o.mvec[:, None] * tr.cheb_to_grid(
+        psi, o.n_r)).T, o.n_phi)
+    broken = np.sum(w * chi * (a["n_om"] - om * divu))
+    assert abs(broken) > 1e4 * 1e-8 * e_scale
