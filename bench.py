@@ -2,8 +2,10 @@
 """Benchmark of the FP64 IMEX step of spherical QG convection on one GPU.
 
 Workload (default): 3072 x 1025 grid (N_m = 1024, N_c = 682), E = 1e-8,
-Pr = 1, Ra = 20 Ra_c, CNAB2, dt = 3e-9, seeded turbulent-like initial
-state (k^-5/3 spectrum, random phases).  A step is one CNAB2 step of the
+Pr = 1, Ra = 20 Ra_c, CNAB2, dt = 1e-9, seeded turbulent-like initial
+state (k^-5/3 spectrum steepening past m ~ 20, random phases, Re = 1e4).
+Beside it: the same steps with FP32 transforms and products, and the
+batched ensemble of 64 runs of uneven size and Ra.  A step is one CNAB2 step of the
 whole hot path: Chebyshev synthesis, azimuthal FFTs and products, radial
 analysis, explicit terms, right-hand sides and the bordered solves of every
 m.  The state is resident in HBM before the timed region; the time-step
@@ -154,6 +156,55 @@ def mixed_run(qg, torch, w, state, args, fp64_solver):
                             "launches": v[1]} for k, v in kern.items()}}
 
 
+def ensemble_run(qg, torch, inputs, args):
+    """The batched ensemble: 64 runs of uneven size and Ra stepped together
+    (one launch per kernel and size group, graph replay), against the same
+    runs stepped one context after another."""
+    ws = inputs.ensemble_workloads()
+    members = [dict(E=w.E, Ra=w.Ra, Pr=w.Pr, eta=w.eta, n_phi=w.n_phi,
+                    n_r=w.n_r, n_c=w.n_c) for w in ws]
+    states = [inputs.workload_state(w) for w in ws]
+    ens = qg.QGEnsemble(members)
+    for i, st in enumerate(states):
+        ens.set_state(i, st.psi, st.theta, st.uphi0)
+    dt = ws[0].dt
+    ens.step(dt, "cnab2", args.warmup)
+    torch.cuda.synchronize()
+    start = torch.cuda.Event(enable_timing=True)
+    stop = torch.cuda.Event(enable_timing=True)
+    start.record(ens.stream)
+    ens.step(dt, "cnab2", args.ens_steps)
+    stop.record(ens.stream)
+    torch.cuda.synchronize()
+    ms = start.elapsed_time(stop) / args.ens_steps
+    gp = sum(w.grid_points for w in ws)
+    bad = [i for i in range(len(ws)) if ens.diagnostics(i)["nonfinite"]]
+    # the same runs, one single-run context after another
+    solos = []
+    for w, st in zip(ws, states):
+        s = qg.QGSolver(w.E, w.Ra, w.Pr, w.eta, w.n_phi, w.n_r, w.n_c,
+                        device="cuda:0")
+        s.set_state(st.psi, st.theta, st.uphi0)
+        s.step(dt, "cnab2", args.warmup)
+        solos.append(s)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for s in solos:
+        s.step(dt, "cnab2", args.ens_steps)
+    torch.cuda.synchronize()
+    solo_ms = (time.perf_counter() - t0) * 1e3 / args.ens_steps
+    sizes = {}
+    for w in ws:
+        sizes[f"{w.n_phi}x{w.n_r}"] = sizes.get(f"{w.n_phi}x{w.n_r}", 0) + 1
+    return {"value": gp / (ms * 1e-3), "unit": "grid-point-steps/s",
+            "ms_per_step": ms, "members": len(ws), "sizes": sizes,
+            "grid_points_per_step": gp, "steps": args.ens_steps,
+            "nonfinite_members": bad,
+            "one_context_after_another": {
+                "value": gp / (solo_ms * 1e-3), "ms_per_step": solo_ms,
+                "timing": "host clock around all contexts' steps"}}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -164,6 +215,9 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-mixed", action="store_true",
                     help="skip the mixed-precision run")
+    ap.add_argument("--no-ensemble", action="store_true",
+                    help="skip the batched-ensemble run")
+    ap.add_argument("--ens-steps", type=int, default=20)
     ap.add_argument("--precision", choices=("fp64", "mixed"), default="fp64",
                     help="precision of the headline run (mixed also runs the "
                          "12288 x 4097 workload, which FP64 does not fit)")
@@ -243,6 +297,10 @@ def main():
         out["mixed"] = mixed_run(qg, torch, w, state, args, solver)
         print(f"[bench] mixed done: {out['mixed']['ms_per_step']:.4f} ms/step",
               file=sys.stderr, flush=True)
+    if not args.no_ensemble and prec == 0:
+        out["batched"] = ensemble_run(qg, torch, inputs, args)
+        print(f"[bench] ensemble done: {out['batched']['ms_per_step']:.4f} "
+              "ms/step", file=sys.stderr, flush=True)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(w, state, args.cpu_steps)
     print(json.dumps(out), flush=True)

@@ -154,6 +154,61 @@ const char *qg_last_error(const qg_ctx *ctx);
 /* Release the context (not the caller's workspace). */
 void qg_destroy(qg_ctx *ctx);
 
+/* ---------------------------------------------------------------------
+ * Ensembles: many runs of the step advanced together (runs of uneven size
+ * and Rayleigh number, as in the paper's range of problem sizes, Sect. 5).
+ * Members that share every parameter except Ra form a group: one launch of
+ * each kernel advances every run of a group (the run is a grid dimension),
+ * and the runs of a group share operators, twiddle tables and LU factors
+ * (the bordered matrices do not depend on Ra, Sect. 3.2 and Appendix A).
+ * Steps after the first are captured once into a HIP graph per (dt,
+ * scheme) and replayed; each member's arithmetic is exactly that of a
+ * single-run context with its parameters, so results are identical to
+ * stepping it alone.
+ */
+typedef struct qg_ensemble qg_ensemble;
+
+/* Device bytes for an ensemble of n members with parameters members[0..n-1]
+ * (each valid for qg_workspace_size).  QG_EINVAL on an invalid member. */
+qg_status qg_ensemble_workspace_size(const qg_params *members, int n,
+                                     size_t *bytes);
+
+/* Create an ensemble on the current device.  workspace: at least
+ * qg_ensemble_workspace_size bytes, 256-byte aligned, caller-owned until
+ * qg_ensemble_destroy.  stream: a hipStream_t; NULL makes the ensemble
+ * create (and later destroy) a stream of its own, since graph capture
+ * needs a stream other than the legacy default one.  States start at
+ * zero. */
+qg_status qg_ensemble_create(qg_ensemble **e, const qg_params *members,
+                             int n, void *workspace, size_t workspace_bytes,
+                             void *stream);
+
+/* Copy member `member`'s state in, with the checks of qg_set_state.  The
+ * ensemble restarts as a whole: time, step counter and the CNAB2 history of
+ * every member are reset, so set every member before stepping. */
+qg_status qg_ensemble_set_state(qg_ensemble *e, int member, const double *psi,
+                                const double *theta, const double *uphi,
+                                int on_device);
+
+/* Copy member `member`'s current state out (as qg_get_state). */
+qg_status qg_ensemble_get_state(qg_ensemble *e, int member, double *psi,
+                                double *theta, double *uphi, int on_device);
+
+/* Advance every member nsteps steps of size dt with the given scheme
+ * (qg_step's rules: refactorisation on a dt change, synchronous; CNAB2's
+ * first step after a restart uses E^{n-1} := E^n).  Asynchronous on the
+ * ensemble's stream otherwise. */
+qg_status qg_ensemble_step(qg_ensemble *e, double dt, int scheme, int nsteps);
+
+/* Diagnostics of member `member` (synchronises the stream). */
+qg_status qg_ensemble_diagnostics(qg_ensemble *e, int member, qg_diag *out);
+
+/* Message of the last error on this ensemble ("" if none). */
+const char *qg_ensemble_last_error(const qg_ensemble *e);
+
+/* Release the ensemble (not the caller's workspace). */
+void qg_ensemble_destroy(qg_ensemble *e);
+
 /* Host-only: the banded integration operators qg_create builds for radius
  * ratio eta and n_c modes (eq. psi_int, uphi_int, temp_int), for checking
  * against a reference without a device.  which = 0..8 selects A0, A2, B0,

@@ -89,6 +89,7 @@ bool sizes_of(const qg_params* p, Sizes& z, std::string& why) {
 }
 
 struct WsMap {
+  size_t ra;
   size_t state, ybuf, eslot, lslot, X, NL, zonal, rate, diag, xk, wq, dsk, twd, twp, twh, wphi,
       twd32, twp32, twh32, wphi32, bands, rhs;
   size_t p_piv, p_L, p_U, p_W, p_C, p_Mi, p_ui;
@@ -96,21 +97,25 @@ struct WsMap {
   size_t total;
 };
 
-WsMap map_workspace(const Sizes& z) {
+// Per-run arrays are sized for nmem runs (run-major inside each array, see
+// Geom); operators, tables and factors are shared by the runs.
+WsMap map_workspace(const Sizes& z, int nmem) {
   Layout L;
   WsMap w;
-  const size_t MK = (size_t)z.M * z.K * sizeof(double2);
-  const size_t RM = (size_t)z.R * z.M * sizeof(double2);
+  const size_t nm = (size_t)nmem;
+  const size_t MK = nm * z.M * z.K * sizeof(double2);
+  const size_t RM = nm * z.R * z.M * sizeof(double2);
   const size_t Sp = z.M - 1;
+  w.ra = L.take(nm * sizeof(double));
   w.state = L.take(2 * MK);
   w.ybuf = L.take(4 * MK);
   w.eslot = L.take(6 * MK);
   w.lslot = L.take(8 * MK);
   w.X = L.take(6 * RM);
   w.NL = L.take(2 * RM);
-  w.zonal = L.take(z.R * sizeof(double));
-  w.rate = L.take(z.R * sizeof(double));
-  w.diag = L.take((size_t)z.M * 8 * sizeof(double));
+  w.zonal = L.take(nm * z.R * sizeof(double));
+  w.rate = L.take(nm * z.R * sizeof(double));
+  w.diag = L.take(nm * z.M * 8 * sizeof(double));
   w.xk = L.take(z.R * sizeof(double));
   w.wq = L.take(z.R * sizeof(double));
   w.dsk = L.take(z.R * sizeof(double));
@@ -123,7 +128,7 @@ WsMap map_workspace(const Sizes& z) {
   w.twh32 = L.take((size_t)z.nphi / 2 * sizeof(float2));
   w.wphi32 = L.take((size_t)(z.nphi / 2 + 1) * sizeof(float2));
   w.bands = L.take((size_t)9 * z.K * BANDW * sizeof(double));
-  w.rhs = L.take((size_t)2 * z.M * z.K * sizeof(double2));
+  w.rhs = L.take(2 * MK);
   w.p_piv = L.take(Sp * z.p4 * sizeof(int));
   w.p_L = L.take(Sp * std::max(z.p4, z.q4) * 8 * sizeof(double2));
   w.p_U = L.take(Sp * std::max(z.p4 * 17, z.q4 * 8) * sizeof(double2));
@@ -149,6 +154,7 @@ struct qg_ctx {
   qg_params p;
   Sizes z;
   WsMap w;
+  int nmem = 1;              // runs stepped together (an ensemble group)
   char* ws = nullptr;
   hipStream_t st = nullptr;
   Operators ops;
@@ -173,10 +179,11 @@ struct qg_ctx {
   std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> ev_marks;
   double2* ptr2(size_t off) { return reinterpret_cast<double2*>(ws + off); }
   double* ptrd(size_t off) { return reinterpret_cast<double*>(ws + off); }
+  size_t mk() const { return (size_t)nmem * z.M * z.K; }   // one field of every run
   double2* psi() { return ptr2(w.state); }
-  double2* th() { return ptr2(w.state) + (size_t)z.M * z.K; }
+  double2* th() { return ptr2(w.state) + mk(); }
   double2* slot(size_t base, int i, int field) {
-    return ptr2(base) + ((size_t)(2 * i + field)) * z.M * z.K;
+    return ptr2(base) + ((size_t)(2 * i + field)) * mk();
   }
 };
 
@@ -579,29 +586,42 @@ qg_status qg_workspace_size(const qg_params* p, size_t* bytes) {
   Sizes z;
   std::string why;
   if (!bytes || !sizes_of(p, z, why)) return QG_EINVAL;
-  *bytes = map_workspace(z).total;
+  *bytes = map_workspace(z, 1).total;
   return QG_OK;
 }
 
-qg_status qg_create(qg_ctx** out, const qg_params* p, void* workspace, size_t workspace_bytes,
-                    void* stream) {
+}  // extern "C"
+
+namespace {
+
+// A context for nmem runs of one size that differ only in Ra (ra[i]; all
+// runs use p->Ra when ra is null).  nmem = 1 is the single-run context.
+qg_status create_ctx(qg_ctx** out, const qg_params* p, int nmem, const double* ra,
+                     void* workspace, size_t workspace_bytes, void* stream) {
   if (!out) return QG_EINVAL;
   *out = nullptr;
   Sizes z;
   std::string why;
-  if (!sizes_of(p, z, why)) return QG_EINVAL;
+  if (!sizes_of(p, z, why) || nmem < 1) return QG_EINVAL;
   const bool mixed = p->precision == 1;
   if (!is_pow2(z.R - 1) || z.nphi % 6 || !transform_sizes_ok(2 * (z.R - 1), z.nphi, mixed))
     return QG_EUNSUPPORTED;
   if (!workspace || ((uintptr_t)workspace & 255)) return QG_EINVAL;
-  WsMap w = map_workspace(z);
+  WsMap w = map_workspace(z, nmem);
   if (workspace_bytes < w.total) return QG_ENOMEM;
+  std::vector<double> ra_pr(nmem);
+  for (int i = 0; i < nmem; ++i) {
+    const double r = ra ? ra[i] : p->Ra;
+    if (!(r > 0) || !std::isfinite(r)) return QG_EINVAL;
+    ra_pr[i] = r / p->Pr;
+  }
 
   qg_ctx* ctx = new qg_ctx();
   ctx->p = *p;
   ctx->p.n_c = z.K;
   ctx->z = z;
   ctx->w = w;
+  ctx->nmem = nmem;
   ctx->ws = static_cast<char*>(workspace);
   ctx->st = static_cast<hipStream_t>(stream);
 
@@ -674,7 +694,8 @@ qg_status qg_create(qg_ctx** out, const qg_params* p, void* workspace, size_t wo
       up(w.twh32, twh32.data(), twh32.size() * 8) != hipSuccess ||
       up(w.wphi32, wphi32.data(), wphi32.size() * 8) != hipSuccess ||
       up(w.bands, bandbuf.data(), bandbuf.size() * 8) != hipSuccess ||
-      hipMemsetAsync(ctx->ws + w.state, 0, 2 * (size_t)z.M * z.K * sizeof(double2), ctx->st) !=
+      up(w.ra, ra_pr.data(), ra_pr.size() * 8) != hipSuccess ||
+      hipMemsetAsync(ctx->ws + w.state, 0, 2 * ctx->mk() * sizeof(double2), ctx->st) !=
           hipSuccess ||
       hipStreamSynchronize(ctx->st) != hipSuccess) {
     delete ctx;
@@ -690,6 +711,8 @@ qg_status qg_create(qg_ctx** out, const qg_params* p, void* workspace, size_t wo
   g.Ra_Pr = p->Ra / p->Pr;
   g.inv_Pr = 1.0 / p->Pr;
   g.two_over_E = 2.0 / p->E;
+  g.nmem = nmem;
+  g.ra_pr = ctx->ptrd(w.ra);
   g.xk = ctx->ptrd(w.xk);
   g.wq = ctx->ptrd(w.wq);
   g.dsk = ctx->ptrd(w.dsk);
@@ -717,9 +740,12 @@ qg_status qg_create(qg_ctx** out, const qg_params* p, void* workspace, size_t wo
   return QG_OK;
 }
 
-qg_status qg_set_state(qg_ctx* ctx, const double* psi, const double* theta, const double* uphi,
-                       int on_device) {
+// State of run `mem` in (resets the time, step counter and multistep
+// history of the whole context) and out.
+qg_status set_state_run(qg_ctx* ctx, int mem, const double* psi, const double* theta,
+                        const double* uphi, int on_device) {
   if (!ctx) return QG_EINVAL;
+  if (mem < 0 || mem >= ctx->nmem) return fail(ctx, QG_EINVAL, "no such run");
   if (!psi || !theta || !uphi) return fail(ctx, QG_EINVAL, "null state pointer");
   const Sizes& z = ctx->z;
   const size_t MK = (size_t)z.M * z.K;
@@ -766,8 +792,10 @@ qg_status qg_set_state(qg_ctx* ctx, const double* psi, const double* theta, cons
   if (!check(hu2.data(), 2, true))
     return fail(ctx, QG_ESTATE, "zonal flow violates the boundary conditions");
   for (int n = 0; n < z.K; ++n) hp[n] = hu2[n];  // row 0 of the psi array holds the zonal flow
-  HIPCHK(hipMemcpyAsync(ctx->psi(), hp.data(), MK * 16, hipMemcpyHostToDevice, ctx->st));
-  HIPCHK(hipMemcpyAsync(ctx->th(), ht.data(), MK * 16, hipMemcpyHostToDevice, ctx->st));
+  HIPCHK(hipMemcpyAsync(ctx->psi() + mem * MK, hp.data(), MK * 16, hipMemcpyHostToDevice,
+                        ctx->st));
+  HIPCHK(hipMemcpyAsync(ctx->th() + mem * MK, ht.data(), MK * 16, hipMemcpyHostToDevice,
+                        ctx->st));
   HIPCHK(hipStreamSynchronize(ctx->st));
   ctx->t = 0.0;
   ctx->step = 0;
@@ -777,13 +805,16 @@ qg_status qg_set_state(qg_ctx* ctx, const double* psi, const double* theta, cons
   return QG_OK;
 }
 
-qg_status qg_get_state(qg_ctx* ctx, double* psi, double* theta, double* uphi, int on_device) {
+qg_status get_state_run(qg_ctx* ctx, int mem, double* psi, double* theta, double* uphi,
+                        int on_device) {
   if (!ctx) return QG_EINVAL;
+  if (mem < 0 || mem >= ctx->nmem) return fail(ctx, QG_EINVAL, "no such run");
   if (!psi || !theta || !uphi) return fail(ctx, QG_EINVAL, "null state pointer");
   const Sizes& z = ctx->z;
   const size_t MK = (size_t)z.M * z.K;
   std::vector<double2> hp(MK);
-  HIPCHK(hipMemcpyAsync(hp.data(), ctx->psi(), MK * 16, hipMemcpyDeviceToHost, ctx->st));
+  HIPCHK(hipMemcpyAsync(hp.data(), ctx->psi() + mem * MK, MK * 16, hipMemcpyDeviceToHost,
+                        ctx->st));
   HIPCHK(hipStreamSynchronize(ctx->st));
   std::vector<double> hu(z.K);
   for (int n = 0; n < z.K; ++n) {
@@ -793,23 +824,36 @@ qg_status qg_get_state(qg_ctx* ctx, double* psi, double* theta, double* uphi, in
   const hipMemcpyKind k1 = on_device ? hipMemcpyHostToDevice : hipMemcpyHostToHost;
   const hipMemcpyKind k2 = on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
   HIPCHK(hipMemcpyAsync(psi, hp.data(), MK * 16, k1, ctx->st));
-  HIPCHK(hipMemcpyAsync(theta, ctx->th(), MK * 16, k2, ctx->st));
+  HIPCHK(hipMemcpyAsync(theta, ctx->th() + mem * MK, MK * 16, k2, ctx->st));
   HIPCHK(hipMemcpyAsync(uphi, hu.data(), z.K * 8, k1, ctx->st));
   HIPCHK(hipStreamSynchronize(ctx->st));
   return QG_OK;
 }
 
-qg_status qg_step(qg_ctx* ctx, double dt, int scheme, int nsteps) {
-  if (!ctx) return QG_EINVAL;
+qg_status check_step_args(qg_ctx* ctx, double dt, int scheme, int nsteps) {
   if (!(dt > 0) || !std::isfinite(dt)) return fail(ctx, QG_EINVAL, "dt must be positive");
   if (scheme != QG_CNAB2 && scheme != QG_BPR353) return fail(ctx, QG_EINVAL, "unknown scheme");
   if (nsteps < 0) return fail(ctx, QG_EINVAL, "nsteps must be >= 0");
+  return QG_OK;
+}
+
+// Factorise for dt if needed (synchronises); drops the multistep history.
+qg_status prepare_dt(qg_ctx* ctx, double dt) {
   const double adt = 0.5 * dt;   // b_0^I of CNAB2 and a_ii of BPR353
   if (adt != ctx->factored_adt) {
     qg_status s = refactor(ctx, adt);
     if (s != QG_OK) return s;
     ctx->have_prev = 0;   // the multistep history belongs to the old dt
   }
+  return QG_OK;
+}
+
+qg_status step_ctx(qg_ctx* ctx, double dt, int scheme, int nsteps) {
+  if (!ctx) return QG_EINVAL;
+  qg_status s0 = check_step_args(ctx, dt, scheme, nsteps);
+  if (s0 != QG_OK) return s0;
+  s0 = prepare_dt(ctx, dt);
+  if (s0 != QG_OK) return s0;
   for (int i = 0; i < nsteps; ++i) {
     qg_status s = (scheme == QG_CNAB2) ? step_cnab2(ctx, dt) : step_bpr353(ctx, dt);
     if (s != QG_OK) return s;
@@ -819,8 +863,10 @@ qg_status qg_step(qg_ctx* ctx, double dt, int scheme, int nsteps) {
   return QG_OK;
 }
 
-qg_status qg_diagnostics(qg_ctx* ctx, qg_diag* out) {
+// Diagnostics of run `mem` (the kernels evaluate every run of the context).
+qg_status diagnostics_run(qg_ctx* ctx, int mem, qg_diag* out) {
   if (!ctx || !out) return QG_EINVAL;
+  if (mem < 0 || mem >= ctx->nmem) return fail(ctx, QG_EINVAL, "no such run");
   const Sizes& z = ctx->z;
   const bool mixed = !ctx->diag64;   // FP64 diagnostics whenever those kernels fit
   if (!launch_synth(ctx->g, ctx->psi(), ctx->th(), ctx->ptr2(ctx->w.X), ctx->ptrd(ctx->w.diag),
@@ -830,10 +876,10 @@ qg_status qg_diagnostics(qg_ctx* ctx, qg_diag* out) {
     return fail(ctx, QG_EUNSUPPORTED, "no transform kernel for these sizes");
   HIPCHK(hipGetLastError());
   std::vector<double> d((size_t)z.M * 8), rate(z.R);
-  HIPCHK(hipMemcpyAsync(d.data(), ctx->ptrd(ctx->w.diag), d.size() * 8, hipMemcpyDeviceToHost,
-                        ctx->st));
-  HIPCHK(hipMemcpyAsync(rate.data(), ctx->ptrd(ctx->w.rate), rate.size() * 8,
+  HIPCHK(hipMemcpyAsync(d.data(), ctx->ptrd(ctx->w.diag) + (size_t)mem * z.M * 8, d.size() * 8,
                         hipMemcpyDeviceToHost, ctx->st));
+  HIPCHK(hipMemcpyAsync(rate.data(), ctx->ptrd(ctx->w.rate) + (size_t)mem * z.R,
+                        rate.size() * 8, hipMemcpyDeviceToHost, ctx->st));
   HIPCHK(hipStreamSynchronize(ctx->st));
   double ek = 0, ez = 0, et = 0, en = 0, bad = 0, rmax = 0;
   for (int m = 0; m < z.M; ++m) {
@@ -860,6 +906,30 @@ qg_status qg_diagnostics(qg_ctx* ctx, qg_diag* out) {
   return QG_OK;
 }
 
+}  // namespace
+
+extern "C" {
+
+qg_status qg_create(qg_ctx** out, const qg_params* p, void* workspace, size_t workspace_bytes,
+                    void* stream) {
+  return create_ctx(out, p, 1, nullptr, workspace, workspace_bytes, stream);
+}
+
+qg_status qg_set_state(qg_ctx* ctx, const double* psi, const double* theta, const double* uphi,
+                       int on_device) {
+  return set_state_run(ctx, 0, psi, theta, uphi, on_device);
+}
+
+qg_status qg_get_state(qg_ctx* ctx, double* psi, double* theta, double* uphi, int on_device) {
+  return get_state_run(ctx, 0, psi, theta, uphi, on_device);
+}
+
+qg_status qg_step(qg_ctx* ctx, double dt, int scheme, int nsteps) {
+  return step_ctx(ctx, dt, scheme, nsteps);
+}
+
+qg_status qg_diagnostics(qg_ctx* ctx, qg_diag* out) { return diagnostics_run(ctx, 0, out); }
+
 qg_status qg_step_timed(qg_ctx* ctx, double dt, int scheme, int nsteps, double* kernel_ms,
                         int* launches) {
   if (!ctx || !kernel_ms || !launches) return QG_EINVAL;
@@ -885,6 +955,269 @@ qg_status qg_step_timed(qg_ctx* ctx, double dt, int scheme, int nsteps, double* 
   }
   ctx->ev_marks.clear();
   return QG_OK;
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------------ ensembles
+#ifndef QG_ENSEMBLE_GRAPH
+#define QG_ENSEMBLE_GRAPH 1   // replay captured steps (0: every step eager)
+#endif
+
+struct qg_ensemble {
+  std::vector<qg_ctx*> groups;   // one context per size class
+  std::vector<int> grp, run;     // member -> (group, run within the group)
+  hipStream_t st = nullptr;
+  bool own_stream = false;
+  std::string err;
+  hipGraphExec_t exec = nullptr;   // captured steps of every group
+  double g_dt = 0.0;
+  int g_scheme = -1, g_cur = -1, g_steps = 0;
+  double t = 0.0;
+  long long step = 0;
+};
+
+namespace {
+
+qg_status efail(qg_ensemble* e, qg_status s, const std::string& msg) {
+  if (e) e->err = msg;
+  return s;
+}
+
+// Members that share every parameter but Ra form one group (they share the
+// operators, tables and LU factors).
+bool same_group(const qg_params& a, const qg_params& b, const Sizes& za, const Sizes& zb) {
+  return a.E == b.E && a.Pr == b.Pr && a.eta == b.eta && za.nphi == zb.nphi && za.R == zb.R &&
+         za.K == zb.K && a.precision == b.precision && a.pivoting == b.pivoting;
+}
+
+struct Grouping {
+  std::vector<int> first;              // first member of each group
+  std::vector<std::vector<int>> mem;   // members of each group
+  std::vector<int> grp, run;
+  std::vector<size_t> off;             // workspace offset of each group
+  size_t total = 0;
+};
+
+bool group_members(const qg_params* ps, int n, Grouping& G) {
+  if (!ps || n < 1) return false;
+  std::vector<Sizes> zs(n);
+  std::string why;
+  G.grp.assign(n, -1);
+  G.run.assign(n, -1);
+  for (int i = 0; i < n; ++i) {
+    if (!sizes_of(&ps[i], zs[i], why)) return false;
+    int g = -1;
+    for (size_t j = 0; j < G.first.size(); ++j)
+      if (same_group(ps[G.first[j]], ps[i], zs[G.first[j]], zs[i])) { g = (int)j; break; }
+    if (g < 0) {
+      g = (int)G.first.size();
+      G.first.push_back(i);
+      G.mem.emplace_back();
+    }
+    G.grp[i] = g;
+    G.run[i] = (int)G.mem[g].size();
+    G.mem[g].push_back(i);
+  }
+  Layout L;
+  for (size_t j = 0; j < G.first.size(); ++j)
+    G.off.push_back(L.take(map_workspace(zs[G.first[j]], (int)G.mem[j].size()).total));
+  G.total = L.total;
+  return true;
+}
+
+qg_status step_groups(qg_ensemble* e, double dt, int scheme) {
+  for (qg_ctx* c : e->groups) {
+    qg_status s = (scheme == QG_CNAB2) ? step_cnab2(c, dt) : step_bpr353(c, dt);
+    if (s != QG_OK) return efail(e, s, c->err);
+  }
+  return QG_OK;
+}
+
+void account(qg_ensemble* e, double dt, int n) {
+  for (qg_ctx* c : e->groups) {
+    c->t += dt * n;
+    c->step += n;
+  }
+  e->t += dt * n;
+  e->step += n;
+}
+
+void drop_graph(qg_ensemble* e) {
+  if (e->exec) (void)hipGraphExecDestroy(e->exec);
+  e->exec = nullptr;
+  e->g_scheme = -1;
+}
+
+// Capture `steps` steps of every group (no launch happens during capture;
+// the host-side step state is restored afterwards).
+qg_status capture(qg_ensemble* e, double dt, int scheme, int steps) {
+  drop_graph(e);
+  std::vector<std::pair<int, int>> saved;
+  for (qg_ctx* c : e->groups) saved.push_back({c->cur, c->have_prev});
+  if (hipStreamBeginCapture(e->st, hipStreamCaptureModeRelaxed) != hipSuccess)
+    return efail(e, QG_EDEVICE, "hipStreamBeginCapture failed");
+  qg_status s = QG_OK;
+  for (int i = 0; i < steps && s == QG_OK; ++i) s = step_groups(e, dt, scheme);
+  hipGraph_t graph = nullptr;
+  const hipError_t ec = hipStreamEndCapture(e->st, &graph);
+  for (size_t j = 0; j < e->groups.size(); ++j) {
+    e->groups[j]->cur = saved[j].first;
+    e->groups[j]->have_prev = saved[j].second;
+  }
+  if (s != QG_OK || ec != hipSuccess || !graph) {
+    if (graph) (void)hipGraphDestroy(graph);
+    return s != QG_OK ? s : efail(e, QG_EDEVICE, "hipStreamEndCapture failed");
+  }
+  const hipError_t ei = hipGraphInstantiate(&e->exec, graph, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(graph);
+  if (ei != hipSuccess) {
+    e->exec = nullptr;
+    return efail(e, QG_EDEVICE, std::string("hipGraphInstantiate: ") + hipGetErrorString(ei));
+  }
+  e->g_dt = dt;
+  e->g_scheme = scheme;
+  e->g_cur = e->groups[0]->cur;
+  e->g_steps = steps;
+  return QG_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+qg_status qg_ensemble_workspace_size(const qg_params* members, int n, size_t* bytes) {
+  Grouping G;
+  if (!bytes || !group_members(members, n, G)) return QG_EINVAL;
+  *bytes = G.total;
+  return QG_OK;
+}
+
+qg_status qg_ensemble_create(qg_ensemble** out, const qg_params* members, int n,
+                             void* workspace, size_t workspace_bytes, void* stream) {
+  if (!out) return QG_EINVAL;
+  *out = nullptr;
+  Grouping G;
+  if (!group_members(members, n, G)) return QG_EINVAL;
+  if (!workspace || ((uintptr_t)workspace & 255)) return QG_EINVAL;
+  if (workspace_bytes < G.total) return QG_ENOMEM;
+  qg_ensemble* e = new qg_ensemble();
+  e->st = static_cast<hipStream_t>(stream);
+  if (!e->st) {   // the legacy default stream cannot be captured
+    if (hipStreamCreateWithFlags(&e->st, hipStreamNonBlocking) != hipSuccess) {
+      delete e;
+      return QG_EDEVICE;
+    }
+    e->own_stream = true;
+  }
+  e->grp = G.grp;
+  e->run = G.run;
+  for (size_t j = 0; j < G.first.size(); ++j) {
+    std::vector<double> ra;
+    for (int i : G.mem[j]) ra.push_back(members[i].Ra);
+    qg_ctx* c = nullptr;
+    const size_t next = (j + 1 < G.off.size()) ? G.off[j + 1] : G.total;
+    qg_status s = create_ctx(&c, &members[G.first[j]], (int)ra.size(), ra.data(),
+                             static_cast<char*>(workspace) + G.off[j], next - G.off[j], e->st);
+    if (s != QG_OK) {
+      qg_ensemble_destroy(e);
+      return s;
+    }
+    e->groups.push_back(c);
+  }
+  *out = e;
+  return QG_OK;
+}
+
+qg_status qg_ensemble_set_state(qg_ensemble* e, int member, const double* psi,
+                                const double* theta, const double* uphi, int on_device) {
+  if (!e) return QG_EINVAL;
+  if (member < 0 || member >= (int)e->grp.size()) return efail(e, QG_EINVAL, "no such member");
+  qg_ctx* c = e->groups[e->grp[member]];
+  qg_status s = set_state_run(c, e->run[member], psi, theta, uphi, on_device);
+  if (s != QG_OK) return efail(e, s, c->err);
+  for (qg_ctx* g : e->groups) {   // the ensemble restarts as a whole
+    g->t = 0.0;
+    g->step = 0;
+    g->have_prev = 0;
+    g->cur = 0;
+  }
+  e->t = 0.0;
+  e->step = 0;
+  e->err.clear();
+  return QG_OK;
+}
+
+qg_status qg_ensemble_get_state(qg_ensemble* e, int member, double* psi, double* theta,
+                                double* uphi, int on_device) {
+  if (!e) return QG_EINVAL;
+  if (member < 0 || member >= (int)e->grp.size()) return efail(e, QG_EINVAL, "no such member");
+  qg_ctx* c = e->groups[e->grp[member]];
+  qg_status s = get_state_run(c, e->run[member], psi, theta, uphi, on_device);
+  return s == QG_OK ? s : efail(e, s, c->err);
+}
+
+qg_status qg_ensemble_step(qg_ensemble* e, double dt, int scheme, int nsteps) {
+  if (!e) return QG_EINVAL;
+  for (qg_ctx* c : e->groups) {
+    qg_status s = check_step_args(c, dt, scheme, nsteps);
+    if (s != QG_OK) return efail(e, s, c->err);
+  }
+  for (qg_ctx* c : e->groups) {
+    const double before = c->factored_adt;
+    qg_status s = prepare_dt(c, dt);
+    if (s != QG_OK) return efail(e, s, c->err);
+    if (c->factored_adt != before) drop_graph(e);
+  }
+  int left = nsteps;
+  // CNAB2's first step after a restart has no history: run it eagerly
+  while (left > 0 && scheme == QG_CNAB2 && !e->groups[0]->have_prev) {
+    qg_status s = step_groups(e, dt, scheme);
+    if (s != QG_OK) return s;
+    account(e, dt, 1);
+    --left;
+  }
+  // CNAB2 alternates its two history slots: a graph holds two steps
+  const int per = (scheme == QG_CNAB2) ? 2 : 1;
+  if (QG_ENSEMBLE_GRAPH && left >= per) {
+    if (!e->exec || e->g_dt != dt || e->g_scheme != scheme || e->g_cur != e->groups[0]->cur ||
+        e->g_steps != per) {
+      qg_status s = capture(e, dt, scheme, per);
+      if (s != QG_OK) return s;
+    }
+    for (; left >= per; left -= per) {
+      if (hipGraphLaunch(e->exec, e->st) != hipSuccess)
+        return efail(e, QG_EDEVICE, "hipGraphLaunch failed");
+      for (qg_ctx* c : e->groups) c->have_prev = 1;
+      account(e, dt, per);
+    }
+  }
+  for (; left > 0; --left) {
+    qg_status s = step_groups(e, dt, scheme);
+    if (s != QG_OK) return s;
+    account(e, dt, 1);
+  }
+  return QG_OK;
+}
+
+qg_status qg_ensemble_diagnostics(qg_ensemble* e, int member, qg_diag* out) {
+  if (!e || !out) return QG_EINVAL;
+  if (member < 0 || member >= (int)e->grp.size()) return efail(e, QG_EINVAL, "no such member");
+  qg_ctx* c = e->groups[e->grp[member]];
+  qg_status s = diagnostics_run(c, e->run[member], out);
+  return s == QG_OK ? s : efail(e, s, c->err);
+}
+
+const char* qg_ensemble_last_error(const qg_ensemble* e) {
+  return e ? e->err.c_str() : "null ensemble";
+}
+
+void qg_ensemble_destroy(qg_ensemble* e) {
+  if (!e) return;
+  drop_graph(e);
+  for (qg_ctx* c : e->groups) qg_destroy(c);
+  if (e->own_stream && e->st) (void)hipStreamDestroy(e->st);
+  delete e;
 }
 
 const char* qg_last_error(const qg_ctx* ctx) { return ctx ? ctx->err.c_str() : "null context"; }

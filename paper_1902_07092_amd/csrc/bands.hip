@@ -30,8 +30,9 @@ __device__ __forceinline__ double2 ld(const double2* p, int i, int K) {
 }  // namespace
 
 // blockIdx.x: rows [RB x, RB x + RB); blockIdx.y: chunk of MCH systems;
-// blockIdx.z: 0 = Psi (m = 1 + MCH y + i), 1 = zonal flow and theta
-// (u = MCH y + i: u = 0 the zonal flow, u >= 1 theta of m = u - 1).
+// blockIdx.z = 2 run + kind, kind 0 = Psi (m = 1 + MCH y + i), 1 = zonal
+// flow and theta (u = MCH y + i: u = 0 the zonal flow, u >= 1 theta of
+// m = u - 1).
 // sys_out: out rows are system indices (Psi m -> m - 1, zonal -> M - 1,
 // theta m -> M + m) in out_psi; else out_psi[m] (Psi, zonal at m = 0) and
 // out_th[m].
@@ -40,10 +41,14 @@ __global__ __launch_bounds__(64) void band_kernel(Geom g, Bands b, RhsSpec rs, d
                                                   double2* __restrict__ out_th, int sys_out) {
   const int K = g.K, M = g.M;
   const int k = blockIdx.x * RB + threadIdx.x;
-  const int kind = blockIdx.z;
+  const int kind = blockIdx.z & 1;
   const int u0 = blockIdx.y * MCH;
   if (k >= K) return;
   const double cL = rs.cL;
+  const size_t mem = blockIdx.z >> 1, mk = (size_t)M * K;
+  const size_t moff = mem * mk;
+  out_psi += sys_out ? 2 * moff : moff;
+  if (!sys_out) out_th += moff;
   if (kind == 0) {
     double P0[BW], P1[BW], P2[BW], P3[BW];
 #pragma unroll
@@ -60,7 +65,7 @@ __global__ __launch_bounds__(64) void band_kernel(Geom g, Bands b, RhsSpec rs, d
       double2 acc = make_double2(0.0, 0.0);
       if (k >= 4) {
         const double dm = (double)m, m2 = dm * dm;
-        const double2* y = rs.base_psi + (size_t)m * K;
+        const double2* y = rs.base_psi + moff + (size_t)m * K;
 #pragma unroll
         for (int o = 0; o < BW; ++o) {
           const double re = P0[o] + m2 * (P1[o] + m2 * P2[o]);
@@ -70,7 +75,7 @@ __global__ __launch_bounds__(64) void band_kernel(Geom g, Bands b, RhsSpec rs, d
           acc.y += re * v.y + im * v.x;
         }
         for (int q = 0; q < rs.nterm; ++q) {
-          const double2 v = rs.term_psi[q][(size_t)m * K + k];
+          const double2 v = rs.term_psi[q][moff + (size_t)m * K + k];
           acc.x += rs.coef[q] * v.x;
           acc.y += rs.coef[q] * v.y;
         }
@@ -96,7 +101,7 @@ __global__ __launch_bounds__(64) void band_kernel(Geom g, Bands b, RhsSpec rs, d
       const double s2 = zonal ? cL : cL * g.inv_Pr * (double)m * (double)m;
       double2 acc = make_double2(0.0, 0.0);
       if (k >= 2) {
-        const double2* y = (zonal ? rs.base_psi : rs.base_th) + (size_t)m * K;
+        const double2* y = (zonal ? rs.base_psi : rs.base_th) + moff + (size_t)m * K;
 #pragma unroll
         for (int o = 0; o < BW; ++o) {
           const double re = D[o] + s1 * F0[o] + s2 * F2[o];
@@ -105,7 +110,7 @@ __global__ __launch_bounds__(64) void band_kernel(Geom g, Bands b, RhsSpec rs, d
           acc.y += re * v.y;
         }
         for (int q = 0; q < rs.nterm; ++q) {
-          const double2 v = (zonal ? rs.term_psi[q] : rs.term_th[q])[(size_t)m * K + k];
+          const double2 v = (zonal ? rs.term_psi[q] : rs.term_th[q])[moff + (size_t)m * K + k];
           acc.x += rs.coef[q] * v.x;
           acc.y += rs.coef[q] * v.y;
         }
@@ -120,7 +125,7 @@ __global__ __launch_bounds__(64) void band_kernel(Geom g, Bands b, RhsSpec rs, d
 namespace {
 dim3 band_grid(const Geom& g) {
   const int chunks = (g.M + 1 + MCH - 1) / MCH;   // covers M - 1 Psi and M + 1 real systems
-  return dim3((g.K + RB - 1) / RB, chunks, 2);
+  return dim3((g.K + RB - 1) / RB, chunks, 2 * g.nmem);
 }
 }  // namespace
 

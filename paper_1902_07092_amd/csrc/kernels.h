@@ -22,6 +22,13 @@ struct Geom {
   const float2* tw_phi32;
   const float2* tw_half32;
   const float2* w_phi32;
+  // Runs stepped together (an ensemble of one size): every launch takes
+  // the run as its grid y (band products: part of z).  Per-run arrays are
+  // run-major with strides M K ([M][K] arrays), 2 M K (right-hand sides),
+  // 6 M R and 2 M R (X, NL), R (zonal, rate) and 8 M (diag).  ra_pr: Ra/Pr
+  // of each run (nullptr: Ra_Pr for all).
+  int nmem;
+  const double* ra_pr;
 };
 
 struct Bands {  // [17][K] each (offset-major): entry (k, n) at [(n - k + 8) * K + k]

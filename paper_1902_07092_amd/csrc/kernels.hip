@@ -259,6 +259,10 @@ __global__ __launch_bounds__(64) void solve_all_kernel(Geom g, FactorSet<double2
                                                        RhsSpec rs) {
   extern __shared__ double2 sm[];
   const int blk = blockIdx.x, M = g.M;
+  const size_t moff = (size_t)blockIdx.y * M * g.K;   // run of an ensemble
+  rhs += 2 * moff;
+  rs.out_psi += moff;
+  rs.out_th += moff;
   if (blk < M - 1) solve_system<double2, 4, 8, KUTP, PIV>(g, Fp, rhs, rs, 0, blk, blk, sm);
   else solve_system<double, 2, 4, KUTR, PIV>(g, Fr, rhs, rs, blk == M - 1 ? 1 : 2, blk,
                                              blk - (M - 1), sm);
@@ -278,7 +282,7 @@ bool launch_solve(const Geom& g, const FactorSet<double2>& Fp, const FactorSet<d
                   double2* rhs, const RhsSpec& rs, int kutp, int kutr, bool pivoted,
                   hipStream_t st) {
   const size_t shm = solve_lds_bytes(g, kutp, kutr);
-  const dim3 grid(2 * g.M), block(64);
+  const dim3 grid(2 * g.M, g.nmem), block(64);
   if (!pivoted && kutp == 8 && kutr == 4)
     hipLaunchKernelGGL((solve_all_kernel<8, 4, false>), grid, block, shm, st, g, Fp, Fr, rhs, rs);
   else if (pivoted && kutp == 12 && kutr == 4)

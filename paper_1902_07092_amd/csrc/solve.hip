@@ -348,6 +348,10 @@ __global__ __launch_bounds__(64) void solve_np_kernel(Geom g, FactorSet<double2>
   const int M = g.M, K = g.K;
   const int nbp = (M - 1 + 3) / 4;
   const int t = threadIdx.x, lane = t & 15, grp = t >> 4;
+  const size_t moff = (size_t)blockIdx.y * M * K;   // run of an ensemble
+  rhs += 2 * moff;
+  rs.out_psi += moff;
+  rs.out_th += moff;
   if ((int)blockIdx.x < nbp) {
     Solver4<double2, 4, 8> s{Fp, rs.out_psi, rs.out_th, M, K};
     s.kind = 0;
@@ -384,7 +388,8 @@ bool launch_solve_np(const Geom& g, const FactorSet<double2>& Fp, const FactorSe
                      double2* rhs, const RhsSpec& rs, int qp, int qr, hipStream_t st) {
   if (qp % (NSET * SB) || qr % (NSET * SB)) return false;
   const int blocks = (g.M - 1 + 3) / 4 + (g.M + 1 + 3) / 4;
-  hipLaunchKernelGGL(solve_np_kernel, dim3(blocks), dim3(64), 0, st, g, Fp, Fr, rhs, rs, qp, qr);
+  hipLaunchKernelGGL(solve_np_kernel, dim3(blocks, g.nmem), dim3(64), 0, st, g, Fp, Fr, rhs, rs,
+                     qp, qr);
   return true;
 }
 

@@ -207,6 +207,13 @@ __global__ __launch_bounds__(T) void synth_kernel(Geom g, const double2* __restr
   const int t = threadIdx.x;
   const int m = xcd_index(M);
   if (m >= M) return;
+  {
+    const size_t mem = blockIdx.y;
+    psi += mem * M * K;
+    th += mem * M * K;
+    X += mem * 6 * R * M;
+    if (diag) diag += mem * 8 * M;
+  }
   C* fb = reinterpret_cast<C*>(sm);
   double2* c = reinterpret_cast<double2*>(reinterpret_cast<char*>(sm) + coef_offset<C>(lds_slots(N2)));
   auto ext = [&](int i) -> C {
@@ -365,6 +372,13 @@ __global__ __launch_bounds__(T) void ring_kernel(Geom g, const C* __restrict__ X
   const int t = threadIdx.x;
   const int k = xcd_index(R);
   if (k >= R) return;
+  {
+    const size_t mem = blockIdx.y;
+    X += mem * 6 * R * M;
+    NL += mem * 2 * M * R;
+    zonal += mem * R;
+    if (rate) rate += mem * R;
+  }
   const double s = g.half * g.xk[k] + g.mid;
   const double h2s = (g.s_o * g.s_o - s * s) / s;
   const C* X0 = X + (size_t)k * M;
@@ -465,11 +479,18 @@ __global__ __launch_bounds__(T) void analysis_kernel(Geom g, Bands b,
   const int t = threadIdx.x;
   const int m = xcd_index(M);
   if (m >= M) return;
+  const size_t mem = blockIdx.y;
+  NL += mem * 2 * M * R;
+  zonal += mem * R;
+  th_state += mem * M * K;
+  Epsi += mem * M * K;
+  Eth += mem * M * K;
   C* fb = reinterpret_cast<C*>(sm);
   double2* c = reinterpret_cast<double2*>(reinterpret_cast<char*>(sm) + coef_offset<C>(lds_slots(N2)));
   const double invN = 1.0 / N;
   const double2* thm = th_state + (size_t)m * K;
-  const double bcoef = g.Ra_Pr * (double)m / g.s_o;   // (Ra/Pr)(m/s_o), times i
+  const double ra_pr = g.ra_pr ? g.ra_pr[mem] : g.Ra_Pr;
+  const double bcoef = ra_pr * (double)m / g.s_o;   // (Ra/Pr)(m/s_o), times i
 #pragma unroll
   for (int f = 0; f < 2; ++f) {
     auto get = [&](int i) -> C {
@@ -535,7 +556,7 @@ void synth_n(const Geom& g, const double2* psi, const double2* th, void* X, doub
   constexpr int T = threads_dct(N2);
   const size_t shm = dct_lds<C>(N2, g.K);
   allow_lds(synth_kernel<N2, T, C>, shm);
-  hipLaunchKernelGGL((synth_kernel<N2, T, C>), dim3(xcd_grid(g.M)), dim3(T), shm, st, g, psi, th,
+  hipLaunchKernelGGL((synth_kernel<N2, T, C>), dim3(xcd_grid(g.M), g.nmem), dim3(T), shm, st, g, psi, th,
                      static_cast<C*>(X), diag);
 }
 
@@ -544,7 +565,7 @@ void ring_n(const Geom& g, const void* X, void* NL, double* zonal, double* rate,
   constexpr int T = threads_phi(NPHI);
   const size_t shm = phi_lds<C>(NPHI);
   allow_lds(ring_kernel<NPHI, T, C>, shm);
-  hipLaunchKernelGGL((ring_kernel<NPHI, T, C>), dim3(xcd_grid(g.R)), dim3(T), shm, st, g,
+  hipLaunchKernelGGL((ring_kernel<NPHI, T, C>), dim3(xcd_grid(g.R), g.nmem), dim3(T), shm, st, g,
                      static_cast<const C*>(X), static_cast<C*>(NL), zonal, rate);
 }
 
@@ -554,7 +575,7 @@ void analysis_n(const Geom& g, const Bands& b, const void* NL, const double* zon
   constexpr int T = threads_dct(N2);
   const size_t shm = dct_lds<C>(N2, g.K);
   allow_lds(analysis_kernel<N2, T, C>, shm);
-  hipLaunchKernelGGL((analysis_kernel<N2, T, C>), dim3(xcd_grid(g.M)), dim3(T), shm, st, g, b,
+  hipLaunchKernelGGL((analysis_kernel<N2, T, C>), dim3(xcd_grid(g.M), g.nmem), dim3(T), shm, st, g, b,
                      static_cast<const C*>(NL), zonal, th, Ep, Et);
 }
 

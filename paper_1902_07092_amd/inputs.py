@@ -47,7 +47,7 @@ class Workload:
     scheme: str          # "cnab2" | "bpr353"
     dt: float
     steps: int
-    ic: str              # "theta_noise" | "decaying" | "kolmogorov"
+    ic: str              # "theta_noise" | "theta_smooth" | "decaying" | "kolmogorov"
     seed: int
 
     @property
@@ -82,22 +82,53 @@ SMALL = _wl("small_96x33_E1e-3_cnab2", 1e-3, 1.5, 96, 33, "cnab2", 1e-4,
 MEDIUM = _wl("medium_768x257_E1e-6_bpr353", 1e-6, 5.0, 768, 257, "bpr353",
              1e-7, 500, "decaying", 2)
 LARGE = _wl("large_3072x1025_E1e-8_cnab2", 1e-8, 20.0, 3072, 1025, "cnab2",
-            3e-9, 50, "kolmogorov", 3)
+            1e-9, 50, "kolmogorov", 3)
 LARGE_TOP = _wl("large_12288x4097_E1e-8_cnab2", 1e-8, 20.0, 12288, 4097,
                 "cnab2", 2e-10, 50, "kolmogorov", 3)
 ADJOINT = _wl("adjoint_768x257_E1e-6_cnab2", 1e-6, 5.0, 768, 257, "cnab2",
               1e-7, 200, "decaying", 2)
 WORKLOADS = {w.name: w for w in (SMALL, MEDIUM, LARGE, LARGE_TOP, ADJOINT)}
 
+# Ensemble of independent runs (sizes across the paper's range of problem
+# sizes): N_r uniform on {65, 129, 257}, N_phi = 3 (N_r - 1), Ra
+# log-uniform on [2, 50] x Ra_c, E = 1e-5, Pr = 1, CNAB2, dt = 1e-6, 200
+# steps; member i starts from the theta_smooth recipe with seed 400 + i.
+ENSEMBLE_SEED = 4
+ENSEMBLE_SIZE = 64
+
+
+def ensemble_workloads(n: int = ENSEMBLE_SIZE,
+                       seed: int = ENSEMBLE_SEED) -> list:
+    rng = np.random.Generator(np.random.PCG64(seed))
+    n_r = rng.choice(np.array([65, 129, 257]), size=n)
+    lo, hi = math.log10(2.0), math.log10(50.0)
+    ra_factor = 10.0 ** rng.uniform(lo, hi, size=n)
+    return [_wl(f"ensemble_{i}_{3 * (int(n_r[i]) - 1)}x{int(n_r[i])}_E1e-5",
+                1e-5, float(ra_factor[i]), 3 * (int(n_r[i]) - 1), int(n_r[i]),
+                "cnab2", 1e-6, 200, "theta_smooth", 400 + i)
+            for i in range(n)]
+
 # Amplitudes of the random initial states (fixed constants of the recipe).
-#   decaying:   Psi ~ A_PSI_DEC e^{-m/64} e^{-n/64} N(0,1)(1+i),
-#               theta ~ A_TH_DEC e^{-m/64} e^{-n/64} N(0,1)(1+i)
-#   kolmogorov: |a_mn| = A k^{-5/3}, k = max(1, sqrt(m^2+n^2)), random phase
+#   theta_noise:  theta ~ A_TH_NOISE N(0,1)(1+i) on every (m, n)
+#   theta_smooth: the same times e^{-n/n_d}, n_d = K/32 (a radial
+#                 dissipation range: the last kept coefficient is ~1e-14 of
+#                 the first, so the state is resolved to FP64)
+#   decaying:     Psi ~ A_PSI_DEC e^{-m/64} e^{-n/64} N(0,1)(1+i),
+#                 theta ~ A_TH_DEC e^{-m/64} e^{-n/64} N(0,1)(1+i)
+#   kolmogorov:   |a_mn| = A k^{-5/3} for k <= K_R = 20 and
+#                 A K_R^{-5/3} (k/K_R)^{-5} beyond (the m^{-5/3} range and the
+#                 steeper m^{-5} range past the Rhines scale m ~ 20 that
+#                 Sect. 6.2 reports for turbulent QG convection), k =
+#                 max(1, sqrt(m^2+n^2)), times e^{-n/n_d}, n_d = K/32, with
+#                 random phases.  A_PSI_KOL gives Re = 1e4 and A_TH_KOL an rms
+#                 theta of 1e-2 alpha at 3072 x 1025 (K = 682).
 A_TH_NOISE = 1.0e-4
 A_PSI_DEC = 6.02e-4
 A_TH_DEC = 1.35e-5
-A_PSI_KOL = 110.5
-A_TH_KOL = 1.59e-3
+A_PSI_KOL = 445.018
+A_TH_KOL = 1.62955e-3
+K_RHINES = 20.0
+N_DISS = 32.0
 
 
 def _gamma(n):
@@ -143,11 +174,14 @@ def make_state(M: int, K: int, ic: str, seed: int) -> State:
     rng = np.random.Generator(np.random.PCG64(seed))
     m = np.arange(M, dtype=np.float64)[:, None]
     n = np.arange(K, dtype=np.float64)[None, :]
-    if ic == "theta_noise":
-        # Psi = 0, zonal flow = 0, theta basis coefficients N(0, 1e-4).
+    if ic in ("theta_noise", "theta_smooth"):
+        # Psi = 0, zonal flow = 0, theta basis coefficients N(0, 1e-4)
+        # (theta_smooth: with the radial dissipation range).
         xi = rng.standard_normal((2, M, K))
         cp = np.zeros((M, K), np.complex128)
         ct = A_TH_NOISE * (xi[0] + 1j * xi[1])
+        if ic == "theta_smooth":
+            ct = ct * np.exp(-n / (K / N_DISS))
     elif ic == "decaying":
         env = np.exp(-m / 64.0) * np.exp(-n / 64.0)
         xp = rng.standard_normal((2, M, K))
@@ -156,7 +190,9 @@ def make_state(M: int, K: int, ic: str, seed: int) -> State:
         ct = A_TH_DEC * env * (xt[0] + 1j * xt[1])
     elif ic == "kolmogorov":
         k = np.maximum(1.0, np.sqrt(m**2 + n**2))
-        env = k ** (-5.0 / 3.0)
+        env = np.where(k <= K_RHINES, k ** (-5.0 / 3.0),
+                       K_RHINES ** (-5.0 / 3.0) * (k / K_RHINES) ** (-5.0))
+        env = env * np.exp(-n / (K / N_DISS))
         ph_p = rng.uniform(0.0, 2.0 * math.pi, (M, K))
         ph_t = rng.uniform(0.0, 2.0 * math.pi, (M, K))
         cp = A_PSI_KOL * env * np.exp(1j * ph_p)

@@ -57,6 +57,9 @@ def load():
         raise RuntimeError(
             f"HIP library {LIB_PATH} is missing; run __graft_entry__.build() "
             "(or python -m paper_1902_07092_amd.build)")
+    # torch first: the library must bind to the HIP runtime that owns the
+    # workspace and the streams torch hands over, not load a second copy
+    import torch  # noqa: F401
     L = ctypes.CDLL(LIB_PATH)
     vp, i, d = ctypes.c_void_p, ctypes.c_int, ctypes.c_double
     sig = {
@@ -72,6 +75,16 @@ def load():
         "qg_destroy": (None, [vp]),
         "qg_operator_band": (i, [d, i, i, vp]),
         "qg_step_timed": (i, [vp, d, i, i, vp, vp]),
+        "qg_ensemble_workspace_size": (i, [vp, i,
+                                           ctypes.POINTER(ctypes.c_size_t)]),
+        "qg_ensemble_create": (i, [ctypes.POINTER(vp), vp, i, vp,
+                                   ctypes.c_size_t, vp]),
+        "qg_ensemble_set_state": (i, [vp, i, vp, vp, vp, i]),
+        "qg_ensemble_get_state": (i, [vp, i, vp, vp, vp, i]),
+        "qg_ensemble_step": (i, [vp, d, i, i]),
+        "qg_ensemble_diagnostics": (i, [vp, i, ctypes.POINTER(qg_diag)]),
+        "qg_ensemble_last_error": (ctypes.c_char_p, [vp]),
+        "qg_ensemble_destroy": (None, [vp]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(L, name)
@@ -156,6 +169,69 @@ def qg_destroy(ctx):
     load().qg_destroy(ctx)
 
 
+def _params_array(members):
+    arr = (qg_params * len(members))(*members)
+    return arr
+
+
+def qg_ensemble_workspace_size(members) -> int:
+    arr = _params_array(members)
+    n = ctypes.c_size_t(0)
+    st = load().qg_ensemble_workspace_size(ctypes.cast(arr, ctypes.c_void_p),
+                                           len(members), ctypes.byref(n))
+    if st != QG_OK:
+        raise QGError(st, "invalid member parameters")
+    return n.value
+
+
+def _echeck(ens, st):
+    if st != QG_OK:
+        msg = load().qg_ensemble_last_error(ens)
+        raise QGError(st, msg.decode() if msg else "")
+
+
+def qg_ensemble_create(members, workspace_ptr, nbytes, stream_ptr):
+    arr = _params_array(members)
+    ens = ctypes.c_void_p()
+    st = load().qg_ensemble_create(ctypes.byref(ens),
+                                   ctypes.cast(arr, ctypes.c_void_p),
+                                   len(members), ctypes.c_void_p(workspace_ptr),
+                                   nbytes, ctypes.c_void_p(stream_ptr))
+    if st != QG_OK:
+        raise QGError(st, "qg_ensemble_create")
+    return ens
+
+
+def qg_ensemble_set_state(ens, member, psi_ptr, theta_ptr, uphi_ptr,
+                          on_device):
+    _echeck(ens, load().qg_ensemble_set_state(ens, int(member), psi_ptr,
+                                              theta_ptr, uphi_ptr,
+                                              int(on_device)))
+
+
+def qg_ensemble_get_state(ens, member, psi_ptr, theta_ptr, uphi_ptr,
+                          on_device):
+    _echeck(ens, load().qg_ensemble_get_state(ens, int(member), psi_ptr,
+                                              theta_ptr, uphi_ptr,
+                                              int(on_device)))
+
+
+def qg_ensemble_step(ens, dt, scheme, nsteps):
+    _echeck(ens, load().qg_ensemble_step(ens, float(dt), int(scheme),
+                                         int(nsteps)))
+
+
+def qg_ensemble_diagnostics(ens, member) -> dict:
+    d = qg_diag()
+    _echeck(ens, load().qg_ensemble_diagnostics(ens, int(member),
+                                                ctypes.byref(d)))
+    return {name: getattr(d, name) for name, _ in qg_diag._fields_}
+
+
+def qg_ensemble_destroy(ens):
+    load().qg_ensemble_destroy(ens)
+
+
 # ---------------------------------------------------------------- wrapper
 class QGSolver:
     """One solver context on a HIP device, workspace allocated by torch."""
@@ -233,3 +309,69 @@ class QGSolver:
 
     def diagnostics(self):
         return qg_diagnostics(self.ctx)
+
+
+class QGEnsemble:
+    """Many runs stepped together (qg_ensemble_*); members is a list of
+    dicts with the QGSolver parameters E, Ra, Pr, eta, n_phi, n_r and
+    optionally n_c, precision, pivoting.  The ensemble gets a stream of its
+    own (graph capture needs one)."""
+
+    def __init__(self, members, device="cuda:0"):
+        import torch
+        self.torch = torch
+        self.device = torch.device(device)
+        self.params = [qg_params(m["E"], m["Ra"], m["Pr"], m["eta"],
+                                 m["n_phi"], m["n_r"], m.get("n_c", 0),
+                                 m.get("precision", 0), m.get("pivoting", 0))
+                       for m in members]
+        self.shapes = [(p.n_phi // 3 + 1,
+                        p.n_c if p.n_c else (2 * (p.n_r - 1)) // 3)
+                       for p in self.params]
+        nbytes = qg_ensemble_workspace_size(self.params)
+        with torch.cuda.device(self.device):
+            self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8,
+                                         device=self.device)
+            aligned = (self.workspace.data_ptr() + 255) // 256 * 256
+            self.stream = torch.cuda.Stream(self.device)
+            self.ens = qg_ensemble_create(self.params, aligned, nbytes,
+                                          self.stream.cuda_stream)
+        self.nbytes = nbytes
+
+    def __len__(self):
+        return len(self.params)
+
+    def __del__(self):
+        ens = getattr(self, "ens", None)
+        if ens:
+            qg_ensemble_destroy(ens)
+            self.ens = None
+
+    def set_state(self, member, psi, theta, uphi):
+        M, K = self.shapes[member]
+        ps = np.ascontiguousarray(psi, np.complex128)
+        th = np.ascontiguousarray(theta, np.complex128)
+        up = np.ascontiguousarray(uphi, np.float64)
+        if ps.shape != (M, K) or th.shape != (M, K) or up.shape != (K,):
+            raise ValueError("state arrays must be (M, K), (M, K), (K,)")
+        qg_ensemble_set_state(self.ens, member,
+                              ctypes.c_void_p(ps.ctypes.data),
+                              ctypes.c_void_p(th.ctypes.data),
+                              ctypes.c_void_p(up.ctypes.data), 0)
+
+    def get_state(self, member):
+        M, K = self.shapes[member]
+        ps = np.empty((M, K), np.complex128)
+        th = np.empty_like(ps)
+        up = np.empty(K)
+        qg_ensemble_get_state(self.ens, member,
+                              ctypes.c_void_p(ps.ctypes.data),
+                              ctypes.c_void_p(th.ctypes.data),
+                              ctypes.c_void_p(up.ctypes.data), 0)
+        return ps, th, up
+
+    def step(self, dt, scheme="cnab2", n=1):
+        qg_ensemble_step(self.ens, dt, SCHEMES[scheme], n)
+
+    def diagnostics(self, member):
+        return qg_ensemble_diagnostics(self.ens, member)

@@ -35,6 +35,9 @@ CASES = {
     "small_cnab2_100": ("SMALL", "cnab2", 100),
     "medium_bpr353_2": ("MEDIUM", "bpr353", 2),
     "large_cnab2_2": ("LARGE", "cnab2", 2),
+    # member 7 of the seeded 64-run ensemble (192 x 65, Ra = 4.02 Ra_c)
+    "ensemble7_cnab2_10": ("ensemble:7", "cnab2", 10),
+    "large_cnab2_50": ("LARGE", "cnab2", 50),
 }
 # Mixed precision (FP32 transforms and products): the same measurement with
 # u = 2^-24; the mixed-precision tests accept 30 x this floor.
@@ -42,6 +45,7 @@ CASES32 = {
     "mixed_small_cnab2_50": ("SMALL", "cnab2", 50),
     "mixed_medium_bpr353_1": ("MEDIUM", "bpr353", 1),
     "mixed_large_cnab2_1": ("LARGE", "cnab2", 1),
+    "mixed_large_cnab2_50": ("LARGE", "cnab2", 50),
 }
 WRAPPED = ("cheb_to_grid", "grid_to_cheb", "phi_to_grid", "grid_to_phi",
            "cheb_ds")
@@ -58,8 +62,14 @@ def _noisy(fn, rng, u):
     return wrapped
 
 
+def workload(name):
+    if name.startswith("ensemble:"):
+        return inputs.ensemble_workloads()[int(name.split(":")[1])]
+    return getattr(inputs, name)
+
+
 def run(name, scheme, steps, seed, u=U):
-    w = getattr(inputs, name)
+    w = workload(name)
     st = inputs.workload_state(w)
     orig = {f: getattr(tr, f) for f in WRAPPED}
     if seed is not None:

@@ -1,0 +1,119 @@
+"""Batched ensemble (qg_ensemble_*) on the GPU, through the C ABI.
+
+Members of uneven size and Rayleigh number are advanced together: one
+launch per kernel and group, steps after the first replayed from a HIP
+graph.  Each member must equal, bit for bit, a single-run context with its
+own parameters stepped eagerly (same kernels, same arithmetic), after every
+call, i.e. after every series of graph replays with the program's own
+eager work and synchronisations in between; one member is also checked
+against the oracle at the parity bar.
+"""
+import json
+import os
+import sys
+
+import numpy as np
+import pytest
+
+from oracle.step import QGOracle
+from paper_1902_07092_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+_TOLS = json.load(open(os.path.join(os.path.dirname(__file__), "golden",
+                                    "parity_tolerances.json")))
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def qg():
+    import torch
+    assert torch.cuda.is_available(), "GPU test needs a HIP device"
+    from paper_1902_07092_amd import qg as mod
+    mod.load()
+    return mod
+
+
+def _member(w):
+    return dict(E=w.E, Ra=w.Ra, Pr=w.Pr, eta=w.eta, n_phi=w.n_phi,
+                n_r=w.n_r, n_c=w.n_c)
+
+
+def _pick(ws, per_size=2):
+    """The first `per_size` members of each radial size, in draw order."""
+    out, seen = [], {}
+    for i, w in enumerate(ws):
+        if seen.get(w.n_r, 0) < per_size:
+            seen[w.n_r] = seen.get(w.n_r, 0) + 1
+            out.append(i)
+    return out
+
+
+def test_ensemble_members_equal_solo_runs(qg):
+    ws = inputs.ensemble_workloads()
+    idx = _pick(ws)
+    sel = [ws[i] for i in idx]
+    _say(f"[ensemble] members {idx} sizes "
+         f"{[(w.n_phi, w.n_r) for w in sel]}")
+    ens = qg.QGEnsemble([_member(w) for w in sel])
+    solos = []
+    for j, w in enumerate(sel):
+        st = inputs.workload_state(w)
+        ens.set_state(j, st.psi, st.theta, st.uphi0)
+        s = qg.QGSolver(w.E, w.Ra, w.Pr, w.eta, w.n_phi, w.n_r, w.n_c)
+        s.set_state(st.psi, st.theta, st.uphi0)
+        solos.append(s)
+    dt = sel[0].dt
+    # first call: eager first step + two replays of the two-step graph +
+    # one eager step; then replays of the cached graph; then a new graph
+    # for BPR353
+    for scheme, n in (("cnab2", 6), ("cnab2", 4), ("cnab2", 7),
+                      ("bpr353", 3)):
+        _say(f"  step {scheme} x{n}")
+        ens.step(dt, scheme, n)
+        for s in solos:
+            s.step(dt, scheme, n)
+        for j, s in enumerate(solos):
+            a = ens.get_state(j)
+            b = s.get_state()
+            for f, x, y in zip(("psi", "theta", "uphi"), a, b):
+                assert np.isfinite(x).all(), (j, f)
+                diff = float(np.abs(x - y).max())
+                assert np.array_equal(x, y), (scheme, n, j, f, diff)
+    d_e = ens.diagnostics(len(sel) - 1)
+    d_s = solos[-1].diagnostics()
+    assert d_e["step"] == d_s["step"] == 20
+    for k in ("E_kin", "E_therm", "enstrophy", "dt_cfl"):
+        assert d_e[k] == d_s[k], k
+
+
+def test_ensemble_member_matches_oracle(qg):
+    ws = inputs.ensemble_workloads()
+    k = 7
+    w = ws[k]
+    others = [ws[i] for i in (0, 3)]   # a 768 x 257 and a 384 x 129 member
+    assert w.n_r == 65 and {o.n_r for o in others} == {257, 129}
+    _say(f"[ensemble] member {k} {w.n_phi}x{w.n_r} beside two others")
+    ens = qg.QGEnsemble([_member(x) for x in [others[0], w, others[1]]])
+    for j, x in enumerate([others[0], w, others[1]]):
+        st = inputs.workload_state(x)
+        ens.set_state(j, st.psi, st.theta, st.uphi0)
+    ens.step(w.dt, "cnab2", 10)
+    st = inputs.workload_state(w)
+    o = QGOracle(w.E, w.Ra, w.Pr, w.eta, w.n_phi, w.n_r, w.n_c)
+    o.set_state(st.psi, st.theta, st.uphi0)
+    o.step(w.dt, "cnab2", 10)
+    psi, th, up = ens.get_state(1)
+    err = {}
+    for f, a, b in (("psi", psi, o.psi), ("theta", th, o.theta),
+                    ("uphi", up, o.uphi)):
+        sc = np.abs(b).max()
+        err[f] = float(np.abs(a - b).max() / sc) if sc > 0 else float(
+            np.abs(a).max())
+    tol = _TOLS["ensemble7_cnab2_10"]["tol"]
+    _say(f"  rel err {err} tol {tol}")
+    assert all(err[f] <= max(1e-11, tol[f]) for f in err), err

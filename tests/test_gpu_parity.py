@@ -153,7 +153,6 @@ def test_large_cnab2_parity(qg):
     _say(f"  rel err {err} ({time.time() - t0:.1f} s)")
     ok, tol = _within(err, "large_cnab2_2")
     assert ok, (err, tol)
-    assert err["theta"] < TOL     # theta's own floor is far below 1e-11
     d = s.diagnostics()
     _say(f"  band LU pivoted={d['pivoted']} growth={d['growth']:.3g}")
     assert d["pivoted"] == 0 and 1.0 <= d["growth"] <= 1e4

@@ -174,7 +174,8 @@ def test_diagnostics_parseval_and_zero_state():
 
 
 def test_inputs_satisfy_boundary_conditions():
-    for ic, seed in (("theta_noise", 1), ("decaying", 2), ("kolmogorov", 3)):
+    for ic, seed in (("theta_noise", 1), ("theta_smooth", 400),
+                     ("decaying", 2), ("kolmogorov", 3)):
         st = inputs.make_state(17, 21, ic, seed)
         for rows, a in ((tau_rows_psi(21), st.psi),
                         (tau_rows_dirichlet(21), st.theta)):
