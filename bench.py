@@ -2,7 +2,7 @@
 """Benchmark of the FP64 IMEX step of spherical QG convection on one GPU.
 
 Workload (default): 3072 x 1025 grid (N_m = 1024, N_c = 682), E = 1e-8,
-Pr = 1, Ra = 20 Ra_c, CNAB2, dt = 1e-9, seeded turbulent-like initial
+Pr = 1, Ra = 20 Ra_c, CNAB2, dt = 2.5e-10, seeded turbulent-like initial
 state (k^-5/3 spectrum steepening past m ~ 20, random phases, Re = 1e4).
 Beside it: the same steps with FP32 transforms and products, and the
 batched ensemble of 64 runs of uneven size and Ra.  A step is one CNAB2 step of the

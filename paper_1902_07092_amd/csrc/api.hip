@@ -969,8 +969,15 @@ struct qg_ensemble {
   std::vector<int> grp, run;     // member -> (group, run within the group)
   hipStream_t st = nullptr;
   bool own_stream = false;
+  // each group runs on a stream of its own, forked from and joined back to
+  // st around every step, so that the groups' kernels overlap
+  std::vector<hipStream_t> gst;
+  std::vector<hipEvent_t> gev;
+  hipEvent_t fork = nullptr;
   std::string err;
-  hipGraphExec_t exec = nullptr;   // captured steps of every group
+  // captured steps, one single-stream graph per group (replayed on the
+  // group's stream between the fork and the join)
+  std::vector<hipGraphExec_t> exec;
   double g_dt = 0.0;
   int g_scheme = -1, g_cur = -1, g_steps = 0;
   double t = 0.0;
@@ -1027,9 +1034,17 @@ bool group_members(const qg_params* ps, int n, Grouping& G) {
 }
 
 qg_status step_groups(qg_ensemble* e, double dt, int scheme) {
-  for (qg_ctx* c : e->groups) {
+  if (hipEventRecord(e->fork, e->st) != hipSuccess)
+    return efail(e, QG_EDEVICE, "hipEventRecord failed");
+  for (size_t j = 0; j < e->groups.size(); ++j) {
+    qg_ctx* c = e->groups[j];
+    if (hipStreamWaitEvent(e->gst[j], e->fork, 0) != hipSuccess)
+      return efail(e, QG_EDEVICE, "hipStreamWaitEvent failed");
     qg_status s = (scheme == QG_CNAB2) ? step_cnab2(c, dt) : step_bpr353(c, dt);
     if (s != QG_OK) return efail(e, s, c->err);
+    if (hipEventRecord(e->gev[j], e->gst[j]) != hipSuccess ||
+        hipStreamWaitEvent(e->st, e->gev[j], 0) != hipSuccess)
+      return efail(e, QG_EDEVICE, "group join failed");
   }
   return QG_OK;
 }
@@ -1044,41 +1059,66 @@ void account(qg_ensemble* e, double dt, int n) {
 }
 
 void drop_graph(qg_ensemble* e) {
-  if (e->exec) (void)hipGraphExecDestroy(e->exec);
-  e->exec = nullptr;
+  if (!e->exec.empty()) {
+    (void)hipStreamSynchronize(e->st);   // no replay may be in flight
+    for (hipStream_t gs : e->gst) (void)hipStreamSynchronize(gs);
+    for (hipGraphExec_t x : e->exec)
+      if (x) (void)hipGraphExecDestroy(x);
+  }
+  e->exec.clear();
   e->g_scheme = -1;
 }
 
-// Capture `steps` steps of every group (no launch happens during capture;
-// the host-side step state is restored afterwards).
+// Capture `steps` steps of each group on its own stream (no launch happens
+// during capture; the host-side step state is restored afterwards).
 qg_status capture(qg_ensemble* e, double dt, int scheme, int steps) {
   drop_graph(e);
-  std::vector<std::pair<int, int>> saved;
-  for (qg_ctx* c : e->groups) saved.push_back({c->cur, c->have_prev});
-  if (hipStreamBeginCapture(e->st, hipStreamCaptureModeRelaxed) != hipSuccess)
-    return efail(e, QG_EDEVICE, "hipStreamBeginCapture failed");
-  qg_status s = QG_OK;
-  for (int i = 0; i < steps && s == QG_OK; ++i) s = step_groups(e, dt, scheme);
-  hipGraph_t graph = nullptr;
-  const hipError_t ec = hipStreamEndCapture(e->st, &graph);
   for (size_t j = 0; j < e->groups.size(); ++j) {
-    e->groups[j]->cur = saved[j].first;
-    e->groups[j]->have_prev = saved[j].second;
-  }
-  if (s != QG_OK || ec != hipSuccess || !graph) {
-    if (graph) (void)hipGraphDestroy(graph);
-    return s != QG_OK ? s : efail(e, QG_EDEVICE, "hipStreamEndCapture failed");
-  }
-  const hipError_t ei = hipGraphInstantiate(&e->exec, graph, nullptr, nullptr, 0);
-  (void)hipGraphDestroy(graph);
-  if (ei != hipSuccess) {
-    e->exec = nullptr;
-    return efail(e, QG_EDEVICE, std::string("hipGraphInstantiate: ") + hipGetErrorString(ei));
+    qg_ctx* c = e->groups[j];
+    const int cur = c->cur, have_prev = c->have_prev;
+    if (hipStreamBeginCapture(e->gst[j], hipStreamCaptureModeRelaxed) != hipSuccess) {
+      drop_graph(e);
+      return efail(e, QG_EDEVICE, "hipStreamBeginCapture failed");
+    }
+    qg_status s = QG_OK;
+    for (int i = 0; i < steps && s == QG_OK; ++i)
+      s = (scheme == QG_CNAB2) ? step_cnab2(c, dt) : step_bpr353(c, dt);
+    hipGraph_t graph = nullptr;
+    const hipError_t ec = hipStreamEndCapture(e->gst[j], &graph);
+    c->cur = cur;
+    c->have_prev = have_prev;
+    if (s != QG_OK || ec != hipSuccess || !graph) {
+      if (graph) (void)hipGraphDestroy(graph);
+      drop_graph(e);
+      return s != QG_OK ? efail(e, s, c->err) : efail(e, QG_EDEVICE, "hipStreamEndCapture failed");
+    }
+    hipGraphExec_t x = nullptr;
+    const hipError_t ei = hipGraphInstantiate(&x, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (ei != hipSuccess) {
+      drop_graph(e);
+      return efail(e, QG_EDEVICE, std::string("hipGraphInstantiate: ") + hipGetErrorString(ei));
+    }
+    e->exec.push_back(x);
   }
   e->g_dt = dt;
   e->g_scheme = scheme;
   e->g_cur = e->groups[0]->cur;
   e->g_steps = steps;
+  return QG_OK;
+}
+
+// One replay of every group's graph, forked from and joined back to e->st.
+qg_status replay(qg_ensemble* e) {
+  if (hipEventRecord(e->fork, e->st) != hipSuccess)
+    return efail(e, QG_EDEVICE, "hipEventRecord failed");
+  for (size_t j = 0; j < e->groups.size(); ++j) {
+    if (hipStreamWaitEvent(e->gst[j], e->fork, 0) != hipSuccess ||
+        hipGraphLaunch(e->exec[j], e->gst[j]) != hipSuccess ||
+        hipEventRecord(e->gev[j], e->gst[j]) != hipSuccess ||
+        hipStreamWaitEvent(e->st, e->gev[j], 0) != hipSuccess)
+      return efail(e, QG_EDEVICE, "graph replay failed");
+  }
   return QG_OK;
 }
 
@@ -1112,13 +1152,34 @@ qg_status qg_ensemble_create(qg_ensemble** out, const qg_params* members, int n,
   }
   e->grp = G.grp;
   e->run = G.run;
+  if (hipEventCreateWithFlags(&e->fork, hipEventDisableTiming) != hipSuccess) {
+    qg_ensemble_destroy(e);
+    return QG_EDEVICE;
+  }
   for (size_t j = 0; j < G.first.size(); ++j) {
+    hipStream_t gs = nullptr;
+    hipEvent_t ge = nullptr;
+    if (hipStreamCreateWithFlags(&gs, hipStreamNonBlocking) != hipSuccess) {
+      qg_ensemble_destroy(e);
+      return QG_EDEVICE;
+    }
+    e->gst.push_back(gs);
+    if (hipEventCreateWithFlags(&ge, hipEventDisableTiming) != hipSuccess) {
+      qg_ensemble_destroy(e);
+      return QG_EDEVICE;
+    }
+    e->gev.push_back(ge);
     std::vector<double> ra;
     for (int i : G.mem[j]) ra.push_back(members[i].Ra);
     qg_ctx* c = nullptr;
     const size_t next = (j + 1 < G.off.size()) ? G.off[j + 1] : G.total;
+    // set-up work on the caller's stream must precede the group's
+    if (hipStreamSynchronize(e->st) != hipSuccess) {
+      qg_ensemble_destroy(e);
+      return QG_EDEVICE;
+    }
     qg_status s = create_ctx(&c, &members[G.first[j]], (int)ra.size(), ra.data(),
-                             static_cast<char*>(workspace) + G.off[j], next - G.off[j], e->st);
+                             static_cast<char*>(workspace) + G.off[j], next - G.off[j], gs);
     if (s != QG_OK) {
       qg_ensemble_destroy(e);
       return s;
@@ -1180,14 +1241,14 @@ qg_status qg_ensemble_step(qg_ensemble* e, double dt, int scheme, int nsteps) {
   // CNAB2 alternates its two history slots: a graph holds two steps
   const int per = (scheme == QG_CNAB2) ? 2 : 1;
   if (QG_ENSEMBLE_GRAPH && left >= per) {
-    if (!e->exec || e->g_dt != dt || e->g_scheme != scheme || e->g_cur != e->groups[0]->cur ||
+    if (e->exec.empty() || e->g_dt != dt || e->g_scheme != scheme || e->g_cur != e->groups[0]->cur ||
         e->g_steps != per) {
       qg_status s = capture(e, dt, scheme, per);
       if (s != QG_OK) return s;
     }
     for (; left >= per; left -= per) {
-      if (hipGraphLaunch(e->exec, e->st) != hipSuccess)
-        return efail(e, QG_EDEVICE, "hipGraphLaunch failed");
+      qg_status sr = replay(e);
+      if (sr != QG_OK) return sr;
       for (qg_ctx* c : e->groups) c->have_prev = 1;
       account(e, dt, per);
     }
@@ -1214,8 +1275,13 @@ const char* qg_ensemble_last_error(const qg_ensemble* e) {
 
 void qg_ensemble_destroy(qg_ensemble* e) {
   if (!e) return;
+  if (e->st) (void)hipStreamSynchronize(e->st);
+  for (hipStream_t gs : e->gst) (void)hipStreamSynchronize(gs);
   drop_graph(e);
   for (qg_ctx* c : e->groups) qg_destroy(c);
+  for (hipEvent_t ge : e->gev) (void)hipEventDestroy(ge);
+  for (hipStream_t gs : e->gst) (void)hipStreamDestroy(gs);
+  if (e->fork) (void)hipEventDestroy(e->fork);
   if (e->own_stream && e->st) (void)hipStreamDestroy(e->st);
   delete e;
 }

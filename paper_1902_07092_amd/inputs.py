@@ -82,9 +82,9 @@ SMALL = _wl("small_96x33_E1e-3_cnab2", 1e-3, 1.5, 96, 33, "cnab2", 1e-4,
 MEDIUM = _wl("medium_768x257_E1e-6_bpr353", 1e-6, 5.0, 768, 257, "bpr353",
              1e-7, 500, "decaying", 2)
 LARGE = _wl("large_3072x1025_E1e-8_cnab2", 1e-8, 20.0, 3072, 1025, "cnab2",
-            1e-9, 50, "kolmogorov", 3)
+            2.5e-10, 50, "kolmogorov", 3)
 LARGE_TOP = _wl("large_12288x4097_E1e-8_cnab2", 1e-8, 20.0, 12288, 4097,
-                "cnab2", 2e-10, 50, "kolmogorov", 3)
+                "cnab2", 2e-11, 50, "kolmogorov", 3)
 ADJOINT = _wl("adjoint_768x257_E1e-6_cnab2", 1e-6, 5.0, 768, 257, "cnab2",
               1e-7, 200, "decaying", 2)
 WORKLOADS = {w.name: w for w in (SMALL, MEDIUM, LARGE, LARGE_TOP, ADJOINT)}

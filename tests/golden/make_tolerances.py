@@ -99,25 +99,31 @@ def floors(name, scheme, steps, u):
     return floor
 
 
+def _store(path, case, entry):
+    """Merge one case into the file (re-read first: several generator
+    processes may run side by side)."""
+    out = json.load(open(path)) if os.path.exists(path) else {}
+    out[case] = entry
+    with open(path + ".tmp", "w") as f:
+        json.dump(out, f, indent=1, sort_keys=True)
+    os.replace(path + ".tmp", path)
+    print(case, entry, flush=True)
+
+
 def main(only=None):
     path = os.path.join(HERE, "parity_tolerances.json")
-    out = json.load(open(path)) if os.path.exists(path) else {}
     for case, (name, scheme, steps) in CASES.items():
         if only and case not in only:
             continue
         floor = floors(name, scheme, steps, U)
         tol = {f: max(1e-11, 10.0 * v) for f, v in floor.items()}
-        out[case] = {"floor": floor, "tol": tol}
-        print(case, out[case], flush=True)
-        json.dump(out, open(path, "w"), indent=1, sort_keys=True)
+        _store(path, case, {"floor": floor, "tol": tol})
     for case, (name, scheme, steps) in CASES32.items():
         if only and case not in only:
             continue
         floor = floors(name, scheme, steps, U32)
         tol = {f: 30.0 * v for f, v in floor.items()}
-        out[case] = {"floor": floor, "tol": tol}
-        print(case, out[case], flush=True)
-        json.dump(out, open(path, "w"), indent=1, sort_keys=True)
+        _store(path, case, {"floor": floor, "tol": tol})
 
 
 if __name__ == "__main__":

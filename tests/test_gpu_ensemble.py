@@ -53,9 +53,12 @@ def _pick(ws, per_size=2):
     return out
 
 
-def test_ensemble_members_equal_solo_runs(qg):
+@pytest.mark.parametrize("sizes", [(65, 129, 257), (257,)])
+def test_ensemble_members_equal_solo_runs(qg, sizes):
+    """Three size groups running side by side, and a single group (whose
+    graph replays follow each other directly on one stream)."""
     ws = inputs.ensemble_workloads()
-    idx = _pick(ws)
+    idx = [i for i in _pick(ws) if ws[i].n_r in sizes]
     sel = [ws[i] for i in idx]
     _say(f"[ensemble] members {idx} sizes "
          f"{[(w.n_phi, w.n_r) for w in sel]}")
