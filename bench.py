@@ -218,6 +218,8 @@ def main():
     ap.add_argument("--no-ensemble", action="store_true",
                     help="skip the batched-ensemble run")
     ap.add_argument("--ens-steps", type=int, default=20)
+    ap.add_argument("--ensemble-only", action="store_true",
+                    help="only the batched-ensemble run (for profiling it)")
     ap.add_argument("--precision", choices=("fp64", "mixed"), default="fp64",
                     help="precision of the headline run (mixed also runs the "
                          "12288 x 4097 workload, which FP64 does not fit)")
@@ -238,6 +240,10 @@ def main():
         return
 
     from paper_1902_07092_amd import inputs, qg
+    if args.ensemble_only:
+        print(json.dumps({"batched": ensemble_run(qg, torch, inputs, args)}),
+              flush=True)
+        return
     w = inputs.WORKLOADS[args.workload]
     state = inputs.workload_state(w)
     prec = 1 if args.precision == "mixed" else 0
