@@ -259,8 +259,11 @@ class QGSolver:
     def __del__(self):
         ctx = getattr(self, "ctx", None)
         if ctx:
-            qg_destroy(ctx)
             self.ctx = None
+            try:
+                qg_destroy(ctx)
+            except TypeError:   # interpreter shutdown: module already torn down
+                pass
 
     def _arrays(self, psi, theta, uphi):
         torch = self.torch
@@ -344,8 +347,11 @@ class QGEnsemble:
     def __del__(self):
         ens = getattr(self, "ens", None)
         if ens:
-            qg_ensemble_destroy(ens)
             self.ens = None
+            try:
+                qg_ensemble_destroy(ens)
+            except TypeError:   # interpreter shutdown: module already torn down
+                pass
 
     def set_state(self, member, psi, theta, uphi):
         M, K = self.shapes[member]

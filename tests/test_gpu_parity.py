@@ -224,3 +224,48 @@ def test_error_paths(qg):
     with pytest.raises(qg.QGError) as e:
         qg.QGSolver(1e-3, 8e4, 1.0, 0.35, 96, 34)
     assert e.value.status == qg.QG_EUNSUPPORTED
+
+
+@pytest.mark.parametrize("n_phi,n_r,precision", [(6144, 2049, 0),
+                                                 (12288, 4097, 1)])
+def test_largest_sizes_axisymmetric_temperature(qg, n_phi, n_r, precision):
+    """The largest sizes each precision accepts, on a state whose step the
+    oracle can take row by row: Psi = 0, zonal flow 0, theta in the m = 0
+    row only.  Then u = 0, every advection product vanishes (also in FP32)
+    and buoyancy has no m = 0 part, so theta_0 evolves by the bordered
+    CNAB2 solve of eq. temp_int alone while every other row must stay
+    exactly zero.  Reference: the oracle's integration operators and
+    bordered solver for the m = 0 system."""
+    from oracle.bordered import BorderedSolver
+    from oracle.operators import (IntegrationOperators, bordered_lhs,
+                                  tau_rows_dirichlet)
+    w = inputs.LARGE
+    K = (2 * (n_r - 1)) // 3
+    M = n_phi // 3 + 1
+    _say(f"[parity] largest size {n_phi}x{n_r} precision {precision}")
+    rng = np.random.default_rng(17)
+    c = 1e-3 * rng.standard_normal(K) * np.exp(-np.arange(K) / (K / 32.0))
+    th0 = inputs.dirichlet_from_basis(c, K)
+    psi = np.zeros((M, K), np.complex128)
+    theta = np.zeros((M, K), np.complex128)
+    theta[0] = th0
+    s = qg.QGSolver(w.E, w.Ra, w.Pr, w.eta, n_phi, n_r, K,
+                    precision=precision)
+    s.set_state(psi, theta, np.zeros(K))
+    dt, steps = 1e-8, 5
+    s.step(dt, "cnab2", steps)
+    p, t, u = s.get_state()
+    ops = IntegrationOperators(w.eta, K)
+    F0 = ops.F(0) / w.Pr
+    S = BorderedSolver(bordered_lhs(tau_rows_dirichlet(K),
+                                    ops.D - 0.5 * dt * F0), 2)
+    y = th0.copy()
+    for _ in range(steps):
+        r = ops.D @ y + 0.5 * dt * (F0 @ y)
+        r[:2] = 0
+        y = S.solve(r)
+    err = float(np.abs(t[0].real - y).max() / np.abs(y).max())
+    _say(f"  theta_0 rel err {err:.2e}")
+    assert err <= 1e-11, err
+    assert not t[0].imag.any() and not t[1:].any()
+    assert not p.any() and not u.any()
