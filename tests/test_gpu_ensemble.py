@@ -120,3 +120,31 @@ def test_ensemble_member_matches_oracle(qg):
     tol = _TOLS["ensemble7_cnab2_10"]["tol"]
     _say(f"  rel err {err} tol {tol}")
     assert all(err[f] <= max(1e-11, tol[f]) for f in err), err
+
+
+def test_ensemble_error_paths(qg):
+    ws = inputs.ensemble_workloads()
+    sel = [ws[7], ws[10]]
+    ens = qg.QGEnsemble([_member(w) for w in sel])
+    st = inputs.workload_state(sel[0])
+    import ctypes
+    ps = np.ascontiguousarray(st.psi)
+    th = np.ascontiguousarray(st.theta)
+    up = np.ascontiguousarray(st.uphi0)
+    with pytest.raises(qg.QGError) as e:                    # no such member
+        qg.qg_ensemble_set_state(ens.ens, 2, ctypes.c_void_p(ps.ctypes.data),
+                                 ctypes.c_void_p(th.ctypes.data),
+                                 ctypes.c_void_p(up.ctypes.data), 0)
+    assert e.value.status == qg.QG_EINVAL
+    bad = st.theta.copy()
+    bad[3, 5] = np.nan
+    with pytest.raises(qg.QGError) as e:
+        ens.set_state(0, st.psi, bad, st.uphi0)
+    assert e.value.status == qg.QG_ENONFINITE
+    with pytest.raises(qg.QGError) as e:
+        ens.step(-1.0, "cnab2", 1)
+    assert e.value.status == qg.QG_EINVAL
+    # the ensemble still works after rejected calls
+    ens.set_state(0, st.psi, st.theta, st.uphi0)
+    ens.step(sel[0].dt, "cnab2", 3)
+    assert np.isfinite(ens.get_state(0)[0]).all()
