@@ -29,14 +29,17 @@ METRIC = "grid-point-steps/s FP64 vs mixed/batched; adjoint/forward time ratio"
 HBM_PEAK_GBS = 8000.0
 
 
-def alg_bytes(kernel, M, R, K, nterm=2):
-    """Compulsory HBM bytes of one launch (FP64 complex = 16 B): the
-    kernel's own inputs and outputs, factor re-reads excluded."""
+def alg_bytes(kernel, M, R, K, nterm=2, mixed=False):
+    """Compulsory HBM bytes of one launch: the kernel's own inputs and
+    outputs, factor re-reads excluded.  Spectral arrays are FP64 complex
+    (16 B); the exchange arrays X and NL are too, or FP32 complex (8 B) in
+    the mixed-precision step."""
     c = 16
+    x = 8 if mixed else 16
     return {
-        "synth": 2 * M * K * c + 6 * R * M * c,
-        "ring": 8 * R * M * c + 8 * R,
-        "analysis": 2 * R * M * c + 8 * R + 3 * M * K * c,
+        "synth": 2 * M * K * c + 6 * R * M * x,
+        "ring": 8 * R * M * x + 8 * R,
+        "analysis": 2 * R * M * x + 8 * R + 3 * M * K * c,
         "solve": 2 * 2 * M * K * c,
         "rhs": (2 + nterm) * 2 * M * K * c,
     }[kernel]
@@ -271,9 +274,10 @@ def main():
     dominant = max(kern, key=lambda k: kern[k][0])
     ms_tot, launches = kern[dominant]
     avg_s = ms_tot / launches * 1e-3
-    ab = alg_bytes(dominant, M, R, K)
+    ab = alg_bytes(dominant, M, R, K, mixed=prec == 1)
     achieved = ab / avg_s / 1e9
-    traffic = traffic_for(dominant, w.name)
+    # counters were taken on the FP64 kernels only
+    traffic = traffic_for(dominant, w.name) if prec == 0 else None
     roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                 "traffic": traffic, "kernel": dominant,
@@ -281,7 +285,8 @@ def main():
                 "avg_launch_us": avg_s * 1e6}
     kernels = {k: {"avg_launch_us": v[0] / max(1, v[1]) * 1e3,
                    "launches": v[1],
-                   "alg_GBps": alg_bytes(k, M, R, K) / (v[0] / max(1, v[1])
+                   "alg_GBps": alg_bytes(k, M, R, K, mixed=prec == 1)
+                   / (v[0] / max(1, v[1])
                                                         * 1e-3) / 1e9,
                    "factor_bytes_per_launch": factor_bytes(k, M, K)}
                for k, v in kern.items()}

@@ -161,10 +161,13 @@ void qg_destroy(qg_ctx *ctx);
  * each kernel advances every run of a group (the run is a grid dimension),
  * and the runs of a group share operators, twiddle tables and LU factors
  * (the bordered matrices do not depend on Ra, Sect. 3.2 and Appendix A).
- * Steps after the first are captured once into a HIP graph per (dt,
- * scheme) and replayed; each member's arithmetic is exactly that of a
- * single-run context with its parameters, so results are identical to
- * stepping it alone.
+ * Each group runs on a stream of its own, forked from and joined back to
+ * the ensemble's stream around every step, so that groups overlap.  Steps
+ * after the first are captured once per (dt, scheme) into one HIP graph
+ * per group (on the group's stream) and replayed; each member's arithmetic
+ * is exactly that of a single-run context with its parameters, so results
+ * are identical to stepping it alone.  An ensemble must not be used from
+ * two threads at once.
  */
 typedef struct qg_ensemble qg_ensemble;
 
