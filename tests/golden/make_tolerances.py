@@ -1,6 +1,9 @@
 """Write tests/golden/parity_tolerances.json: the FP64 rounding floor of
 the oracle for each GPU parity case, measured by re-running the oracle with
-rounding-level noise injected into every transform and derivative.
+rounding-level noise injected into every transform and derivative, the
+advection products and the zonal average, and (always at the FP64 level:
+the solves are FP64 in both precisions) the right-hand side of every
+bordered solve.
 
 A backward-stable transform (FFT, DCT, coefficient recurrence) returns y
 with |y - y_exact| <= c u ||y||, u = 2^-53 (2^-24 for the FP32 transforms
@@ -62,6 +65,39 @@ def _noisy(fn, rng, u):
     return wrapped
 
 
+def _noisy_products(fn, rng, u):
+    """Rounding of the advection products: relative u per grid point; the
+    zonal forcing is an average of N_phi products with cancellation (a
+    Parseval sum over m on the GPU), rounded at u times the mean magnitude
+    of its terms."""
+    def wrapped(psi, theta, uphi):
+        a = fn(psi, theta, uphi)
+        for key in ("n_om", "n_th"):
+            g = a[key]
+            a[key] = g + u * np.abs(g) * rng.standard_normal(g.shape)
+        scale = np.mean(np.abs(a["us"] * a["om"]), axis=1)
+        a["n_u"] = a["n_u"] + u * scale * rng.standard_normal(scale.shape)
+        return a
+    return wrapped
+
+
+def _noisy_solve(fn, rng, u):
+    """A backward-stable bordered solve returns the exact solution of a
+    right-hand side perturbed componentwise at u (the rows of the
+    integrated equations differ in size by many orders): the two
+    implementations' solves differ by that, amplified by the
+    conditioning."""
+    def pert(r):
+        n = rng.standard_normal(r.shape)
+        if np.iscomplexobj(r):
+            n = n + 1j * rng.standard_normal(r.shape)
+        return r + u * np.abs(r) * n
+
+    def wrapped(a_dt, rp, rt, ru):
+        return fn(a_dt, pert(rp), pert(rt), pert(ru))
+    return wrapped
+
+
 def workload(name):
     if name.startswith("ensemble:"):
         return inputs.ensemble_workloads()[int(name.split(":")[1])]
@@ -78,6 +114,9 @@ def run(name, scheme, steps, seed, u=U):
             setattr(tr, f, _noisy(orig[f], rng, u))
     try:
         o = QGOracle(w.E, w.Ra, w.Pr, w.eta, w.n_phi, w.n_r, w.n_c)
+        if seed is not None:
+            o.advection_grid = _noisy_products(o.advection_grid, rng, u)
+            o.solve = _noisy_solve(o.solve, rng, U)
         o.set_state(st.psi, st.theta, st.uphi0)
         o.step(w.dt, scheme, steps)
     finally:
