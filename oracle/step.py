@@ -161,7 +161,8 @@ class QGOracle:
         """Advection terms on the (N_r, N_phi) grid, eqs. vort, uphi, temp:
         N_omega = div(u omega), N_theta = u.grad(theta) + u_s dT_c/ds
         (div(u theta) + beta u_s theta = u.grad(theta) by eq. cont) and the
-        zonal forcing mean_phi(u_s omega); also u_s and theta on the grid."""
+        zonal forcing mean_phi(u_s omega); also u_s, omega and theta on the
+        grid."""
         f = self.spectral_fields(psi, theta, uphi)
         n_phi = self.n_phi
         im = 1j * self.mvec[:, None]
@@ -178,7 +179,7 @@ class QGOracle:
         n_om = us * dom + uph / s * dpom + om * divu
         n_th = us * (dth + self.dtc[:, None]) + uph / s * dpth
         n_u = np.mean(us * om, axis=1)
-        return dict(n_om=n_om, n_th=n_th, n_u=n_u, us=us, th=th)
+        return dict(n_om=n_om, n_th=n_th, n_u=n_u, us=us, th=th, om=om)
 
     def explicit(self, psi, theta, uphi):
         """Explicit right-hand sides (K-vectors, rows >= q meaningful):
