@@ -4,7 +4,8 @@
 Workload (default): 3072 x 1025 grid (N_m = 1024, N_c = 682), E = 1e-8,
 Pr = 1, Ra = 20 Ra_c, CNAB2, dt = 2.5e-10, seeded turbulent-like initial
 state (k^-5/3 spectrum steepening past m ~ 20, random phases, Re = 1e4).
-Beside it: the same steps with FP32 transforms and products, and the
+Beside it: the same steps with FP32 transforms and products, the cost of
+one step of every other time scheme of Table 1 relative to CNAB2, and the
 batched ensemble of 64 runs of uneven size and Ra.  A step is one CNAB2 step of the
 whole hot path: Chebyshev synthesis, azimuthal FFTs and products, radial
 analysis, explicit terms, right-hand sides and the bordered solves of every
@@ -159,6 +160,37 @@ def mixed_run(qg, torch, w, state, args, fp64_solver):
                             "launches": v[1]} for k, v in kern.items()}}
 
 
+# Cost of one step relative to CNAB2, Table 1 of the paper (its own
+# CPU runs, integration + Galerkin at 1025 x 682 x 1280): context only.
+TABLE1_COST = {"sbdf4": 1.01, "sbdf3": 0.97, "sbdf2": 0.96, "cnab2": 1.0,
+               "bpr353": 3.24, "ars443": 3.66, "ars222": 1.81}
+
+
+def schemes_run(qg, torch, w, state, args):
+    """Every time scheme of Table 1 (except LZ232) on the same workload:
+    a fresh start per scheme, warm-up steps past the SBDF start-up and the
+    refactorisation, then args.scheme_steps timed steps."""
+    s = qg.QGSolver(w.E, w.Ra, w.Pr, w.eta, w.n_phi, w.n_r, w.n_c,
+                    device="cuda:0")
+    out = {}
+    for name in ("cnab2", "sbdf2", "sbdf3", "sbdf4", "bpr353", "ars222",
+                 "ars443"):
+        s.set_state(state.psi, state.theta, state.uphi0)
+        s.step(w.dt, name, 4)
+        torch.cuda.synchronize()
+        start = torch.cuda.Event(enable_timing=True)
+        stop = torch.cuda.Event(enable_timing=True)
+        start.record(s.stream)
+        s.step(w.dt, name, args.scheme_steps)
+        stop.record(s.stream)
+        torch.cuda.synchronize()
+        out[name] = {"ms_per_step": start.elapsed_time(stop) / args.scheme_steps}
+    for name, v in out.items():
+        v["cost_vs_cnab2"] = v["ms_per_step"] / out["cnab2"]["ms_per_step"]
+        v["table1_cost_vs_cnab2"] = TABLE1_COST[name]
+    return out
+
+
 def ensemble_run(qg, torch, inputs, args):
     """The batched ensemble: 64 runs of uneven size and Ra stepped together
     (one launch per kernel and size group, graph replay), against the same
@@ -221,6 +253,9 @@ def main():
     ap.add_argument("--no-ensemble", action="store_true",
                     help="skip the batched-ensemble run")
     ap.add_argument("--ens-steps", type=int, default=20)
+    ap.add_argument("--no-schemes", action="store_true",
+                    help="skip the per-scheme step costs")
+    ap.add_argument("--scheme-steps", type=int, default=10)
     ap.add_argument("--ensemble-only", action="store_true",
                     help="only the batched-ensemble run (for profiling it)")
     ap.add_argument("--precision", choices=("fp64", "mixed"), default="fp64",
@@ -308,6 +343,9 @@ def main():
         out["mixed"] = mixed_run(qg, torch, w, state, args, solver)
         print(f"[bench] mixed done: {out['mixed']['ms_per_step']:.4f} ms/step",
               file=sys.stderr, flush=True)
+    if not args.no_schemes and prec == 0:
+        out["schemes"] = schemes_run(qg, torch, w, state, args)
+        print("[bench] schemes done", file=sys.stderr, flush=True)
     if not args.no_ensemble and prec == 0:
         out["batched"] = ensemble_run(qg, torch, inputs, args)
         print(f"[bench] ensemble done: {out['batched']['ms_per_step']:.4f} "

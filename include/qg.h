@@ -55,7 +55,26 @@ typedef enum {
   QG_EUNSUPPORTED = -6  /* valid for the method, not for this build's kernels */
 } qg_status;
 
-typedef enum { QG_CNAB2 = 0, QG_BPR353 = 1 } qg_scheme;
+/* IMEX time schemes of Table 1 (Sect. 4), explicit buoyancy:
+ *   QG_CNAB2   Crank-Nicolson / Adams-Bashforth 2 (multistep, order 2)
+ *   QG_BPR353  Boscarino-Pareschi-Russo SDIRK, 5 stages (order 3)
+ *   QG_ARS222  Ascher-Ruuth-Spiteri SDIRK (2,2,2) (order 2)
+ *   QG_ARS443  Ascher-Ruuth-Spiteri SDIRK (4,4,3) (order 3)
+ *   QG_SBDF2..4  semi-implicit backward differences (multistep, order
+ *              2..4); not self-starting: while fewer than k levels are
+ *              stored, SBDFk takes BPR353 steps (their factorisation is
+ *              rebuilt on the switch, synchronously).
+ * Multistep histories belong to the scheme and dt that made them: a step
+ * with another scheme or dt restarts the history. */
+typedef enum {
+  QG_CNAB2 = 0,
+  QG_BPR353 = 1,
+  QG_ARS222 = 2,
+  QG_ARS443 = 3,
+  QG_SBDF2 = 4,
+  QG_SBDF3 = 5,
+  QG_SBDF4 = 6
+} qg_scheme;
 
 typedef struct {
   double E;      /* Ekman number  nu / (Omega d^2)            (eq. controls) */
@@ -118,7 +137,7 @@ qg_status qg_create(qg_ctx **ctx, const qg_params *p, void *workspace,
 /* Copy a state in.  Host inputs are checked: non-finite values give
  * QG_ENONFINITE, boundary-condition residuals above 1e-10 relative give
  * QG_ESTATE (tau conditions, Sect. 3.2.2).  Resets t, the step counter and
- * the CNAB2 history. */
+ * the multistep history. */
 qg_status qg_set_state(qg_ctx *ctx, const double *psi, const double *theta,
                        const double *uphi, int on_device);
 
@@ -127,10 +146,11 @@ qg_status qg_get_state(qg_ctx *ctx, double *psi, double *theta, double *uphi,
                        int on_device);
 
 /* Advance nsteps steps of size dt with the given scheme (qg_scheme).  The
- * bordered LU factors of every m are rebuilt on the host whenever dt
- * changes (Sect. 3.1: factorisation at start-up and on a time-step
- * change).  CNAB2 uses E^{n-1} := E^n on its first step after
- * qg_set_state. */
+ * bordered LU factors of every m are rebuilt on the host (synchronously)
+ * whenever the implicit coefficient a_ii dt changes (Sect. 3.1:
+ * factorisation at start-up and on a time-step change).  CNAB2 uses
+ * E^{n-1} := E^n on the first step of its history.  QG_EINVAL for an
+ * unknown scheme, dt <= 0 or nsteps < 0. */
 qg_status qg_step(qg_ctx *ctx, double dt, int scheme, int nsteps);
 
 /* qg_step with per-kernel timing, for benchmarks: HIP events are recorded
@@ -141,7 +161,8 @@ qg_status qg_step(qg_ctx *ctx, double dt, int scheme, int nsteps);
  *   products (per radial level)   2 analysis (forward DCT + explicit terms,
  *   per m)   3 bordered solves of every system (one launch)   4 right-hand
  *   sides of every system (one launch).
- * A dt change refactorises before the timed steps. */
+ * A dt or scheme change refactorises before the timed steps (SBDF
+ * start-up steps refactorise inside them). */
 qg_status qg_step_timed(qg_ctx *ctx, double dt, int scheme, int nsteps,
                         double *kernel_ms, int *launches);
 
@@ -164,7 +185,8 @@ void qg_destroy(qg_ctx *ctx);
  * Each group runs on a stream of its own, forked from and joined back to
  * the ensemble's stream around every step, so that groups overlap.  Steps
  * after the first are captured once per (dt, scheme) into one HIP graph
- * per group (on the group's stream) and replayed; each member's arithmetic
+ * per group (on the group's stream) and replayed (CNAB2 and the SDIRK
+ * schemes; SBDF steps run eagerly); each member's arithmetic
  * is exactly that of a single-run context with its parameters, so results
  * are identical to stepping it alone.  An ensemble must not be used from
  * two threads at once.
@@ -198,9 +220,9 @@ qg_status qg_ensemble_get_state(qg_ensemble *e, int member, double *psi,
                                 double *theta, double *uphi, int on_device);
 
 /* Advance every member nsteps steps of size dt with the given scheme
- * (qg_step's rules: refactorisation on a dt change, synchronous; CNAB2's
- * first step after a restart uses E^{n-1} := E^n).  Asynchronous on the
- * ensemble's stream otherwise. */
+ * (qg_step's rules: refactorisation on a change of a_ii dt, synchronous;
+ * the multistep history rules).  Asynchronous on the ensemble's stream
+ * otherwise. */
 qg_status qg_ensemble_step(qg_ensemble *e, double dt, int scheme, int nsteps);
 
 /* Diagnostics of member `member` (synchronises the stream). */

@@ -25,6 +25,16 @@ Readings (where the paper is silent or inconsistent):
   * CNAB2 starts with E^{n-1} := E^n.
   * BPR353: the tableau of Boscarino, Pareschi & Russo (2013, Sect. 8.3),
     five stages, a_ii = 1/2, first stage explicit, stiffly accurate.
+  * ARS222 and ARS443 (Table 1): the stiffly accurate SDIRK tableaux of
+    Ascher, Ruuth & Spiteri (1997, Sects. 2.6 and 2.8); a_ii = 1 - 1/sqrt 2
+    and 1/2.
+  * SBDF2, SBDF3, SBDF4 (Table 1): the semi-implicit backward-difference
+    schemes sum_j a_j y^{n+1-j} = dt (L y^{n+1} + sum_j b_j E^{n+1-j}), with
+    the mass matrix on every y (as for CNAB2).  They are not self-starting:
+    SBDFk takes BPR353 steps until k levels are stored, which keeps the
+    global order k for k <= 4.
+  * A multistep history belongs to the scheme and dt that made it: a step
+    with another scheme or dt starts afresh.
 """
 import numpy as np
 
@@ -49,6 +59,43 @@ BPR353_AI = np.array([[0, 0, 0, 0, 0],
                       [5 / 18, -1 / 9, 1 / 2, 0, 0],
                       [1 / 2, 0, 0, 1 / 2, 0],
                       [1 / 4, 0, 3 / 4, -1 / 2, 1 / 2]], dtype=np.float64)
+
+
+# ARS(2,2,2) (Ascher, Ruuth & Spiteri 1997, Sect. 2.6): gamma = 1 - 1/sqrt 2,
+# delta = 1 - 1/(2 gamma); first stage explicit, stiffly accurate.
+_GAM = 1.0 - 1.0 / np.sqrt(2.0)
+_DEL = 1.0 - 1.0 / (2.0 * _GAM)
+ARS222_AE = np.array([[0, 0, 0],
+                      [_GAM, 0, 0],
+                      [_DEL, 1 - _DEL, 0]], dtype=np.float64)
+ARS222_AI = np.array([[0, 0, 0],
+                      [0, _GAM, 0],
+                      [0, 1 - _GAM, _GAM]], dtype=np.float64)
+
+# ARS(4,4,3) (same paper, Sect. 2.8): a_ii = 1/2, stiffly accurate.
+ARS443_AE = np.array([[0, 0, 0, 0, 0],
+                      [1 / 2, 0, 0, 0, 0],
+                      [11 / 18, 1 / 18, 0, 0, 0],
+                      [5 / 6, -5 / 6, 1 / 2, 0, 0],
+                      [1 / 4, 7 / 4, 3 / 4, -7 / 4, 0]], dtype=np.float64)
+ARS443_AI = np.array([[0, 0, 0, 0, 0],
+                      [0, 1 / 2, 0, 0, 0],
+                      [0, 1 / 6, 1 / 2, 0, 0],
+                      [0, -1 / 2, 1 / 2, 1 / 2, 0],
+                      [0, 3 / 2, -3 / 2, 1 / 2, 1 / 2]], dtype=np.float64)
+
+DIRK = {"bpr353": (BPR353_AE, BPR353_AI),
+        "ars222": (ARS222_AE, ARS222_AI),
+        "ars443": (ARS443_AE, ARS443_AI)}
+
+# SBDFk: a = (a_0 .. a_k) on y^{n+1} .. y^{n+1-k}, b = (b_1 .. b_k) on
+# E^n .. E^{n+1-k} (backward-difference formulas of orders 2, 3, 4 with
+# explicit terms extrapolated to the same order).
+SBDF = {"sbdf2": ((3 / 2, -2, 1 / 2), (2, -1)),
+        "sbdf3": ((11 / 6, -3, 3 / 2, -1 / 3), (3, -3, 1)),
+        "sbdf4": ((25 / 12, -4, 3, -4 / 3, 1 / 4), (4, -6, 4, -1))}
+
+SCHEMES = ("cnab2", "sbdf2", "sbdf3", "sbdf4", "bpr353", "ars222", "ars443")
 
 
 class QGOracle:
@@ -77,6 +124,8 @@ class QGOracle:
         self.t = 0.0
         self.nstep = 0
         self._hist = None
+        self._ms = None
+        self._last = None
 
     # ---------------------------------------------------------------- state
     def set_state(self, psi, theta, uphi0):
@@ -84,6 +133,8 @@ class QGOracle:
         self.theta = np.array(theta, np.complex128, copy=True)
         self.uphi = np.array(uphi0, np.float64, copy=True)
         self._hist = None
+        self._ms = None
+        self._last = None
 
     # ------------------------------------------------------------ operators
     def mass(self, psi, theta, uphi):
@@ -218,8 +269,10 @@ class QGOracle:
         self.t += dt
         self.nstep += 1
 
-    def step_bpr353(self, dt):
-        AE, AI = BPR353_AE, BPR353_AI
+    def step_dirk(self, dt, AE, AI):
+        """One stiffly accurate IMEX DIRK step with a first explicit stage
+        (Sect. 4, eq. dirks): (M - a_ii dt L) y_i = M y^n
+        + dt sum_{j<i} (aE_ij E(y_j) + aI_ij L y_j); y^{n+1} = y_last."""
         nu = AE.shape[0]
         y = [(self.psi, self.theta, self.uphi)]
         My = self.mass(*y[0])
@@ -245,11 +298,46 @@ class QGOracle:
         self.t += dt
         self.nstep += 1
 
+    def step_bpr353(self, dt):
+        self.step_dirk(dt, BPR353_AE, BPR353_AI)
+
+    def step_sbdf(self, dt, a, b):
+        """One SBDFk step, k = len(b):
+        (M - (dt/a_0) L) y^{n+1} = sum_{j=1}^{k} (-a_j/a_0) M y^{n+1-j}
+                                   + (dt/a_0) sum_{j=1}^{k} b_j E^{n+1-j};
+        BPR353 steps while fewer than k levels are stored."""
+        k = len(b)
+        y = (self.psi, self.theta, self.uphi)
+        if self._ms is None:
+            self._ms = []
+        self._ms.insert(0, (y, self.explicit(*y)))     # most recent first
+        del self._ms[k:]
+        if len(self._ms) < k:
+            self.step_dirk(dt, BPR353_AE, BPR353_AI)
+            return
+        masses = [self.mass(*lev[0]) for lev in self._ms]
+        rhs = []
+        for f in range(3):
+            r = np.zeros_like(y[f])
+            for j in range(k):
+                r = r + (-a[j + 1] / a[0]) * masses[j][f]
+                r = r + (dt * b[j] / a[0]) * self._ms[j][1][f]
+            rhs.append(r)
+        self.psi, self.theta, self.uphi = self.solve(dt / a[0], *rhs)
+        self.t += dt
+        self.nstep += 1
+
     def step(self, dt, scheme="cnab2", n=1):
+        if scheme not in SCHEMES:
+            raise ValueError(scheme)
         for _ in range(n):
+            if self._last != (scheme, dt):
+                self._hist = None
+                self._ms = None
+                self._last = (scheme, dt)
             if scheme == "cnab2":
                 self.step_cnab2(dt)
-            elif scheme == "bpr353":
-                self.step_bpr353(dt)
+            elif scheme in DIRK:
+                self.step_dirk(dt, *DIRK[scheme])
             else:
-                raise ValueError(scheme)
+                self.step_sbdf(dt, *SBDF[scheme])

@@ -1,5 +1,6 @@
 // C ABI of the QG step: context, workspace layout, host-side factorisation,
-// and the kernel sequence of the CNAB2 and BPR353 schemes.
+// and the kernel sequences of the time schemes (CNAB2, SBDF2-4, BPR353,
+// ARS222, ARS443).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -19,6 +20,7 @@ size_t solve_lds_bytes(const Geom& g, int kutp, int kutr);
 void launch_rhs(const Geom& g, const Bands& b, const RhsSpec& rs, double2* rhs, hipStream_t st);
 void launch_lin(const Geom& g, const Bands& b, const double2* ypsi, const double2* yth,
                 double2* lpsi, double2* lth, hipStream_t st);
+void launch_combine(const Combine& cb, double2* out, size_t n, hipStream_t st);
 bool launch_solve(const Geom& g, const FactorSet<double2>& Fp, const FactorSet<double>& Fr,
                   double2* rhs, const RhsSpec& rs, int kutp, int kutr, bool pivoted,
                   hipStream_t st);
@@ -32,19 +34,81 @@ using namespace qg;
 
 namespace {
 
-// BPR353 Butcher tables (Boscarino, Pareschi & Russo 2013, Sect. 8.3):
-// explicit and implicit, five stages, a_ii = 1/2 after an explicit first
-// stage, stiffly accurate (paper Table 1, eq. dirks).
-const double BPR_AE[5][5] = {{0, 0, 0, 0, 0},
-                             {1, 0, 0, 0, 0},
-                             {4.0 / 9, 2.0 / 9, 0, 0, 0},
-                             {0.25, 0, 0.75, 0, 0},
-                             {0.25, 0, 0.75, 0, 0}};
-const double BPR_AI[5][5] = {{0, 0, 0, 0, 0},
-                             {0.5, 0.5, 0, 0, 0},
-                             {5.0 / 18, -1.0 / 9, 0.5, 0, 0},
-                             {0.5, 0, 0, 0.5, 0},
-                             {0.25, 0, 0.75, -0.5, 0.5}};
+// Stiffly accurate SDIRK schemes with an explicit first stage (paper
+// Sect. 4, eq. dirks; Table 1): s stages, a_ii = diag for i >= 1, the last
+// stage is the new state.
+struct Dirk {
+  int s;
+  double diag;
+  double AE[5][5];
+  double AI[5][5];
+};
+
+// BPR353: Boscarino, Pareschi & Russo (2013), Sect. 8.3.
+const Dirk BPR353 = {5,
+                     0.5,
+                     {{0, 0, 0, 0, 0},
+                      {1, 0, 0, 0, 0},
+                      {4.0 / 9, 2.0 / 9, 0, 0, 0},
+                      {0.25, 0, 0.75, 0, 0},
+                      {0.25, 0, 0.75, 0, 0}},
+                     {{0, 0, 0, 0, 0},
+                      {0.5, 0.5, 0, 0, 0},
+                      {5.0 / 18, -1.0 / 9, 0.5, 0, 0},
+                      {0.5, 0, 0, 0.5, 0},
+                      {0.25, 0, 0.75, -0.5, 0.5}}};
+
+// ARS222: Ascher, Ruuth & Spiteri (1997), Sect. 2.6, with
+// gamma = 1 - 1/sqrt 2 and delta = 1 - 1/(2 gamma).
+const double ARS_G = 1.0 - 1.0 / std::sqrt(2.0);
+const double ARS_D = 1.0 - 1.0 / (2.0 * ARS_G);
+const Dirk ARS222 = {3,
+                     ARS_G,
+                     {{0, 0, 0}, {ARS_G, 0, 0}, {ARS_D, 1.0 - ARS_D, 0}},
+                     {{0, 0, 0}, {0, ARS_G, 0}, {0, 1.0 - ARS_G, ARS_G}}};
+
+// ARS443: the same paper, Sect. 2.8.
+const Dirk ARS443 = {5,
+                     0.5,
+                     {{0, 0, 0, 0, 0},
+                      {0.5, 0, 0, 0, 0},
+                      {11.0 / 18, 1.0 / 18, 0, 0, 0},
+                      {5.0 / 6, -5.0 / 6, 0.5, 0, 0},
+                      {0.25, 1.75, 0.75, -1.75, 0}},
+                     {{0, 0, 0, 0, 0},
+                      {0, 0.5, 0, 0, 0},
+                      {0, 1.0 / 6, 0.5, 0, 0},
+                      {0, -0.5, 0.5, 0.5, 0},
+                      {0, 1.5, -1.5, 0.5, 0.5}}};
+
+// SBDFk (Table 1): sum_{j=0}^{k} a_j y^{n+1-j} = dt (L y^{n+1}
+// + sum_{j=1}^{k} b_j E^{n+1-j}), the mass matrix on every y.
+struct Sbdf {
+  int k;
+  double a[5];
+  double b[4];
+};
+const Sbdf SBDF2 = {2, {1.5, -2.0, 0.5}, {2.0, -1.0}};
+const Sbdf SBDF3 = {3, {11.0 / 6, -3.0, 1.5, -1.0 / 3}, {3.0, -3.0, 1.0}};
+const Sbdf SBDF4 = {4, {25.0 / 12, -4.0, 3.0, -4.0 / 3, 0.25}, {4.0, -6.0, 4.0, -1.0}};
+
+const Dirk* dirk_of(int scheme) {
+  switch (scheme) {
+    case QG_BPR353: return &BPR353;
+    case QG_ARS222: return &ARS222;
+    case QG_ARS443: return &ARS443;
+    default: return nullptr;
+  }
+}
+
+const Sbdf* sbdf_of(int scheme) {
+  switch (scheme) {
+    case QG_SBDF2: return &SBDF2;
+    case QG_SBDF3: return &SBDF3;
+    case QG_SBDF4: return &SBDF4;
+    default: return nullptr;
+  }
+}
 
 bool is_pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
 
@@ -90,7 +154,7 @@ bool sizes_of(const qg_params* p, Sizes& z, std::string& why) {
 
 struct WsMap {
   size_t ra;
-  size_t state, ybuf, eslot, lslot, X, NL, zonal, rate, diag, xk, wq, dsk, twd, twp, twh, wphi,
+  size_t state, ybuf, eslot, lslot, mE, mY, X, NL, zonal, rate, diag, xk, wq, dsk, twd, twp, twh, wphi,
       twd32, twp32, twh32, wphi32, bands, rhs;
   size_t p_piv, p_L, p_U, p_W, p_C, p_Mi, p_ui;
   size_t r_piv, r_L, r_U, r_W, r_C, r_Mi, r_ui;
@@ -109,8 +173,10 @@ WsMap map_workspace(const Sizes& z, int nmem) {
   w.ra = L.take(nm * sizeof(double));
   w.state = L.take(2 * MK);
   w.ybuf = L.take(4 * MK);
-  w.eslot = L.take(6 * MK);
-  w.lslot = L.take(8 * MK);
+  w.eslot = L.take(8 * MK);   // DIRK explicit stages (4)
+  w.lslot = L.take(8 * MK);   // DIRK implicit stage products (4)
+  w.mE = L.take(8 * MK);      // SBDF explicit terms E^n .. E^{n-3}
+  w.mY = L.take(6 * MK);      // SBDF past states y^{n-1} .. y^{n-3}
   w.X = L.take(6 * RM);
   w.NL = L.take(2 * RM);
   w.zonal = L.take(nm * z.R * sizeof(double));
@@ -168,7 +234,10 @@ struct qg_ctx {
   bool diag64 = true;        // FP64 transform kernels exist for the diagnostics
   double growth = 0.0;       // largest growth factor of the band LUs in use
   double factored_adt = -1.0;
-  int have_prev = 0, cur = 0;
+  int have_prev = 0, cur = 0;   // CNAB2 history
+  int ms_n = 0;                 // SBDF levels stored since the history began
+  int last_scheme = -1;         // scheme and dt of the history
+  double last_dt = 0.0;
   double t = 0.0;
   long long step = 0;
   std::string err;
@@ -522,17 +591,19 @@ qg_status step_cnab2(qg_ctx* ctx, double dt) {
   return QG_OK;
 }
 
-qg_status step_bpr353(qg_ctx* ctx, double dt) {
-  // y_1 = y_n (explicit first stage); stages 2..5 solve (M - dt/2 L) y_i =
-  // M y_n + dt sum_{j<i} (aE_ij E_j + aI_ij L y_j); y_{n+1} = y_5.
+qg_status step_dirk(qg_ctx* ctx, double dt, const Dirk& T) {
+  // y_1 = y_n (explicit first stage); stages i = 2..s solve
+  // (M - a_ii dt L) y_i = M y_n + dt sum_{j<i} (aE_ij E_j + aI_ij L y_j);
+  // y_{n+1} = y_s.
+  const int S = T.s;
   const double2* y0p = ctx->psi();
   const double2* y0t = ctx->th();
   const double2* yp[5] = {y0p, nullptr, nullptr, nullptr, nullptr};
   const double2* yt[5] = {y0t, nullptr, nullptr, nullptr, nullptr};
-  for (int i = 1; i < 5; ++i) {
+  for (int i = 1; i < S; ++i) {
     const int j = i - 1;
     bool need_e = false;
-    for (int r = 0; r < 5; ++r) need_e = need_e || BPR_AE[r][j] != 0.0;
+    for (int r = 0; r < S; ++r) need_e = need_e || T.AE[r][j] != 0.0;
     if (need_e) {
       qg_status s = explicit_terms(ctx, yp[j], yt[j], ctx->slot(ctx->w.eslot, j, 0),
                                    ctx->slot(ctx->w.eslot, j, 1));
@@ -541,22 +612,22 @@ qg_status step_bpr353(qg_ctx* ctx, double dt) {
     RhsSpec rs{};
     rs.base_psi = y0p;
     rs.base_th = y0t;
-    rs.cL = dt * BPR_AI[i][0];
+    rs.cL = dt * T.AI[i][0];
     rs.nterm = 0;
     for (int jj = 0; jj < i; ++jj) {
-      if (BPR_AE[i][jj] != 0.0) {
+      if (T.AE[i][jj] != 0.0) {
         rs.term_psi[rs.nterm] = ctx->slot(ctx->w.eslot, jj, 0);
         rs.term_th[rs.nterm] = ctx->slot(ctx->w.eslot, jj, 1);
-        rs.coef[rs.nterm++] = dt * BPR_AE[i][jj];
+        rs.coef[rs.nterm++] = dt * T.AE[i][jj];
       }
-      if (jj >= 1 && BPR_AI[i][jj] != 0.0) {
+      if (jj >= 1 && T.AI[i][jj] != 0.0) {
         rs.term_psi[rs.nterm] = ctx->slot(ctx->w.lslot, jj, 0);
         rs.term_th[rs.nterm] = ctx->slot(ctx->w.lslot, jj, 1);
-        rs.coef[rs.nterm++] = dt * BPR_AI[i][jj];
+        rs.coef[rs.nterm++] = dt * T.AI[i][jj];
       }
     }
     double2 *op, *ot;
-    if (i == 4) {
+    if (i == S - 1) {
       op = ctx->psi();
       ot = ctx->th();
     } else {
@@ -567,7 +638,7 @@ qg_status step_bpr353(qg_ctx* ctx, double dt) {
     rs.out_psi = op;
     rs.out_th = ot;
     bool need_l = false;
-    for (int r = i + 1; r < 5; ++r) need_l = need_l || BPR_AI[r][i] != 0.0;
+    for (int r = i + 1; r < S; ++r) need_l = need_l || T.AI[r][i] != 0.0;
     rs.lin_psi = need_l ? ctx->slot(ctx->w.lslot, i, 0) : nullptr;
     rs.lin_th = need_l ? ctx->slot(ctx->w.lslot, i, 1) : nullptr;
     qg_status s = implicit_solve(ctx, rs);
@@ -576,6 +647,86 @@ qg_status step_bpr353(qg_ctx* ctx, double dt) {
     yt[i] = ot;
   }
   return QG_OK;
+}
+
+// The factorisation (mass - adt L) is refactored when adt changes
+// (synchronises the stream).
+qg_status prepare(qg_ctx* ctx, double adt) {
+  if (adt != ctx->factored_adt) return refactor(ctx, adt);
+  return QG_OK;
+}
+
+qg_status step_sbdf(qg_ctx* ctx, double dt, const Sbdf& S) {
+  // Level n: E^n into ring slot n % 4, y^n into ring slot n % 3 (after
+  // the combination has read y^{n-3} from that slot).  While fewer than k
+  // levels exist the step is a BPR353 step (start-up).
+  const int n = ctx->ms_n, k = S.k;
+  qg_status s = explicit_terms(ctx, ctx->psi(), ctx->th(), ctx->slot(ctx->w.mE, n % 4, 0),
+                               ctx->slot(ctx->w.mE, n % 4, 1));
+  if (s != QG_OK) return s;
+  double2* Yn = ctx->slot(ctx->w.mY, n % 3, 0);
+  const size_t bytes = 2 * ctx->mk() * sizeof(double2);
+  if (n + 1 < k) {
+    HIPCHK(hipMemcpyAsync(Yn, ctx->psi(), bytes, hipMemcpyDeviceToDevice, ctx->st));
+    s = prepare(ctx, BPR353.diag * dt);
+    if (s == QG_OK) s = step_dirk(ctx, dt, BPR353);
+  } else {
+    s = prepare(ctx, dt / S.a[0]);
+    if (s != QG_OK) return s;
+    // (M - dt/a_0 L) y^{n+1} = M [sum_j (-a_{j+1}/a_0) y^{n-j}]
+    //                          + dt/a_0 sum_j b_{j+1} E^{n-j}
+    Combine cb{};
+    cb.nb = k;
+    cb.in[0] = ctx->psi();
+    cb.c[0] = -S.a[1] / S.a[0];
+    for (int j = 1; j < k; ++j) {
+      cb.in[j] = ctx->slot(ctx->w.mY, (n - j) % 3, 0);
+      cb.c[j] = -S.a[j + 1] / S.a[0];
+    }
+    double2* yc = ctx->slot(ctx->w.ybuf, 0, 0);
+    launch_combine(cb, yc, 2 * ctx->mk(), ctx->st);
+    HIPCHK(hipMemcpyAsync(Yn, ctx->psi(), bytes, hipMemcpyDeviceToDevice, ctx->st));
+    RhsSpec rs{};
+    rs.base_psi = yc;
+    rs.base_th = ctx->slot(ctx->w.ybuf, 0, 1);
+    rs.cL = 0.0;
+    rs.nterm = k;
+    for (int j = 0; j < k; ++j) {
+      rs.term_psi[j] = ctx->slot(ctx->w.mE, (n - j) % 4, 0);
+      rs.term_th[j] = ctx->slot(ctx->w.mE, (n - j) % 4, 1);
+      rs.coef[j] = dt * S.b[j] / S.a[0];
+    }
+    rs.out_psi = ctx->psi();
+    rs.out_th = ctx->th();
+    s = implicit_solve(ctx, rs);
+  }
+  if (s != QG_OK) return s;
+  ctx->ms_n = n + 1;
+  return QG_OK;
+}
+
+// a_ii dt (or b_0 dt) of the scheme's implicit solves; SBDF start-up steps
+// use BPR353's.
+double scheme_adt(int scheme, double dt) {
+  if (const Dirk* T = dirk_of(scheme)) return T->diag * dt;
+  if (const Sbdf* S = sbdf_of(scheme)) return dt / S->a[0];
+  return 0.5 * dt;   // CNAB2
+}
+
+qg_status step_scheme(qg_ctx* ctx, double dt, int scheme) {
+  if (const Dirk* T = dirk_of(scheme)) return step_dirk(ctx, dt, *T);
+  if (const Sbdf* S = sbdf_of(scheme)) return step_sbdf(ctx, dt, *S);
+  return step_cnab2(ctx, dt);
+}
+
+// A multistep history belongs to the scheme and dt that made it.
+void begin_history(qg_ctx* ctx, double dt, int scheme) {
+  if (scheme != ctx->last_scheme || dt != ctx->last_dt) {
+    ctx->have_prev = 0;
+    ctx->ms_n = 0;
+    ctx->last_scheme = scheme;
+    ctx->last_dt = dt;
+  }
 }
 
 }  // namespace
@@ -801,6 +952,8 @@ qg_status set_state_run(qg_ctx* ctx, int mem, const double* psi, const double* t
   ctx->step = 0;
   ctx->have_prev = 0;
   ctx->cur = 0;
+  ctx->ms_n = 0;
+  ctx->last_scheme = -1;
   ctx->err.clear();
   return QG_OK;
 }
@@ -832,19 +985,8 @@ qg_status get_state_run(qg_ctx* ctx, int mem, double* psi, double* theta, double
 
 qg_status check_step_args(qg_ctx* ctx, double dt, int scheme, int nsteps) {
   if (!(dt > 0) || !std::isfinite(dt)) return fail(ctx, QG_EINVAL, "dt must be positive");
-  if (scheme != QG_CNAB2 && scheme != QG_BPR353) return fail(ctx, QG_EINVAL, "unknown scheme");
+  if (scheme < QG_CNAB2 || scheme > QG_SBDF4) return fail(ctx, QG_EINVAL, "unknown scheme");
   if (nsteps < 0) return fail(ctx, QG_EINVAL, "nsteps must be >= 0");
-  return QG_OK;
-}
-
-// Factorise for dt if needed (synchronises); drops the multistep history.
-qg_status prepare_dt(qg_ctx* ctx, double dt) {
-  const double adt = 0.5 * dt;   // b_0^I of CNAB2 and a_ii of BPR353
-  if (adt != ctx->factored_adt) {
-    qg_status s = refactor(ctx, adt);
-    if (s != QG_OK) return s;
-    ctx->have_prev = 0;   // the multistep history belongs to the old dt
-  }
   return QG_OK;
 }
 
@@ -852,10 +994,14 @@ qg_status step_ctx(qg_ctx* ctx, double dt, int scheme, int nsteps) {
   if (!ctx) return QG_EINVAL;
   qg_status s0 = check_step_args(ctx, dt, scheme, nsteps);
   if (s0 != QG_OK) return s0;
-  s0 = prepare_dt(ctx, dt);
-  if (s0 != QG_OK) return s0;
+  if (nsteps == 0) return QG_OK;
+  begin_history(ctx, dt, scheme);
+  if (!sbdf_of(scheme)) {   // SBDF steps pick their factorisation per step
+    s0 = prepare(ctx, scheme_adt(scheme, dt));
+    if (s0 != QG_OK) return s0;
+  }
   for (int i = 0; i < nsteps; ++i) {
-    qg_status s = (scheme == QG_CNAB2) ? step_cnab2(ctx, dt) : step_bpr353(ctx, dt);
+    qg_status s = step_scheme(ctx, dt, scheme);
     if (s != QG_OK) return s;
     ctx->t += dt;
     ctx->step += 1;
@@ -934,10 +1080,9 @@ qg_status qg_step_timed(qg_ctx* ctx, double dt, int scheme, int nsteps, double* 
                         int* launches) {
   if (!ctx || !kernel_ms || !launches) return QG_EINVAL;
   // factorise first so that the refactorisation is outside the timing
-  if (0.5 * dt != ctx->factored_adt && dt > 0 && std::isfinite(dt)) {
-    qg_status s = refactor(ctx, 0.5 * dt);
+  if (dt > 0 && std::isfinite(dt) && scheme >= QG_CNAB2 && scheme <= QG_SBDF4) {
+    qg_status s = prepare(ctx, scheme_adt(scheme, dt));
     if (s != QG_OK) return s;
-    ctx->have_prev = 0;
   }
   ctx->prof = true;
   ctx->ev_used = 0;
@@ -1040,7 +1185,7 @@ qg_status step_groups(qg_ensemble* e, double dt, int scheme) {
     qg_ctx* c = e->groups[j];
     if (hipStreamWaitEvent(e->gst[j], e->fork, 0) != hipSuccess)
       return efail(e, QG_EDEVICE, "hipStreamWaitEvent failed");
-    qg_status s = (scheme == QG_CNAB2) ? step_cnab2(c, dt) : step_bpr353(c, dt);
+    qg_status s = step_scheme(c, dt, scheme);
     if (s != QG_OK) return efail(e, s, c->err);
     if (hipEventRecord(e->gev[j], e->gst[j]) != hipSuccess ||
         hipStreamWaitEvent(e->st, e->gev[j], 0) != hipSuccess)
@@ -1082,7 +1227,7 @@ qg_status capture(qg_ensemble* e, double dt, int scheme, int steps) {
     }
     qg_status s = QG_OK;
     for (int i = 0; i < steps && s == QG_OK; ++i)
-      s = (scheme == QG_CNAB2) ? step_cnab2(c, dt) : step_bpr353(c, dt);
+      s = step_scheme(c, dt, scheme);
     hipGraph_t graph = nullptr;
     const hipError_t ec = hipStreamEndCapture(e->gst[j], &graph);
     c->cur = cur;
@@ -1202,6 +1347,8 @@ qg_status qg_ensemble_set_state(qg_ensemble* e, int member, const double* psi,
     g->step = 0;
     g->have_prev = 0;
     g->cur = 0;
+    g->ms_n = 0;
+    g->last_scheme = -1;
   }
   e->t = 0.0;
   e->step = 0;
@@ -1224,9 +1371,22 @@ qg_status qg_ensemble_step(qg_ensemble* e, double dt, int scheme, int nsteps) {
     qg_status s = check_step_args(c, dt, scheme, nsteps);
     if (s != QG_OK) return efail(e, s, c->err);
   }
+  if (nsteps == 0) return QG_OK;
+  for (qg_ctx* c : e->groups) begin_history(c, dt, scheme);
+  if (sbdf_of(scheme)) {
+    // SBDF steps run eagerly: start-up steps refactor, and the history
+    // ring turns every step
+    drop_graph(e);
+    for (int i = 0; i < nsteps; ++i) {
+      qg_status s = step_groups(e, dt, scheme);
+      if (s != QG_OK) return s;
+      account(e, dt, 1);
+    }
+    return QG_OK;
+  }
   for (qg_ctx* c : e->groups) {
     const double before = c->factored_adt;
-    qg_status s = prepare_dt(c, dt);
+    qg_status s = prepare(c, scheme_adt(scheme, dt));
     if (s != QG_OK) return efail(e, s, c->err);
     if (c->factored_adt != before) drop_graph(e);
   }

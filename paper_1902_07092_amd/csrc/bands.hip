@@ -13,6 +13,8 @@
 // of once per system.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "kernels.h"
 
 namespace qg {
@@ -128,6 +130,29 @@ dim3 band_grid(const Geom& g) {
   return dim3((g.K + RB - 1) / RB, chunks, 2 * g.nmem);
 }
 }  // namespace
+
+// out = sum_{b < nb} c_b in_b over n complex entries: the combination of
+// past states whose mass product a multistep right-hand side needs
+// (M applied once to the combination instead of once per level).
+__global__ __launch_bounds__(256) void combine_kernel(Combine cb, double2* __restrict__ out,
+                                                      size_t n) {
+  const size_t stride = (size_t)gridDim.x * blockDim.x;
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+    double2 acc = make_double2(0.0, 0.0);
+    for (int q = 0; q < cb.nb; ++q) {
+      const double2 v = cb.in[q][i];
+      acc.x += cb.c[q] * v.x;
+      acc.y += cb.c[q] * v.y;
+    }
+    out[i] = acc;
+  }
+}
+
+void launch_combine(const Combine& cb, double2* out, size_t n, hipStream_t st) {
+  const size_t blocks = std::min<size_t>((n + 255) / 256, 4096);
+  hipLaunchKernelGGL(combine_kernel, dim3((unsigned)std::max<size_t>(blocks, 1)), dim3(256), 0,
+                     st, cb, out, n);
+}
 
 void launch_rhs(const Geom& g, const Bands& b, const RhsSpec& rs, double2* rhs, hipStream_t st) {
   hipLaunchKernelGGL(band_kernel, band_grid(g), dim3(RB), 0, st, g, b, rs, 1.0, rhs,

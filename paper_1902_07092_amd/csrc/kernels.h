@@ -70,6 +70,14 @@ struct RhsSpec {
   double2* lin_th;
 };
 
+// A linear combination of up to MAX_LEVELS arrays (multistep levels).
+constexpr int MAX_LEVELS = 4;
+struct Combine {
+  int nb;
+  const double2* in[MAX_LEVELS];
+  double c[MAX_LEVELS];
+};
+
 // Transform kernels (transforms.hip), FP64 or, with `mixed`, FP32 for the
 // transforms and products (exchange arrays X and NL in float2).  The
 // launchers return false for a size without a compiled plan.

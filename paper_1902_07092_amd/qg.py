@@ -16,7 +16,8 @@ LIB_PATH = os.path.join(HERE, "libqg.so")
 
 QG_OK, QG_EINVAL, QG_ENOMEM, QG_EDEVICE = 0, -1, -2, -3
 QG_ENONFINITE, QG_ESTATE, QG_EUNSUPPORTED = -4, -5, -6
-SCHEMES = {"cnab2": 0, "bpr353": 1}
+SCHEMES = {"cnab2": 0, "bpr353": 1, "ars222": 2, "ars443": 3,
+           "sbdf2": 4, "sbdf3": 5, "sbdf4": 6}
 STATUS_NAMES = {0: "QG_OK", -1: "QG_EINVAL", -2: "QG_ENOMEM",
                 -3: "QG_EDEVICE", -4: "QG_ENONFINITE", -5: "QG_ESTATE",
                 -6: "QG_EUNSUPPORTED"}

@@ -72,10 +72,12 @@ def test_ensemble_members_equal_solo_runs(qg, sizes):
         solos.append(s)
     dt = sel[0].dt
     # first call: eager first step + two replays of the two-step graph +
-    # one eager step; then replays of the cached graph; then a new graph
-    # for BPR353
+    # one eager step; then replays of the cached graph; then new graphs
+    # for BPR353, ARS443 and ARS222 (another factorisation), eager SBDF3
+    # steps (start-up included), and CNAB2 again from a fresh history
     for scheme, n in (("cnab2", 6), ("cnab2", 4), ("cnab2", 7),
-                      ("bpr353", 3)):
+                      ("bpr353", 3), ("ars443", 2), ("ars222", 3),
+                      ("sbdf3", 5), ("cnab2", 3)):
         _say(f"  step {scheme} x{n}")
         ens.step(dt, scheme, n)
         for s in solos:
@@ -89,7 +91,7 @@ def test_ensemble_members_equal_solo_runs(qg, sizes):
                 assert np.array_equal(x, y), (scheme, n, j, f, diff)
     d_e = ens.diagnostics(len(sel) - 1)
     d_s = solos[-1].diagnostics()
-    assert d_e["step"] == d_s["step"] == 20
+    assert d_e["step"] == d_s["step"] == 33
     for k in ("E_kin", "E_therm", "enstrophy", "dt_cfl"):
         assert d_e[k] == d_s[k], k
 

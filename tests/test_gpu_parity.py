@@ -68,7 +68,9 @@ def _compare(s, o):
 
 
 @pytest.mark.parametrize("scheme,nsteps", [("cnab2", 1), ("cnab2", 20),
-                                           ("bpr353", 5)])
+                                           ("bpr353", 5), ("ars222", 6),
+                                           ("ars443", 5), ("sbdf2", 8),
+                                           ("sbdf3", 8), ("sbdf4", 8)])
 def test_small_parity(qg, scheme, nsteps):
     w = inputs.SMALL
     _say(f"[parity] small {w.n_phi}x{w.n_r} {scheme} x{nsteps}")
@@ -80,6 +82,26 @@ def test_small_parity(qg, scheme, nsteps):
     _say(f"  rel err {err}")
     ok, tol = _within(err, f"small_{scheme}_{nsteps}")
     assert ok, (err, tol)
+
+
+def test_scheme_switches_restart_histories(qg):
+    """Every scheme of Table 1 in one run, switching scheme and dt: each
+    switch starts the multistep history afresh (SBDF start-up steps
+    included), identically on both sides."""
+    w = inputs.SMALL
+    _say("[parity] small, scheme and dt switches")
+    s, o = _pair(qg, w, inputs.workload_state(w))
+    plan = [("cnab2", w.dt, 3), ("sbdf3", w.dt, 5), ("ars222", w.dt, 2),
+            ("sbdf4", 0.5 * w.dt, 5), ("sbdf2", 0.5 * w.dt, 3),
+            ("ars443", w.dt, 2), ("cnab2", w.dt, 3), ("bpr353", w.dt, 1)]
+    for scheme, dt, n in plan:
+        s.step(dt, scheme, n)
+        o.step(dt, scheme, n)
+    err = _compare(s, o)
+    _say(f"  rel err {err}")
+    assert max(err.values()) < TOL, err
+    d = s.diagnostics()
+    assert d["step"] == sum(n for _, _, n in plan)
 
 
 def test_small_full_run_100_steps(qg):
