@@ -10,7 +10,8 @@ batched ensemble of 64 runs of uneven size and Ra.  A step is one CNAB2 step of 
 whole hot path: Chebyshev synthesis, azimuthal FFTs and products, radial
 analysis, explicit terms, right-hand sides and the bordered solves of every
 m.  The state is resident in HBM before the timed region; the time-step
-factorisation is done once before it (as in the paper's timings).
+factorisation is done once before it (as in the paper's timings), and so
+are the library's autotuner steps (launch shape of the band products).
 
 Prints one JSON line (metric, value = grid-point-steps/s, roofline of the
 dominant kernel measured with HIP events on the solver's stream, CPU
@@ -145,6 +146,8 @@ def mixed_run(qg, torch, w, state, args, fp64_solver):
                     device="cuda:0", precision=1)
     s.set_state(state.psi, state.theta, state.uphi0)
     s.step(w.dt, w.scheme, 0)
+    tuned = (s.step_autotune(w.dt, w.scheme, args.tune_steps)
+             if args.tune_steps else None)
     s.step(w.dt, w.scheme, args.warmup)
     ms = timed_steps(torch, s, w, args.steps) / args.steps
     kern = s.step_timed(w.dt, w.scheme, args.steps)
@@ -155,7 +158,8 @@ def mixed_run(qg, torch, w, state, args, fp64_solver):
             "ms_per_step": ms, "precision": "FP32 transforms and products, "
             "FP64 solves/state/diagnostics",
             "rel_diff_vs_fp64_run": rel,
-            "rel_diff_after_steps": args.warmup + 2 * args.steps,
+            "rel_diff_after_steps": args.tune_steps + args.warmup + 2 * args.steps,
+            "band_systems_per_thread": tuned,
             "kernels": {k: {"avg_launch_us": v[0] / max(1, v[1]) * 1e3,
                             "launches": v[1]} for k, v in kern.items()}}
 
@@ -204,6 +208,8 @@ def ensemble_run(qg, torch, inputs, args):
         ens.set_state(i, st.psi, st.theta, st.uphi0)
     dt = ws[0].dt
     ens.step(dt, "cnab2", args.warmup)
+    tuned = (ens.step_autotune(dt, "cnab2", args.ens_tune_steps)
+             if args.ens_tune_steps else None)
     torch.cuda.synchronize()
     start = torch.cuda.Event(enable_timing=True)
     stop = torch.cuda.Event(enable_timing=True)
@@ -234,6 +240,7 @@ def ensemble_run(qg, torch, inputs, args):
     return {"value": gp / (ms * 1e-3), "unit": "grid-point-steps/s",
             "ms_per_step": ms, "members": len(ws), "sizes": sizes,
             "grid_points_per_step": gp, "steps": args.ens_steps,
+            "band_systems_per_thread": tuned,
             "nonfinite_members": bad,
             "one_context_after_another": {
                 "value": gp / (solo_ms * 1e-3), "ms_per_step": solo_ms,
@@ -256,6 +263,10 @@ def main():
     ap.add_argument("--no-schemes", action="store_true",
                     help="skip the per-scheme step costs")
     ap.add_argument("--scheme-steps", type=int, default=10)
+    ap.add_argument("--tune-steps", type=int, default=21,
+                    help="untimed steps of the band-product autotuner "
+                    "before the warm-up (0: compiled default shape)")
+    ap.add_argument("--ens-tune-steps", type=int, default=22)
     ap.add_argument("--ensemble-only", action="store_true",
                     help="only the batched-ensemble run (for profiling it)")
     ap.add_argument("--precision", choices=("fp64", "mixed"), default="fp64",
@@ -289,6 +300,10 @@ def main():
                          device="cuda:0", precision=prec)
     solver.set_state(state.psi, state.theta, state.uphi0)
     solver.step(w.dt, w.scheme, 0)            # factorise (untimed)
+    # band-product launch shape picked by the library's autotuner (untimed
+    # steps; the results do not depend on the shape)
+    tuned = (solver.step_autotune(w.dt, w.scheme, args.tune_steps)
+             if args.tune_steps else None)
     solver.step(w.dt, w.scheme, args.warmup)
     stream = solver.stream
     torch.cuda.synchronize()
@@ -333,6 +348,7 @@ def main():
            "config": {"workload": w.name, "n_phi": w.n_phi, "n_r": w.n_r,
                       "n_c": w.n_c, "E": w.E, "Ra": w.Ra, "Pr": w.Pr,
                       "eta": w.eta, "scheme": w.scheme, "dt": w.dt,
+                      "band_systems_per_thread": tuned,
                       "parallelism": "single GPU"},
            "roofline": roofline, "kernels": kernels}
     print(f"[bench] gpu done: {ms_per_step:.4f} ms/step", file=sys.stderr,

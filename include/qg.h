@@ -166,6 +166,20 @@ qg_status qg_step(qg_ctx *ctx, double dt, int scheme, int nsteps);
 qg_status qg_step_timed(qg_ctx *ctx, double dt, int scheme, int nsteps,
                         double *kernel_ms, int *launches);
 
+/* qg_step with an autotuner for the launch shape of the band-product
+ * kernel (right-hand sides and stage products, Sect. 4 with the operators
+ * of Sect. 3.2): after an untimed warm-up (1 step; k steps for SBDFk, which
+ * covers its start-up), the steps are split evenly over the candidate
+ * shapes of 4, 8, 16 and 32 systems per thread, each candidate's steps
+ * timed with HIP events on the context's stream; the fastest shape is kept
+ * for this and later calls and written to *systems_per_thread.  Every
+ * entry of a product is computed by one thread in the same order for
+ * every shape, so the run is exactly that of qg_step with the same
+ * arguments.  Synchronises once.  QG_EINVAL if fewer than 4 steps remain
+ * after the warm-up, or for qg_step's invalid arguments. */
+qg_status qg_step_autotune(qg_ctx *ctx, double dt, int scheme, int nsteps,
+                           int *systems_per_thread);
+
 /* Diagnostics of the current state (synchronises the stream). */
 qg_status qg_diagnostics(qg_ctx *ctx, qg_diag *out);
 
@@ -224,6 +238,16 @@ qg_status qg_ensemble_get_state(qg_ensemble *e, int member, double *psi,
  * the multistep history rules).  Asynchronous on the ensemble's stream
  * otherwise. */
 qg_status qg_ensemble_step(qg_ensemble *e, double dt, int scheme, int nsteps);
+
+/* qg_ensemble_step with the band-product autotuner of qg_step_autotune,
+ * applied to every group at once and timed on the ensemble's stream: per
+ * candidate an untimed lead-in of 1 + G steps (G = 2 for CNAB2, else 1:
+ * history start, refactorisation, capture of the graph for the new shape),
+ * then timed steps (a multiple of G, replays only).  The members' results
+ * equal those of qg_ensemble_step.  QG_EINVAL if nsteps leaves fewer than
+ * G timed steps per candidate. */
+qg_status qg_ensemble_step_autotune(qg_ensemble *e, double dt, int scheme,
+                                    int nsteps, int *systems_per_thread);
 
 /* Diagnostics of member `member` (synchronises the stream). */
 qg_status qg_ensemble_diagnostics(qg_ensemble *e, int member, qg_diag *out);

@@ -17,9 +17,11 @@
 
 namespace qg {
 size_t solve_lds_bytes(const Geom& g, int kutp, int kutr);
-void launch_rhs(const Geom& g, const Bands& b, const RhsSpec& rs, double2* rhs, hipStream_t st);
+void launch_rhs(const Geom& g, const Bands& b, const RhsSpec& rs, double2* rhs, int mch,
+                hipStream_t st);
 void launch_lin(const Geom& g, const Bands& b, const double2* ypsi, const double2* yth,
-                double2* lpsi, double2* lth, hipStream_t st);
+                double2* lpsi, double2* lth, int mch, hipStream_t st);
+bool band_mch_ok(int mch);
 void launch_combine(const Combine& cb, double2* out, size_t n, hipStream_t st);
 bool launch_solve(const Geom& g, const FactorSet<double2>& Fp, const FactorSet<double>& Fr,
                   double2* rhs, const RhsSpec& rs, int kutp, int kutr, bool pivoted,
@@ -229,6 +231,7 @@ struct qg_ctx {
   FactorSet<double2> Fp;
   FactorSet<double> Fr;
   int kutp = 16, kutr = 8;   // stored U super-diagonals (Psi, real systems)
+  int band_mch = 16;         // systems per thread of the band products
   bool pivoted = true;       // band LU with row interchanges in use
   bool mixed = false;        // FP32 transforms and products (qg_params.precision = 1)
   bool diag64 = true;        // FP64 transform kernels exist for the diagnostics
@@ -550,7 +553,7 @@ qg_status explicit_terms(qg_ctx* ctx, const double2* psi, const double2* th, dou
 
 qg_status implicit_solve(qg_ctx* ctx, const RhsSpec& rs) {
   double2* rhs = ctx->ptr2(ctx->w.rhs);
-  timed(ctx, K_RHS, [&] { launch_rhs(ctx->g, ctx->b, rs, rhs, ctx->st); });
+  timed(ctx, K_RHS, [&] { launch_rhs(ctx->g, ctx->b, rs, rhs, ctx->band_mch, ctx->st); });
   bool ok = true;
   timed(ctx, K_SOLVE, [&] {
     ok = ctx->pivoted
@@ -561,7 +564,8 @@ qg_status implicit_solve(qg_ctx* ctx, const RhsSpec& rs) {
   });
   if (!ok) return fail(ctx, QG_EUNSUPPORTED, "no solve kernel for this band width");
   if (rs.lin_psi)
-    launch_lin(ctx->g, ctx->b, rs.out_psi, rs.out_th, rs.lin_psi, rs.lin_th, ctx->st);
+    launch_lin(ctx->g, ctx->b, rs.out_psi, rs.out_th, rs.lin_psi, rs.lin_th, ctx->band_mch,
+               ctx->st);
   HIPCHK(hipGetLastError());
   return QG_OK;
 }
@@ -648,6 +652,40 @@ qg_status step_dirk(qg_ctx* ctx, double dt, const Dirk& T) {
   }
   return QG_OK;
 }
+
+// Autotuner candidates: systems per thread of the band products.
+constexpr int TUNE_N = 4;
+const int TUNE_MCH[TUNE_N] = {4, 8, 16, 32};
+
+// Start and stop events of each candidate's timed steps.
+struct Events {
+  hipEvent_t a[TUNE_N] = {}, b[TUNE_N] = {};
+  bool ok = true;
+  Events() {
+    for (int c = 0; c < TUNE_N; ++c)
+      ok = ok && hipEventCreate(&a[c]) == hipSuccess && hipEventCreate(&b[c]) == hipSuccess;
+  }
+  ~Events() {
+    for (int c = 0; c < TUNE_N; ++c) {
+      if (a[c]) (void)hipEventDestroy(a[c]);
+      if (b[c]) (void)hipEventDestroy(b[c]);
+    }
+  }
+  // index of the shortest interval a[c] -> b[c] (ties: the first); the
+  // events must have completed
+  bool fastest(int& pick) {
+    float best = 0.f;
+    for (int c = 0; c < TUNE_N; ++c) {
+      float ms = 0.f;
+      if (hipEventElapsedTime(&ms, a[c], b[c]) != hipSuccess) return false;
+      if (c == 0 || ms < best) {
+        best = ms;
+        pick = c;
+      }
+    }
+    return true;
+  }
+};
 
 // The factorisation (mass - adt L) is refactored when adt changes
 // (synchronises the stream).
@@ -1076,6 +1114,34 @@ qg_status qg_step(qg_ctx* ctx, double dt, int scheme, int nsteps) {
 
 qg_status qg_diagnostics(qg_ctx* ctx, qg_diag* out) { return diagnostics_run(ctx, 0, out); }
 
+qg_status qg_step_autotune(qg_ctx* ctx, double dt, int scheme, int nsteps,
+                           int* systems_per_thread) {
+  if (!ctx || !systems_per_thread) return QG_EINVAL;
+  qg_status s = check_step_args(ctx, dt, scheme, nsteps);
+  if (s != QG_OK) return s;
+  const Sbdf* sb = sbdf_of(scheme);
+  const int warm = sb ? sb->k : 1;   // start-up and factorisation, untimed
+  const int per = (nsteps - warm) / TUNE_N;
+  if (per < 1) return fail(ctx, QG_EINVAL, "autotune needs 4 timed steps after the warm-up");
+  s = step_ctx(ctx, dt, scheme, warm);
+  if (s != QG_OK) return s;
+  Events ev;
+  if (!ev.ok) return fail(ctx, QG_EDEVICE, "hipEventCreate failed");
+  for (int c = 0; c < TUNE_N; ++c) {
+    ctx->band_mch = TUNE_MCH[c];
+    HIPCHK(hipEventRecord(ev.a[c], ctx->st));
+    s = step_ctx(ctx, dt, scheme, per);
+    if (s != QG_OK) return s;
+    HIPCHK(hipEventRecord(ev.b[c], ctx->st));
+  }
+  HIPCHK(hipEventSynchronize(ev.b[TUNE_N - 1]));
+  int pick = 0;
+  if (!ev.fastest(pick)) return fail(ctx, QG_EDEVICE, "hipEventElapsedTime failed");
+  ctx->band_mch = TUNE_MCH[pick];
+  *systems_per_thread = ctx->band_mch;
+  return step_ctx(ctx, dt, scheme, nsteps - warm - TUNE_N * per);
+}
+
 qg_status qg_step_timed(qg_ctx* ctx, double dt, int scheme, int nsteps, double* kernel_ms,
                         int* launches) {
   if (!ctx || !kernel_ms || !launches) return QG_EINVAL;
@@ -1124,7 +1190,7 @@ struct qg_ensemble {
   // group's stream between the fork and the join)
   std::vector<hipGraphExec_t> exec;
   double g_dt = 0.0;
-  int g_scheme = -1, g_cur = -1, g_steps = 0;
+  int g_scheme = -1, g_cur = -1, g_steps = 0, g_mch = 0;
   double t = 0.0;
   long long step = 0;
 };
@@ -1250,6 +1316,7 @@ qg_status capture(qg_ensemble* e, double dt, int scheme, int steps) {
   e->g_scheme = scheme;
   e->g_cur = e->groups[0]->cur;
   e->g_steps = steps;
+  e->g_mch = e->groups[0]->band_mch;
   return QG_OK;
 }
 
@@ -1402,7 +1469,7 @@ qg_status qg_ensemble_step(qg_ensemble* e, double dt, int scheme, int nsteps) {
   const int per = (scheme == QG_CNAB2) ? 2 : 1;
   if (QG_ENSEMBLE_GRAPH && left >= per) {
     if (e->exec.empty() || e->g_dt != dt || e->g_scheme != scheme || e->g_cur != e->groups[0]->cur ||
-        e->g_steps != per) {
+        e->g_steps != per || e->g_mch != e->groups[0]->band_mch) {
       qg_status s = capture(e, dt, scheme, per);
       if (s != QG_OK) return s;
     }
@@ -1419,6 +1486,41 @@ qg_status qg_ensemble_step(qg_ensemble* e, double dt, int scheme, int nsteps) {
     account(e, dt, 1);
   }
   return QG_OK;
+}
+
+qg_status qg_ensemble_step_autotune(qg_ensemble* e, double dt, int scheme, int nsteps,
+                                    int* systems_per_thread) {
+  if (!e || !systems_per_thread) return QG_EINVAL;
+  for (qg_ctx* c : e->groups) {
+    qg_status s = check_step_args(c, dt, scheme, nsteps);
+    if (s != QG_OK) return efail(e, s, c->err);
+  }
+  // each candidate: an untimed lead-in (one step, then one graph's worth of
+  // steps: history start, refactorisation, graph capture for the new
+  // shape at the current CNAB2 slot parity), then timed steps that only
+  // replay that graph (a multiple of its steps)
+  const int G = (scheme == QG_CNAB2) ? 2 : 1;
+  const int lead = 1 + G;
+  const int per = (nsteps - TUNE_N * lead) / TUNE_N / G * G;
+  if (per < G) return efail(e, QG_EINVAL, "autotune needs more steps per candidate");
+  Events ev;
+  if (!ev.ok) return efail(e, QG_EDEVICE, "hipEventCreate failed");
+  for (int c = 0; c < TUNE_N; ++c) {
+    for (qg_ctx* g : e->groups) g->band_mch = TUNE_MCH[c];
+    qg_status s = qg_ensemble_step(e, dt, scheme, 1);
+    if (s == QG_OK) s = qg_ensemble_step(e, dt, scheme, G);
+    if (s != QG_OK) return s;
+    if (hipEventRecord(ev.a[c], e->st) != hipSuccess) return efail(e, QG_EDEVICE, "event");
+    s = qg_ensemble_step(e, dt, scheme, per);
+    if (s != QG_OK) return s;
+    if (hipEventRecord(ev.b[c], e->st) != hipSuccess) return efail(e, QG_EDEVICE, "event");
+  }
+  if (hipEventSynchronize(ev.b[TUNE_N - 1]) != hipSuccess) return efail(e, QG_EDEVICE, "event");
+  int pick = 0;
+  if (!ev.fastest(pick)) return efail(e, QG_EDEVICE, "hipEventElapsedTime failed");
+  for (qg_ctx* g : e->groups) g->band_mch = TUNE_MCH[pick];
+  *systems_per_thread = TUNE_MCH[pick];
+  return qg_ensemble_step(e, dt, scheme, nsteps - TUNE_N * (lead + per));
 }
 
 qg_status qg_ensemble_diagnostics(qg_ensemble* e, int member, qg_diag* out) {

@@ -9,8 +9,11 @@
 // The operators split in powers of m (A_m = A0 + m^2 A2, B_m = B0 + m^2 B2
 // + m^4 B4 + (2/E) i m C, F_m = F0 + m^2 F2), so a thread keeps the
 // m-independent combinations of its row's 17 band entries in registers and
-// runs over a chunk of m: the bands are read once per (row, chunk) instead
-// of once per system.
+// runs over a chunk of MCH systems: the bands are read once per (row,
+// chunk) instead of once per system.  MCH trades band reuse against
+// parallelism; it is chosen per context (4, 8, 16 or 32; qg_step_autotune
+// times them).  Every output entry is computed by one thread in the same
+// order whatever MCH is, so the results do not depend on it.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -22,7 +25,6 @@ namespace qg {
 namespace {
 
 constexpr int BW = 17;    // band entries per row (offsets -8..8)
-constexpr int MCH = 16;   // systems per thread
 constexpr int RB = 64;    // rows per block
 
 __device__ __forceinline__ double2 ld(const double2* p, int i, int K) {
@@ -38,6 +40,7 @@ __device__ __forceinline__ double2 ld(const double2* p, int i, int K) {
 // sys_out: out rows are system indices (Psi m -> m - 1, zonal -> M - 1,
 // theta m -> M + m) in out_psi; else out_psi[m] (Psi, zonal at m = 0) and
 // out_th[m].
+template <int MCH>
 __global__ __launch_bounds__(64) void band_kernel(Geom g, Bands b, RhsSpec rs, double alpha,
                                                   double2* __restrict__ out_psi,
                                                   double2* __restrict__ out_th, int sys_out) {
@@ -125,11 +128,32 @@ __global__ __launch_bounds__(64) void band_kernel(Geom g, Bands b, RhsSpec rs, d
 }
 
 namespace {
-dim3 band_grid(const Geom& g) {
-  const int chunks = (g.M + 1 + MCH - 1) / MCH;   // covers M - 1 Psi and M + 1 real systems
+dim3 band_grid(const Geom& g, int mch) {
+  const int chunks = (g.M + 1 + mch - 1) / mch;   // covers M - 1 Psi and M + 1 real systems
   return dim3((g.K + RB - 1) / RB, chunks, 2 * g.nmem);
 }
+
+void launch_band(const Geom& g, const Bands& b, const RhsSpec& rs, double alpha, double2* o1,
+                 double2* o2, int sys_out, int mch, hipStream_t st) {
+  const dim3 grid = band_grid(g, mch);
+  switch (mch) {
+    case 4:
+      hipLaunchKernelGGL(band_kernel<4>, grid, dim3(RB), 0, st, g, b, rs, alpha, o1, o2, sys_out);
+      break;
+    case 8:
+      hipLaunchKernelGGL(band_kernel<8>, grid, dim3(RB), 0, st, g, b, rs, alpha, o1, o2, sys_out);
+      break;
+    case 32:
+      hipLaunchKernelGGL(band_kernel<32>, grid, dim3(RB), 0, st, g, b, rs, alpha, o1, o2, sys_out);
+      break;
+    default:
+      hipLaunchKernelGGL(band_kernel<16>, grid, dim3(RB), 0, st, g, b, rs, alpha, o1, o2, sys_out);
+      break;
+  }
+}
 }  // namespace
+
+bool band_mch_ok(int mch) { return mch == 4 || mch == 8 || mch == 16 || mch == 32; }
 
 // out = sum_{b < nb} c_b in_b over n complex entries: the combination of
 // past states whose mass product a multistep right-hand side needs
@@ -154,19 +178,19 @@ void launch_combine(const Combine& cb, double2* out, size_t n, hipStream_t st) {
                      st, cb, out, n);
 }
 
-void launch_rhs(const Geom& g, const Bands& b, const RhsSpec& rs, double2* rhs, hipStream_t st) {
-  hipLaunchKernelGGL(band_kernel, band_grid(g), dim3(RB), 0, st, g, b, rs, 1.0, rhs,
-                     (double2*)nullptr, 1);
+void launch_rhs(const Geom& g, const Bands& b, const RhsSpec& rs, double2* rhs, int mch,
+                hipStream_t st) {
+  launch_band(g, b, rs, 1.0, rhs, nullptr, 1, mch, st);
 }
 
 void launch_lin(const Geom& g, const Bands& b, const double2* ypsi, const double2* yth,
-                double2* lpsi, double2* lth, hipStream_t st) {
+                double2* lpsi, double2* lth, int mch, hipStream_t st) {
   RhsSpec rs{};
   rs.base_psi = ypsi;
   rs.base_th = yth;
   rs.cL = 1.0;
   rs.nterm = 0;
-  hipLaunchKernelGGL(band_kernel, band_grid(g), dim3(RB), 0, st, g, b, rs, 0.0, lpsi, lth, 0);
+  launch_band(g, b, rs, 0.0, lpsi, lth, 0, mch, st);
 }
 
 }  // namespace qg

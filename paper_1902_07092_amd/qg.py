@@ -76,6 +76,7 @@ def load():
         "qg_destroy": (None, [vp]),
         "qg_operator_band": (i, [d, i, i, vp]),
         "qg_step_timed": (i, [vp, d, i, i, vp, vp]),
+        "qg_step_autotune": (i, [vp, d, i, i, ctypes.POINTER(i)]),
         "qg_ensemble_workspace_size": (i, [vp, i,
                                            ctypes.POINTER(ctypes.c_size_t)]),
         "qg_ensemble_create": (i, [ctypes.POINTER(vp), vp, i, vp,
@@ -83,6 +84,7 @@ def load():
         "qg_ensemble_set_state": (i, [vp, i, vp, vp, vp, i]),
         "qg_ensemble_get_state": (i, [vp, i, vp, vp, vp, i]),
         "qg_ensemble_step": (i, [vp, d, i, i]),
+        "qg_ensemble_step_autotune": (i, [vp, d, i, i, ctypes.POINTER(i)]),
         "qg_ensemble_diagnostics": (i, [vp, i, ctypes.POINTER(qg_diag)]),
         "qg_ensemble_last_error": (ctypes.c_char_p, [vp]),
         "qg_ensemble_destroy": (None, [vp]),
@@ -155,6 +157,14 @@ def qg_step_timed(ctx, dt, scheme, nsteps):
     return {k: (ms[i], n[i]) for i, k in enumerate(KERNEL_CLASSES) if n[i]}
 
 
+def qg_step_autotune(ctx, dt, scheme, nsteps) -> int:
+    """Returns the chosen systems per thread of the band products."""
+    out = ctypes.c_int(0)
+    _check(ctx, load().qg_step_autotune(ctx, float(dt), int(scheme),
+                                        int(nsteps), ctypes.byref(out)))
+    return out.value
+
+
 def qg_diagnostics(ctx) -> dict:
     d = qg_diag()
     _check(ctx, load().qg_diagnostics(ctx, ctypes.byref(d)))
@@ -220,6 +230,14 @@ def qg_ensemble_get_state(ens, member, psi_ptr, theta_ptr, uphi_ptr,
 def qg_ensemble_step(ens, dt, scheme, nsteps):
     _echeck(ens, load().qg_ensemble_step(ens, float(dt), int(scheme),
                                          int(nsteps)))
+
+
+def qg_ensemble_step_autotune(ens, dt, scheme, nsteps) -> int:
+    out = ctypes.c_int(0)
+    _echeck(ens, load().qg_ensemble_step_autotune(ens, float(dt), int(scheme),
+                                                  int(nsteps),
+                                                  ctypes.byref(out)))
+    return out.value
 
 
 def qg_ensemble_diagnostics(ens, member) -> dict:
@@ -311,6 +329,11 @@ class QGSolver:
         """Returns {kernel class: (total ms, launches)}."""
         return qg_step_timed(self.ctx, dt, SCHEMES[scheme], n)
 
+    def step_autotune(self, dt, scheme="cnab2", n=9):
+        """n steps while timing the band-product shapes; returns the
+        chosen systems per thread."""
+        return qg_step_autotune(self.ctx, dt, SCHEMES[scheme], n)
+
     def diagnostics(self):
         return qg_diagnostics(self.ctx)
 
@@ -379,6 +402,9 @@ class QGEnsemble:
 
     def step(self, dt, scheme="cnab2", n=1):
         qg_ensemble_step(self.ens, dt, SCHEMES[scheme], n)
+
+    def step_autotune(self, dt, scheme="cnab2", n=20):
+        return qg_ensemble_step_autotune(self.ens, dt, SCHEMES[scheme], n)
 
     def diagnostics(self, member):
         return qg_ensemble_diagnostics(self.ens, member)

@@ -96,6 +96,35 @@ def test_ensemble_members_equal_solo_runs(qg, sizes):
         assert d_e[k] == d_s[k], k
 
 
+@pytest.mark.parametrize("scheme,nsteps", [("cnab2", 22), ("bpr353", 12)])
+def test_ensemble_autotune_equals_solo_runs(qg, scheme, nsteps):
+    """The ensemble autotuner's candidate runs (graphs recaptured per
+    shape) leave every member equal to its solo run."""
+    ws = inputs.ensemble_workloads()
+    idx = _pick(ws, per_size=1)
+    sel = [ws[i] for i in idx]
+    _say(f"[ensemble autotune] {scheme} x{nsteps} members {idx}")
+    ens = qg.QGEnsemble([_member(w) for w in sel])
+    solos = []
+    for j, w in enumerate(sel):
+        st = inputs.workload_state(w)
+        ens.set_state(j, st.psi, st.theta, st.uphi0)
+        s = qg.QGSolver(w.E, w.Ra, w.Pr, w.eta, w.n_phi, w.n_r, w.n_c)
+        s.set_state(st.psi, st.theta, st.uphi0)
+        solos.append(s)
+    dt = sel[0].dt
+    pick = ens.step_autotune(dt, scheme, nsteps)
+    _say(f"  systems per thread: {pick}")
+    assert pick in (4, 8, 16, 32)
+    ens.step(dt, scheme, 4)
+    for s in solos:
+        s.step(dt, scheme, nsteps + 4)
+    for j, s in enumerate(solos):
+        for x, y in zip(ens.get_state(j), s.get_state()):
+            assert np.array_equal(x, y), j
+    assert ens.diagnostics(0)["step"] == nsteps + 4
+
+
 def test_ensemble_member_matches_oracle(qg):
     ws = inputs.ensemble_workloads()
     k = 7

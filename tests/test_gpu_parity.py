@@ -104,6 +104,34 @@ def test_scheme_switches_restart_histories(qg):
     assert d["step"] == sum(n for _, _, n in plan)
 
 
+@pytest.mark.parametrize("wname,scheme,nsteps", [("SMALL", "cnab2", 13),
+                                                 ("MEDIUM", "sbdf3", 11),
+                                                 ("MEDIUM", "ars222", 6)])
+def test_autotune_equals_plain_steps(qg, wname, scheme, nsteps):
+    """qg_step_autotune runs its steps over every band-product shape; the
+    run equals plain qg_step bit for bit, and the chosen shape is kept."""
+    w = getattr(inputs, wname)
+    _say(f"[autotune] {wname} {scheme} x{nsteps}")
+    st = inputs.workload_state(w)
+    a = qg.QGSolver(w.E, w.Ra, w.Pr, w.eta, w.n_phi, w.n_r, w.n_c)
+    b = qg.QGSolver(w.E, w.Ra, w.Pr, w.eta, w.n_phi, w.n_r, w.n_c)
+    for s in (a, b):
+        s.set_state(st.psi, st.theta, st.uphi0)
+    pick = a.step_autotune(w.dt, scheme, nsteps)
+    b.step(w.dt, scheme, nsteps)
+    _say(f"  systems per thread: {pick}")
+    assert pick in (4, 8, 16, 32)
+    for x, y in zip(a.get_state(), b.get_state()):
+        assert np.array_equal(x, y)
+    a.step(w.dt, scheme, 3)
+    b.step(w.dt, scheme, 3)
+    for x, y in zip(a.get_state(), b.get_state()):
+        assert np.array_equal(x, y)
+    with pytest.raises(qg.QGError) as e:       # too few steps to tune
+        a.step_autotune(w.dt, scheme, 4)
+    assert e.value.status == qg.QG_EINVAL
+
+
 def test_small_full_run_100_steps(qg):
     """The small workload in full: 100 CNAB2 steps at dt = 1e-4."""
     w = inputs.SMALL
