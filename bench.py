@@ -208,8 +208,12 @@ def ensemble_run(qg, torch, inputs, args):
         ens.set_state(i, st.psi, st.theta, st.uphi0)
     dt = ws[0].dt
     ens.step(dt, "cnab2", args.warmup)
-    tuned = (ens.step_autotune(dt, "cnab2", args.ens_tune_steps)
-             if args.ens_tune_steps else None)
+    tuned = None
+    if args.ens_tune_steps:
+        picks = ens.step_autotune(dt, "cnab2", args.ens_tune_steps)
+        _, grp = ens.groups()
+        tuned = {f"{ws[i].n_phi}x{ws[i].n_r}": picks[grp[i]]
+                 for i in range(len(ws))}
     torch.cuda.synchronize()
     start = torch.cuda.Event(enable_timing=True)
     stop = torch.cuda.Event(enable_timing=True)
@@ -266,7 +270,7 @@ def main():
     ap.add_argument("--tune-steps", type=int, default=21,
                     help="untimed steps of the band-product autotuner "
                     "before the warm-up (0: compiled default shape)")
-    ap.add_argument("--ens-tune-steps", type=int, default=22)
+    ap.add_argument("--ens-tune-steps", type=int, default=21)
     ap.add_argument("--ensemble-only", action="store_true",
                     help="only the batched-ensemble run (for profiling it)")
     ap.add_argument("--precision", choices=("fp64", "mixed"), default="fp64",

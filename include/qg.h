@@ -239,13 +239,20 @@ qg_status qg_ensemble_get_state(qg_ensemble *e, int member, double *psi,
  * otherwise. */
 qg_status qg_ensemble_step(qg_ensemble *e, double dt, int scheme, int nsteps);
 
+/* Number of size groups of the ensemble, and (if group_of_member is not
+ * NULL) the group of each member (an array of n ints). */
+qg_status qg_ensemble_groups(const qg_ensemble *e, int *ngroups,
+                             int *group_of_member);
+
 /* qg_ensemble_step with the band-product autotuner of qg_step_autotune,
- * applied to every group at once and timed on the ensemble's stream: per
- * candidate an untimed lead-in of 1 + G steps (G = 2 for CNAB2, else 1:
- * history start, refactorisation, capture of the graph for the new shape),
- * then timed steps (a multiple of G, replays only).  The members' results
- * equal those of qg_ensemble_step.  QG_EINVAL if nsteps leaves fewer than
- * G timed steps per candidate. */
+ * per size group: after work queued on the ensemble's stream, each group in
+ * turn runs the warm-up and candidate steps alone on its own stream,
+ * eagerly, timing its band-product launches; it keeps its fastest shape
+ * (systems_per_thread[g] for group g: an array of at least ngroups ints).
+ * Every group takes the same steps; the remaining steps follow as in
+ * qg_ensemble_step (graphs captured for the new shapes).  The members'
+ * results equal those of qg_ensemble_step.  QG_EINVAL if fewer than 4
+ * steps remain after the warm-up. */
 qg_status qg_ensemble_step_autotune(qg_ensemble *e, double dt, int scheme,
                                     int nsteps, int *systems_per_thread);
 

@@ -657,36 +657,6 @@ qg_status step_dirk(qg_ctx* ctx, double dt, const Dirk& T) {
 constexpr int TUNE_N = 4;
 const int TUNE_MCH[TUNE_N] = {4, 8, 16, 32};
 
-// Start and stop events of each candidate's timed steps.
-struct Events {
-  hipEvent_t a[TUNE_N] = {}, b[TUNE_N] = {};
-  bool ok = true;
-  Events() {
-    for (int c = 0; c < TUNE_N; ++c)
-      ok = ok && hipEventCreate(&a[c]) == hipSuccess && hipEventCreate(&b[c]) == hipSuccess;
-  }
-  ~Events() {
-    for (int c = 0; c < TUNE_N; ++c) {
-      if (a[c]) (void)hipEventDestroy(a[c]);
-      if (b[c]) (void)hipEventDestroy(b[c]);
-    }
-  }
-  // index of the shortest interval a[c] -> b[c] (ties: the first); the
-  // events must have completed
-  bool fastest(int& pick) {
-    float best = 0.f;
-    for (int c = 0; c < TUNE_N; ++c) {
-      float ms = 0.f;
-      if (hipEventElapsedTime(&ms, a[c], b[c]) != hipSuccess) return false;
-      if (c == 0 || ms < best) {
-        best = ms;
-        pick = c;
-      }
-    }
-    return true;
-  }
-};
-
 // The factorisation (mass - adt L) is refactored when adt changes
 // (synchronises the stream).
 qg_status prepare(qg_ctx* ctx, double adt) {
@@ -1047,6 +1017,52 @@ qg_status step_ctx(qg_ctx* ctx, double dt, int scheme, int nsteps) {
   return QG_OK;
 }
 
+// One autotuner candidate: `per` steps with band-product shape mch, the
+// band-product launches timed with events on the context's stream
+// (synchronises); *ms = mean duration of one right-hand-side launch.
+qg_status tune_candidate(qg_ctx* ctx, double dt, int scheme, int per, int mch, double* ms) {
+  ctx->band_mch = mch;
+  ctx->prof = true;
+  ctx->ev_used = 0;
+  ctx->ev_marks.clear();
+  qg_status s = step_ctx(ctx, dt, scheme, per);
+  ctx->prof = false;
+  if (s != QG_OK) return s;
+  HIPCHK(hipStreamSynchronize(ctx->st));
+  double tot = 0.0;
+  int n = 0;
+  for (auto& mk : ctx->ev_marks) {
+    if (mk.first != K_RHS) continue;
+    float t = 0.f;
+    HIPCHK(hipEventElapsedTime(&t, mk.second.first, mk.second.second));
+    tot += t;
+    ++n;
+  }
+  ctx->ev_marks.clear();
+  *ms = n ? tot / n : 0.0;
+  return QG_OK;
+}
+
+// Runs warm + TUNE_N * per steps of ctx (untimed warm-up, then every
+// candidate) and keeps the shape with the shortest band-product launches.
+qg_status tune_ctx(qg_ctx* ctx, double dt, int scheme, int warm, int per) {
+  qg_status s = step_ctx(ctx, dt, scheme, warm);
+  if (s != QG_OK) return s;
+  double best = 0.0;
+  int pick = ctx->band_mch;
+  for (int c = 0; c < TUNE_N; ++c) {
+    double ms = 0.0;
+    s = tune_candidate(ctx, dt, scheme, per, TUNE_MCH[c], &ms);
+    if (s != QG_OK) return s;
+    if (c == 0 || ms < best) {
+      best = ms;
+      pick = TUNE_MCH[c];
+    }
+  }
+  ctx->band_mch = pick;
+  return QG_OK;
+}
+
 // Diagnostics of run `mem` (the kernels evaluate every run of the context).
 qg_status diagnostics_run(qg_ctx* ctx, int mem, qg_diag* out) {
   if (!ctx || !out) return QG_EINVAL;
@@ -1123,21 +1139,8 @@ qg_status qg_step_autotune(qg_ctx* ctx, double dt, int scheme, int nsteps,
   const int warm = sb ? sb->k : 1;   // start-up and factorisation, untimed
   const int per = (nsteps - warm) / TUNE_N;
   if (per < 1) return fail(ctx, QG_EINVAL, "autotune needs 4 timed steps after the warm-up");
-  s = step_ctx(ctx, dt, scheme, warm);
+  s = tune_ctx(ctx, dt, scheme, warm, per);
   if (s != QG_OK) return s;
-  Events ev;
-  if (!ev.ok) return fail(ctx, QG_EDEVICE, "hipEventCreate failed");
-  for (int c = 0; c < TUNE_N; ++c) {
-    ctx->band_mch = TUNE_MCH[c];
-    HIPCHK(hipEventRecord(ev.a[c], ctx->st));
-    s = step_ctx(ctx, dt, scheme, per);
-    if (s != QG_OK) return s;
-    HIPCHK(hipEventRecord(ev.b[c], ctx->st));
-  }
-  HIPCHK(hipEventSynchronize(ev.b[TUNE_N - 1]));
-  int pick = 0;
-  if (!ev.fastest(pick)) return fail(ctx, QG_EDEVICE, "hipEventElapsedTime failed");
-  ctx->band_mch = TUNE_MCH[pick];
   *systems_per_thread = ctx->band_mch;
   return step_ctx(ctx, dt, scheme, nsteps - warm - TUNE_N * per);
 }
@@ -1190,7 +1193,8 @@ struct qg_ensemble {
   // group's stream between the fork and the join)
   std::vector<hipGraphExec_t> exec;
   double g_dt = 0.0;
-  int g_scheme = -1, g_cur = -1, g_steps = 0, g_mch = 0;
+  int g_scheme = -1, g_cur = -1, g_steps = 0;
+  std::vector<int> g_mch;   // band-product shape of each group at capture
   double t = 0.0;
   long long step = 0;
 };
@@ -1316,8 +1320,16 @@ qg_status capture(qg_ensemble* e, double dt, int scheme, int steps) {
   e->g_scheme = scheme;
   e->g_cur = e->groups[0]->cur;
   e->g_steps = steps;
-  e->g_mch = e->groups[0]->band_mch;
+  e->g_mch.clear();
+  for (qg_ctx* c : e->groups) e->g_mch.push_back(c->band_mch);
   return QG_OK;
+}
+
+bool same_shapes(const qg_ensemble* e) {
+  if (e->g_mch.size() != e->groups.size()) return false;
+  for (size_t j = 0; j < e->groups.size(); ++j)
+    if (e->g_mch[j] != e->groups[j]->band_mch) return false;
+  return true;
 }
 
 // One replay of every group's graph, forked from and joined back to e->st.
@@ -1469,7 +1481,7 @@ qg_status qg_ensemble_step(qg_ensemble* e, double dt, int scheme, int nsteps) {
   const int per = (scheme == QG_CNAB2) ? 2 : 1;
   if (QG_ENSEMBLE_GRAPH && left >= per) {
     if (e->exec.empty() || e->g_dt != dt || e->g_scheme != scheme || e->g_cur != e->groups[0]->cur ||
-        e->g_steps != per || e->g_mch != e->groups[0]->band_mch) {
+        e->g_steps != per || !same_shapes(e)) {
       qg_status s = capture(e, dt, scheme, per);
       if (s != QG_OK) return s;
     }
@@ -1495,32 +1507,33 @@ qg_status qg_ensemble_step_autotune(qg_ensemble* e, double dt, int scheme, int n
     qg_status s = check_step_args(c, dt, scheme, nsteps);
     if (s != QG_OK) return efail(e, s, c->err);
   }
-  // each candidate: an untimed lead-in (one step, then one graph's worth of
-  // steps: history start, refactorisation, graph capture for the new
-  // shape at the current CNAB2 slot parity), then timed steps that only
-  // replay that graph (a multiple of its steps)
-  const int G = (scheme == QG_CNAB2) ? 2 : 1;
-  const int lead = 1 + G;
-  const int per = (nsteps - TUNE_N * lead) / TUNE_N / G * G;
-  if (per < G) return efail(e, QG_EINVAL, "autotune needs more steps per candidate");
-  Events ev;
-  if (!ev.ok) return efail(e, QG_EDEVICE, "hipEventCreate failed");
-  for (int c = 0; c < TUNE_N; ++c) {
-    for (qg_ctx* g : e->groups) g->band_mch = TUNE_MCH[c];
-    qg_status s = qg_ensemble_step(e, dt, scheme, 1);
-    if (s == QG_OK) s = qg_ensemble_step(e, dt, scheme, G);
-    if (s != QG_OK) return s;
-    if (hipEventRecord(ev.a[c], e->st) != hipSuccess) return efail(e, QG_EDEVICE, "event");
-    s = qg_ensemble_step(e, dt, scheme, per);
-    if (s != QG_OK) return s;
-    if (hipEventRecord(ev.b[c], e->st) != hipSuccess) return efail(e, QG_EDEVICE, "event");
+  const Sbdf* sb = sbdf_of(scheme);
+  const int warm = sb ? sb->k : 1;
+  const int per = (nsteps - warm) / TUNE_N;
+  if (per < 1) return efail(e, QG_EINVAL, "autotune needs 4 timed steps after the warm-up");
+  // each group in turn, alone on its stream, eagerly (no graph): its own
+  // shape from its own band-product timings; every group takes the same
+  // steps, so the ensemble stays in step.  Work queued on the ensemble's
+  // stream comes first.
+  if (hipStreamSynchronize(e->st) != hipSuccess) return efail(e, QG_EDEVICE, "sync failed");
+  drop_graph(e);
+  for (size_t j = 0; j < e->groups.size(); ++j) {
+    qg_ctx* c = e->groups[j];
+    qg_status s = tune_ctx(c, dt, scheme, warm, per);
+    if (s != QG_OK) return efail(e, s, c->err);
+    systems_per_thread[j] = c->band_mch;
   }
-  if (hipEventSynchronize(ev.b[TUNE_N - 1]) != hipSuccess) return efail(e, QG_EDEVICE, "event");
-  int pick = 0;
-  if (!ev.fastest(pick)) return efail(e, QG_EDEVICE, "hipEventElapsedTime failed");
-  for (qg_ctx* g : e->groups) g->band_mch = TUNE_MCH[pick];
-  *systems_per_thread = TUNE_MCH[pick];
-  return qg_ensemble_step(e, dt, scheme, nsteps - TUNE_N * (lead + per));
+  e->t += dt * (warm + TUNE_N * per);
+  e->step += warm + TUNE_N * per;
+  return qg_ensemble_step(e, dt, scheme, nsteps - warm - TUNE_N * per);
+}
+
+qg_status qg_ensemble_groups(const qg_ensemble* e, int* ngroups, int* group_of_member) {
+  if (!e || !ngroups) return QG_EINVAL;
+  *ngroups = (int)e->groups.size();
+  if (group_of_member)
+    for (size_t i = 0; i < e->grp.size(); ++i) group_of_member[i] = e->grp[i];
+  return QG_OK;
 }
 
 qg_status qg_ensemble_diagnostics(qg_ensemble* e, int member, qg_diag* out) {

@@ -85,6 +85,7 @@ def load():
         "qg_ensemble_get_state": (i, [vp, i, vp, vp, vp, i]),
         "qg_ensemble_step": (i, [vp, d, i, i]),
         "qg_ensemble_step_autotune": (i, [vp, d, i, i, ctypes.POINTER(i)]),
+        "qg_ensemble_groups": (i, [vp, ctypes.POINTER(i), ctypes.POINTER(i)]),
         "qg_ensemble_diagnostics": (i, [vp, i, ctypes.POINTER(qg_diag)]),
         "qg_ensemble_last_error": (ctypes.c_char_p, [vp]),
         "qg_ensemble_destroy": (None, [vp]),
@@ -232,12 +233,20 @@ def qg_ensemble_step(ens, dt, scheme, nsteps):
                                          int(nsteps)))
 
 
-def qg_ensemble_step_autotune(ens, dt, scheme, nsteps) -> int:
-    out = ctypes.c_int(0)
+def qg_ensemble_groups(ens, n_members):
+    """(number of size groups, group of each member)."""
+    ng = ctypes.c_int(0)
+    gm = (ctypes.c_int * max(1, n_members))()
+    _echeck(ens, load().qg_ensemble_groups(ens, ctypes.byref(ng), gm))
+    return ng.value, list(gm)[:n_members]
+
+
+def qg_ensemble_step_autotune(ens, dt, scheme, nsteps, ngroups) -> list:
+    """Returns the chosen systems per thread of each size group."""
+    out = (ctypes.c_int * max(1, ngroups))()
     _echeck(ens, load().qg_ensemble_step_autotune(ens, float(dt), int(scheme),
-                                                  int(nsteps),
-                                                  ctypes.byref(out)))
-    return out.value
+                                                  int(nsteps), out))
+    return list(out)[:ngroups]
 
 
 def qg_ensemble_diagnostics(ens, member) -> dict:
@@ -403,8 +412,15 @@ class QGEnsemble:
     def step(self, dt, scheme="cnab2", n=1):
         qg_ensemble_step(self.ens, dt, SCHEMES[scheme], n)
 
-    def step_autotune(self, dt, scheme="cnab2", n=20):
-        return qg_ensemble_step_autotune(self.ens, dt, SCHEMES[scheme], n)
+    def groups(self):
+        """(number of size groups, group of each member)."""
+        return qg_ensemble_groups(self.ens, len(self.shapes))
+
+    def step_autotune(self, dt, scheme="cnab2", n=21):
+        """n steps while each size group times the band-product shapes;
+        returns the chosen systems per thread of each group."""
+        return qg_ensemble_step_autotune(self.ens, dt, SCHEMES[scheme], n,
+                                         self.groups()[0])
 
     def diagnostics(self, member):
         return qg_ensemble_diagnostics(self.ens, member)

@@ -98,8 +98,9 @@ def test_ensemble_members_equal_solo_runs(qg, sizes):
 
 @pytest.mark.parametrize("scheme,nsteps", [("cnab2", 22), ("bpr353", 12)])
 def test_ensemble_autotune_equals_solo_runs(qg, scheme, nsteps):
-    """The ensemble autotuner's candidate runs (graphs recaptured per
-    shape) leave every member equal to its solo run."""
+    """The ensemble autotuner (each size group tunes its own shape, eagerly,
+    then graphs are captured for the chosen shapes) leaves every member
+    equal to its solo run."""
     ws = inputs.ensemble_workloads()
     idx = _pick(ws, per_size=1)
     sel = [ws[i] for i in idx]
@@ -113,9 +114,11 @@ def test_ensemble_autotune_equals_solo_runs(qg, scheme, nsteps):
         s.set_state(st.psi, st.theta, st.uphi0)
         solos.append(s)
     dt = sel[0].dt
+    ngroups, grp = ens.groups()
+    assert ngroups == 3 and sorted(grp) == [0, 1, 2]
     pick = ens.step_autotune(dt, scheme, nsteps)
-    _say(f"  systems per thread: {pick}")
-    assert pick in (4, 8, 16, 32)
+    _say(f"  systems per thread per group: {pick}")
+    assert len(pick) == 3 and all(p in (4, 8, 16, 32) for p in pick)
     ens.step(dt, scheme, 4)
     for s in solos:
         s.step(dt, scheme, nsteps + 4)
