@@ -84,8 +84,10 @@ typedef struct {
   int n_phi;     /* azimuthal grid points, multiple of 3; this build needs
                     n_phi = 3 * 2^a >= 24 */
   int n_r;       /* radial Gauss-Lobatto points; this build needs
-                    n_r - 1 = 2^a >= 16.  Sizes whose per-workgroup LDS
-                    needs exceed the device limit give QG_EUNSUPPORTED */
+                    n_r - 1 = 2^a >= 16 or 3 * 2^a >= 24, with
+                    2 (n_r - 1) <= 6144 (FP64) or 12288 (mixed).  Sizes
+                    whose per-workgroup LDS needs exceed the device limit
+                    give QG_EUNSUPPORTED */
   int n_c;       /* Chebyshev modes kept, 8 <= n_c < n_r; 0 selects
                     floor(2 (n_r - 1) / 3) (radial dealiasing, Sect. 3.2.1) */
   int precision; /* 0 = FP64 throughout.  1 = mixed: the transforms and

@@ -112,8 +112,6 @@ const Sbdf* sbdf_of(int scheme) {
   }
 }
 
-bool is_pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
-
 struct Layout {
   size_t total = 0;
   size_t take(size_t bytes) {
@@ -763,8 +761,7 @@ qg_status create_ctx(qg_ctx** out, const qg_params* p, int nmem, const double* r
   std::string why;
   if (!sizes_of(p, z, why) || nmem < 1) return QG_EINVAL;
   const bool mixed = p->precision == 1;
-  if (!is_pow2(z.R - 1) || z.nphi % 6 || !transform_sizes_ok(2 * (z.R - 1), z.nphi, mixed))
-    return QG_EUNSUPPORTED;
+  if (z.nphi % 6 || !transform_sizes_ok(2 * (z.R - 1), z.nphi, mixed)) return QG_EUNSUPPORTED;
   if (!workspace || ((uintptr_t)workspace & 255)) return QG_EINVAL;
   WsMap w = map_workspace(z, nmem);
   if (workspace_bytes < w.total) return QG_ENOMEM;

@@ -579,11 +579,15 @@ void analysis_n(const Geom& g, const Bands& b, const void* NL, const double* zon
                      static_cast<const C*>(NL), zonal, th, Ep, Et);
 }
 
-// Compiled lengths: FP64 up to 2 (N_r - 1) = 4096 and N_phi = 6144 (the LDS
-// bound of the FP64 rings), FP32 up to 8192 and 12288.
-#define QG_DCT64(X) X(32) X(64) X(128) X(256) X(512) X(1024) X(2048) X(4096)
+// Compiled lengths: 2 (N_r - 1) = 2^a or 3 * 2^a (the paper's radial
+// resolutions 193, 769 and 3073 are of the second kind), FP64 up to 6144
+// (the LDS bound of the FP64 radial transforms), FP32 up to 12288;
+// N_phi = 3 * 2^a, FP64 up to 6144 (the LDS bound of the FP64 rings),
+// FP32 up to 12288.
+#define QG_DCT64(X) X(32) X(48) X(64) X(96) X(128) X(192) X(256) X(384) X(512) X(768) \
+  X(1024) X(1536) X(2048) X(3072) X(4096) X(6144)
 #define QG_PHI64(X) X(24) X(48) X(96) X(192) X(384) X(768) X(1536) X(3072) X(6144)
-#define QG_DCT32(X) QG_DCT64(X) X(8192)
+#define QG_DCT32(X) QG_DCT64(X) X(8192) X(12288)
 #define QG_PHI32(X) QG_PHI64(X) X(12288)
 
 }  // namespace

@@ -132,6 +132,26 @@ def test_autotune_equals_plain_steps(qg, wname, scheme, nsteps):
     assert e.value.status == qg.QG_EINVAL
 
 
+@pytest.mark.parametrize("n_phi,n_r", [(48, 49), (384, 193)])
+def test_radial_sizes_three_times_power_of_two(qg, n_phi, n_r):
+    """2 (N_r - 1) = 3 * 2^a: the radial transforms end with a radix-3
+    pass (the paper's N_r = 193, 769 and 3073 are of this kind)."""
+    w = inputs.SMALL
+    K = (2 * (n_r - 1)) // 3
+    _say(f"[parity] {n_phi}x{n_r} K={K} cnab2 x2")
+    st = inputs.make_state(n_phi // 3 + 1, K, "decaying", 7)
+    st.theta *= 1e2
+    s = qg.QGSolver(w.E, w.Ra, w.Pr, w.eta, n_phi, n_r, K)
+    o = QGOracle(w.E, w.Ra, w.Pr, w.eta, n_phi, n_r, K)
+    for x in (s, o):
+        x.set_state(st.psi, st.theta, st.uphi0)
+    s.step(w.dt, "cnab2", 2)
+    o.step(w.dt, "cnab2", 2)
+    err = _compare(s, o)
+    _say(f"  rel err {err}")
+    assert max(err.values()) < TOL, err
+
+
 def test_small_full_run_100_steps(qg):
     """The small workload in full: 100 CNAB2 steps at dt = 1e-4."""
     w = inputs.SMALL
@@ -270,7 +290,7 @@ def test_error_paths(qg):
     with pytest.raises(qg.QGError) as e:
         s.step(-1.0, "cnab2", 1)
     assert e.value.status == qg.QG_EINVAL
-    # n_r - 1 not a power of two: valid for the method, not these kernels
+    # n_r - 1 neither 2^a nor 3 * 2^a: valid for the method, not these kernels
     with pytest.raises(qg.QGError) as e:
         qg.QGSolver(1e-3, 8e4, 1.0, 0.35, 96, 34)
     assert e.value.status == qg.QG_EUNSUPPORTED
