@@ -20,6 +20,19 @@ the two-field splitting G = L_I Psi of the vorticity/streamfunction form
     theta rows: as above, boundary rows theta = 0.
 Readings: the 1/Pr on the diffusion term, missing from eq. (lin) as
 printed, follows eq. (temp), as does the sign of the background advection.
+
+Ekman pumping (optional, `pumping=True`): the G rows gain -F with
+F = -Upsilon [omega - (beta/2) u_phi + beta (d/dphi - 5 s_o/(2h)) u_s]
+(eq. pumping_full), Upsilon = (s_o/E)^{1/2} (s_o^2 - s^2)^{-3/4}; written
+for Psi (omega = -G, u_phi = -h^2 Psi' + 3 s Psi, u_s = (h^2/s) i m Psi,
+beta = -s/h^2) it is
+    F = Upsilon [G + (s/2) Psi' - (3 s^2/(2 h^2) + m^2 + 5 i m s_o/(2h)) Psi],
+evaluated at the interior points only (Upsilon is singular at s_o, where
+the boundary rows stand).  The integration-method operators take the
+approximated form F_eps of eq. approx_pump (h -> h_eps = ((s_o + eps)^2 -
+s^2)^{1/2} in Upsilon and in the bracket's coefficients, L_I unchanged),
+projected on the Chebyshev basis through the n_r-point grid as the time
+step evaluates it (an explicit term there).
 """
 import numpy as np
 import scipy.linalg as sla
@@ -41,7 +54,7 @@ def cheb_diff_matrix(N):
     return Dm
 
 
-def linear_operator(E, Ra, Pr, eta, m, N):
+def linear_operator(E, Ra, Pr, eta, m, N, pumping=False):
     """(A, B), A v = lambda B v, v = (G, Psi, theta) on the grid."""
     s_i, s_o = grid.radii(eta)
     s = grid.s_nodes(eta, N)
@@ -61,6 +74,14 @@ def linear_operator(E, Ra, Pr, eta, m, N):
     A[g, p] = (2.0j * m / E) * I
     A[g, t] = (Ra / Pr) * (1j * m / s_o) * I
     B[g, g] = I
+    if pumping:
+        h2 = s_o**2 - s**2
+        ii = np.arange(1, N - 1)                 # interior points
+        ups = np.sqrt(s_o / E) / h2[ii]**0.75
+        coef = 1.5 * s[ii]**2 / h2[ii] + m * m + 2.5j * m * s_o / np.sqrt(h2[ii])
+        A[ii, ii] -= ups
+        A[ii, N:2 * N] -= (0.5 * ups * s[ii])[:, None] * Dx[ii]
+        A[ii, N + ii] += ups * coef
     # Psi rows
     A[p, g] = I
     A[p, p] = -LI
@@ -83,15 +104,15 @@ def linear_operator(E, Ra, Pr, eta, m, N):
     return A, B
 
 
-def eigenvalues(E, Ra, Pr, eta, m, N):
-    A, B = linear_operator(E, Ra, Pr, eta, m, N)
+def eigenvalues(E, Ra, Pr, eta, m, N, pumping=False):
+    A, B = linear_operator(E, Ra, Pr, eta, m, N, pumping)
     lam = sla.eig(A, B, right=False)
     return lam[np.isfinite(lam)]
 
 
-def leading(E, Ra, Pr, eta, m, N):
+def leading(E, Ra, Pr, eta, m, N, pumping=False):
     """Finite eigenvalue with the largest real part."""
-    lam = eigenvalues(E, Ra, Pr, eta, m, N)
+    lam = eigenvalues(E, Ra, Pr, eta, m, N, pumping)
     return lam[np.argmax(lam.real)]
 
 
@@ -119,13 +140,35 @@ def critical_rayleigh(E, Pr, eta, m, N, lo, hi, rtol=1e-8):
     return 0.5 * (lo + hi)
 
 
-def integration_operator(E, Ra, Pr, eta, m, K):
+def pumping_matrix(E, eta, m, K, n_r, eps):
+    """Chebyshev coefficients (n < K) of F_eps(Psi) for Psi = T_n, n < K,
+    evaluated on the n_r-point radial grid (eq. approx_pump)."""
+    from . import transforms as tr
+    s_i, s_o = grid.radii(eta)
+    s = grid.s_nodes(eta, n_r)
+    he2 = (s_o + eps)**2 - s**2
+    he = np.sqrt(he2)
+    ups = np.sqrt(s_o / E) / he**1.5
+    LI = qg_operators(eta)["L_I"]
+    F = np.zeros((K, K), np.complex128)
+    for n in range(K):
+        e = np.zeros(K)
+        e[n] = 1.0
+        P = [tr.cheb_to_grid(tr.cheb_ds(e, q), n_r) for q in range(4)]
+        f = ups * (evaluate_op(LI, m, P, s) + 0.5 * s * P[1]
+                   - (1.5 * s**2 / he2 + m * m + 2.5j * m * s_o / he) * P[0])
+        F[:, n] = tr.grid_to_cheb(f, K)
+    return F
+
+
+def integration_operator(E, Ra, Pr, eta, m, K, pump=None):
     """(A, B) for the same eigenproblem posed with the integration-method
     matrices of Sect. 3.2 (eq. psi_int, temp_int) and their tau rows:
         lambda [A_m Psi; D theta] = [B_m Psi + C (Ra/Pr)(i m/s_o) theta;
                                      (1/Pr) F_m theta - i m D_bg Psi],
     D_bg = int^2 s^2 (h^2/s) dTc/ds = (alpha/ln eta) int^2 h^2 (exact, the
-    background coefficient times s^2 being a polynomial)."""
+    background coefficient times s^2 being a polynomial).  pump = (n_r, eps)
+    adds -C F_eps to the Psi rows (pumping_matrix)."""
     from .operators import (PAD, ChebAlgebra, IntegrationOperators,
                             tau_rows_dirichlet, tau_rows_psi)
     s_i, s_o = grid.radii(eta)
@@ -137,6 +180,8 @@ def integration_operator(E, Ra, Pr, eta, m, K):
     A = np.zeros((2 * K, 2 * K), np.complex128)
     B = np.zeros_like(A)
     A[:K, :K] = o.B(m, E)
+    if pump is not None:
+        A[:K, :K] -= o.C @ pumping_matrix(E, eta, m, K, *pump)
     A[:K, K:] = (Ra / Pr) * (1j * m / s_o) * o.C
     B[:K, :K] = o.A(m)
     A[K:, K:] = o.F(m) / Pr
