@@ -106,6 +106,13 @@ typedef struct {
                         partial pivoting (the choice is made at each
                         factorisation and reported in qg_diag);
                     1 = always with partial pivoting */
+  int ekman;     /* 1: Ekman pumping, explicit like the advection (Sect. 3.2):
+                    the approximated F_eps of eq. approx_pump in the Psi
+                    equation, and Upsilon_eps u (1 + (E/2) omega_0) in the
+                    zonal-flow equation (its pumping term, eq. uphi, and the
+                    zonal wind's self-interaction in N_uphi); 0: none */
+  double eps;    /* eps of F_eps (h_eps^2 = (s_o + eps)^2 - s^2); > 0 and
+                    finite when ekman = 1, ignored otherwise */
 } qg_params;
 
 typedef struct {

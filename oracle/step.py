@@ -35,6 +35,15 @@ Readings (where the paper is silent or inconsistent):
     global order k for k <= 4.
   * A multistep history belongs to the scheme and dt that made it: a step
     with another scheme or dt starts afresh.
+  * Ekman pumping (optional, ekman_eps = eps > 0), explicit like the
+    advection (Sect. 3.2: its coefficients are not rational): E_psi gains
+    -C[F_eps], F_eps = Upsilon_eps [L_I + (s/2) d/ds - (3 s^2/(2 h_eps^2)
+    + m^2 + 5 i m s_o/(2 h_eps))] Psi (eq. approx_pump), and the zonal flow
+    -D[Upsilon_eps u + (E/2) Upsilon_eps u omega_0] (the pumping term of
+    eq. uphi and the self-interaction of the zonal wind in N_uphi, with
+    Upsilon_eps for Upsilon as the integration method needs), all
+    evaluated on the radial grid and transformed with the other explicit
+    terms.
 """
 import numpy as np
 
@@ -99,10 +108,11 @@ SCHEMES = ("cnab2", "sbdf2", "sbdf3", "sbdf4", "bpr353", "ars222", "ars443")
 
 
 class QGOracle:
-    def __init__(self, E, Ra, Pr, eta, n_phi, n_r, n_c=None):
+    def __init__(self, E, Ra, Pr, eta, n_phi, n_r, n_c=None, ekman_eps=None):
         if n_phi % 3:
             raise ValueError("N_phi must be a multiple of 3 (N_m = N_phi/3)")
         self.E, self.Ra, self.Pr, self.eta = E, Ra, Pr, eta
+        self.ekman_eps = ekman_eps
         self.n_phi, self.n_r = n_phi, n_r
         self.M = n_phi // 3 + 1
         self.K = (2 * (n_r - 1)) // 3 if n_c is None else n_c
@@ -232,6 +242,24 @@ class QGOracle:
         n_u = np.mean(us * om, axis=1)
         return dict(n_om=n_om, n_th=n_th, n_u=n_u, us=us, th=th, om=om)
 
+    def pumping_grid(self, psi, uphi):
+        """Ekman pumping terms on the radial grid, (M, N_r): F_eps(Psi_m)
+        for m >= 1, Upsilon_eps u (1 + (E/2) omega_0) for m = 0."""
+        R, eps = self.n_r, self.ekman_eps
+        s = self.s
+        he2 = (self.s_o + eps)**2 - s**2
+        he = np.sqrt(he2)
+        ups = np.sqrt(self.s_o / self.E) / he**1.5
+        m = self.mvec[:, None]
+        P = [tr.cheb_to_grid(tr.cheb_ds(psi, p), R) for p in range(4)]
+        li = evaluate_op(self.L_I, m, P, s[None, :])
+        F = ups * (li + 0.5 * s * P[1]
+                   - (1.5 * s**2 / he2 + m * m + 2.5j * m * self.s_o / he) * P[0])
+        U = [tr.cheb_to_grid(tr.cheb_ds(uphi, p), R) for p in range(2)]
+        om0 = evaluate_op(self.om0, 0, U, s)
+        F[0] = ups * U[0] * (1.0 + 0.5 * self.E * om0)
+        return F
+
     def explicit(self, psi, theta, uphi):
         """Explicit right-hand sides (K-vectors, rows >= q meaningful):
         E_psi = C[(Ra/Pr)(i m/s_o) theta + N_omega], E_theta = -D[N_theta],
@@ -247,6 +275,10 @@ class QGOracle:
         Nth = to_spec(n_th)
         Nth[0] = Nth[0].real
         Nu = tr.grid_to_cheb(n_u, K)
+        if self.ekman_eps is not None:
+            Fk = tr.grid_to_cheb(self.pumping_grid(psi, uphi), K)
+            Nom[1:] -= Fk[1:]
+            Nu = Nu + Fk[0].real
         o = self.ops
         buoy = (self.Ra / self.Pr) * im / self.s_o * theta
         Ep = (buoy + Nom) @ o.C.T

@@ -123,6 +123,7 @@ struct Layout {
 
 struct Sizes {
   int M, K, R, nphi, n4, n2, Sr;
+  bool pump;    // Ekman pumping terms
   int p4, p2;   // n4, n2 padded to whole 16-step batches (pivoted solve)
   int q4, q2;   // n4, n2 padded to whole groups of solve batches (unpivoted solve)
 };
@@ -137,6 +138,12 @@ bool sizes_of(const qg_params* p, Sizes& z, std::string& why) {
   if (K < 8 || K >= p->n_r) { why = "n_c must satisfy 8 <= n_c < n_r"; return false; }
   if (p->precision != 0 && p->precision != 1) { why = "precision must be 0 or 1"; return false; }
   if (p->pivoting != 0 && p->pivoting != 1) { why = "pivoting must be 0 or 1"; return false; }
+  if (p->ekman != 0 && p->ekman != 1) { why = "ekman must be 0 or 1"; return false; }
+  if (p->ekman && !(p->eps > 0 && std::isfinite(p->eps))) {
+    why = "eps must be positive with Ekman pumping";
+    return false;
+  }
+  z.pump = p->ekman == 1;
   z.M = p->n_phi / 3 + 1;
   z.K = K;
   z.R = p->n_r;
@@ -154,7 +161,7 @@ bool sizes_of(const qg_params* p, Sizes& z, std::string& why) {
 
 struct WsMap {
   size_t ra;
-  size_t state, ybuf, eslot, lslot, mE, mY, X, NL, zonal, rate, diag, xk, wq, dsk, twd, twp, twh, wphi,
+  size_t state, ybuf, eslot, lslot, mE, mY, pump, X, NL, zonal, rate, diag, xk, wq, dsk, twd, twp, twh, wphi,
       twd32, twp32, twh32, wphi32, bands, rhs;
   size_t p_piv, p_L, p_U, p_W, p_C, p_Mi, p_ui;
   size_t r_piv, r_L, r_U, r_W, r_C, r_Mi, r_ui;
@@ -177,6 +184,7 @@ WsMap map_workspace(const Sizes& z, int nmem) {
   w.lslot = L.take(8 * MK);   // DIRK implicit stage products (4)
   w.mE = L.take(8 * MK);      // SBDF explicit terms E^n .. E^{n-3}
   w.mY = L.take(6 * MK);      // SBDF past states y^{n-1} .. y^{n-3}
+  w.pump = L.take(z.pump ? RM : 0);   // Ekman pumping terms [M][R] per run
   w.X = L.take(6 * RM);
   w.NL = L.take(2 * RM);
   w.zonal = L.take(nm * z.R * sizeof(double));
@@ -868,6 +876,10 @@ qg_status create_ctx(qg_ctx** out, const qg_params* p, int nmem, const double* r
   g.inv_Pr = 1.0 / p->Pr;
   g.two_over_E = 2.0 / p->E;
   g.nmem = nmem;
+  g.pump = z.pump ? ctx->ptr2(w.pump) : nullptr;
+  g.pump_ups = std::sqrt(s_o / p->E);
+  g.pump_so2e = z.pump ? (s_o + p->eps) * (s_o + p->eps) : 0.0;
+  g.half_E = 0.5 * p->E;
   g.ra_pr = ctx->ptrd(w.ra);
   g.xk = ctx->ptrd(w.xk);
   g.wq = ctx->ptrd(w.wq);
@@ -1207,7 +1219,8 @@ qg_status efail(qg_ensemble* e, qg_status s, const std::string& msg) {
 // operators, tables and LU factors).
 bool same_group(const qg_params& a, const qg_params& b, const Sizes& za, const Sizes& zb) {
   return a.E == b.E && a.Pr == b.Pr && a.eta == b.eta && za.nphi == zb.nphi && za.R == zb.R &&
-         za.K == zb.K && a.precision == b.precision && a.pivoting == b.pivoting;
+         za.K == zb.K && a.precision == b.precision && a.pivoting == b.pivoting &&
+         a.ekman == b.ekman && (!a.ekman || a.eps == b.eps);
 }
 
 struct Grouping {

@@ -29,6 +29,12 @@ struct Geom {
   // of each run (nullptr: Ra_Pr for all).
   int nmem;
   const double* ra_pr;
+  // Ekman pumping (nullptr: none): per run [M][R], the synthesis writes
+  // F_eps(Psi_m)(s_k) for m >= 1 and Upsilon_eps u (1 + (E/2) omega_0) at
+  // m = 0; the analysis subtracts it from N_omega (adds it to the zonal
+  // forcing).  Upsilon_eps = pump_ups / h_eps^{3/2}, h_eps^2 = pump_so2e - s^2.
+  double2* pump;
+  double pump_ups, pump_so2e, half_E;
 };
 
 struct Bands {  // [17][K] each (offset-major): entry (k, n) at [(n - k + 8) * K + k]

@@ -207,13 +207,25 @@ __global__ __launch_bounds__(T) void synth_kernel(Geom g, const double2* __restr
   const int t = threadIdx.x;
   const int m = xcd_index(M);
   if (m >= M) return;
+  double2* pump = g.pump;
   {
     const size_t mem = blockIdx.y;
     psi += mem * M * K;
     th += mem * M * K;
     X += mem * 6 * R * M;
     if (diag) diag += mem * 8 * M;
+    if (pump) pump += mem * M * R + (size_t)m * R;
   }
+  // Ekman pumping, eq. approx_pump, accumulated in this block's row of
+  // g.pump (each entry by the thread that owns its radial point):
+  //   d = 0: -(3 s^2/(2 h_e^2) + m^2 + 5 i m s_o/(2 h_e)) Psi
+  //   d = 1: + (s/2) Psi'            d = 2: + L_I Psi = -omega, times Upsilon_e
+  // and at m = 0 Upsilon_e u (1 + (E/2) omega_0) once omega_0 is known.
+  auto ups_e = [&](double s, double& he2, double& he) {
+    he2 = g.pump_so2e - s * s;
+    he = sqrt(he2);
+    return g.pump_ups / (he * sqrt(he));
+  };
   C* fb = reinterpret_cast<C*>(sm);
   double2* c = reinterpret_cast<double2*>(reinterpret_cast<char*>(sm) + coef_offset<C>(lds_slots(N2)));
   auto ext = [&](int i) -> C {
@@ -254,6 +266,12 @@ __global__ __launch_bounds__(T) void synth_kernel(Geom g, const double2* __restr
         const double mh = m2 * h2 * is * is;
         if (d == 0) {
           store(0, k, ix(dm, p));
+          if (pump) {
+            double he2, he;
+            (void)ups_e(s, he2, he);
+            const double cr = 1.5 * s * s / he2 + m2, ci = 2.5 * dm * g.s_o / he;
+            pump[k] = make_double2(-(cr * p.x - ci * p.y), -(cr * p.y + ci * p.x));
+          }
           a1[i] = scl2(3.0 * s, p);
           a2[i] = scl2(6.0 + mh, p);
           a3[i] = scl2(6.0 + mh - h2s * 2.0 * m2 * so2 * is * is * is, p);
@@ -261,12 +279,18 @@ __global__ __launch_bounds__(T) void synth_kernel(Geom g, const double2* __restr
         } else if (d == 1) {
           const double2 uph = sub2(a1[i], scl2(h2, p));
           store(1, k, scl2(is, uph));
+          if (pump) pump[k] = add2(pump[k], scl2(0.5 * s, p));
           if (diag) ek += 2.0 * g.wq[k] * abs2(uph);
           a2[i] = sub2(a2[i], scl2(h2s - 5.0 * s, p));
           a3[i] = add2(a3[i], scl2(-(h2s - 5.0 * s) + h2s * (so2 * is * is + 12.0 + mh), p));
         } else if (d == 2) {
           const double2 om = sub2(a2[i], scl2(h2, p));
           store(3, k, ix(dm, om));
+          if (pump) {
+            double he2, he;
+            const double ue = ups_e(s, he2, he);
+            pump[k] = scl2(ue, sub2(pump[k], om));
+          }
           if (diag) ens += 2.0 * g.wq[k] * abs2(om);
           a3[i] = sub2(a3[i], scl2(h2 + h2s * (h2s - 7.0 * s), p));
         } else {
@@ -288,6 +312,11 @@ __global__ __launch_bounds__(T) void synth_kernel(Geom g, const double2* __restr
         } else if (d == 1) {
           a2[i] = add2(a2[i], p);
           a3[i] = add2(a3[i], scl2(1.0 + h2s * is, p));
+          if (pump) {
+            double he2, he;
+            const double ue = ups_e(s, he2, he);
+            pump[k] = make_double2(ue * a1[i].x * (1.0 + g.half_E * a2[i].x), 0.0);
+          }
           if (diag) ens += g.wq[k] * a2[i].x * a2[i].x;
         } else {
           store(2, k, add2(a3[i], scl2(h2s, p)));
@@ -482,6 +511,7 @@ __global__ __launch_bounds__(T) void analysis_kernel(Geom g, Bands b,
   const size_t mem = blockIdx.y;
   NL += mem * 2 * M * R;
   zonal += mem * R;
+  const double2* pump = g.pump ? g.pump + mem * M * R + (size_t)m * R : nullptr;
   th_state += mem * M * K;
   Epsi += mem * M * K;
   Eth += mem * M * K;
@@ -495,7 +525,9 @@ __global__ __launch_bounds__(T) void analysis_kernel(Geom g, Bands b,
   for (int f = 0; f < 2; ++f) {
     auto get = [&](int i) -> C {
       const int kk = (i <= N) ? i : N2 - i;
-      if (f == 0 && m == 0) return to_c<C>(make_double2(zonal[kk], 0.0));
+      if (f == 0 && m == 0)
+        return to_c<C>(make_double2(zonal[kk] + (pump ? pump[kk].x : 0.0), 0.0));
+      if (f == 0 && pump) return to_c<C>(sub2(to_d2(NL[(size_t)m * R + kk]), pump[kk]));
       return NL[((size_t)f * M + m) * R + kk];
     };
     C o[E];

@@ -28,7 +28,8 @@ class qg_params(ctypes.Structure):
                 ("Pr", ctypes.c_double), ("eta", ctypes.c_double),
                 ("n_phi", ctypes.c_int), ("n_r", ctypes.c_int),
                 ("n_c", ctypes.c_int), ("precision", ctypes.c_int),
-                ("pivoting", ctypes.c_int)]
+                ("pivoting", ctypes.c_int), ("ekman", ctypes.c_int),
+                ("eps", ctypes.c_double)]
 
 
 class qg_diag(ctypes.Structure):
@@ -265,12 +266,13 @@ class QGSolver:
     """One solver context on a HIP device, workspace allocated by torch."""
 
     def __init__(self, E, Ra, Pr, eta, n_phi, n_r, n_c=0, device="cuda:0",
-                 stream=None, pivoting=0, precision=0):
+                 stream=None, pivoting=0, precision=0, ekman_eps=None):
         import torch
         self.torch = torch
         self.device = torch.device(device)
         self.params = qg_params(E, Ra, Pr, eta, n_phi, n_r, n_c, precision,
-                                pivoting)
+                                pivoting, 0 if ekman_eps is None else 1,
+                                0.0 if ekman_eps is None else ekman_eps)
         self.M = n_phi // 3 + 1
         self.K = n_c if n_c else (2 * (n_r - 1)) // 3
         nbytes = qg_workspace_size(self.params)
@@ -359,7 +361,9 @@ class QGEnsemble:
         self.device = torch.device(device)
         self.params = [qg_params(m["E"], m["Ra"], m["Pr"], m["eta"],
                                  m["n_phi"], m["n_r"], m.get("n_c", 0),
-                                 m.get("precision", 0), m.get("pivoting", 0))
+                                 m.get("precision", 0), m.get("pivoting", 0),
+                                 0 if m.get("ekman_eps") is None else 1,
+                                 m.get("ekman_eps") or 0.0)
                        for m in members]
         self.shapes = [(p.n_phi // 3 + 1,
                         p.n_c if p.n_c else (2 * (p.n_r - 1)) // 3)

@@ -35,7 +35,8 @@ def test_header_symbols_exported(qg):
 @pytest.mark.parametrize("bad", [
     dict(n_phi=95), dict(n_phi=12), dict(eta=1.2), dict(eta=0.0),
     dict(n_c=33), dict(n_c=5), dict(precision=2), dict(E=0.0),
-    dict(Pr=-1.0), dict(n_r=9), dict(pivoting=2), dict(pivoting=-1)])
+    dict(Pr=-1.0), dict(n_r=9), dict(pivoting=2), dict(pivoting=-1),
+    dict(ekman=2), dict(ekman=1, eps=0.0), dict(ekman=1, eps=float("inf"))])
 def test_workspace_size_rejects_invalid(qg, bad):
     p = dict(E=1e-3, Ra=8e4, Pr=1.0, eta=0.35, n_phi=96, n_r=33, n_c=0,
              precision=0, pivoting=0)

@@ -152,6 +152,46 @@ def test_radial_sizes_three_times_power_of_two(qg, n_phi, n_r):
     assert max(err.values()) < TOL, err
 
 
+@pytest.mark.parametrize("precision", [0, 1])
+def test_ekman_pumping_parity(qg, precision):
+    """Explicit Ekman pumping (F_eps in the Psi equation, the zonal
+    pumping and self-interaction terms) on a nonlinear state with a zonal
+    flow: FP64 at the parity bar; mixed precision no further from the
+    oracle than 10 x the same run without pumping is (the pumping terms
+    are FP64 functions of FP32-transformed fields, like the products)."""
+    w = inputs.SMALL
+    eps = 1e-2
+    st = inputs.make_state(w.M, w.n_c, "decaying", 21)
+    st.psi *= 10.0
+    st.theta *= 1e3
+    st.uphi0 = inputs.dirichlet_from_basis(
+        np.linspace(1.0, 0.1, w.n_c), w.n_c).real * 0.5
+    plan = (("cnab2", 4), ("bpr353", 2))
+
+    def run(pump):
+        _say(f"[parity] pumping {pump} precision {precision}")
+        s = qg.QGSolver(w.E, w.Ra, w.Pr, w.eta, w.n_phi, w.n_r, w.n_c,
+                        precision=precision, ekman_eps=pump)
+        o = QGOracle(w.E, w.Ra, w.Pr, w.eta, w.n_phi, w.n_r, w.n_c,
+                     ekman_eps=pump)
+        for x in (s, o):
+            x.set_state(st.psi, st.theta, st.uphi0)
+        for scheme, n in plan:
+            s.step(w.dt, scheme, n)
+            o.step(w.dt, scheme, n)
+        err = _compare(s, o)
+        _say(f"  rel err {err}")
+        return err, o
+    err, o = run(eps)
+    err0, o0 = run(None)
+    if precision == 0:
+        assert max(err.values()) < TOL, err
+    else:
+        assert max(err.values()) <= 10 * max(err0.values()), (err, err0)
+    # the pumping changes the run
+    assert _rel(o0.uphi, o.uphi) > 1e-3 and _rel(o0.psi, o.psi) > 1e-6
+
+
 def test_small_full_run_100_steps(qg):
     """The small workload in full: 100 CNAB2 steps at dt = 1e-4."""
     w = inputs.SMALL

@@ -40,8 +40,8 @@ def qg():
     return mod
 
 
-def _eigenmode():
-    A, B = eigen.integration_operator(E, RA, PR, ETA, MODE, N_C)
+def _eigenmode(pump=None):
+    A, B = eigen.integration_operator(E, RA, PR, ETA, MODE, N_C, pump)
     sc = 1 / np.maximum(np.abs(A).max(1), np.abs(B).max(1))
     lam, V = sla.eig(A * sc[:, None], B * sc[:, None])
     ok = np.isfinite(lam)
@@ -75,3 +75,27 @@ def test_onset_dns_reproduces_table3(qg, scheme, dt, n):
     # and reproduces the digits Table 3 marks as significant
     assert abs(lam.real - TAB3_DNS_TAU) < 1e-2, lam
     assert abs(lam.imag - TAB3_DNS_OMEGA) < 1e-2, lam
+
+
+# Table 3, integration + tau, BPR353*, (193, 128, 128), eps = 3e-3, with
+# Ekman pumping: 2.148113e2 and -9.436745e3, of which 2.1 and -9.436 are
+# marked correct
+def test_onset_dns_with_pumping(qg):
+    """With the approximated Ekman pumping (eps = 3e-3, explicit): the GPU
+    DNS grows at the eigenvalue of the integration operators with F_eps
+    (the oracle's, 214.384 - 9436.842 i) and has Table 3's marked digits."""
+    eps, dt, n = 3e-3, 1e-6, 30
+    lam0, psi, th = _eigenmode(pump=(N_R, eps))
+    _say(f"[table 3, pumping] eigenvalue {lam0}")
+    s = qg.QGSolver(E, RA, PR, ETA, N_PHI, N_R, N_C, ekman_eps=eps)
+    s.set_state(psi, th, np.zeros(N_C))
+    s.step(dt, "bpr353", n)
+    p1, t1, _ = s.get_state()
+    s.step(dt, "bpr353", n)
+    p2, t2, _ = s.get_state()
+    y1 = np.concatenate([p1[MODE], t1[MODE]])
+    y2 = np.concatenate([p2[MODE], t2[MODE]])
+    lam = np.log(np.vdot(y1, y2) / np.vdot(y1, y1)) / (n * dt)
+    _say(f"  DNS growth rate {lam.real:.7f}, drift {lam.imag:.6f}")
+    assert abs(lam - lam0) / abs(lam0) < 1e-6, (lam, lam0)
+    assert 210.0 <= lam.real < 220.0 and -9437.0 < lam.imag <= -9436.0, lam

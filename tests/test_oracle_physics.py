@@ -181,6 +181,34 @@ def test_integration_pumping_approximation():
     assert lam.real > TAB3_PUMP_TAU
 
 
+def test_dns_with_pumping_follows_its_eigenvalue():
+    """The time step's explicit pumping (grid evaluation, transforms and
+    the C band product) against the integration operators with F_eps: a
+    DNS from the leading m = 12 mode grows at the eigenvalue (BPR353,
+    measured at the time of writing: 4e-8 relative)."""
+    K, n_r, eps, m = 64, 97, 3e-3, 12
+    A, B = eigen.integration_operator(3e-6, 1e7, 0.025, 0.35, m, K,
+                                      pump=(n_r, eps))
+    sc = 1 / np.maximum(np.abs(A).max(1), np.abs(B).max(1))
+    lam, V = sla.eig(A * sc[:, None], B * sc[:, None])
+    ok = np.isfinite(lam)
+    i = np.flatnonzero(ok)[np.argmax(lam[ok].real)]
+    o = QGOracle(3e-6, 1e7, 0.025, 0.35, 39, n_r, K, ekman_eps=eps)
+    v = V[:, i] * 1e-8 / np.abs(V[:, i]).max()
+    psi = np.zeros((o.M, K), complex)
+    th = np.zeros_like(psi)
+    psi[m], th[m] = v[:K], v[K:]
+    o.set_state(psi, th, np.zeros(K))
+    o.step(1e-6, "bpr353", 30)
+    y1 = np.concatenate([o.psi[m], o.theta[m]])
+    o.step(1e-6, "bpr353", 30)
+    y2 = np.concatenate([o.psi[m], o.theta[m]])
+    got = np.log(np.vdot(y1, y2) / np.vdot(y1, y1)) / 30e-6
+    assert abs(got - lam[i]) / abs(lam[i]) < 3e-7, (got, lam[i])
+    # pumping lowers the growth rate from ~615 to ~214
+    assert 200 < got.real < 230
+
+
 def _small_oracle(scale=1.0):
     o = QGOracle(1e-3, 8e4, 1.0, 0.35, 24, 17, 10)
     st = inputs.make_state(o.M, o.K, "decaying", 5)
