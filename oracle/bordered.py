@@ -35,8 +35,8 @@ class BorderedSolver:
         L = np.asarray(L)
         self.p = p
         self.cplx = np.iscomplexobj(L)
-        self.A = L[:p, :p]
-        self.B = L[:p, p:]
+        self.A = L[:p, :p].copy()        # copies: the dense L is not kept
+        self.B = L[:p, p:].copy()
         C = L[p:, :p]
         D = L[p:, p:]
         self.kl, self.ku = _bandwidths(D)

@@ -192,7 +192,7 @@ __device__ double block_max(double v, double* red) {
 // coefficient row a_n (n < K) is the FFT of the even extension e_0 = a_0,
 // e_n = e_{2N-n} = a_n / 2 (eq. cheb).  Thread t owns the radial points
 // k = t + i T, and the fields are accumulated derivative by derivative.
-template <int N2, int T, typename C>
+template <int N2, int T, typename C, bool PUMP>
 __global__ __launch_bounds__(T) void synth_kernel(Geom g, const double2* __restrict__ psi,
                                                   const double2* __restrict__ th,
                                                   C* __restrict__ X,
@@ -214,7 +214,7 @@ __global__ __launch_bounds__(T) void synth_kernel(Geom g, const double2* __restr
     th += mem * M * K;
     X += mem * 6 * R * M;
     if (diag) diag += mem * 8 * M;
-    if (pump) pump += mem * M * R + (size_t)m * R;
+    if (PUMP) pump += mem * M * R + (size_t)m * R;
   }
   // Ekman pumping, eq. approx_pump, accumulated in this block's row of
   // g.pump (each entry by the thread that owns its radial point):
@@ -266,7 +266,7 @@ __global__ __launch_bounds__(T) void synth_kernel(Geom g, const double2* __restr
         const double mh = m2 * h2 * is * is;
         if (d == 0) {
           store(0, k, ix(dm, p));
-          if (pump) {
+          if constexpr (PUMP) {
             double he2, he;
             (void)ups_e(s, he2, he);
             const double cr = 1.5 * s * s / he2 + m2, ci = 2.5 * dm * g.s_o / he;
@@ -279,14 +279,14 @@ __global__ __launch_bounds__(T) void synth_kernel(Geom g, const double2* __restr
         } else if (d == 1) {
           const double2 uph = sub2(a1[i], scl2(h2, p));
           store(1, k, scl2(is, uph));
-          if (pump) pump[k] = add2(pump[k], scl2(0.5 * s, p));
+          if constexpr (PUMP) pump[k] = add2(pump[k], scl2(0.5 * s, p));
           if (diag) ek += 2.0 * g.wq[k] * abs2(uph);
           a2[i] = sub2(a2[i], scl2(h2s - 5.0 * s, p));
           a3[i] = add2(a3[i], scl2(-(h2s - 5.0 * s) + h2s * (so2 * is * is + 12.0 + mh), p));
         } else if (d == 2) {
           const double2 om = sub2(a2[i], scl2(h2, p));
           store(3, k, ix(dm, om));
-          if (pump) {
+          if constexpr (PUMP) {
             double he2, he;
             const double ue = ups_e(s, he2, he);
             pump[k] = scl2(ue, sub2(pump[k], om));
@@ -312,7 +312,7 @@ __global__ __launch_bounds__(T) void synth_kernel(Geom g, const double2* __restr
         } else if (d == 1) {
           a2[i] = add2(a2[i], p);
           a3[i] = add2(a3[i], scl2(1.0 + h2s * is, p));
-          if (pump) {
+          if constexpr (PUMP) {
             double he2, he;
             const double ue = ups_e(s, he2, he);
             pump[k] = make_double2(ue * a1[i].x * (1.0 + g.half_E * a2[i].x), 0.0);
@@ -582,14 +582,25 @@ size_t dct_lds(int n2, int K) { return coef_offset<C>(lds_slots(n2)) + sizeof(do
 template <typename C>
 size_t phi_lds(int nphi) { return sizeof(C) * lds_slots(nphi); }
 
+template <int N2, typename C, bool PUMP>
+void synth_np(const Geom& g, const double2* psi, const double2* th, void* X, double* diag,
+              hipStream_t st) {
+  constexpr int T = threads_dct(N2);
+  const size_t shm = dct_lds<C>(N2, g.K);
+  allow_lds(synth_kernel<N2, T, C, PUMP>, shm);
+  hipLaunchKernelGGL((synth_kernel<N2, T, C, PUMP>), dim3(xcd_grid(g.M), g.nmem), dim3(T), shm, st,
+                     g, psi, th, static_cast<C*>(X), diag);
+}
+
+// The pumping terms are a separate instantiation: without them the kernel
+// carries no pumping code (and no extra registers).
 template <int N2, typename C>
 void synth_n(const Geom& g, const double2* psi, const double2* th, void* X, double* diag,
              hipStream_t st) {
-  constexpr int T = threads_dct(N2);
-  const size_t shm = dct_lds<C>(N2, g.K);
-  allow_lds(synth_kernel<N2, T, C>, shm);
-  hipLaunchKernelGGL((synth_kernel<N2, T, C>), dim3(xcd_grid(g.M), g.nmem), dim3(T), shm, st, g, psi, th,
-                     static_cast<C*>(X), diag);
+  if (g.pump)
+    synth_np<N2, C, true>(g, psi, th, X, diag, st);
+  else
+    synth_np<N2, C, false>(g, psi, th, X, diag, st);
 }
 
 template <int NPHI, typename C>
