@@ -1,7 +1,8 @@
 """One IMEX step of the spherical QG equations, integration method + tau
 (oracle; test infrastructure only).
 
-Equations (paper Sect. 2 and 3.2), no Ekman pumping:
+Equations (paper Sect. 2 and 3.2), without Ekman pumping (for the optional
+explicit pumping see the last reading below):
   Psi, m >= 1 (eq. psi_int):
     d/dt A_m Psi - B_m Psi = C [ (Ra/Pr)(i m/s_o) theta_m + N_omega,m ]
   theta, m >= 0 (eq. temp_int):
