@@ -128,6 +128,43 @@ def test_ensemble_autotune_equals_solo_runs(qg, scheme, nsteps):
     assert ens.diagnostics(0)["step"] == nsteps + 4
 
 
+def test_ensemble_with_pumping_equals_solo_runs(qg):
+    """Members with Ekman pumping (one group per eps, a member without
+    pumping in a group of its own) equal their solo runs."""
+    ws = inputs.ensemble_workloads()
+    base = [ws[i] for i in _pick(ws, per_size=1)][:2]
+    specs = [(base[0], 1e-2), (base[0], 1e-2), (base[0], None), (base[1], 3e-3)]
+    members = []
+    for w, eps in specs:
+        d = _member(w)
+        d["ekman_eps"] = eps
+        members.append(d)
+    ens = qg.QGEnsemble(members)
+    ngroups, _ = ens.groups()
+    assert ngroups == 3
+    solos = []
+    for j, (w, eps) in enumerate(specs):
+        st = inputs.workload_state(w)
+        ens.set_state(j, st.psi, st.theta, st.uphi0)
+        s = qg.QGSolver(w.E, w.Ra, w.Pr, w.eta, w.n_phi, w.n_r, w.n_c,
+                        ekman_eps=eps)
+        s.set_state(st.psi, st.theta, st.uphi0)
+        solos.append(s)
+    dt = base[0].dt
+    _say(f"[ensemble pumping] {[(w.n_phi, w.n_r, e) for w, e in specs]}")
+    for scheme, n in (("cnab2", 5), ("bpr353", 2)):
+        ens.step(dt, scheme, n)
+        for s in solos:
+            s.step(dt, scheme, n)
+    for j, s in enumerate(solos):
+        for x, y in zip(ens.get_state(j), s.get_state()):
+            assert np.array_equal(x, y), j
+    # members 0 and 1 share the group and the state: equal; member 2
+    # (no pumping) differs
+    assert np.array_equal(ens.get_state(0)[2], ens.get_state(1)[2])
+    assert not np.array_equal(ens.get_state(0)[2], ens.get_state(2)[2])
+
+
 def test_ensemble_member_matches_oracle(qg):
     ws = inputs.ensemble_workloads()
     k = 7
