@@ -37,6 +37,7 @@ CASES = {
     "small_bpr353_5": ("SMALL", "bpr353", 5),
     "small_cnab2_100": ("SMALL", "cnab2", 100),
     "medium_bpr353_2": ("MEDIUM", "bpr353", 2),
+    "medium_bpr353_20": ("MEDIUM", "bpr353", 20),
     "large_cnab2_2": ("LARGE", "cnab2", 2),
     # member 7 of the seeded 64-run ensemble (192 x 65, Ra = 4.02 Ra_c)
     "ensemble7_cnab2_10": ("ensemble:7", "cnab2", 10),
