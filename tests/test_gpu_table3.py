@@ -55,7 +55,10 @@ def _eigenmode(pump=None):
 
 
 @pytest.mark.parametrize("scheme,dt,n", [("bpr353", 1e-6, 30),
-                                         ("cnab2", 5e-8, 200)])
+                                         ("cnab2", 5e-8, 200),
+                                         ("ars443", 5e-7, 60),
+                                         ("ars222", 5e-8, 200),
+                                         ("sbdf3", 1e-7, 120)])
 def test_onset_dns_reproduces_table3(qg, scheme, dt, n):
     lam0, psi, th = _eigenmode()
     _say(f"[table 3] {N_PHI}x{N_R} K={N_C} {scheme} dt={dt}: eigenvalue {lam0}")
