@@ -119,7 +119,11 @@ def run(name, scheme, steps, seed, u=U):
             o.advection_grid = _noisy_products(o.advection_grid, rng, u)
             o.solve = _noisy_solve(o.solve, rng, U)
         o.set_state(st.psi, st.theta, st.uphi0)
-        o.step(w.dt, scheme, steps)
+        for i in range(steps):      # one step at a time: progress lines
+            o.step(w.dt, scheme, 1)
+            if (i + 1) % 5 == 0 or i + 1 == steps:
+                print(f"  {name} {scheme} seed {seed}: step {i + 1}/{steps}",
+                      flush=True)
     finally:
         for f in WRAPPED:
             setattr(tr, f, orig[f])
