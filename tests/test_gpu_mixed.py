@@ -84,3 +84,45 @@ def test_mixed_and_fp64_share_the_solves(qg):
         p, t, u = s.get_state()
         assert not p.any() and not t.any() and not u.any()
         assert s.diagnostics()["pivoted"] == 0
+
+
+def _sample_errors(s, ref):
+    """max |gpu - oracle| over the stored rows / max |oracle| over the whole
+    field, per field (tests/golden/large_cnab2_50_samples.json)."""
+    psi, th, up = s.get_state()
+    out = {}
+    for f, arr in (("psi", psi), ("theta", th)):
+        d = 0.0
+        for m, row in ref[f].items():
+            r = np.array(row)
+            d = max(d, float(np.abs(arr[int(m)] - (r[:, 0] + 1j * r[:, 1])).max()))
+        out[f] = d / ref["max_abs"][f]
+    out["uphi"] = float(np.abs(up - np.array(ref["uphi"])).max()
+                        / ref["max_abs"]["uphi"])
+    return out
+
+
+@pytest.mark.parametrize("precision,case", [(0, "large_cnab2_50"),
+                                            (1, "mixed_large_cnab2_50")])
+def test_large_after_50_steps(qg, precision, case):
+    """50 CNAB2 steps at 3072 x 1025 in FP64 and in mixed precision against
+    the oracle's state after the same steps (sampled rows), in the launch
+    configuration the benchmark times: the first 21 steps run the
+    band-product autotuner, the rest use its choice."""
+    ref = json.load(open(os.path.join(os.path.dirname(__file__), "golden",
+                                      "large_cnab2_50_samples.json")))
+    w = inputs.LARGE
+    assert ref["workload"] == w.name and ref["dt"] == w.dt
+    _say(f"[large 50] precision {precision}")
+    st = inputs.workload_state(w)
+    s = qg.QGSolver(w.E, w.Ra, w.Pr, w.eta, w.n_phi, w.n_r, w.n_c,
+                    precision=precision)
+    s.set_state(st.psi, st.theta, st.uphi0)
+    pick = s.step_autotune(w.dt, w.scheme, 21)
+    s.step(w.dt, w.scheme, ref["steps"] - 21)
+    err = _sample_errors(s, ref)
+    _say(f"  band systems per thread {pick}")
+    tol = _TOLS[case]["tol"]
+    _say(f"  rel err {err}; bound {tol}")
+    for f in err:
+        assert err[f] <= max(1e-11, tol[f]), (f, err[f], tol[f])

@@ -238,15 +238,23 @@ def test_diagnostics_match_oracle(qg):
     assert dg["step"] == 2 and dg["nonfinite"] == 0
 
 
-def test_medium_bpr353_parity(qg):
+@pytest.mark.parametrize("nsteps", [2, 20])
+def test_medium_bpr353_parity(qg, nsteps):
+    """The 768 x 257 BPR353 workload, 2 and 20 steps, in the launch
+    configuration of a tuned run (the 20-step run's first 9 steps run the
+    band-product autotuner)."""
     w = inputs.MEDIUM
-    _say(f"[parity] medium {w.n_phi}x{w.n_r} bpr353 x2")
+    _say(f"[parity] medium {w.n_phi}x{w.n_r} bpr353 x{nsteps}")
     s, o = _pair(qg, w, inputs.workload_state(w))
-    s.step(w.dt, "bpr353", 2)
-    o.step(w.dt, "bpr353", 2)
+    if nsteps >= 9:
+        s.step_autotune(w.dt, "bpr353", 9)
+        s.step(w.dt, "bpr353", nsteps - 9)
+    else:
+        s.step(w.dt, "bpr353", nsteps)
+    o.step(w.dt, "bpr353", nsteps)
     err = _compare(s, o)
     _say(f"  rel err {err}")
-    ok, tol = _within(err, "medium_bpr353_2")
+    ok, tol = _within(err, f"medium_bpr353_{nsteps}")
     assert ok, (err, tol)
 
 
