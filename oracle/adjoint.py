@@ -211,6 +211,37 @@ class CNAB2Adjoint:
         return J, yb[1]
 
 
+def transpose_map(adj, y0, dt, nsteps, w):
+    """J^T w for the map y^0 -> y^N of nsteps CNAB2 steps from y0 (J its
+    derivative at y0; real inner product sum Re(conj(a) b) over every
+    component): the reverse sweep of CNAB2Adjoint.gradient with the
+    terminal adjoint w and no energy terms."""
+    o = adj.o
+    o.set_state(*y0)
+    ys = [tuple(np.copy(v) for v in y0)]
+    for _ in range(nsteps):
+        o.step(dt, "cnab2", 1)
+        ys.append((o.psi.copy(), o.theta.copy(), o.uphi.copy()))
+    adt = CNAB2_BI0 * dt
+    rb = [None] * (nsteps + 1)
+    yb = None
+    for n in range(nsteps, -1, -1):
+        if n == nsteps:
+            acc = [np.array(v, dtype=np.result_type(v, np.float64)) for v in w]
+        else:
+            ml = adj.mass_lin_T(0.5 * dt, rb[n])
+            c1 = 1.0 if n == 0 else 1.5
+            eb = [c1 * dt * v for v in rb[n]]
+            if n + 1 < nsteps:
+                eb = [a - 0.5 * dt * b for a, b in zip(eb, rb[n + 1])]
+            ex = adj.explicit_T(ys[n], *eb)
+            acc = [a + b for a, b in zip(ml, ex)]
+        yb = acc
+        if n > 0:
+            rb[n - 1] = adj.solve_T(adt, yb)
+    return yb
+
+
 def dirichlet_free_to_full(c):
     """theta coefficients from the free ones (n >= 2) by the Dirichlet rows:
     theta_0 = -sum of even n >= 2, theta_1 = -sum of odd n >= 3."""
