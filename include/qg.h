@@ -189,6 +189,26 @@ qg_status qg_step_timed(qg_ctx *ctx, double dt, int scheme, int nsteps,
 qg_status qg_step_autotune(qg_ctx *ctx, double dt, int scheme, int nsteps,
                            int *systems_per_thread);
 
+/* Tangent-linear runs (toward the adjoint of the time-integrated kinetic
+ * energy; single-run contexts): qg_tangent_set loads a perturbation d of
+ * the current state (same layout and checks as qg_set_state: it must meet
+ * the homogeneous boundary conditions); qg_step_tangent advances the state
+ * and d together by CNAB2 steps, d by the derivative of the step at the
+ * current state,
+ *   (M - dt/2 L) d^{n+1} = (M + dt/2 L) d^n + dt (3/2 T^n - 1/2 T^{n-1}),
+ *   T^n = E'(y^n) d^n = (E(y^n + c d^n) - E(y^n - c d^n)) / (2c)
+ * (exact for the quadratic explicit terms E of Sect. 3.2, c = max|y| /
+ * max|d| at qg_tangent_set), with qg_step's rules for dt and the history
+ * (T^{-1} := T^0 when the state's history starts at the same step, else
+ * 0); qg_tangent_get copies d out.  Each tangent step costs two explicit
+ * evaluations, one band product and one solve more than a CNAB2 step.
+ * QG_ESTATE if no tangent state was set (qg_set_state clears it). */
+qg_status qg_tangent_set(qg_ctx *ctx, const double *dpsi, const double *dtheta,
+                         const double *duphi, int on_device);
+qg_status qg_step_tangent(qg_ctx *ctx, double dt, int nsteps);
+qg_status qg_tangent_get(qg_ctx *ctx, double *dpsi, double *dtheta,
+                         double *duphi, int on_device);
+
 /* Diagnostics of the current state (synchronises the stream). */
 qg_status qg_diagnostics(qg_ctx *ctx, qg_diag *out);
 

@@ -161,7 +161,7 @@ bool sizes_of(const qg_params* p, Sizes& z, std::string& why) {
 
 struct WsMap {
   size_t ra;
-  size_t state, ybuf, eslot, lslot, mE, mY, pump, X, NL, zonal, rate, diag, xk, wq, dsk, twd, twp, twh, wphi,
+  size_t state, ybuf, eslot, lslot, mE, mY, pump, tan, X, NL, zonal, rate, diag, xk, wq, dsk, twd, twp, twh, wphi,
       twd32, twp32, twh32, wphi32, bands, rhs;
   size_t p_piv, p_L, p_U, p_W, p_C, p_Mi, p_ui;
   size_t r_piv, r_L, r_U, r_W, r_C, r_Mi, r_ui;
@@ -185,6 +185,7 @@ WsMap map_workspace(const Sizes& z, int nmem) {
   w.mE = L.take(8 * MK);      // SBDF explicit terms E^n .. E^{n-3}
   w.mY = L.take(6 * MK);      // SBDF past states y^{n-1} .. y^{n-3}
   w.pump = L.take(z.pump ? RM : 0);   // Ekman pumping terms [M][R] per run
+  w.tan = L.take(nmem == 1 ? 10 * MK : 0);   // tangent state, its E history, y +- c d
   w.X = L.take(6 * RM);
   w.NL = L.take(2 * RM);
   w.zonal = L.take(nm * z.R * sizeof(double));
@@ -245,6 +246,8 @@ struct qg_ctx {
   double factored_adt = -1.0;
   int have_prev = 0, cur = 0;   // CNAB2 history
   int ms_n = 0;                 // SBDF levels stored since the history began
+  int t_set = 0, t_have_prev = 0, t_cur = 0;   // tangent-linear run (qg_step_tangent)
+  double t_scale = 1.0;                        // c of the difference quotient
   int last_scheme = -1;         // scheme and dt of the history
   double last_dt = 0.0;
   double t = 0.0;
@@ -263,6 +266,9 @@ struct qg_ctx {
   double2* slot(size_t base, int i, int field) {
     return ptr2(base) + ((size_t)(2 * i + field)) * mk();
   }
+  // tangent region: [0] the tangent state d (Psi/u, theta), [1], [2] its
+  // explicit-term history, [3] y + c d, [4] y - c d; each 2 mk entries
+  double2* tng(int i) { return ptr2(w.tan) + (size_t)(2 * i) * mk(); }
 };
 
 #define HIPCHK(expr)                                                           \
@@ -601,6 +607,65 @@ qg_status step_cnab2(qg_ctx* ctx, double dt) {
   return QG_OK;
 }
 
+// One step of the tangent-linear CNAB2 model about the current state y^n
+// (before y^n itself is stepped): with T^n = E'(y^n) d^n,
+//   (M - dt/2 L) d^{n+1} = (M + dt/2 L) d^n + dt (3/2 T^n - 1/2 T^{n-1}),
+// tau rows and projections as in the step.  E is quadratic in the state,
+// so T^n = (E(y + c d) - E(y - c d)) / (2c) exactly in exact arithmetic;
+// c ~ max|y| / max|d| balances the two roundings.  The first tangent step
+// takes T^{-1} := T^0 if the state's own history starts there as well
+// (E^{-1} := E^0, a function of y^0), else T^{-1} := 0 (the history is
+// not perturbed).
+qg_status step_tangent(qg_ctx* ctx, double dt) {
+  const size_t mk = ctx->mk(), n2 = 2 * mk;
+  const double cs = ctx->t_scale;
+  Combine cb{};
+  cb.nb = 2;
+  cb.in[0] = ctx->psi();
+  cb.in[1] = ctx->tng(0);
+  cb.c[0] = 1.0;
+  cb.c[1] = cs;
+  launch_combine(cb, ctx->tng(3), n2, ctx->st);
+  cb.c[1] = -cs;
+  launch_combine(cb, ctx->tng(4), n2, ctx->st);
+  double2* Ea = ctx->slot(ctx->w.eslot, 2, 0);   // E(y + c d), E(y - c d): DIRK
+  double2* Eb = ctx->slot(ctx->w.eslot, 3, 0);   // stage slots, unused by CNAB2
+  qg_status s = explicit_terms(ctx, ctx->tng(3), ctx->tng(3) + mk, Ea, Ea + mk);
+  if (s == QG_OK) s = explicit_terms(ctx, ctx->tng(4), ctx->tng(4) + mk, Eb, Eb + mk);
+  if (s != QG_OK) return s;
+  const int cur = ctx->t_cur, prev = 1 - cur;
+  Combine dq{};
+  dq.nb = 2;
+  dq.in[0] = Ea;
+  dq.in[1] = Eb;
+  dq.c[0] = 0.5 / cs;
+  dq.c[1] = -0.5 / cs;
+  launch_combine(dq, ctx->tng(1 + cur), n2, ctx->st);
+  RhsSpec rs{};
+  rs.base_psi = ctx->tng(0);
+  rs.base_th = ctx->tng(0) + mk;
+  rs.cL = 0.5 * dt;
+  rs.nterm = 1;
+  rs.term_psi[0] = ctx->tng(1 + cur);
+  rs.term_th[0] = ctx->tng(1 + cur) + mk;
+  rs.coef[0] = 1.5 * dt;
+  const double2* pe = ctx->t_have_prev ? ctx->tng(1 + prev)
+                                       : (ctx->have_prev ? nullptr : ctx->tng(1 + cur));
+  if (pe) {
+    rs.term_psi[1] = pe;
+    rs.term_th[1] = pe + mk;
+    rs.coef[1] = -0.5 * dt;
+    rs.nterm = 2;
+  }
+  rs.out_psi = ctx->tng(0);
+  rs.out_th = ctx->tng(0) + mk;
+  s = implicit_solve(ctx, rs);
+  if (s != QG_OK) return s;
+  ctx->t_have_prev = 1;
+  ctx->t_cur = prev;
+  return QG_OK;
+}
+
 qg_status step_dirk(qg_ctx* ctx, double dt, const Dirk& T) {
   // y_1 = y_n (explicit first stage); stages i = 2..s solve
   // (M - a_ii dt L) y_i = M y_n + dt sum_{j<i} (aE_ij E_j + aI_ij L y_j);
@@ -910,10 +975,10 @@ qg_status create_ctx(qg_ctx** out, const qg_params* p, int nmem, const double* r
 
 // State of run `mem` in (resets the time, step counter and multistep
 // history of the whole context) and out.
-qg_status set_state_run(qg_ctx* ctx, int mem, const double* psi, const double* theta,
-                        const double* uphi, int on_device) {
-  if (!ctx) return QG_EINVAL;
-  if (mem < 0 || mem >= ctx->nmem) return fail(ctx, QG_EINVAL, "no such run");
+// Validates a caller's state (finite, boundary conditions) and uploads it
+// to dst_psi (row 0 := zonal flow) and dst_th; *amax = its largest entry.
+qg_status load_state(qg_ctx* ctx, const double* psi, const double* theta, const double* uphi,
+                     int on_device, double2* dst_psi, double2* dst_th, double* amax) {
   if (!psi || !theta || !uphi) return fail(ctx, QG_EINVAL, "null state pointer");
   const Sizes& z = ctx->z;
   const size_t MK = (size_t)z.M * z.K;
@@ -960,11 +1025,25 @@ qg_status set_state_run(qg_ctx* ctx, int mem, const double* psi, const double* t
   if (!check(hu2.data(), 2, true))
     return fail(ctx, QG_ESTATE, "zonal flow violates the boundary conditions");
   for (int n = 0; n < z.K; ++n) hp[n] = hu2[n];  // row 0 of the psi array holds the zonal flow
-  HIPCHK(hipMemcpyAsync(ctx->psi() + mem * MK, hp.data(), MK * 16, hipMemcpyHostToDevice,
-                        ctx->st));
-  HIPCHK(hipMemcpyAsync(ctx->th() + mem * MK, ht.data(), MK * 16, hipMemcpyHostToDevice,
-                        ctx->st));
+  double mx = 0.0;
+  for (size_t i = 0; i < MK; ++i)
+    mx = std::max(mx, std::max(std::hypot(hp[i].x, hp[i].y), std::hypot(ht[i].x, ht[i].y)));
+  if (amax) *amax = mx;
+  HIPCHK(hipMemcpyAsync(dst_psi, hp.data(), MK * 16, hipMemcpyHostToDevice, ctx->st));
+  HIPCHK(hipMemcpyAsync(dst_th, ht.data(), MK * 16, hipMemcpyHostToDevice, ctx->st));
   HIPCHK(hipStreamSynchronize(ctx->st));
+  return QG_OK;
+}
+
+qg_status set_state_run(qg_ctx* ctx, int mem, const double* psi, const double* theta,
+                        const double* uphi, int on_device) {
+  if (!ctx) return QG_EINVAL;
+  if (mem < 0 || mem >= ctx->nmem) return fail(ctx, QG_EINVAL, "no such run");
+  const size_t MK = (size_t)ctx->z.M * ctx->z.K;
+  qg_status s = load_state(ctx, psi, theta, uphi, on_device, ctx->psi() + mem * MK,
+                           ctx->th() + mem * MK, nullptr);
+  if (s != QG_OK) return s;
+  ctx->t_set = 0;
   ctx->t = 0.0;
   ctx->step = 0;
   ctx->have_prev = 0;
@@ -975,16 +1054,15 @@ qg_status set_state_run(qg_ctx* ctx, int mem, const double* psi, const double* t
   return QG_OK;
 }
 
-qg_status get_state_run(qg_ctx* ctx, int mem, double* psi, double* theta, double* uphi,
-                        int on_device) {
-  if (!ctx) return QG_EINVAL;
-  if (mem < 0 || mem >= ctx->nmem) return fail(ctx, QG_EINVAL, "no such run");
+// Copies a state out of the workspace (row 0 of src_psi holds the zonal
+// flow; the psi output gets zeros there).
+qg_status read_state(qg_ctx* ctx, const double2* src_psi, const double2* src_th, double* psi,
+                     double* theta, double* uphi, int on_device) {
   if (!psi || !theta || !uphi) return fail(ctx, QG_EINVAL, "null state pointer");
   const Sizes& z = ctx->z;
   const size_t MK = (size_t)z.M * z.K;
   std::vector<double2> hp(MK);
-  HIPCHK(hipMemcpyAsync(hp.data(), ctx->psi() + mem * MK, MK * 16, hipMemcpyDeviceToHost,
-                        ctx->st));
+  HIPCHK(hipMemcpyAsync(hp.data(), src_psi, MK * 16, hipMemcpyDeviceToHost, ctx->st));
   HIPCHK(hipStreamSynchronize(ctx->st));
   std::vector<double> hu(z.K);
   for (int n = 0; n < z.K; ++n) {
@@ -994,10 +1072,19 @@ qg_status get_state_run(qg_ctx* ctx, int mem, double* psi, double* theta, double
   const hipMemcpyKind k1 = on_device ? hipMemcpyHostToDevice : hipMemcpyHostToHost;
   const hipMemcpyKind k2 = on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
   HIPCHK(hipMemcpyAsync(psi, hp.data(), MK * 16, k1, ctx->st));
-  HIPCHK(hipMemcpyAsync(theta, ctx->th() + mem * MK, MK * 16, k2, ctx->st));
+  HIPCHK(hipMemcpyAsync(theta, src_th, MK * 16, k2, ctx->st));
   HIPCHK(hipMemcpyAsync(uphi, hu.data(), z.K * 8, k1, ctx->st));
   HIPCHK(hipStreamSynchronize(ctx->st));
   return QG_OK;
+}
+
+qg_status get_state_run(qg_ctx* ctx, int mem, double* psi, double* theta, double* uphi,
+                        int on_device) {
+  if (!ctx) return QG_EINVAL;
+  if (mem < 0 || mem >= ctx->nmem) return fail(ctx, QG_EINVAL, "no such run");
+  const size_t MK = (size_t)ctx->z.M * ctx->z.K;
+  return read_state(ctx, ctx->psi() + mem * MK, ctx->th() + mem * MK, psi, theta, uphi,
+                    on_device);
 }
 
 qg_status check_step_args(qg_ctx* ctx, double dt, int scheme, int nsteps) {
@@ -1135,6 +1222,57 @@ qg_status qg_get_state(qg_ctx* ctx, double* psi, double* theta, double* uphi, in
 
 qg_status qg_step(qg_ctx* ctx, double dt, int scheme, int nsteps) {
   return step_ctx(ctx, dt, scheme, nsteps);
+}
+
+qg_status qg_tangent_set(qg_ctx* ctx, const double* dpsi, const double* dtheta,
+                         const double* duphi, int on_device) {
+  if (!ctx) return QG_EINVAL;
+  if (ctx->nmem != 1) return fail(ctx, QG_EINVAL, "tangent runs need a single-run context");
+  double dmax = 0.0;
+  qg_status s = load_state(ctx, dpsi, dtheta, duphi, on_device, ctx->tng(0), ctx->tng(0) + ctx->mk(),
+                           &dmax);
+  if (s != QG_OK) return s;
+  const size_t MK = (size_t)ctx->z.M * ctx->z.K;
+  std::vector<double2> hp(MK), ht(MK);
+  HIPCHK(hipMemcpyAsync(hp.data(), ctx->psi(), MK * 16, hipMemcpyDeviceToHost, ctx->st));
+  HIPCHK(hipMemcpyAsync(ht.data(), ctx->th(), MK * 16, hipMemcpyDeviceToHost, ctx->st));
+  HIPCHK(hipStreamSynchronize(ctx->st));
+  double ymax = 0.0;
+  for (size_t i = 0; i < MK; ++i)
+    ymax = std::max(ymax, std::max(std::hypot(hp[i].x, hp[i].y), std::hypot(ht[i].x, ht[i].y)));
+  ctx->t_scale = (ymax > 0.0 && dmax > 0.0) ? ymax / dmax : 1.0;
+  ctx->t_set = 1;
+  ctx->t_have_prev = 0;
+  ctx->t_cur = 0;
+  return QG_OK;
+}
+
+qg_status qg_tangent_get(qg_ctx* ctx, double* dpsi, double* dtheta, double* duphi,
+                         int on_device) {
+  if (!ctx) return QG_EINVAL;
+  if (!ctx->t_set) return fail(ctx, QG_ESTATE, "no tangent state (qg_tangent_set)");
+  return read_state(ctx, ctx->tng(0), ctx->tng(0) + ctx->mk(), dpsi, dtheta, duphi, on_device);
+}
+
+qg_status qg_step_tangent(qg_ctx* ctx, double dt, int nsteps) {
+  if (!ctx) return QG_EINVAL;
+  qg_status s = check_step_args(ctx, dt, QG_CNAB2, nsteps);
+  if (s != QG_OK) return s;
+  if (!ctx->t_set) return fail(ctx, QG_ESTATE, "no tangent state (qg_tangent_set)");
+  if (nsteps == 0) return QG_OK;
+  const bool fresh = ctx->last_scheme != QG_CNAB2 || ctx->last_dt != dt;
+  begin_history(ctx, dt, QG_CNAB2);
+  if (fresh) ctx->t_have_prev = 0;
+  s = prepare(ctx, 0.5 * dt);
+  if (s != QG_OK) return s;
+  for (int i = 0; i < nsteps; ++i) {
+    s = step_tangent(ctx, dt);
+    if (s == QG_OK) s = step_cnab2(ctx, dt);
+    if (s != QG_OK) return s;
+    ctx->t += dt;
+    ctx->step += 1;
+  }
+  return QG_OK;
 }
 
 qg_status qg_diagnostics(qg_ctx* ctx, qg_diag* out) { return diagnostics_run(ctx, 0, out); }

@@ -78,6 +78,9 @@ def load():
         "qg_operator_band": (i, [d, i, i, vp]),
         "qg_step_timed": (i, [vp, d, i, i, vp, vp]),
         "qg_step_autotune": (i, [vp, d, i, i, ctypes.POINTER(i)]),
+        "qg_tangent_set": (i, [vp, vp, vp, vp, i]),
+        "qg_tangent_get": (i, [vp, vp, vp, vp, i]),
+        "qg_step_tangent": (i, [vp, d, i]),
         "qg_ensemble_workspace_size": (i, [vp, i,
                                            ctypes.POINTER(ctypes.c_size_t)]),
         "qg_ensemble_create": (i, [ctypes.POINTER(vp), vp, i, vp,
@@ -339,6 +342,28 @@ class QGSolver:
     def step_timed(self, dt, scheme="cnab2", n=1):
         """Returns {kernel class: (total ms, launches)}."""
         return qg_step_timed(self.ctx, dt, SCHEMES[scheme], n)
+
+    def tangent_set(self, dpsi, dtheta, duphi):
+        """Perturbation of the current state for qg_step_tangent (host
+        arrays, the layout of set_state)."""
+        import numpy as np
+        a = [np.ascontiguousarray(x, dtype=t) for x, t in
+             ((dpsi, np.complex128), (dtheta, np.complex128), (duphi, np.float64))]
+        _check(self.ctx, load().qg_tangent_set(
+            self.ctx, *[ctypes.c_void_p(x.ctypes.data) for x in a], 0))
+
+    def step_tangent(self, dt, n=1):
+        _check(self.ctx, load().qg_step_tangent(self.ctx, float(dt), int(n)))
+
+    def tangent_get(self):
+        import numpy as np
+        ps = np.empty((self.M, self.K), np.complex128)
+        th = np.empty_like(ps)
+        up = np.empty(self.K)
+        _check(self.ctx, load().qg_tangent_get(
+            self.ctx, ctypes.c_void_p(ps.ctypes.data),
+            ctypes.c_void_p(th.ctypes.data), ctypes.c_void_p(up.ctypes.data), 0))
+        return ps, th, up
 
     def step_autotune(self, dt, scheme="cnab2", n=9):
         """n steps while timing the band-product shapes; returns the
