@@ -5,7 +5,8 @@ Workload (default): 3072 x 1025 grid (N_m = 1024, N_c = 682), E = 1e-8,
 Pr = 1, Ra = 20 Ra_c, CNAB2, dt = 2.5e-10, seeded turbulent-like initial
 state (k^-5/3 spectrum steepening past m ~ 20, random phases, Re = 1e4).
 Beside it: the same steps with FP32 transforms and products, the cost of
-one step of every other time scheme of Table 1 relative to CNAB2, and the
+one step of every other time scheme of Table 1 relative to CNAB2, the cost
+of a tangent-linear step against a forward step at 768 x 257, and the
 batched ensemble of 64 runs of uneven size and Ra.  A step is one CNAB2 step of the
 whole hot path: Chebyshev synthesis, azimuthal FFTs and products, radial
 analysis, explicit terms, right-hand sides and the bordered solves of every
@@ -195,6 +196,43 @@ def schemes_run(qg, torch, w, state, args):
     return out
 
 
+def tangent_run(qg, torch, inputs, args):
+    """The 768 x 257 adjoint-study workload (E = 1e-6, Ra = 5 Ra_c, CNAB2):
+    forward steps against tangent-linear steps (state and perturbation
+    advanced together), both timed on the solver's stream."""
+    import numpy as np
+    w = inputs.ADJOINT
+    st = inputs.workload_state(w)
+    rng = np.random.default_rng(500)
+    cth = (rng.standard_normal((w.M, w.n_c))
+           + 1j * rng.standard_normal((w.M, w.n_c)))
+    cth[0] = cth[0].real
+    d = (np.zeros_like(st.psi), inputs.dirichlet_from_basis(cth, w.n_c),
+         np.zeros(w.n_c))
+    s = qg.QGSolver(w.E, w.Ra, w.Pr, w.eta, w.n_phi, w.n_r, w.n_c,
+                    device="cuda:0")
+    out = {}
+    for mode in ("forward", "tangent"):
+        s.set_state(st.psi, st.theta, st.uphi0)
+        if mode == "tangent":
+            s.tangent_set(*d)
+        run = (lambda n: s.step(w.dt, "cnab2", n)) if mode == "forward" \
+            else (lambda n: s.step_tangent(w.dt, n))
+        run(args.warmup)
+        torch.cuda.synchronize()
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record(s.stream)
+        run(args.ens_steps)
+        b.record(s.stream)
+        torch.cuda.synchronize()
+        out[mode] = a.elapsed_time(b) / args.ens_steps
+    return {"workload": w.name, "ms_per_forward_step": out["forward"],
+            "ms_per_tangent_step": out["tangent"],
+            "tangent_vs_forward": out["tangent"] / out["forward"],
+            "perturbation": "random initial-temperature coefficients, seed 500"}
+
+
 def ensemble_run(qg, torch, inputs, args):
     """The batched ensemble: 64 runs of uneven size and Ra stepped together
     (one launch per kernel and size group, graph replay), against the same
@@ -366,6 +404,9 @@ def main():
     if not args.no_schemes and prec == 0:
         out["schemes"] = schemes_run(qg, torch, w, state, args)
         print("[bench] schemes done", file=sys.stderr, flush=True)
+    if not args.no_schemes and prec == 0:
+        out["tangent_linear"] = tangent_run(qg, torch, inputs, args)
+        print("[bench] tangent done", file=sys.stderr, flush=True)
     if not args.no_ensemble and prec == 0:
         out["batched"] = ensemble_run(qg, torch, inputs, args)
         print(f"[bench] ensemble done: {out['batched']['ms_per_step']:.4f} "
