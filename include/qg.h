@@ -209,6 +209,19 @@ qg_status qg_step_tangent(qg_ctx *ctx, double dt, int nsteps);
 qg_status qg_tangent_get(qg_ctx *ctx, double *dpsi, double *dtheta,
                          double *duphi, int on_device);
 
+/* The adjoint (in the real inner product) of the implicit solve of a
+ * CNAB2 step of size dt, Appendix A: per system, r = Z S^-H P x, S the
+ * bordered tau matrix (S^-T for the real theta and zonal-flow systems), P
+ * the projection that keeps theta at m = 0 real, Z the zeroing of the tau
+ * rows of the right-hand side; computed with the stored band-LU factors
+ * (refactorised first if dt differs, synchronously).  In place on arrays
+ * in the state layout (psi row 0 is written as zeros, the zonal flow is
+ * uphi).  The first piece of a reverse sweep; single-run contexts only.
+ * QG_EUNSUPPORTED when the factors use row interchanges (qg_params.pivoting
+ * or a growth factor above the unpivoted bound). */
+qg_status qg_adjoint_solve(qg_ctx *ctx, double dt, double *psi, double *theta,
+                           double *uphi, int on_device);
+
 /* Diagnostics of the current state (synchronises the stream). */
 qg_status qg_diagnostics(qg_ctx *ctx, qg_diag *out);
 

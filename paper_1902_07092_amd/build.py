@@ -29,7 +29,8 @@ def build(verbose: bool = False) -> str:
     _run(["g++", "-O2", "-fPIC", "-std=c++17", "-c",
           os.path.join(CSRC, "host_ops.cpp"), "-o", host], verbose)
     objs.append(host)
-    for src in ("transforms.hip", "bands.hip", "kernels.hip", "solve.hip", "api.hip"):
+    for src in ("transforms.hip", "bands.hip", "kernels.hip", "solve.hip", "adjoint.hip",
+                "api.hip"):
         obj = os.path.join(BUILD, src.replace(".hip", ".o"))
         _run([hipcc, *HIPFLAGS, "-c", os.path.join(CSRC, src), "-o", obj],
              verbose)

@@ -23,6 +23,8 @@ void launch_lin(const Geom& g, const Bands& b, const double2* ypsi, const double
                 double2* lpsi, double2* lth, int mch, hipStream_t st);
 bool band_mch_ok(int mch);
 void launch_combine(const Combine& cb, double2* out, size_t n, hipStream_t st);
+void launch_solve_adjoint(const Geom& g, const FactorSet<double2>& Fp, const FactorSet<double>& Fr,
+                          int q4, int q2, double2* psi, double2* th, hipStream_t st);
 bool launch_solve(const Geom& g, const FactorSet<double2>& Fp, const FactorSet<double>& Fr,
                   double2* rhs, const RhsSpec& rs, int kutp, int kutr, bool pivoted,
                   hipStream_t st);
@@ -1245,6 +1247,35 @@ qg_status qg_tangent_set(qg_ctx* ctx, const double* dpsi, const double* dtheta,
   ctx->t_have_prev = 0;
   ctx->t_cur = 0;
   return QG_OK;
+}
+
+qg_status qg_adjoint_solve(qg_ctx* ctx, double dt, double* psi, double* theta, double* uphi,
+                           int on_device) {
+  if (!ctx) return QG_EINVAL;
+  if (ctx->nmem != 1) return fail(ctx, QG_EINVAL, "adjoint solves need a single-run context");
+  if (!psi || !theta || !uphi) return fail(ctx, QG_EINVAL, "null pointer");
+  if (!(dt > 0) || !std::isfinite(dt)) return fail(ctx, QG_EINVAL, "dt must be positive");
+  qg_status s = prepare(ctx, 0.5 * dt);
+  if (s != QG_OK) return s;
+  if (ctx->pivoted)
+    return fail(ctx, QG_EUNSUPPORTED, "adjoint solves use the unpivoted factors");
+  const Sizes& z = ctx->z;
+  const size_t MK = (size_t)z.M * z.K;
+  std::vector<double2> hp(MK);
+  std::vector<double> hu(z.K);
+  const hipMemcpyKind kind = on_device ? hipMemcpyDeviceToHost : hipMemcpyHostToHost;
+  HIPCHK(hipMemcpyAsync(hp.data(), psi, MK * 16, kind, ctx->st));
+  HIPCHK(hipMemcpyAsync(hu.data(), uphi, z.K * 8, kind, ctx->st));
+  HIPCHK(hipStreamSynchronize(ctx->st));
+  for (int n = 0; n < z.K; ++n) hp[n] = make_double2(hu[n], 0.0);   // row 0: the zonal flow
+  double2* bp = ctx->tng(3);
+  double2* bt = ctx->tng(3) + ctx->mk();
+  HIPCHK(hipMemcpyAsync(bp, hp.data(), MK * 16, hipMemcpyHostToDevice, ctx->st));
+  HIPCHK(hipMemcpyAsync(bt, theta, MK * 16,
+                        on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, ctx->st));
+  launch_solve_adjoint(ctx->g, ctx->Fp, ctx->Fr, z.q4, z.q2, bp, bt, ctx->st);
+  HIPCHK(hipGetLastError());
+  return read_state(ctx, bp, bt, psi, theta, uphi, on_device);
 }
 
 qg_status qg_tangent_get(qg_ctx* ctx, double* dpsi, double* dtheta, double* duphi,

@@ -81,6 +81,7 @@ def load():
         "qg_tangent_set": (i, [vp, vp, vp, vp, i]),
         "qg_tangent_get": (i, [vp, vp, vp, vp, i]),
         "qg_step_tangent": (i, [vp, d, i]),
+        "qg_adjoint_solve": (i, [vp, d, vp, vp, vp, i]),
         "qg_ensemble_workspace_size": (i, [vp, i,
                                            ctypes.POINTER(ctypes.c_size_t)]),
         "qg_ensemble_create": (i, [ctypes.POINTER(vp), vp, i, vp,
@@ -354,6 +355,17 @@ class QGSolver:
 
     def step_tangent(self, dt, n=1):
         _check(self.ctx, load().qg_step_tangent(self.ctx, float(dt), int(n)))
+
+    def adjoint_solve(self, dt, psi, theta, uphi):
+        """qg_adjoint_solve on host arrays (copies; returns the result)."""
+        import numpy as np
+        ps = np.array(psi, dtype=np.complex128, order="C")
+        th = np.array(theta, dtype=np.complex128, order="C")
+        up = np.array(uphi, dtype=np.float64, order="C")
+        _check(self.ctx, load().qg_adjoint_solve(
+            self.ctx, float(dt), ctypes.c_void_p(ps.ctypes.data),
+            ctypes.c_void_p(th.ctypes.data), ctypes.c_void_p(up.ctypes.data), 0))
+        return ps, th, up
 
     def tangent_get(self):
         import numpy as np

@@ -115,3 +115,27 @@ def test_tangent_errors(qg, case):
     with pytest.raises(qg.QGError) as e:
         s.tangent_set(v[0], bad, v[2])
     assert e.value.status == qg.QG_ESTATE
+
+
+@pytest.mark.parametrize("wname", ["SMALL", "MEDIUM"])
+def test_adjoint_solve_matches_oracle(qg, wname):
+    """qg_adjoint_solve (the transposed bordered solves with the stored
+    band-LU factors) against the oracle's transposed solve (dense solves
+    with S^H), on random adjoint inputs."""
+    w = getattr(inputs, wname)
+    o = QGOracle(w.E, w.Ra, w.Pr, w.eta, w.n_phi, w.n_r, w.n_c)
+    adj = CNAB2Adjoint.__new__(CNAB2Adjoint)   # the solve needs no field maps
+    adj.o, adj.M, adj._S = o, o.M, {}
+    rng = np.random.default_rng(21)
+    yb = (rng.standard_normal((o.M, o.K)) + 1j * rng.standard_normal((o.M, o.K)),
+          rng.standard_normal((o.M, o.K)) + 1j * rng.standard_normal((o.M, o.K)),
+          rng.standard_normal(o.K))
+    rp, rt, ru = adj.solve_T(0.5 * w.dt, yb)
+    s = qg.QGSolver(w.E, w.Ra, w.Pr, w.eta, w.n_phi, w.n_r, w.n_c)
+    gp, gt, gu = s.adjoint_solve(w.dt, *yb)
+    err = {"psi": float(np.abs(gp[1:] - rp[1:]).max() / np.abs(rp[1:]).max()),
+           "theta": float(np.abs(gt - rt).max() / np.abs(rt).max()),
+           "uphi": float(np.abs(gu - ru).max() / np.abs(ru).max())}
+    _say(f"[adjoint solve] {wname} rel err {err}")
+    assert not gp[0].any()
+    assert max(err.values()) < 1e-10, err
