@@ -222,6 +222,14 @@ qg_status qg_tangent_get(qg_ctx *ctx, double *dpsi, double *dtheta,
 qg_status qg_adjoint_solve(qg_ctx *ctx, double dt, double *psi, double *theta,
                            double *uphi, int on_device);
 
+/* The adjoint of the band products of a step's right-hand side (Sect. 4,
+ * eq. multistep1): x <- (Mass + c Lin)^H x per system (Psi: A_m + c B_m;
+ * theta: D + c F_m / Pr; zonal flow: D + c E), the rows below the tau rows
+ * of x only (those of the solve's adjoint are zero).  In place, state
+ * layout as qg_adjoint_solve; single-run contexts only. */
+qg_status qg_adjoint_mass_lin(qg_ctx *ctx, double c, double *psi,
+                              double *theta, double *uphi, int on_device);
+
 /* Diagnostics of the current state (synchronises the stream). */
 qg_status qg_diagnostics(qg_ctx *ctx, qg_diag *out);
 

@@ -12,7 +12,8 @@
 // right-hand side (its own adjoint) y_a is then set to zero, and theta at
 // m = 0 takes real inputs (the adjoint of keeping theta_0 real).  One
 // thread per system: this is the transposition of the step's solve for
-// gradients, not a tuned kernel.
+// gradients, not a tuned kernel.  The band products of the step's
+// right-hand side are transposed here as well.
 #include <hip/hip_runtime.h>
 
 #include "kernels.h"
@@ -92,7 +93,61 @@ __global__ __launch_bounds__(64) void solve_adjoint_kernel(FactorSet<double2> Fp
   }
 }
 
+// out = (Mass + c Lin)^H mu per system, column n of the band operators
+// (entry (k, n) at [(n - k + 8) K + k], rows k >= p: the tau rows of mu are
+// zero): Psi (A_m + c B_m, with the Coriolis part (2/E) i m C conjugated),
+// the zonal flow (D + c E, E = F at m = 1) and theta (D + c F_m / Pr).
+// blockIdx.y: 0..M-2 Psi of m = y + 1, M-1 the zonal flow, M + m theta.
+__global__ __launch_bounds__(64) void band_adjoint_kernel(Geom g, Bands b, double c,
+                                                          const double2* __restrict__ mu_psi,
+                                                          const double2* __restrict__ mu_th,
+                                                          double2* __restrict__ out_psi,
+                                                          double2* __restrict__ out_th) {
+  const int K = g.K, M = g.M;
+  const int n = blockIdx.x * 64 + threadIdx.x;
+  const int sys = blockIdx.y;
+  if (n >= K) return;
+  double2 acc = make_double2(0.0, 0.0);
+  if (sys < M - 1) {
+    const int m = sys + 1;
+    const double dm = (double)m, m2 = dm * dm;
+    const double2* mu = mu_psi + (size_t)m * K;
+    for (int o = 0; o < 17; ++o) {
+      const int k = n - o + 8;
+      if (k < 4 || k >= K) continue;
+      const size_t i = (size_t)o * K + k;
+      const double re = b.A0[i] + m2 * b.A2[i] + c * (b.B0[i] + m2 * (b.B2[i] + m2 * b.B4[i]));
+      const double im = c * g.two_over_E * dm * b.C[i];
+      const double2 v = mu[k];
+      acc.x += re * v.x + im * v.y;
+      acc.y += re * v.y - im * v.x;
+    }
+    out_psi[(size_t)m * K + n] = acc;
+  } else {
+    const bool zonal = (sys == M - 1);
+    const int m = zonal ? 0 : sys - M;
+    const double s1 = zonal ? c : c * g.inv_Pr;
+    const double s2 = zonal ? c : c * g.inv_Pr * (double)m * (double)m;
+    const double2* mu = zonal ? mu_psi : mu_th + (size_t)m * K;
+    for (int o = 0; o < 17; ++o) {
+      const int k = n - o + 8;
+      if (k < 2 || k >= K) continue;
+      const size_t i = (size_t)o * K + k;
+      const double re = b.D[i] + s1 * b.F0[i] + s2 * b.F2[i];
+      acc.x += re * mu[k].x;
+      acc.y += re * mu[k].y;
+    }
+    (zonal ? out_psi : out_th + (size_t)m * K)[n] = acc;
+  }
+}
+
 }  // namespace
+
+void launch_band_adjoint(const Geom& g, const Bands& b, double c, const double2* mu_psi,
+                         const double2* mu_th, double2* out_psi, double2* out_th, hipStream_t st) {
+  hipLaunchKernelGGL(band_adjoint_kernel, dim3((g.K + 63) / 64, 2 * g.M), dim3(64), 0, st, g, b,
+                     c, mu_psi, mu_th, out_psi, out_th);
+}
 
 void launch_solve_adjoint(const Geom& g, const FactorSet<double2>& Fp, const FactorSet<double>& Fr,
                           int q4, int q2, double2* psi, double2* th, hipStream_t st) {

@@ -25,6 +25,8 @@ bool band_mch_ok(int mch);
 void launch_combine(const Combine& cb, double2* out, size_t n, hipStream_t st);
 void launch_solve_adjoint(const Geom& g, const FactorSet<double2>& Fp, const FactorSet<double>& Fr,
                           int q4, int q2, double2* psi, double2* th, hipStream_t st);
+void launch_band_adjoint(const Geom& g, const Bands& b, double c, const double2* mu_psi,
+                         const double2* mu_th, double2* out_psi, double2* out_th, hipStream_t st);
 bool launch_solve(const Geom& g, const FactorSet<double2>& Fp, const FactorSet<double>& Fr,
                   double2* rhs, const RhsSpec& rs, int kutp, int kutr, bool pivoted,
                   hipStream_t st);
@@ -1276,6 +1278,31 @@ qg_status qg_adjoint_solve(qg_ctx* ctx, double dt, double* psi, double* theta, d
   launch_solve_adjoint(ctx->g, ctx->Fp, ctx->Fr, z.q4, z.q2, bp, bt, ctx->st);
   HIPCHK(hipGetLastError());
   return read_state(ctx, bp, bt, psi, theta, uphi, on_device);
+}
+
+qg_status qg_adjoint_mass_lin(qg_ctx* ctx, double c, double* psi, double* theta,
+                              double* uphi, int on_device) {
+  if (!ctx) return QG_EINVAL;
+  if (ctx->nmem != 1) return fail(ctx, QG_EINVAL, "adjoint products need a single-run context");
+  if (!psi || !theta || !uphi) return fail(ctx, QG_EINVAL, "null pointer");
+  if (!std::isfinite(c)) return fail(ctx, QG_EINVAL, "c must be finite");
+  const Sizes& z = ctx->z;
+  const size_t MK = (size_t)z.M * z.K;
+  std::vector<double2> hp(MK);
+  std::vector<double> hu(z.K);
+  const hipMemcpyKind kind = on_device ? hipMemcpyDeviceToHost : hipMemcpyHostToHost;
+  HIPCHK(hipMemcpyAsync(hp.data(), psi, MK * 16, kind, ctx->st));
+  HIPCHK(hipMemcpyAsync(hu.data(), uphi, z.K * 8, kind, ctx->st));
+  HIPCHK(hipStreamSynchronize(ctx->st));
+  for (int n = 0; n < z.K; ++n) hp[n] = make_double2(hu[n], 0.0);   // row 0: the zonal flow
+  double2 *ip = ctx->tng(3), *it = ctx->tng(3) + ctx->mk();
+  double2 *op = ctx->tng(4), *ot = ctx->tng(4) + ctx->mk();
+  HIPCHK(hipMemcpyAsync(ip, hp.data(), MK * 16, hipMemcpyHostToDevice, ctx->st));
+  HIPCHK(hipMemcpyAsync(it, theta, MK * 16,
+                        on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, ctx->st));
+  launch_band_adjoint(ctx->g, ctx->b, c, ip, it, op, ot, ctx->st);
+  HIPCHK(hipGetLastError());
+  return read_state(ctx, op, ot, psi, theta, uphi, on_device);
 }
 
 qg_status qg_tangent_get(qg_ctx* ctx, double* dpsi, double* dtheta, double* duphi,

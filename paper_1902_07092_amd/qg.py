@@ -82,6 +82,7 @@ def load():
         "qg_tangent_get": (i, [vp, vp, vp, vp, i]),
         "qg_step_tangent": (i, [vp, d, i]),
         "qg_adjoint_solve": (i, [vp, d, vp, vp, vp, i]),
+        "qg_adjoint_mass_lin": (i, [vp, d, vp, vp, vp, i]),
         "qg_ensemble_workspace_size": (i, [vp, i,
                                            ctypes.POINTER(ctypes.c_size_t)]),
         "qg_ensemble_create": (i, [ctypes.POINTER(vp), vp, i, vp,
@@ -364,6 +365,17 @@ class QGSolver:
         up = np.array(uphi, dtype=np.float64, order="C")
         _check(self.ctx, load().qg_adjoint_solve(
             self.ctx, float(dt), ctypes.c_void_p(ps.ctypes.data),
+            ctypes.c_void_p(th.ctypes.data), ctypes.c_void_p(up.ctypes.data), 0))
+        return ps, th, up
+
+    def adjoint_mass_lin(self, c, psi, theta, uphi):
+        """qg_adjoint_mass_lin on host arrays (copies; returns the result)."""
+        import numpy as np
+        ps = np.array(psi, dtype=np.complex128, order="C")
+        th = np.array(theta, dtype=np.complex128, order="C")
+        up = np.array(uphi, dtype=np.float64, order="C")
+        _check(self.ctx, load().qg_adjoint_mass_lin(
+            self.ctx, float(c), ctypes.c_void_p(ps.ctypes.data),
             ctypes.c_void_p(th.ctypes.data), ctypes.c_void_p(up.ctypes.data), 0))
         return ps, th, up
 

@@ -139,3 +139,31 @@ def test_adjoint_solve_matches_oracle(qg, wname):
     _say(f"[adjoint solve] {wname} rel err {err}")
     assert not gp[0].any()
     assert max(err.values()) < 1e-10, err
+
+
+@pytest.mark.parametrize("wname", ["SMALL", "MEDIUM"])
+def test_adjoint_band_products_match_oracle(qg, wname):
+    """qg_adjoint_mass_lin ((Mass + c Lin)^H with the band storage of the
+    step) against the oracle's transposed operators, on random inputs
+    whose tau rows are zero (as the transposed solve leaves them)."""
+    w = getattr(inputs, wname)
+    o = QGOracle(w.E, w.Ra, w.Pr, w.eta, w.n_phi, w.n_r, w.n_c)
+    adj = CNAB2Adjoint.__new__(CNAB2Adjoint)
+    adj.o, adj.M, adj._S = o, o.M, {}
+    rng = np.random.default_rng(22)
+    mp = rng.standard_normal((o.M, o.K)) + 1j * rng.standard_normal((o.M, o.K))
+    mt = rng.standard_normal((o.M, o.K)) + 1j * rng.standard_normal((o.M, o.K))
+    mu = rng.standard_normal(o.K)
+    mp[:, :4] = 0.0
+    mp[0] = 0.0
+    mt[:, :2] = 0.0
+    mu[:2] = 0.0
+    c = 0.5 * w.dt
+    pb, tb, ub = adj.mass_lin_T(c, (mp, mt, mu))
+    s = qg.QGSolver(w.E, w.Ra, w.Pr, w.eta, w.n_phi, w.n_r, w.n_c)
+    gp, gt, gu = s.adjoint_mass_lin(c, mp, mt, mu)
+    err = {"psi": float(np.abs(gp[1:] - pb[1:]).max() / np.abs(pb[1:]).max()),
+           "theta": float(np.abs(gt - tb).max() / np.abs(tb).max()),
+           "uphi": float(np.abs(gu - ub).max() / np.abs(ub).max())}
+    _say(f"[adjoint band products] {wname} rel err {err}")
+    assert max(err.values()) < 1e-12, err
