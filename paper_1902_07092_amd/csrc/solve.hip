@@ -339,23 +339,33 @@ struct Solver4 {
 
 }  // namespace
 
-// Block: one wavefront, four systems.  Blocks [0, nbp) take the Psi systems
-// (m = 1..M-1), the rest the real systems (zonal flow, theta of every m).
+// Block: one wavefront, four systems.  System blocks [0, nbp) take the Psi
+// systems (m = 1..M-1), the rest the real systems (zonal flow, theta of
+// every m).  The runs of an ensemble share the factors: the 1D grid puts
+// system block b of every run on the same XCD (the hardware hands block
+// ids to the eight XCDs round robin) and back to back, so each XCD reads
+// a factor batch from HBM once for all runs:
+//   id = ((b / 8) nmem + run) 8 + b % 8,   b < nb (padded ids exit).
 __global__ __launch_bounds__(64) void solve_np_kernel(Geom g, FactorSet<double2> Fp,
                                                       FactorSet<double> Fr, double2* rhs,
                                                       RhsSpec rs, int qp, int qr) {
   __shared__ double2 ring_mem[2 * 4 * (SB * 8 + 1)];
   const int M = g.M, K = g.K;
   const int nbp = (M - 1 + 3) / 4;
+  const int nb = nbp + (M + 1 + 3) / 4;
+  const int id = blockIdx.x, rest = id >> 3;
+  const int run = rest % g.nmem;
+  const int b = (rest / g.nmem) * 8 + (id & 7);   // system block
+  if (b >= nb) return;
   const int t = threadIdx.x, lane = t & 15, grp = t >> 4;
-  const size_t moff = (size_t)blockIdx.y * M * K;   // run of an ensemble
+  const size_t moff = (size_t)run * M * K;   // run of an ensemble
   rhs += 2 * moff;
   rs.out_psi += moff;
   rs.out_th += moff;
-  if ((int)blockIdx.x < nbp) {
+  if (b < nbp) {
     Solver4<double2, 4, 8> s{Fp, rs.out_psi, rs.out_th, M, K};
     s.kind = 0;
-    s.sys0 = 4 * blockIdx.x;
+    s.sys0 = 4 * b;
     s.so0 = s.sys0;
     s.nsys = min(4, M - 1 - s.sys0);
     s.n = K - 4; s.q = qp; s.nb = qp / SB;
@@ -367,7 +377,7 @@ __global__ __launch_bounds__(64) void solve_np_kernel(Geom g, FactorSet<double2>
     s.run(s.out_ptr());
   } else {
     Solver4<double, 2, 4> s{Fr, rs.out_psi, rs.out_th, M, K};
-    const int r0 = 4 * (blockIdx.x - nbp);     // first real-system index
+    const int r0 = 4 * (b - nbp);              // first real-system index
     s.kind = (r0 == 0) ? 1 : 2;                // the zonal flow leads the first block
     s.sys0 = (M - 1) + r0;
     s.so0 = r0;
@@ -387,9 +397,9 @@ __global__ __launch_bounds__(64) void solve_np_kernel(Geom g, FactorSet<double2>
 bool launch_solve_np(const Geom& g, const FactorSet<double2>& Fp, const FactorSet<double>& Fr,
                      double2* rhs, const RhsSpec& rs, int qp, int qr, hipStream_t st) {
   if (qp % (NSET * SB) || qr % (NSET * SB)) return false;
-  const int blocks = (g.M - 1 + 3) / 4 + (g.M + 1 + 3) / 4;
-  hipLaunchKernelGGL(solve_np_kernel, dim3(blocks, g.nmem), dim3(64), 0, st, g, Fp, Fr, rhs, rs,
-                     qp, qr);
+  const int nb = (g.M - 1 + 3) / 4 + (g.M + 1 + 3) / 4;
+  const int blocks = 8 * ((nb + 7) / 8) * g.nmem;
+  hipLaunchKernelGGL(solve_np_kernel, dim3(blocks), dim3(64), 0, st, g, Fp, Fr, rhs, rs, qp, qr);
   return true;
 }
 
