@@ -12,8 +12,11 @@
  * banded operators; boundary conditions are imposed as tau rows on top
  * (eq. bc_d3psi_coll and Fig. 1b), and every m is solved as a bordered
  * band system (Appendix A).  Nonlinear advection is pseudo-spectral.  Time
- * stepping is IMEX: CNAB2 (eq. multistep1) or BPR353 (Table 1, eq. dirks).
- * No Ekman pumping.
+ * stepping is IMEX with explicit buoyancy: the multistep schemes CNAB2
+ * (eq. multistep1) and SBDF2/3/4, and the stiffly accurate SDIRK schemes
+ * BPR353, ARS222 and ARS443 (Table 1, eq. dirks).  Ekman pumping is
+ * optional (qg_params.ekman: the approximated F_eps of eq. approx_pump,
+ * explicit).
  *
  * Conventions shared by every entry point
  *   - Coefficients are standard Chebyshev coefficients a_n, f(x) =
@@ -27,9 +30,13 @@
  *   - Pointers flagged on_device = 1 are device pointers on the context's
  *     device; on_device = 0 means host memory.  The caller owns them; the
  *     library copies in or out and keeps nothing.
- *   - Every call is asynchronous on the context's stream except those that
- *     return host data (qg_get_state into host memory, qg_diagnostics) or
- *     that refactor (qg_step after a change of dt), which synchronise it.
+ *   - Calls that step a single-run context (qg_step and its timed and
+ *     autotuned forms, qg_step_tangent) queue their kernels on the
+ *     context's stream and synchronise it once at the end, to read the
+ *     non-finite flag the solves set (see qg_step).  Calls that return host
+ *     data (qg_get_state into host memory, qg_diagnostics, checkpoints)
+ *     or refactor (a change of dt) synchronise as well.  Ensemble steps
+ *     are asynchronous.
  *   - Errors are returned as qg_status; qg_last_error gives a message.
  *     Nothing is thrown across the ABI.  A context must not be used from
  *     two threads at once; distinct contexts are independent.
@@ -159,8 +166,32 @@ qg_status qg_get_state(qg_ctx *ctx, double *psi, double *theta, double *uphi,
  * whenever the implicit coefficient a_ii dt changes (Sect. 3.1:
  * factorisation at start-up and on a time-step change).  CNAB2 uses
  * E^{n-1} := E^n on the first step of its history.  QG_EINVAL for an
- * unknown scheme, dt <= 0 or nsteps < 0. */
+ * unknown scheme, dt <= 0 or nsteps < 0.
+ *
+ * Non-finite values: every solve checks the new state it writes.  A step
+ * whose new state (or a stage of it) holds NaN or Inf is discarded: the
+ * call returns QG_ENONFINITE, the context keeps the state, multistep
+ * history, time and step count from before that step (steps before it in
+ * the same call are kept), and qg_last_error names the step.  The steps
+ * queued after it do nothing.  The call synchronises the stream once at
+ * its end to read the flag. */
 qg_status qg_step(qg_ctx *ctx, double dt, int scheme, int nsteps);
+
+/* Checkpoints of a single-run context: the state and the multistep history
+ * of the scheme in use (CNAB2's stored E^{n-1}; for SBDFk the stored
+ * explicit terms and states, at most three levels each; the SDIRK
+ * schemes keep none), with the time, step count, scheme and dt.  A run
+ * resumed with qg_checkpoint_load (into this or another context with the
+ * same parameters) and stepped on with the same scheme and dt equals the
+ * uninterrupted run bit for bit.  The buffer is the caller's, host memory
+ * or (on_device = 1) device memory, at least qg_checkpoint_size bytes
+ * (which depends on the history held when it is asked).  qg_checkpoint_load
+ * returns QG_EINVAL for a buffer that is too short, not a checkpoint, or
+ * one of a problem with other sizes or parameters; it resets a tangent
+ * run.  Both synchronise the stream. */
+qg_status qg_checkpoint_size(const qg_ctx *ctx, size_t *bytes);
+qg_status qg_checkpoint_save(qg_ctx *ctx, void *buf, size_t bytes, int on_device);
+qg_status qg_checkpoint_load(qg_ctx *ctx, const void *buf, size_t bytes, int on_device);
 
 /* qg_step with per-kernel timing, for benchmarks: HIP events are recorded
  * on the context's stream around every kernel launch.  On return (stream
@@ -202,7 +233,9 @@ qg_status qg_step_autotune(qg_ctx *ctx, double dt, int scheme, int nsteps,
  * (T^{-1} := T^0 when the state's history starts at the same step, else
  * 0); qg_tangent_get copies d out.  Each tangent step costs two explicit
  * evaluations, one band product and one solve more than a CNAB2 step.
- * QG_ESTATE if no tangent state was set (qg_set_state clears it). */
+ * QG_ESTATE if no tangent state was set (qg_set_state clears it).  A
+ * non-finite state or tangent discards the step as in qg_step and clears
+ * the tangent (it is updated in place). */
 qg_status qg_tangent_set(qg_ctx *ctx, const double *dpsi, const double *dtheta,
                          const double *duphi, int on_device);
 qg_status qg_step_tangent(qg_ctx *ctx, double dt, int nsteps);

@@ -1,4 +1,5 @@
 """Build the HIP library libqg.so in-tree for gfx950."""
+import concurrent.futures
 import os
 import shutil
 import subprocess
@@ -21,20 +22,26 @@ def _run(cmd, verbose):
     subprocess.run(cmd, check=True)
 
 
+SOURCES = ("transforms.hip", "bands.hip", "kernels.hip", "solve.hip", "adjoint.hip",
+           "api.hip")
+
+
 def build(verbose: bool = False) -> str:
     hipcc = shutil.which("hipcc") or "/opt/rocm/bin/hipcc"
     os.makedirs(BUILD, exist_ok=True)
-    objs = []
     host = os.path.join(BUILD, "host_ops.o")
-    _run(["g++", "-O2", "-fPIC", "-std=c++17", "-c",
-          os.path.join(CSRC, "host_ops.cpp"), "-o", host], verbose)
-    objs.append(host)
-    for src in ("transforms.hip", "bands.hip", "kernels.hip", "solve.hip", "adjoint.hip",
-                "api.hip"):
+    cmds = [["g++", "-O2", "-fPIC", "-std=c++17", "-c",
+             os.path.join(CSRC, "host_ops.cpp"), "-o", host]]
+    objs = [host]
+    for src in SOURCES:
         obj = os.path.join(BUILD, src.replace(".hip", ".o"))
-        _run([hipcc, *HIPFLAGS, "-c", os.path.join(CSRC, src), "-o", obj],
-             verbose)
+        cmds.append([hipcc, *HIPFLAGS, "-c", os.path.join(CSRC, src), "-o", obj])
         objs.append(obj)
+    # the translation units are independent: compile them side by side
+    jobs = max(1, min(len(cmds), int(os.environ.get("MAX_JOBS", os.cpu_count() or 1))))
+    with concurrent.futures.ThreadPoolExecutor(jobs) as ex:
+        for f in [ex.submit(_run, c, verbose) for c in cmds]:
+            f.result()
     tmp = LIB + ".tmp"
     _run([hipcc, f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, "-o", tmp,
           "-lpthread"], verbose)

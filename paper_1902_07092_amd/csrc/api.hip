@@ -22,7 +22,8 @@ void launch_rhs(const Geom& g, const Bands& b, const RhsSpec& rs, double2* rhs, 
 void launch_lin(const Geom& g, const Bands& b, const double2* ypsi, const double2* yth,
                 double2* lpsi, double2* lth, int mch, hipStream_t st);
 bool band_mch_ok(int mch);
-void launch_combine(const Combine& cb, double2* out, size_t n, hipStream_t st);
+void launch_combine(const Combine& cb, double2* out, size_t n, const int* nf, hipStream_t st);
+void launch_copy(const double2* in, double2* out, size_t n, const int* nf, hipStream_t st);
 void launch_solve_adjoint(const Geom& g, const FactorSet<double2>& Fp, const FactorSet<double>& Fr,
                           int q4, int q2, double2* psi, double2* th, hipStream_t st);
 void launch_band_adjoint(const Geom& g, const Bands& b, double c, const double2* mu_psi,
@@ -164,7 +165,7 @@ bool sizes_of(const qg_params* p, Sizes& z, std::string& why) {
 }
 
 struct WsMap {
-  size_t ra;
+  size_t ra, flag;
   size_t state, ybuf, eslot, lslot, mE, mY, pump, tan, X, NL, zonal, rate, diag, xk, wq, dsk, twd, twp, twh, wphi,
       twd32, twp32, twh32, wphi32, bands, rhs;
   size_t p_piv, p_L, p_U, p_W, p_C, p_Mi, p_ui;
@@ -174,7 +175,7 @@ struct WsMap {
 
 // Per-run arrays are sized for nmem runs (run-major inside each array, see
 // Geom); operators, tables and factors are shared by the runs.
-WsMap map_workspace(const Sizes& z, int nmem) {
+WsMap map_workspace(const Sizes& z, int nmem, bool single) {
   Layout L;
   WsMap w;
   const size_t nm = (size_t)nmem;
@@ -182,14 +183,17 @@ WsMap map_workspace(const Sizes& z, int nmem) {
   const size_t RM = nm * z.R * z.M * sizeof(double2);
   const size_t Sp = z.M - 1;
   w.ra = L.take(nm * sizeof(double));
-  w.state = L.take(2 * MK);
+  w.flag = L.take(sizeof(int));
+  // single runs keep two state slots: a step writes the other one, so that
+  // a step that produces a non-finite state can be discarded
+  w.state = L.take((single ? 4 : 2) * MK);
   w.ybuf = L.take(4 * MK);
   w.eslot = L.take(8 * MK);   // DIRK explicit stages (4)
   w.lslot = L.take(8 * MK);   // DIRK implicit stage products (4)
   w.mE = L.take(8 * MK);      // SBDF explicit terms E^n .. E^{n-3}
   w.mY = L.take(6 * MK);      // SBDF past states y^{n-1} .. y^{n-3}
   w.pump = L.take(z.pump ? RM : 0);   // Ekman pumping terms [M][R] per run
-  w.tan = L.take(nmem == 1 ? 10 * MK : 0);   // tangent state, its E history, y +- c d
+  w.tan = L.take(single ? 10 * MK : 0);   // tangent state, its E history, y +- c d
   w.X = L.take(6 * RM);
   w.NL = L.take(2 * RM);
   w.zonal = L.take(nm * z.R * sizeof(double));
@@ -234,6 +238,7 @@ struct qg_ctx {
   Sizes z;
   WsMap w;
   int nmem = 1;              // runs stepped together (an ensemble group)
+  bool single = true;        // a qg_create context (not an ensemble group)
   char* ws = nullptr;
   hipStream_t st = nullptr;
   Operators ops;
@@ -265,8 +270,17 @@ struct qg_ctx {
   double2* ptr2(size_t off) { return reinterpret_cast<double2*>(ws + off); }
   double* ptrd(size_t off) { return reinterpret_cast<double*>(ws + off); }
   size_t mk() const { return (size_t)nmem * z.M * z.K; }   // one field of every run
-  double2* psi() { return ptr2(w.state); }
-  double2* th() { return ptr2(w.state) + mk(); }
+  int sidx = 0;               // state slot of a single run (two slots)
+  int tag = 0;                // step number within the current call (non-finite flag)
+  double2* psi() { return ptr2(w.state) + (size_t)(2 * sidx) * mk(); }
+  double2* th() { return psi() + mk(); }
+  // where a step writes the new state: the other slot of a single run,
+  // in place for the runs of an ensemble group (their graphs capture the
+  // pointers)
+  double2* nxt_psi() { return single ? ptr2(w.state) + (size_t)(2 * (1 - sidx)) * mk() : psi(); }
+  double2* nxt_th() { return nxt_psi() + mk(); }
+  void flip() { if (single) sidx ^= 1; }
+  int* nf_flag() { return reinterpret_cast<int*>(ws + w.flag); }
   double2* slot(size_t base, int i, int field) {
     return ptr2(base) + ((size_t)(2 * i + field)) * mk();
   }
@@ -567,7 +581,9 @@ qg_status explicit_terms(qg_ctx* ctx, const double2* psi, const double2* th, dou
   return QG_OK;
 }
 
-qg_status implicit_solve(qg_ctx* ctx, const RhsSpec& rs) {
+qg_status implicit_solve(qg_ctx* ctx, const RhsSpec& rs_in) {
+  RhsSpec rs = rs_in;
+  rs.tag = ctx->tag;
   double2* rhs = ctx->ptr2(ctx->w.rhs);
   timed(ctx, K_RHS, [&] { launch_rhs(ctx->g, ctx->b, rs, rhs, ctx->band_mch, ctx->st); });
   bool ok = true;
@@ -602,8 +618,8 @@ qg_status step_cnab2(qg_ctx* ctx, double dt) {
   rs.term_psi[1] = ctx->have_prev ? ctx->slot(ctx->w.eslot, prev, 0) : Ep;
   rs.term_th[1] = ctx->have_prev ? ctx->slot(ctx->w.eslot, prev, 1) : Et;
   rs.coef[1] = -0.5 * dt;
-  rs.out_psi = ctx->psi();
-  rs.out_th = ctx->th();
+  rs.out_psi = ctx->nxt_psi();
+  rs.out_th = ctx->nxt_th();
   s = implicit_solve(ctx, rs);
   if (s != QG_OK) return s;
   ctx->have_prev = 1;
@@ -629,9 +645,9 @@ qg_status step_tangent(qg_ctx* ctx, double dt) {
   cb.in[1] = ctx->tng(0);
   cb.c[0] = 1.0;
   cb.c[1] = cs;
-  launch_combine(cb, ctx->tng(3), n2, ctx->st);
+  launch_combine(cb, ctx->tng(3), n2, ctx->g.nf, ctx->st);
   cb.c[1] = -cs;
-  launch_combine(cb, ctx->tng(4), n2, ctx->st);
+  launch_combine(cb, ctx->tng(4), n2, ctx->g.nf, ctx->st);
   double2* Ea = ctx->slot(ctx->w.eslot, 2, 0);   // E(y + c d), E(y - c d): DIRK
   double2* Eb = ctx->slot(ctx->w.eslot, 3, 0);   // stage slots, unused by CNAB2
   qg_status s = explicit_terms(ctx, ctx->tng(3), ctx->tng(3) + mk, Ea, Ea + mk);
@@ -644,7 +660,7 @@ qg_status step_tangent(qg_ctx* ctx, double dt) {
   dq.in[1] = Eb;
   dq.c[0] = 0.5 / cs;
   dq.c[1] = -0.5 / cs;
-  launch_combine(dq, ctx->tng(1 + cur), n2, ctx->st);
+  launch_combine(dq, ctx->tng(1 + cur), n2, ctx->g.nf, ctx->st);
   RhsSpec rs{};
   rs.base_psi = ctx->tng(0);
   rs.base_th = ctx->tng(0) + mk;
@@ -707,8 +723,8 @@ qg_status step_dirk(qg_ctx* ctx, double dt, const Dirk& T) {
     }
     double2 *op, *ot;
     if (i == S - 1) {
-      op = ctx->psi();
-      ot = ctx->th();
+      op = ctx->nxt_psi();
+      ot = ctx->nxt_th();
     } else {
       int b = (i - 1) % 2;
       op = ctx->slot(ctx->w.ybuf, b, 0);
@@ -748,9 +764,9 @@ qg_status step_sbdf(qg_ctx* ctx, double dt, const Sbdf& S) {
                                ctx->slot(ctx->w.mE, n % 4, 1));
   if (s != QG_OK) return s;
   double2* Yn = ctx->slot(ctx->w.mY, n % 3, 0);
-  const size_t bytes = 2 * ctx->mk() * sizeof(double2);
+  const size_t count = 2 * ctx->mk();
   if (n + 1 < k) {
-    HIPCHK(hipMemcpyAsync(Yn, ctx->psi(), bytes, hipMemcpyDeviceToDevice, ctx->st));
+    launch_copy(ctx->psi(), Yn, count, ctx->g.nf, ctx->st);
     s = prepare(ctx, BPR353.diag * dt);
     if (s == QG_OK) s = step_dirk(ctx, dt, BPR353);
   } else {
@@ -767,8 +783,8 @@ qg_status step_sbdf(qg_ctx* ctx, double dt, const Sbdf& S) {
       cb.c[j] = -S.a[j + 1] / S.a[0];
     }
     double2* yc = ctx->slot(ctx->w.ybuf, 0, 0);
-    launch_combine(cb, yc, 2 * ctx->mk(), ctx->st);
-    HIPCHK(hipMemcpyAsync(Yn, ctx->psi(), bytes, hipMemcpyDeviceToDevice, ctx->st));
+    launch_combine(cb, yc, 2 * ctx->mk(), ctx->g.nf, ctx->st);
+    launch_copy(ctx->psi(), Yn, count, ctx->g.nf, ctx->st);
     RhsSpec rs{};
     rs.base_psi = yc;
     rs.base_th = ctx->slot(ctx->w.ybuf, 0, 1);
@@ -779,8 +795,8 @@ qg_status step_sbdf(qg_ctx* ctx, double dt, const Sbdf& S) {
       rs.term_th[j] = ctx->slot(ctx->w.mE, (n - j) % 4, 1);
       rs.coef[j] = dt * S.b[j] / S.a[0];
     }
-    rs.out_psi = ctx->psi();
-    rs.out_th = ctx->th();
+    rs.out_psi = ctx->nxt_psi();
+    rs.out_th = ctx->nxt_th();
     s = implicit_solve(ctx, rs);
   }
   if (s != QG_OK) return s;
@@ -796,10 +812,15 @@ double scheme_adt(int scheme, double dt) {
   return 0.5 * dt;   // CNAB2
 }
 
+// One step of any scheme; the new state goes to the other slot, which
+// becomes the current one.
 qg_status step_scheme(qg_ctx* ctx, double dt, int scheme) {
-  if (const Dirk* T = dirk_of(scheme)) return step_dirk(ctx, dt, *T);
-  if (const Sbdf* S = sbdf_of(scheme)) return step_sbdf(ctx, dt, *S);
-  return step_cnab2(ctx, dt);
+  qg_status s;
+  if (const Dirk* T = dirk_of(scheme)) s = step_dirk(ctx, dt, *T);
+  else if (const Sbdf* S = sbdf_of(scheme)) s = step_sbdf(ctx, dt, *S);
+  else s = step_cnab2(ctx, dt);
+  if (s == QG_OK) ctx->flip();
+  return s;
 }
 
 // A multistep history belongs to the scheme and dt that made it.
@@ -820,7 +841,7 @@ qg_status qg_workspace_size(const qg_params* p, size_t* bytes) {
   Sizes z;
   std::string why;
   if (!bytes || !sizes_of(p, z, why)) return QG_EINVAL;
-  *bytes = map_workspace(z, 1).total;
+  *bytes = map_workspace(z, 1, true).total;
   return QG_OK;
 }
 
@@ -831,7 +852,7 @@ namespace {
 // A context for nmem runs of one size that differ only in Ra (ra[i]; all
 // runs use p->Ra when ra is null).  nmem = 1 is the single-run context.
 qg_status create_ctx(qg_ctx** out, const qg_params* p, int nmem, const double* ra,
-                     void* workspace, size_t workspace_bytes, void* stream) {
+                     void* workspace, size_t workspace_bytes, void* stream, bool single) {
   if (!out) return QG_EINVAL;
   *out = nullptr;
   Sizes z;
@@ -840,7 +861,7 @@ qg_status create_ctx(qg_ctx** out, const qg_params* p, int nmem, const double* r
   const bool mixed = p->precision == 1;
   if (z.nphi % 6 || !transform_sizes_ok(2 * (z.R - 1), z.nphi, mixed)) return QG_EUNSUPPORTED;
   if (!workspace || ((uintptr_t)workspace & 255)) return QG_EINVAL;
-  WsMap w = map_workspace(z, nmem);
+  WsMap w = map_workspace(z, nmem, single);
   if (workspace_bytes < w.total) return QG_ENOMEM;
   std::vector<double> ra_pr(nmem);
   for (int i = 0; i < nmem; ++i) {
@@ -855,6 +876,7 @@ qg_status create_ctx(qg_ctx** out, const qg_params* p, int nmem, const double* r
   ctx->z = z;
   ctx->w = w;
   ctx->nmem = nmem;
+  ctx->single = single;
   ctx->ws = static_cast<char*>(workspace);
   ctx->st = static_cast<hipStream_t>(stream);
 
@@ -928,8 +950,9 @@ qg_status create_ctx(qg_ctx** out, const qg_params* p, int nmem, const double* r
       up(w.wphi32, wphi32.data(), wphi32.size() * 8) != hipSuccess ||
       up(w.bands, bandbuf.data(), bandbuf.size() * 8) != hipSuccess ||
       up(w.ra, ra_pr.data(), ra_pr.size() * 8) != hipSuccess ||
-      hipMemsetAsync(ctx->ws + w.state, 0, 2 * ctx->mk() * sizeof(double2), ctx->st) !=
-          hipSuccess ||
+      hipMemsetAsync(ctx->ws + w.state, 0, (single ? 4 : 2) * ctx->mk() * sizeof(double2),
+                     ctx->st) != hipSuccess ||
+      hipMemsetAsync(ctx->ws + w.flag, 0, sizeof(int), ctx->st) != hipSuccess ||
       hipStreamSynchronize(ctx->st) != hipSuccess) {
     delete ctx;
     return QG_EDEVICE;
@@ -949,6 +972,7 @@ qg_status create_ctx(qg_ctx** out, const qg_params* p, int nmem, const double* r
   g.pump_ups = std::sqrt(s_o / p->E);
   g.pump_so2e = z.pump ? (s_o + p->eps) * (s_o + p->eps) : 0.0;
   g.half_E = 0.5 * p->E;
+  g.nf = single ? ctx->nf_flag() : nullptr;
   g.ra_pr = ctx->ptrd(w.ra);
   g.xk = ctx->ptrd(w.xk);
   g.wq = ctx->ptrd(w.wq);
@@ -1098,6 +1122,46 @@ qg_status check_step_args(qg_ctx* ctx, double dt, int scheme, int nsteps) {
   return QG_OK;
 }
 
+// Host-side position of a single run at a step boundary: what a step that
+// turns out non-finite must restore (its device state and history are
+// left untouched by the guarded kernels, see Geom::nf).
+struct Mark {
+  int sidx, cur, have_prev, ms_n, t_cur, t_have_prev;
+  double t;
+  long long step;
+};
+Mark mark_of(const qg_ctx* c) {
+  return Mark{c->sidx, c->cur, c->have_prev, c->ms_n, c->t_cur, c->t_have_prev, c->t, c->step};
+}
+
+// After a run of steps: reads the non-finite flag (synchronises).  If step
+// i of the run (tag i + 1) produced a non-finite value, the run is rolled
+// back to the boundary before it: marks[i] holds that boundary.
+qg_status check_finite(qg_ctx* ctx, const std::vector<Mark>& marks) {
+  int tag = 0;
+  HIPCHK(hipMemcpyAsync(&tag, ctx->nf_flag(), sizeof(int), hipMemcpyDeviceToHost, ctx->st));
+  HIPCHK(hipStreamSynchronize(ctx->st));
+  if (tag == 0) return QG_OK;
+  const int i = tag - 1;
+  if (i < 0 || i >= (int)marks.size())
+    return fail(ctx, QG_EDEVICE, "internal: non-finite flag out of range");
+  const Mark& m = marks[i];
+  ctx->sidx = m.sidx;
+  ctx->cur = m.cur;
+  ctx->have_prev = m.have_prev;
+  ctx->ms_n = m.ms_n;
+  ctx->t_cur = m.t_cur;
+  ctx->t_have_prev = m.t_have_prev;
+  ctx->t = m.t;
+  ctx->step = m.step;
+  const int zero = 0;
+  HIPCHK(hipMemcpyAsync(ctx->nf_flag(), &zero, sizeof(int), hipMemcpyHostToDevice, ctx->st));
+  HIPCHK(hipStreamSynchronize(ctx->st));
+  return fail(ctx, QG_ENONFINITE,
+              "non-finite state produced by step " + std::to_string(m.step + 1) +
+                  "; the state is the last finite one (step " + std::to_string(m.step) + ")");
+}
+
 qg_status step_ctx(qg_ctx* ctx, double dt, int scheme, int nsteps) {
   if (!ctx) return QG_EINVAL;
   qg_status s0 = check_step_args(ctx, dt, scheme, nsteps);
@@ -1108,13 +1172,17 @@ qg_status step_ctx(qg_ctx* ctx, double dt, int scheme, int nsteps) {
     s0 = prepare(ctx, scheme_adt(scheme, dt));
     if (s0 != QG_OK) return s0;
   }
+  std::vector<Mark> marks;
+  if (ctx->single) marks.reserve(nsteps);
   for (int i = 0; i < nsteps; ++i) {
+    if (ctx->single) marks.push_back(mark_of(ctx));
+    ctx->tag = i + 1;
     qg_status s = step_scheme(ctx, dt, scheme);
     if (s != QG_OK) return s;
     ctx->t += dt;
     ctx->step += 1;
   }
-  return QG_OK;
+  return ctx->single ? check_finite(ctx, marks) : QG_OK;
 }
 
 // One autotuner candidate: `per` steps with band-product shape mch, the
@@ -1212,7 +1280,7 @@ extern "C" {
 
 qg_status qg_create(qg_ctx** out, const qg_params* p, void* workspace, size_t workspace_bytes,
                     void* stream) {
-  return create_ctx(out, p, 1, nullptr, workspace, workspace_bytes, stream);
+  return create_ctx(out, p, 1, nullptr, workspace, workspace_bytes, stream, true);
 }
 
 qg_status qg_set_state(qg_ctx* ctx, const double* psi, const double* theta, const double* uphi,
@@ -1323,17 +1391,157 @@ qg_status qg_step_tangent(qg_ctx* ctx, double dt, int nsteps) {
   if (fresh) ctx->t_have_prev = 0;
   s = prepare(ctx, 0.5 * dt);
   if (s != QG_OK) return s;
+  std::vector<Mark> marks;
+  marks.reserve(nsteps);
   for (int i = 0; i < nsteps; ++i) {
+    marks.push_back(mark_of(ctx));
+    ctx->tag = i + 1;
     s = step_tangent(ctx, dt);
     if (s == QG_OK) s = step_cnab2(ctx, dt);
     if (s != QG_OK) return s;
+    ctx->flip();
     ctx->t += dt;
     ctx->step += 1;
   }
-  return QG_OK;
+  s = check_finite(ctx, marks);
+  if (s == QG_ENONFINITE) ctx->t_set = 0;   // the tangent was updated in place
+  return s;
 }
 
 qg_status qg_diagnostics(qg_ctx* ctx, qg_diag* out) { return diagnostics_run(ctx, 0, out); }
+
+}  // extern "C"
+
+// ---------------------------------------------------------- checkpoints
+namespace {
+
+// Fixed header of a checkpoint, followed by `narr` arrays of 2 M K
+// complex entries: the state (Psi with the zonal flow in row 0, theta),
+// then the stored explicit terms E^{n-1}, .., E^{n-nE}, then the stored
+// states y^{n-1}, .., y^{n-nY} (multistep levels).
+struct CkptHeader {
+  char magic[8];
+  int version, n_phi, n_r, n_c, precision, ekman;
+  double E, Ra, Pr, eta, eps;
+  int scheme;          // scheme of the history (-1: none)
+  int have_prev;       // CNAB2: E^{n-1} stored
+  int ms_n;            // SBDF: levels since the history began
+  int nE, nY;          // arrays of explicit terms and of past states
+  int pad;
+  double dt, t;
+  long long step;
+  char reserved[256 - 8 - 6 * 4 - 5 * 8 - 6 * 4 - 2 * 8 - 8];
+};
+static_assert(sizeof(CkptHeader) == 256, "checkpoint header size");
+const char CKPT_MAGIC[8] = {'Q', 'G', 'C', 'K', 'P', 'T', '0', '1'};
+
+// Arrays the current history needs (CNAB2: E^{n-1}; SBDFk: up to three
+// levels of E and y; the SDIRK schemes keep none).
+void ckpt_levels(const qg_ctx* c, int& nE, int& nY) {
+  nE = nY = 0;
+  if (c->last_scheme == QG_CNAB2 && c->have_prev) nE = 1;
+  if (sbdf_of(c->last_scheme)) nE = nY = std::min(c->ms_n, 3);
+}
+
+size_t ckpt_bytes(const qg_ctx* c) {
+  int nE, nY;
+  ckpt_levels(c, nE, nY);
+  return sizeof(CkptHeader) + (size_t)(1 + nE + nY) * 2 * c->mk() * sizeof(double2);
+}
+
+// Workspace location of array a of a checkpoint (see CkptHeader).
+double2* ckpt_array(qg_ctx* c, int a, int nE) {
+  if (a == 0) return c->psi();
+  const int n = c->ms_n;
+  if (a <= nE) {
+    const int j = a;   // E^{n-j}
+    if (c->last_scheme == QG_CNAB2) return c->slot(c->w.eslot, 1 - c->cur, 0);
+    return c->slot(c->w.mE, ((n - j) % 4 + 4) % 4, 0);
+  }
+  const int j = a - nE;   // y^{n-j}
+  return c->slot(c->w.mY, ((n - j) % 3 + 3) % 3, 0);
+}
+
+}  // namespace
+
+extern "C" {
+
+qg_status qg_checkpoint_size(const qg_ctx* ctx, size_t* bytes) {
+  if (!ctx || !bytes) return QG_EINVAL;
+  if (!ctx->single) return QG_EINVAL;
+  *bytes = ckpt_bytes(ctx);
+  return QG_OK;
+}
+
+qg_status qg_checkpoint_save(qg_ctx* ctx, void* buf, size_t bytes, int on_device) {
+  if (!ctx) return QG_EINVAL;
+  if (!ctx->single) return fail(ctx, QG_EINVAL, "checkpoints need a single-run context");
+  if (!buf) return fail(ctx, QG_EINVAL, "null checkpoint buffer");
+  if (bytes < ckpt_bytes(ctx)) return fail(ctx, QG_EINVAL, "checkpoint buffer too small");
+  CkptHeader h;
+  std::memset(&h, 0, sizeof(h));
+  std::memcpy(h.magic, CKPT_MAGIC, 8);
+  h.version = 1;
+  h.n_phi = ctx->p.n_phi; h.n_r = ctx->p.n_r; h.n_c = ctx->z.K;
+  h.precision = ctx->p.precision; h.ekman = ctx->p.ekman;
+  h.E = ctx->p.E; h.Ra = ctx->p.Ra; h.Pr = ctx->p.Pr; h.eta = ctx->p.eta;
+  h.eps = ctx->p.ekman ? ctx->p.eps : 0.0;
+  h.scheme = ctx->last_scheme;
+  h.have_prev = ctx->have_prev;
+  h.ms_n = ctx->ms_n;
+  ckpt_levels(ctx, h.nE, h.nY);
+  h.dt = ctx->last_dt; h.t = ctx->t; h.step = ctx->step;
+  const size_t arr = 2 * ctx->mk() * sizeof(double2);
+  char* dst = static_cast<char*>(buf);
+  const hipMemcpyKind k = on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+  if (on_device) HIPCHK(hipMemcpyAsync(dst, &h, sizeof(h), hipMemcpyHostToDevice, ctx->st));
+  else std::memcpy(dst, &h, sizeof(h));
+  for (int a = 0; a < 1 + h.nE + h.nY; ++a)
+    HIPCHK(hipMemcpyAsync(dst + sizeof(h) + a * arr, ckpt_array(ctx, a, h.nE), arr, k, ctx->st));
+  HIPCHK(hipStreamSynchronize(ctx->st));
+  return QG_OK;
+}
+
+qg_status qg_checkpoint_load(qg_ctx* ctx, const void* buf, size_t bytes, int on_device) {
+  if (!ctx) return QG_EINVAL;
+  if (!ctx->single) return fail(ctx, QG_EINVAL, "checkpoints need a single-run context");
+  if (!buf || bytes < sizeof(CkptHeader)) return fail(ctx, QG_EINVAL, "checkpoint too short");
+  CkptHeader h;
+  const char* src = static_cast<const char*>(buf);
+  if (on_device) {
+    HIPCHK(hipMemcpyAsync(&h, src, sizeof(h), hipMemcpyDeviceToHost, ctx->st));
+    HIPCHK(hipStreamSynchronize(ctx->st));
+  } else {
+    std::memcpy(&h, src, sizeof(h));
+  }
+  if (std::memcmp(h.magic, CKPT_MAGIC, 8) != 0 || h.version != 1)
+    return fail(ctx, QG_EINVAL, "not a checkpoint of this library");
+  const qg_params& p = ctx->p;
+  if (h.n_phi != p.n_phi || h.n_r != p.n_r || h.n_c != ctx->z.K || h.precision != p.precision ||
+      h.ekman != p.ekman || h.E != p.E || h.Ra != p.Ra || h.Pr != p.Pr || h.eta != p.eta ||
+      (p.ekman && h.eps != p.eps))
+    return fail(ctx, QG_EINVAL, "checkpoint of a different problem (sizes or parameters)");
+  if (h.nE < 0 || h.nE > 3 || h.nY < 0 || h.nY > 3 || h.ms_n < 0)
+    return fail(ctx, QG_EINVAL, "corrupt checkpoint header");
+  const size_t arr = 2 * ctx->mk() * sizeof(double2);
+  if (bytes < sizeof(h) + (size_t)(1 + h.nE + h.nY) * arr)
+    return fail(ctx, QG_EINVAL, "checkpoint truncated");
+  // host position first: the array locations depend on it
+  ctx->last_scheme = h.scheme;
+  ctx->last_dt = h.dt;
+  ctx->t = h.t;
+  ctx->step = h.step;
+  ctx->have_prev = h.have_prev;
+  ctx->cur = 0;
+  ctx->ms_n = h.ms_n;
+  ctx->t_set = 0;
+  const hipMemcpyKind k = on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+  for (int a = 0; a < 1 + h.nE + h.nY; ++a)
+    HIPCHK(hipMemcpyAsync(ckpt_array(ctx, a, h.nE), src + sizeof(h) + a * arr, arr, k, ctx->st));
+  HIPCHK(hipStreamSynchronize(ctx->st));
+  ctx->err.clear();
+  return QG_OK;
+}
 
 qg_status qg_step_autotune(qg_ctx* ctx, double dt, int scheme, int nsteps,
                            int* systems_per_thread) {
@@ -1449,7 +1657,7 @@ bool group_members(const qg_params* ps, int n, Grouping& G) {
   }
   Layout L;
   for (size_t j = 0; j < G.first.size(); ++j)
-    G.off.push_back(L.take(map_workspace(zs[G.first[j]], (int)G.mem[j].size()).total));
+    G.off.push_back(L.take(map_workspace(zs[G.first[j]], (int)G.mem[j].size(), false).total));
   G.total = L.total;
   return true;
 }
@@ -1609,7 +1817,8 @@ qg_status qg_ensemble_create(qg_ensemble** out, const qg_params* members, int n,
       return QG_EDEVICE;
     }
     qg_status s = create_ctx(&c, &members[G.first[j]], (int)ra.size(), ra.data(),
-                             static_cast<char*>(workspace) + G.off[j], next - G.off[j], gs);
+                             static_cast<char*>(workspace) + G.off[j], next - G.off[j], gs,
+                             false);
     if (s != QG_OK) {
       qg_ensemble_destroy(e);
       return s;

@@ -48,7 +48,7 @@ __global__ __launch_bounds__(64) void band_kernel(Geom g, Bands b, RhsSpec rs, d
   const int k = blockIdx.x * RB + threadIdx.x;
   const int kind = blockIdx.z & 1;
   const int u0 = blockIdx.y * MCH;
-  if (k >= K) return;
+  if (k >= K || nf_stop(g.nf)) return;
   const double cL = rs.cL;
   const size_t mem = blockIdx.z >> 1, mk = (size_t)M * K;
   const size_t moff = mem * mk;
@@ -159,7 +159,8 @@ bool band_mch_ok(int mch) { return mch == 4 || mch == 8 || mch == 16 || mch == 3
 // past states whose mass product a multistep right-hand side needs
 // (M applied once to the combination instead of once per level).
 __global__ __launch_bounds__(256) void combine_kernel(Combine cb, double2* __restrict__ out,
-                                                      size_t n) {
+                                                      size_t n, const int* nf) {
+  if (nf_stop(nf)) return;
   const size_t stride = (size_t)gridDim.x * blockDim.x;
   for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
     double2 acc = make_double2(0.0, 0.0);
@@ -172,10 +173,26 @@ __global__ __launch_bounds__(256) void combine_kernel(Combine cb, double2* __res
   }
 }
 
-void launch_combine(const Combine& cb, double2* out, size_t n, hipStream_t st) {
+void launch_combine(const Combine& cb, double2* out, size_t n, const int* nf, hipStream_t st) {
   const size_t blocks = std::min<size_t>((n + 255) / 256, 4096);
   hipLaunchKernelGGL(combine_kernel, dim3((unsigned)std::max<size_t>(blocks, 1)), dim3(256), 0,
-                     st, cb, out, n);
+                     st, cb, out, n, nf);
+}
+
+// out = in over n complex entries (a stored multistep level), skipped
+// while the non-finite guard is set.
+__global__ __launch_bounds__(256) void copy_kernel(const double2* __restrict__ in,
+                                                   double2* __restrict__ out, size_t n,
+                                                   const int* nf) {
+  if (nf_stop(nf)) return;
+  const size_t stride = (size_t)gridDim.x * blockDim.x;
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) out[i] = in[i];
+}
+
+void launch_copy(const double2* in, double2* out, size_t n, const int* nf, hipStream_t st) {
+  const size_t blocks = std::min<size_t>((n + 255) / 256, 4096);
+  hipLaunchKernelGGL(copy_kernel, dim3((unsigned)std::max<size_t>(blocks, 1)), dim3(256), 0, st,
+                     in, out, n, nf);
 }
 
 void launch_rhs(const Geom& g, const Bands& b, const RhsSpec& rs, double2* rhs, int mch,

@@ -35,7 +35,22 @@ struct Geom {
   // forcing).  Upsilon_eps = pump_ups / h_eps^{3/2}, h_eps^2 = pump_so2e - s^2.
   double2* pump;
   double pump_ups, pump_so2e, half_E;
+  // Non-finite guard of a single run (nullptr: none).  The solves set it
+  // to the step's tag when a new state holds NaN or Inf; while it is set,
+  // every kernel of the step sequence returns at once, so that nothing
+  // after the failing step overwrites the last finite state or history.
+  int* nf;
 };
+
+// True when the non-finite guard is set: the kernel must return.
+__device__ __forceinline__ bool nf_stop(const int* nf) {
+  return nf && *reinterpret_cast<const volatile int*>(nf) != 0;
+}
+
+// Records a non-finite output (any lane of the wavefront) under `tag`.
+__device__ __forceinline__ void nf_mark(int* nf, bool bad, int tag) {
+  if (nf && __any(bad) && (threadIdx.x & 63) == 0) atomicCAS(nf, 0, tag);
+}
 
 struct Bands {  // [17][K] each (offset-major): entry (k, n) at [(n - k + 8) * K + k]
   const double *A0, *A2, *B0, *B2, *B4, *C, *D, *F0, *F2;
@@ -74,6 +89,7 @@ struct RhsSpec {
   double2* out_th;
   double2* lin_psi;          // optional: Lin y_new (nullptr: not needed)
   double2* lin_th;
+  int tag;                   // non-finite tag of this step (Geom::nf)
 };
 
 // A linear combination of up to MAX_LEVELS arrays (multistep levels).

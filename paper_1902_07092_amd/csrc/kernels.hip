@@ -242,6 +242,7 @@ __device__ void solve_system(const Geom& g, const FactorSet<TF>& F, double2* rhs
   __threadfence();
   double2* out = (kind == 2 ? rs.out_th : rs.out_psi) + (size_t)m * K;
   const bool real_row = (kind != 0 && m == 0);   // zonal flow and theta_0
+  bool bad = false;
   for (int k = t; k < K; k += 64) {
     double2 v = zero2();
 #pragma unroll
@@ -250,7 +251,9 @@ __device__ void solve_system(const Geom& g, const FactorSet<TF>& F, double2* rhs
     if (k >= P) v = hg[k - P];
     if (real_row) v.y = 0.0;
     out[k] = v;
+    bad = bad || !isfinite(v.x) || !isfinite(v.y);
   }
+  nf_mark(g.nf, bad, rs.tag);
 }
 
 template <int KUTP, int KUTR, bool PIV>
@@ -258,6 +261,7 @@ __global__ __launch_bounds__(64) void solve_all_kernel(Geom g, FactorSet<double2
                                                        FactorSet<double> Fr, double2* rhs,
                                                        RhsSpec rs) {
   extern __shared__ double2 sm[];
+  if (nf_stop(g.nf)) return;
   const int blk = blockIdx.x, M = g.M;
   const size_t moff = (size_t)blockIdx.y * M * g.K;   // run of an ensemble
   rhs += 2 * moff;

@@ -87,6 +87,7 @@ struct Solver4 {
   bool valid;
   int so;                      // factor index of this lane's system (clamped)
   double2* hg;                 // this system's h / y' (rhs rows p..)
+  bool bad = false;            // a stored entry of the new state is not finite
 
   struct Batch {
     double2 v[NCH];
@@ -229,6 +230,7 @@ struct Solver4 {
         if (lane == i) v = psi1[i];
       if (kind != 0 && (kind == 1 || sys0 + grp == M)) v.y = 0.0;
       out_state[lane] = v;
+      bad = bad || !isfinite(v.x) || !isfinite(v.y);
     }
   }
 
@@ -315,6 +317,7 @@ struct Solver4 {
           double2 v = bw;
           if (real_row) v.y = 0.0;
           xo[row] = v;
+          bad = bad || !isfinite(v.x) || !isfinite(v.y);
         }
         bw = hr;
       }
@@ -324,6 +327,7 @@ struct Solver4 {
           double2 v = bw;
           if (real_row) v.y = 0.0;
           xo[row] = v;
+          bad = bad || !isfinite(v.x) || !isfinite(v.y);
         }
         bw = hr;
       }
@@ -356,7 +360,7 @@ __global__ __launch_bounds__(64) void solve_np_kernel(Geom g, FactorSet<double2>
   const int id = blockIdx.x, rest = id >> 3;
   const int run = rest % g.nmem;
   const int b = (rest / g.nmem) * 8 + (id & 7);   // system block
-  if (b >= nb) return;
+  if (b >= nb || nf_stop(g.nf)) return;
   const int t = threadIdx.x, lane = t & 15, grp = t >> 4;
   const size_t moff = (size_t)run * M * K;   // run of an ensemble
   rhs += 2 * moff;
@@ -375,6 +379,7 @@ __global__ __launch_bounds__(64) void solve_np_kernel(Geom g, FactorSet<double2>
     s.so = s.so0 + min(grp, s.nsys - 1);
     s.hg = rhs + (size_t)(s.sys0 + min(grp, s.nsys - 1)) * K + 4;
     s.run(s.out_ptr());
+    nf_mark(g.nf, s.bad, rs.tag);
   } else {
     Solver4<double, 2, 4> s{Fr, rs.out_psi, rs.out_th, M, K};
     const int r0 = 4 * (b - nbp);              // first real-system index
@@ -391,6 +396,7 @@ __global__ __launch_bounds__(64) void solve_np_kernel(Geom g, FactorSet<double2>
     // system kind per group: only group 0 of block 0 is the zonal flow
     if (r0 == 0 && grp > 0) s.kind = 2;
     s.run(s.out_ptr());
+    nf_mark(g.nf, s.bad, rs.tag);
   }
 }
 

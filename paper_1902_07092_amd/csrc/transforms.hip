@@ -206,7 +206,7 @@ __global__ __launch_bounds__(T) void synth_kernel(Geom g, const double2* __restr
   const int K = g.K, R = g.R, M = g.M;
   const int t = threadIdx.x;
   const int m = xcd_index(M);
-  if (m >= M) return;
+  if (m >= M || nf_stop(g.nf)) return;
   double2* pump = g.pump;
   {
     const size_t mem = blockIdx.y;
@@ -400,7 +400,7 @@ __global__ __launch_bounds__(T) void ring_kernel(Geom g, const C* __restrict__ X
   const int R = g.R, M = g.M;
   const int t = threadIdx.x;
   const int k = xcd_index(R);
-  if (k >= R) return;
+  if (k >= R || nf_stop(g.nf)) return;
   {
     const size_t mem = blockIdx.y;
     X += mem * 6 * R * M;
@@ -507,7 +507,7 @@ __global__ __launch_bounds__(T) void analysis_kernel(Geom g, Bands b,
   const int K = g.K, R = g.R, M = g.M;
   const int t = threadIdx.x;
   const int m = xcd_index(M);
-  if (m >= M) return;
+  if (m >= M || nf_stop(g.nf)) return;
   const size_t mem = blockIdx.y;
   NL += mem * 2 * M * R;
   zonal += mem * R;

@@ -83,6 +83,9 @@ def load():
         "qg_step_tangent": (i, [vp, d, i]),
         "qg_adjoint_solve": (i, [vp, d, vp, vp, vp, i]),
         "qg_adjoint_mass_lin": (i, [vp, d, vp, vp, vp, i]),
+        "qg_checkpoint_size": (i, [vp, ctypes.POINTER(ctypes.c_size_t)]),
+        "qg_checkpoint_save": (i, [vp, vp, ctypes.c_size_t, i]),
+        "qg_checkpoint_load": (i, [vp, vp, ctypes.c_size_t, i]),
         "qg_ensemble_workspace_size": (i, [vp, i,
                                            ctypes.POINTER(ctypes.c_size_t)]),
         "qg_ensemble_create": (i, [ctypes.POINTER(vp), vp, i, vp,
@@ -340,6 +343,38 @@ class QGSolver:
 
     def step(self, dt, scheme="cnab2", n=1):
         qg_step(self.ctx, dt, SCHEMES[scheme], n)
+
+    def checkpoint(self):
+        """qg_checkpoint_save into a host buffer: the state and the
+        multistep history of the current scheme (numpy uint8 array)."""
+        n = ctypes.c_size_t(0)
+        _check(self.ctx, load().qg_checkpoint_size(self.ctx, ctypes.byref(n)))
+        buf = np.zeros(n.value, np.uint8)
+        _check(self.ctx, load().qg_checkpoint_save(
+            self.ctx, ctypes.c_void_p(buf.ctypes.data), n.value, 0))
+        return buf
+
+    def restore(self, buf):
+        """qg_checkpoint_load from a host buffer written by checkpoint()
+        (or a device tensor holding one)."""
+        torch = self.torch
+        if isinstance(buf, torch.Tensor):
+            _check(self.ctx, load().qg_checkpoint_load(
+                self.ctx, ctypes.c_void_p(buf.data_ptr()), buf.numel(), 1))
+            return
+        b = np.ascontiguousarray(buf, np.uint8)
+        _check(self.ctx, load().qg_checkpoint_load(
+            self.ctx, ctypes.c_void_p(b.ctypes.data), b.size, 0))
+
+    def checkpoint_device(self):
+        """qg_checkpoint_save into a device tensor (uint8)."""
+        torch = self.torch
+        n = ctypes.c_size_t(0)
+        _check(self.ctx, load().qg_checkpoint_size(self.ctx, ctypes.byref(n)))
+        buf = torch.empty(n.value, dtype=torch.uint8, device=self.device)
+        _check(self.ctx, load().qg_checkpoint_save(
+            self.ctx, ctypes.c_void_p(buf.data_ptr()), n.value, 1))
+        return buf
 
     def step_timed(self, dt, scheme="cnab2", n=1):
         """Returns {kernel class: (total ms, launches)}."""
