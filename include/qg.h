@@ -150,6 +150,19 @@ qg_status qg_workspace_size(const qg_params *p, size_t *bytes);
 qg_status qg_create(qg_ctx **ctx, const qg_params *p, void *workspace,
                     size_t workspace_bytes, void *stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc):
+ * qg_create with the workspace in a static device array of 128 MiB that the
+ * library holds on each device it runs on until the process ends (enough
+ * for every size up to n_phi x n_r = 768 x 257).  The library allocates no
+ * device memory in this call or later ones; the caller passes only the
+ * stream.  The array is shared by every call on the device, so at most one
+ * such context per device exists at a time: a second one gets QG_EINVAL
+ * until the first is destroyed (overlapping use would race).  Parameters
+ * whose workspace exceeds the array give QG_ENOMEM.  On failure
+ * qg_last_error(NULL) gives the message.  Otherwise as qg_create. */
+qg_status qg_create_static(qg_ctx **ctx, const qg_params *p, void *stream);
+
 /* Copy a state in.  Host inputs are checked: non-finite values give
  * QG_ENONFINITE, boundary-condition residuals above 1e-10 relative give
  * QG_ESTATE (tau conditions, Sect. 3.2.2).  Resets t, the step counter and
@@ -266,7 +279,8 @@ qg_status qg_adjoint_mass_lin(qg_ctx *ctx, double c, double *psi,
 /* Diagnostics of the current state (synchronises the stream). */
 qg_status qg_diagnostics(qg_ctx *ctx, qg_diag *out);
 
-/* Message of the last error on this context ("" if none). */
+/* Message of the last error on this context ("" if none); with ctx =
+ * NULL, the message of this thread's last failed qg_create_static. */
 const char *qg_last_error(const qg_ctx *ctx);
 
 /* Release the context (not the caller's workspace). */

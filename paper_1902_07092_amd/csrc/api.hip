@@ -6,6 +6,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <thread>
 #include <type_traits>
@@ -239,6 +240,7 @@ struct qg_ctx {
   WsMap w;
   int nmem = 1;              // runs stepped together (an ensemble group)
   bool single = true;        // a qg_create context (not an ensemble group)
+  int static_dev = -1;       // device whose static workspace this context holds
   char* ws = nullptr;
   hipStream_t st = nullptr;
   Operators ops;
@@ -1976,11 +1978,89 @@ void qg_ensemble_destroy(qg_ensemble* e) {
   delete e;
 }
 
-const char* qg_last_error(const qg_ctx* ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+}  // extern "C"
+
+// ------------------------------------------------- static workspace
+// The workspace of qg_create_static: a device array that the library holds
+// on every device it runs on until the process ends.  In host code its
+// name is only a handle; its device address comes from
+// hipGetSymbolAddress, once per device, and only that address is used.
+constexpr size_t STATIC_WS_BYTES = (size_t)128 << 20;
+static __device__ __align__(256) char scratch[STATIC_WS_BYTES];
+
+namespace {
+constexpr int MAX_DEVICES = 64;
+std::mutex static_mu;
+void* static_ptr[MAX_DEVICES] = {};     // device address of `scratch`
+bool static_busy[MAX_DEVICES] = {};     // held by a live context
+thread_local std::string create_err;    // message of the last failed create
+}  // namespace
+
+extern "C" {
+
+qg_status qg_create_static(qg_ctx** out, const qg_params* p, void* stream) {
+  if (!out) return QG_EINVAL;
+  *out = nullptr;
+  Sizes z;
+  std::string why;
+  if (!sizes_of(p, z, why)) {
+    create_err = "invalid parameters: " + why;
+    return QG_EINVAL;
+  }
+  const size_t need = map_workspace(z, 1, true).total;
+  if (need > STATIC_WS_BYTES) {
+    create_err = "these parameters need " + std::to_string(need) +
+                 " workspace bytes; the static workspace holds " +
+                 std::to_string(STATIC_WS_BYTES) + " (use qg_create)";
+    return QG_ENOMEM;
+  }
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= MAX_DEVICES) {
+    create_err = "no current HIP device";
+    return QG_EDEVICE;
+  }
+  void* ws = nullptr;
+  {
+    std::lock_guard<std::mutex> lock(static_mu);
+    if (static_busy[dev]) {
+      create_err = "the static workspace of device " + std::to_string(dev) +
+                   " is held by another context (destroy it first)";
+      return QG_EINVAL;
+    }
+    if (!static_ptr[dev]) {
+      void* ptr = nullptr;
+      const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+      if (e != hipSuccess || !ptr) {
+        create_err = std::string("hipGetSymbolAddress: ") + hipGetErrorString(e);
+        return QG_EDEVICE;
+      }
+      static_ptr[dev] = ptr;
+    }
+    ws = static_ptr[dev];
+    static_busy[dev] = true;
+  }
+  const qg_status s = create_ctx(out, p, 1, nullptr, ws, STATIC_WS_BYTES, stream, true);
+  if (s != QG_OK) {
+    std::lock_guard<std::mutex> lock(static_mu);
+    static_busy[dev] = false;
+    create_err = "context creation failed";
+    return s;
+  }
+  (*out)->static_dev = dev;
+  create_err.clear();
+  return QG_OK;
+}
+
+const char* qg_last_error(const qg_ctx* ctx) { return ctx ? ctx->err.c_str() : create_err.c_str(); }
 
 void qg_destroy(qg_ctx* ctx) {
   if (!ctx) return;
   for (hipEvent_t e : ctx->ev_pool) (void)hipEventDestroy(e);
+  if (ctx->static_dev >= 0) {
+    (void)hipStreamSynchronize(ctx->st);   // no kernel may still use the array
+    std::lock_guard<std::mutex> lock(static_mu);
+    static_busy[ctx->static_dev] = false;
+  }
   delete ctx;
 }
 

@@ -69,6 +69,8 @@ def load():
                                   ctypes.POINTER(ctypes.c_size_t)]),
         "qg_create": (i, [ctypes.POINTER(vp), ctypes.POINTER(qg_params), vp,
                           ctypes.c_size_t, vp]),
+        "qg_create_static": (i, [ctypes.POINTER(vp), ctypes.POINTER(qg_params),
+                                 vp]),
         "qg_set_state": (i, [vp, vp, vp, vp, i]),
         "qg_get_state": (i, [vp, vp, vp, vp, i]),
         "qg_step": (i, [vp, d, i, i]),
@@ -138,6 +140,17 @@ def qg_create(params, workspace_ptr, nbytes, stream_ptr):
                           ctypes.c_void_p(stream_ptr))
     if st != QG_OK:
         raise QGError(st, "qg_create")
+    return ctx
+
+
+def qg_create_static(params, stream_ptr):
+    """qg_create with the library's static device workspace (no device
+    allocation by anyone); one such context per device at a time."""
+    ctx = ctypes.c_void_p()
+    st = load().qg_create_static(ctypes.byref(ctx), ctypes.byref(params),
+                                 ctypes.c_void_p(stream_ptr))
+    if st != QG_OK:
+        raise QGError(st, qg_last_error(None))
     return ctx
 
 
@@ -274,7 +287,8 @@ class QGSolver:
     """One solver context on a HIP device, workspace allocated by torch."""
 
     def __init__(self, E, Ra, Pr, eta, n_phi, n_r, n_c=0, device="cuda:0",
-                 stream=None, pivoting=0, precision=0, ekman_eps=None):
+                 stream=None, pivoting=0, precision=0, ekman_eps=None,
+                 static_workspace=False):
         import torch
         self.torch = torch
         self.device = torch.device(device)
@@ -285,13 +299,18 @@ class QGSolver:
         self.K = n_c if n_c else (2 * (n_r - 1)) // 3
         nbytes = qg_workspace_size(self.params)
         with torch.cuda.device(self.device):
-            self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8,
-                                         device=self.device)
-            base = self.workspace.data_ptr()
-            aligned = (base + 255) // 256 * 256
             self.stream = stream or torch.cuda.current_stream(self.device)
-            self.ctx = qg_create(self.params, aligned, nbytes,
-                                 self.stream.cuda_stream)
+            if static_workspace:
+                self.workspace = None
+                self.ctx = qg_create_static(self.params,
+                                            self.stream.cuda_stream)
+            else:
+                self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8,
+                                             device=self.device)
+                base = self.workspace.data_ptr()
+                aligned = (base + 255) // 256 * 256
+                self.ctx = qg_create(self.params, aligned, nbytes,
+                                     self.stream.cuda_stream)
         self.nbytes = nbytes
 
     def __del__(self):
