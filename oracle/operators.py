@@ -23,6 +23,10 @@ not clip the band).  Only rows k >= q are meaningful (paper: "for k>4",
 
 Coefficients depend on m through m^2 only, apart from the Coriolis term, so
 every operator is stored as its m^0, m^2, m^4 parts.
+
+Arithmetic is in the floating type `dtype` (FP64 by default; long double
+for the extended-precision reference), with eta taken as the exact value of
+the binary64 number passed in.
 """
 from math import comb
 
@@ -107,10 +111,10 @@ def laplacian_m(m2=None):
     return {2: mono(0), 1: mono(-1), 0: third}
 
 
-def qg_operators(eta):
+def qg_operators(eta, dtype=np.float64):
     """The polynomial-coefficient differential operators of Sect. 3.2."""
-    s_i, s_o = radii(eta)
-    h2 = {(0, 0): s_o**2, (2, 0): -1.0}
+    s_i, s_o = radii(dtype(eta))
+    h2 = {(0, 0): s_o**2, (2, 0): dtype(-1)}
     lap = laplacian_m()
     L_I = op_add(op_compose(lap, mult(h2)),
                  op_compose(mult(mono(-1)), op_compose(D1, mult(mono(2)))),
@@ -154,41 +158,44 @@ def integrate_by_parts(op, q):
 # ----------------------------------------------------------------------------
 # Sparse Chebyshev matrices on a padded basis of size N.
 
-def int_matrix_x(N):
+def int_matrix_x(N, dtype=np.float64):
     """eq. (int1): int T_n dx = (T_{n+1}/(n+1) - T_{n-1}/(n-1))/2, n > 1,
     with int T_0 = T_1 and int T_1 = T_2/4 (+const).  Row 0 (the constant)
     is left zero."""
     rows, cols, vals = [], [], []
+    one = dtype(1)
     for k in range(1, N):
-        cprev = 2.0 if k == 1 else 1.0
-        rows.append(k), cols.append(k - 1), vals.append(cprev / (2.0 * k))
+        cprev = 2 * one if k == 1 else one
+        rows.append(k), cols.append(k - 1), vals.append(cprev / (2 * k))
         if k + 1 < N:
-            rows.append(k), cols.append(k + 1), vals.append(-1.0 / (2.0 * k))
-    return sp.csr_matrix((vals, (rows, cols)), shape=(N, N))
+            rows.append(k), cols.append(k + 1), vals.append(-one / (2 * k))
+    return sp.csr_matrix((np.array(vals, dtype), (rows, cols)), shape=(N, N))
 
 
-def mulx_matrix(N):
+def mulx_matrix(N, dtype=np.float64):
     """x T_0 = T_1, x T_n = (T_{n-1} + T_{n+1})/2."""
     rows, cols, vals = [1], [0], [1.0]
     for n in range(1, N):
         rows.append(n - 1), cols.append(n), vals.append(0.5)
         if n + 1 < N:
             rows.append(n + 1), cols.append(n), vals.append(0.5)
-    return sp.csr_matrix((vals, (rows, cols)), shape=(N, N))
+    return sp.csr_matrix((np.array(vals, dtype), (rows, cols)), shape=(N, N))
 
 
 class ChebAlgebra:
     """Integration in s and multiplication by s on the padded basis
     (s = x/2 + c, ds = dx/2)."""
 
-    def __init__(self, eta, N):
-        s_i, s_o = radii(eta)
+    def __init__(self, eta, N, dtype=np.float64):
+        s_i, s_o = radii(dtype(eta))
         self.N = N
-        half_gap = 0.5 * (s_o - s_i)
-        c = 0.5 * (s_o + s_i)
-        self.I = (half_gap * int_matrix_x(N)).tocsr()
-        self.S = (half_gap * mulx_matrix(N) + c * sp.identity(N)).tocsr()
-        self._spow = [sp.identity(N, format="csr")]
+        self.dtype = dtype
+        half_gap = (s_o - s_i) / 2
+        c = (s_o + s_i) / 2
+        self.I = (half_gap * int_matrix_x(N, dtype)).tocsr()
+        self.S = (half_gap * mulx_matrix(N, dtype)
+                  + c * sp.identity(N, dtype=dtype)).tocsr()
+        self._spow = [sp.identity(N, dtype=dtype, format="csr")]
 
     def spow(self, e):
         while len(self._spow) <= e:
@@ -196,13 +203,13 @@ class ChebAlgebra:
         return self._spow[e]
 
     def mul_poly(self, poly_by_power):
-        out = sp.csr_matrix((self.N, self.N))
+        out = sp.csr_matrix((self.N, self.N), dtype=self.dtype)
         for e, c in poly_by_power.items():
             out = out + c * self.spow(e)
         return out
 
     def ipow(self, j):
-        out = sp.identity(self.N, format="csr")
+        out = sp.identity(self.N, dtype=self.dtype, format="csr")
         for _ in range(j):
             out = (self.I @ out).tocsr()
         return out
@@ -217,7 +224,7 @@ class ChebAlgebra:
                 by_k[k][j][e] = by_k[k][j].get(e, 0.0) + c
         mats = {}
         for k, per_j in by_k.items():
-            out = sp.csr_matrix((self.N, self.N))
+            out = sp.csr_matrix((self.N, self.N), dtype=self.dtype)
             for j, poly in per_j.items():
                 out = out + self.ipow(j) @ self.mul_poly(poly)
             mats[k] = out.tocsr()
@@ -230,11 +237,12 @@ PAD = 16
 class IntegrationOperators:
     """K x K dense parts of the integration-method operators (m-split)."""
 
-    def __init__(self, eta, K):
+    def __init__(self, eta, K, dtype=np.float64):
         self.eta, self.K = eta, K
+        self.dtype = dtype
         N = K + PAD
-        alg = ChebAlgebra(eta, N)
-        ops = qg_operators(eta)
+        alg = ChebAlgebra(eta, N, dtype)
+        ops = qg_operators(eta, dtype)
 
         def dense(mats):
             return {k: np.asarray(m[:K, :K].todense()) for k, m in
@@ -245,7 +253,7 @@ class IntegrationOperators:
         d = dense(alg.integrated(mult(mono(2)), 2))
         f = dense(alg.integrated(ops["s2Lap"], 2))
         e = dense(alg.integrated(ops["s2Lap1"], 2))
-        z = np.zeros((K, K))
+        z = np.zeros((K, K), dtype)
         self.A0, self.A2 = a.get(0, z), a.get(1, z)
         self.B0, self.B2, self.B4 = b.get(0, z), b.get(1, z), b.get(2, z)
         self.C = c[0]
@@ -258,12 +266,13 @@ class IntegrationOperators:
 
     def B(self, m, E):
         """B_m including the implicit Coriolis term (2/E) i m C."""
-        m2 = float(m * m)
+        dt = self.dtype
+        m2 = dt(m * m)
         return (self.B0 + m2 * self.B2 + m2 * m2 * self.B4
-                + (2.0j * m / E) * self.C)
+                + (1j * (dt(2) * m / dt(E))) * self.C)
 
     def F(self, m):
-        return self.F0 + float(m * m) * self.F2
+        return self.F0 + self.dtype(m * m) * self.F2
 
 
 # ----------------------------------------------------------------------------
@@ -273,16 +282,16 @@ class IntegrationOperators:
 # f'(s_i) ~ sum T_n'(-1) a_n.  Row order: Dirichlet s_o, Dirichlet s_i,
 # third derivative at s_o, Neumann at s_i (Sect. 3.2.2, Fig. 1b).
 
-def tau_rows_psi(K):
-    n = np.arange(K, dtype=np.float64)
-    return np.array([np.ones(K), (-1.0) ** n,
-                     n**2 * (n**2 - 1) * (n**2 - 4) / 15.0,
-                     (-1.0) ** (n + 1) * n**2])
+def tau_rows_psi(K, dtype=np.float64):
+    n = np.arange(K, dtype=dtype)
+    return np.array([np.ones(K, dtype), (-1) ** n,
+                     n**2 * (n**2 - 1) * (n**2 - 4) / 15,
+                     (-1) ** (n + 1) * n**2])
 
 
-def tau_rows_dirichlet(K):
-    n = np.arange(K, dtype=np.float64)
-    return np.array([np.ones(K), (-1.0) ** n])
+def tau_rows_dirichlet(K, dtype=np.float64):
+    n = np.arange(K, dtype=dtype)
+    return np.array([np.ones(K, dtype), (-1) ** n])
 
 
 def bordered_lhs(bc_rows, op_rows):
@@ -298,7 +307,7 @@ def bordered_lhs(bc_rows, op_rows):
 def evaluate_op(op, m, derivs, s):
     """sum_p a_p(s; m^2) f^(p)(s) on a grid; derivs[p] holds f^(p)(s);
     m and s broadcast against each other."""
-    m2 = np.asarray(m, dtype=np.float64) ** 2
+    m2 = np.asarray(m, dtype=np.result_type(np.asarray(s).real, np.float64)) ** 2
     out = 0.0
     for p, a in op.items():
         coef = 0.0

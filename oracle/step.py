@@ -47,6 +47,7 @@ Readings (where the paper is silent or inconsistent):
     terms.
 """
 import numpy as np
+import scipy.sparse as sp
 
 from . import grid, transforms as tr
 from .bordered import BorderedSolver
@@ -108,29 +109,58 @@ SBDF = {"sbdf2": ((3 / 2, -2, 1 / 2), (2, -1)),
 SCHEMES = ("cnab2", "sbdf2", "sbdf3", "sbdf4", "bpr353", "ars222", "ars443")
 
 
+# Extended-precision reference mode: the bordered solves iterate a
+# correction (an FP64 bordered solve of the residual, the residual in the
+# working precision) until it falls below REFINE_TOL of the solution or
+# stops shrinking (the floor of the working precision times the
+# conditioning); a floor above REFINE_FAIL would make the reference no
+# better than FP64, and is an error.
+REFINE_TOL = 2.0**-60
+REFINE_FAIL = 2.0**-43
+REFINE_MAXIT = 12
+
+
 class QGOracle:
-    def __init__(self, E, Ra, Pr, eta, n_phi, n_r, n_c=None, ekman_eps=None):
+    """The step in the floating type `dtype`: FP64 (default), or numpy's
+    long double as an extended-precision reference for measuring FP64
+    rounding.  In long double every product, transform and operator is
+    evaluated in long double (parameters are the exact values of the
+    binary64 numbers given) and each bordered solve is refined: starting
+    from the FP64 solve, the residual of the long-double system is solved
+    again in FP64 and added, until the correction is below REFINE_TOL of
+    the solution (LAPACK has no long-double band LU)."""
+
+    def __init__(self, E, Ra, Pr, eta, n_phi, n_r, n_c=None, ekman_eps=None,
+                 dtype=np.float64):
         if n_phi % 3:
             raise ValueError("N_phi must be a multiple of 3 (N_m = N_phi/3)")
         self.E, self.Ra, self.Pr, self.eta = E, Ra, Pr, eta
         self.ekman_eps = ekman_eps
+        self.rdt = dtype
+        self.cdt = np.result_type(dtype, 1j).type
         self.n_phi, self.n_r = n_phi, n_r
         self.M = n_phi // 3 + 1
         self.K = (2 * (n_r - 1)) // 3 if n_c is None else n_c
-        self.s_i, self.s_o = grid.radii(eta)
-        self.s = grid.s_nodes(eta, n_r)
+        d = dtype
+        self.s_i, self.s_o = grid.radii(d(eta))
+        self.s = grid.s_nodes(eta, n_r, d)
         self.h2 = self.s_o**2 - self.s**2
-        self.dtc = grid.dtc_ds(self.s, eta)
+        self.dtc = grid.dtc_ds(self.s, d(eta))
         self.mvec = np.arange(self.M)
-        self.ops = IntegrationOperators(eta, self.K)
-        defs = qg_operators(eta)
+        self.ops = IntegrationOperators(eta, self.K, d)
+        # the factorisations are FP64 (LAPACK); in long double they serve
+        # as the preconditioner of the refined solves
+        self.ops64 = (self.ops if d is np.float64
+                      else IntegrationOperators(eta, self.K))
+        defs = qg_operators(eta, d)
         self.L_I = defs["L_I"]
         self.dL_I = op_compose(D1, self.L_I)
         # zonal vorticity omega_0 = (1/s) d(s u)/ds and its s-derivative
         self.om0 = op_compose(mult(mono(-1)), op_compose(D1, mult(mono(1))))
         self.dom0 = op_compose(D1, self.om0)
-        self.bc_psi = tau_rows_psi(self.K)
-        self.bc_dir = tau_rows_dirichlet(self.K)
+        self.bc_psi = tau_rows_psi(self.K, d)
+        self.bc_dir = tau_rows_dirichlet(self.K, d)
+        self.refine_its = []      # refinement iterations of the last solves
         self._factors = {}
         self.t = 0.0
         self.nstep = 0
@@ -140,9 +170,9 @@ class QGOracle:
 
     # ---------------------------------------------------------------- state
     def set_state(self, psi, theta, uphi0):
-        self.psi = np.array(psi, np.complex128, copy=True)
-        self.theta = np.array(theta, np.complex128, copy=True)
-        self.uphi = np.array(uphi0, np.float64, copy=True)
+        self.psi = np.array(psi, self.cdt, copy=True)
+        self.theta = np.array(theta, self.cdt, copy=True)
+        self.uphi = np.array(uphi0, self.rdt, copy=True)
         self._hist = None
         self._ms = None
         self._last = None
@@ -167,36 +197,102 @@ class QGOracle:
         return lp, lt, o.E @ uphi
 
     def factor(self, a_dt):
-        """Bordered LU of (mass - a dt L) for every m (Appendix A)."""
+        """Bordered LU of (mass - a dt L) for every m (Appendix A), FP64."""
         key = float(a_dt)
         if key in self._factors:
             return self._factors[key]
-        o = self.ops
+        o = self.ops64
+        bp, bd = tau_rows_psi(self.K), tau_rows_dirichlet(self.K)
         fp = [None]
         for m in range(1, self.M):
             fp.append(BorderedSolver(
-                bordered_lhs(self.bc_psi, o.A(m) - a_dt * o.B(m, self.E)), 4))
+                bordered_lhs(bp, o.A(m) - a_dt * o.B(m, self.E)), 4))
         ft = [BorderedSolver(bordered_lhs(
-            self.bc_dir, o.D - a_dt * o.F(m) / self.Pr), 2)
+            bd, o.D - a_dt * o.F(m) / self.Pr), 2)
             for m in range(self.M)]
-        fu = BorderedSolver(bordered_lhs(self.bc_dir, o.D - a_dt * o.E), 2)
+        fu = BorderedSolver(bordered_lhs(bd, o.D - a_dt * o.E), 2)
         self._factors = {key: (fp, ft, fu)}
         return self._factors[key]
 
-    def solve(self, a_dt, rp, rt, ru):
+    def _bordered_solve(self, a_dt, rp, rt, ru):
+        """The bordered systems of every m with right-hand sides whose tau
+        rows are taken as given (FP64 solves)."""
         fp, ft, fu = self.factor(a_dt)
+        c128 = np.complex128
+        psi = np.zeros(rp.shape, c128)
+        for m in range(1, self.M):
+            psi[m] = fp[m].solve(rp[m].astype(c128))
+        theta = np.stack([ft[m].solve(rt[m].astype(c128))
+                          for m in range(self.M)])
+        return psi, theta, fu.solve(ru.astype(np.float64))
+
+    def _apply_bordered(self, a_dt, xp, xt, xu):
+        """S x for every system in the working precision: tau rows on top,
+        rows p.. of (mass - a dt L) below (the matrices the solves invert),
+        using the sparse band form of the m-split operators."""
+        if not hasattr(self, "_sparse"):
+            o = self.ops
+            self._sparse = {n: sp.csr_matrix(getattr(o, n)) for n in
+                            ("A0", "A2", "B0", "B2", "B4", "C", "D", "F0",
+                             "F2", "E")}
+        S = self._sparse
+        d = self.rdt
+        a = d(a_dt)
+        m = self.mvec.astype(d)
+        m2 = m * m
+        X = xp.T
+        yp = (S["A0"] @ X + (S["A2"] @ X) * m2
+              - a * (S["B0"] @ X + (S["B2"] @ X) * m2 + (S["B4"] @ X) * m2 * m2
+                     + (S["C"] @ X) * (1j * (d(2) * m / d(self.E)))))
+        yp[:4] = self.bc_psi @ X
+        T = xt.T
+        yt = S["D"] @ T - (a / d(self.Pr)) * (S["F0"] @ T + (S["F2"] @ T) * m2)
+        yt[:2] = self.bc_dir @ T
+        yu = S["D"] @ xu - a * (S["E"] @ xu)
+        yu[:2] = self.bc_dir @ xu
+        return yp.T, yt.T, yu
+
+    def solve(self, a_dt, rp, rt, ru):
+        """New state from a step's right-hand sides: tau rows set to zero
+        (homogeneous boundary conditions), the bordered solves, Psi_0 = 0
+        and theta_0 real."""
         rp = rp.copy()
         rt = rt.copy()
         ru = ru.copy()
         rp[:, :4] = 0
         rt[:, :2] = 0
         ru[:2] = 0
-        psi = np.zeros_like(rp)
-        for m in range(1, self.M):
-            psi[m] = fp[m].solve(rp[m])
-        theta = np.stack([ft[m].solve(rt[m]) for m in range(self.M)])
+        x = list(self._bordered_solve(a_dt, rp, rt, ru))
+        if self.rdt is not np.float64:
+            x = [x[0].astype(self.cdt), x[1].astype(self.cdt),
+                 x[2].astype(self.rdt)]
+            x[0][0] = 0
+            x[1][0] = x[1][0].real
+            prev = np.inf
+            for it in range(1, REFINE_MAXIT + 1):
+                sx = self._apply_bordered(a_dt, *x)
+                r = [rp - sx[0], rt - sx[1], ru - sx[2]]
+                r[0][0] = 0                  # Psi_0 is not solved for
+                r[1][0] = r[1][0].real       # theta_0 is kept real
+                dx = self._bordered_solve(a_dt, *r)
+                rel = 0.0
+                for i in range(3):
+                    scale = float(np.abs(x[i]).max())
+                    if scale > 0:
+                        rel = max(rel, float(np.abs(dx[i]).max()) / scale)
+                    x[i] = x[i] + dx[i]
+                x[0][0] = 0
+                x[1][0] = x[1][0].real
+                if rel <= REFINE_TOL or rel > 0.5 * prev:
+                    break
+                prev = rel
+            if rel > REFINE_FAIL:
+                raise RuntimeError(
+                    f"refined bordered solve stalled at {rel:.2e} relative")
+            self.refine_its.append((it, rel))
+        psi, theta, u = x
         theta[0] = theta[0].real
-        return psi, theta, fu.solve(ru)
+        return psi, theta, u
 
     # ------------------------------------------------------- explicit terms
     def spectral_fields(self, psi, theta, uphi):
@@ -281,7 +377,8 @@ class QGOracle:
             Nom[1:] -= Fk[1:]
             Nu = Nu + Fk[0].real
         o = self.ops
-        buoy = (self.Ra / self.Pr) * im / self.s_o * theta
+        d = self.rdt
+        buoy = (d(self.Ra) / d(self.Pr)) * im / self.s_o * theta
         Ep = (buoy + Nom) @ o.C.T
         Ep[0] = 0
         Et = -(Nth @ o.D.T)

@@ -28,7 +28,7 @@ def phi_to_grid(fm, n_phi):
     N_phi real grid values.  numpy's irfft applies the Hermitian sum."""
     fm = np.asarray(fm)
     M = fm.shape[-1]
-    F = np.zeros(fm.shape[:-1] + (n_phi // 2 + 1,), np.complex128)
+    F = np.zeros(fm.shape[:-1] + (n_phi // 2 + 1,), np.result_type(fm, 1j))
     F[..., :M] = fm * n_phi
     return sfft.irfft(F, n=n_phi, axis=-1, workers=WORKERS)
 
@@ -105,7 +105,7 @@ def cheb_ds(a, order=1):
     if order == 0:
         return a
     K = a.shape[-1]
-    out = npcheb.chebder(a, m=order, scl=2.0, axis=-1)
+    out = npcheb.chebder(a, m=order, scl=a.real.dtype.type(2), axis=-1)
     pad = np.zeros(a.shape[:-1] + (K,), out.dtype)
     pad[..., :out.shape[-1]] = out
     return pad

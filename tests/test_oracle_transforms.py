@@ -96,3 +96,36 @@ def test_alpha_value():
     assert abs(grid.alpha_tc(0.35) - 0.4449580) < 5e-8
     s_i, s_o = grid.radii(0.35)
     assert abs(s_o - s_i - 1) < 1e-15 and abs(s_i / s_o - 0.35) < 1e-15
+
+
+def test_derivatives_match_closed_forms(rng):
+    """cheb_ds against the closed forms of Chebyshev derivatives (not a
+    library call): with x = cos(theta), T_n'(x) = n sin(n theta)/sin(theta)
+    inside, T_n'(+-1) = (+-1)^(n+1) n^2; T_n'' from the Chebyshev equation
+    (1 - x^2) T_n'' = x T_n' - n^2 T_n inside; T_n'''(1) =
+    n^2 (n^2 - 1)(n^2 - 4)/15.  d/ds = 2 d/dx on the unit gap.  A missing
+    factor 2 (d/dx for d/ds) or an index shift in the recurrence fails."""
+    n_r, K = 33, 21
+    a = rng.standard_normal(K)
+    k = np.arange(n_r)
+    th = np.pi * k / (n_r - 1)
+    x = np.cos(th)
+    n = np.arange(K)
+    inner = slice(1, n_r - 1)
+    T = np.cos(np.outer(th, n))
+    dT = np.empty((n_r, K))
+    dT[inner] = n[None, :] * np.sin(np.outer(th[inner], n)) / np.sin(th[inner])[:, None]
+    dT[0] = n**2
+    dT[-1] = (-1.0) ** (n + 1) * n**2
+    d2T = np.zeros((n_r, K))
+    d2T[inner] = ((x[inner, None] * dT[inner] - n[None, :] ** 2 * T[inner])
+                  / (1 - x[inner] ** 2)[:, None])
+    d1 = tr.cheb_to_grid(tr.cheb_ds(a, 1), n_r)
+    d2 = tr.cheb_to_grid(tr.cheb_ds(a, 2), n_r)
+    scale1 = np.abs(dT @ a).max()
+    assert np.allclose(d1, 2 * dT @ a, rtol=0, atol=1e-12 * scale1)
+    scale2 = np.abs(d2T @ a).max()
+    assert np.allclose(d2[inner], 4 * d2T[inner] @ a, rtol=0, atol=1e-11 * scale2)
+    d3_outer = tr.cheb_to_grid(tr.cheb_ds(a, 3), n_r)[0]
+    exact3 = 8 * np.sum(a * n**2 * (n**2 - 1) * (n**2 - 4) / 15.0)
+    assert abs(d3_outer - exact3) <= 1e-12 * np.sum(np.abs(a) * n**6)
