@@ -6,6 +6,12 @@ Paper Appendix A.  The K x K tau matrix is split as
 A: p x p, B: p x (K-p) dense boundary rows, C: (K-p) x p sparse, D: band.
 Solve D x = h and D y = C (band LU, LAPACK ?gbtrf/?gbtrs), form the Schur
 complement M = A - B y, solve M psi_1 = g - B x, then psi_2 = x - y psi_1.
+
+pivot=False replaces the LAPACK band LU by a plain band LU without row
+interchanges (Doolittle, written out below).  The appendix does not fix
+the elimination order; the two are equally valid binary64 implementations
+of the same solve, and their difference measures how much the rounding
+of the solve alone moves a step's result.
 """
 import numpy as np
 import scipy.linalg as sla
@@ -31,15 +37,22 @@ class BorderedSolver:
     """Factor once (init or on a dt change), then solve many right-hand
     sides; matrix real or complex, right-hand sides complex or real."""
 
-    def __init__(self, L, p):
+    def __init__(self, L, p, pivot=True):
         L = np.asarray(L)
         self.p = p
+        self.pivot = pivot
         self.cplx = np.iscomplexobj(L)
         self.A = L[:p, :p].copy()        # copies: the dense L is not kept
         self.B = L[:p, p:].copy()
         C = L[p:, :p]
         D = L[p:, p:]
         self.kl, self.ku = _bandwidths(D)
+        if not pivot:
+            self._factor_plain(D)
+            self.y = self._band_solve(C)
+            self.M = self.A - self.B @ self.y
+            self.Mlu = sla.lu_factor(self.M)
+            return
         ab = _to_lapack_band(D, self.kl, self.ku)
         if self.cplx:
             self._trf, self._trs = lapack.zgbtrf, lapack.zgbtrs
@@ -52,8 +65,39 @@ class BorderedSolver:
         self.M = self.A - self.B @ self.y
         self.Mlu = sla.lu_factor(self.M)
 
+    def _factor_plain(self, D):
+        """Band LU without row interchanges: column j's multipliers
+        l_ij = a_ij / u_jj (i = j+1..j+kl), then row i -= l_ij row j over
+        the band; L and U overwrite a copy of the band."""
+        n, kl, ku = D.shape[0], self.kl, self.ku
+        a = np.array(D, dtype=np.complex128 if self.cplx else np.float64)
+        for j in range(n):
+            piv = a[j, j]
+            if piv == 0:
+                raise np.linalg.LinAlgError(f"zero pivot at step {j}")
+            lo, hi = j + 1, min(n, j + kl + 1)
+            ce = min(n, j + ku + 1)
+            a[lo:hi, j] /= piv
+            a[lo:hi, lo:ce] -= np.outer(a[lo:hi, j], a[j, lo:ce])
+        self._plain = a
+
+    def _plain_solve(self, rhs):
+        a, kl, ku = self._plain, self.kl, self.ku
+        n = a.shape[0]
+        x = np.array(rhs, dtype=np.result_type(a, rhs), copy=True)
+        for j in range(n):                      # L z = rhs (unit diagonal)
+            hi = min(n, j + kl + 1)
+            x[j + 1:hi] -= np.multiply.outer(a[j + 1:hi, j], x[j])
+        for j in range(n - 1, -1, -1):          # U x = z
+            x[j] = x[j] / a[j, j]
+            lo = max(0, j - ku)
+            x[lo:j] -= np.multiply.outer(a[lo:j, j], x[j])
+        return x
+
     def _band_solve(self, rhs):
         rhs = np.asarray(rhs)
+        if not self.pivot:
+            return self._plain_solve(rhs)
         if not self.cplx and np.iscomplexobj(rhs):
             return (self._band_solve(rhs.real)
                     + 1j * self._band_solve(rhs.imag))

@@ -128,14 +128,20 @@ class QGOracle:
     binary64 numbers given) and each bordered solve is refined: starting
     from the FP64 solve, the residual of the long-double system is solved
     again in FP64 and added, until the correction is below REFINE_TOL of
-    the solution (LAPACK has no long-double band LU)."""
+    the solution (LAPACK has no long-double band LU).
+
+    pivot=False factors the band blocks without row interchanges
+    (oracle.bordered): a second binary64 implementation of the same step,
+    whose distance from the first measures the rounding spread of the
+    solves."""
 
     def __init__(self, E, Ra, Pr, eta, n_phi, n_r, n_c=None, ekman_eps=None,
-                 dtype=np.float64):
+                 dtype=np.float64, pivot=True):
         if n_phi % 3:
             raise ValueError("N_phi must be a multiple of 3 (N_m = N_phi/3)")
         self.E, self.Ra, self.Pr, self.eta = E, Ra, Pr, eta
         self.ekman_eps = ekman_eps
+        self.pivot = pivot
         self.rdt = dtype
         self.cdt = np.result_type(dtype, 1j).type
         self.n_phi, self.n_r = n_phi, n_r
@@ -206,11 +212,12 @@ class QGOracle:
         fp = [None]
         for m in range(1, self.M):
             fp.append(BorderedSolver(
-                bordered_lhs(bp, o.A(m) - a_dt * o.B(m, self.E)), 4))
+                bordered_lhs(bp, o.A(m) - a_dt * o.B(m, self.E)), 4,
+                self.pivot))
         ft = [BorderedSolver(bordered_lhs(
-            bd, o.D - a_dt * o.F(m) / self.Pr), 2)
+            bd, o.D - a_dt * o.F(m) / self.Pr), 2, self.pivot)
             for m in range(self.M)]
-        fu = BorderedSolver(bordered_lhs(bd, o.D - a_dt * o.E), 2)
+        fu = BorderedSolver(bordered_lhs(bd, o.D - a_dt * o.E), 2, self.pivot)
         self._factors = {key: (fp, ft, fu)}
         return self._factors[key]
 

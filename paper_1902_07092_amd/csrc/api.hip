@@ -374,6 +374,16 @@ int max_pivot(const BorderedFactor<T>& f) {
   return mx;
 }
 
+// A host factor entry (long double, real or complex) rounded to the
+// device type.
+template <typename D2, typename T>
+D2 to_dev(const T& v) {
+  if constexpr (std::is_same<D2, double2>::value)
+    return make_double2((double)std::real(v), (double)std::imag(v));
+  else
+    return (double)std::real(v);
+}
+
 // Device layout of one system: steps padded to npad with identity steps
 // (no interchange, zero multipliers, U = 1), U truncated to wu columns
 // (the dropped fill is checked to be exactly zero).
@@ -381,10 +391,7 @@ template <typename T, typename D2>
 bool pack(const BorderedFactor<T>& f, size_t s, int kl, int wu, int p, int npad, int* piv, D2* L,
           D2* U, D2* W, D2* C, D2* Mi) {
   const int n = f.n, wfull = f.kut + 1;
-  auto cvt = [](const T& v) -> D2 {
-    if constexpr (std::is_same<T, cplx>::value) return make_double2(v.real(), v.imag());
-    else return v;
-  };
+  auto cvt = [](const T& v) -> D2 { return to_dev<D2>(v); };
   const T one(1.0);
   for (int j = 0; j < npad; ++j) {
     piv[s * npad + j] = (j < n) ? f.piv[j] : 0;
@@ -409,10 +416,7 @@ template <typename T, typename D2>
 void pack_np(const BorderedFactor<T>& f, size_t s, int kl, int ku, int p, int q, D2* L, D2* U,
              D2* ui, D2* W, D2* C, D2* Mi) {
   const int n = f.n, wf = f.kut + 1;
-  auto cvt = [](const T& v) -> D2 {
-    if constexpr (std::is_same<T, cplx>::value) return make_double2(v.real(), v.imag());
-    else return v;
-  };
+  auto cvt = [](const T& v) -> D2 { return to_dev<D2>(v); };
   for (int j = 0; j < q; ++j) {
     for (int d = 0; d < kl; ++d)
       L[(s * q + j) * kl + d] = cvt(j < n ? f.Lc[(size_t)j * kl + d] : T(0));
@@ -447,22 +451,28 @@ constexpr double MAX_UNPIVOTED_GROWTH = 1e4;
 qg_status refactor(qg_ctx* ctx, double adt) {
   const Sizes& z = ctx->z;
   const size_t Sp = z.M - 1, Sr = z.Sr;
-  std::vector<BorderedFactor<cplx>> fp(Sp);
-  std::vector<BorderedFactor<double>> fr(Sr);
+  std::vector<BorderedFactor<cplxl>> fp(Sp);
+  std::vector<BorderedFactor<long double>> fr(Sr);
   std::vector<int> ok(Sp + Sr, 1);
   bool pivot = ctx->p.pivoting != 0;
   for (int attempt = 0; attempt < 2; ++attempt) {
+    // each factorisation runs in long double (the band LU, the border data
+    // w = B D^-1 with its long recurrences, and M^-1), then every entry is
+    // rounded once to FP64: the stored factors are accurate to the last bit
+    // and only the device's substitutions round in FP64
     parallel_for((int)(Sp + Sr), [&](int idx) {
       int p;
       if (idx < (int)Sp) {
         std::vector<cplx> full;
         assemble<cplx>(ctx, 0, idx + 1, adt, full, p);
-        ok[idx] = factor_bordered<cplx>(full, z.K, 4, 8, 8, pivot, fp[idx]);
+        std::vector<cplxl> fl(full.begin(), full.end());
+        ok[idx] = factor_bordered<cplxl>(fl, z.K, 4, 8, 8, pivot, fp[idx]);
       } else {
         const int s = idx - (int)Sp;
         std::vector<double> full;
         assemble<double>(ctx, s == 0 ? 1 : 2, s == 0 ? 0 : s - 1, adt, full, p);
-        ok[idx] = factor_bordered<double>(full, z.K, 2, 4, 4, pivot, fr[s]);
+        std::vector<long double> fl(full.begin(), full.end());
+        ok[idx] = factor_bordered<long double>(fl, z.K, 2, 4, 4, pivot, fr[s]);
       }
     });
     double growth = 0.0;
@@ -494,10 +504,10 @@ qg_status refactor(qg_ctx* ctx, double adt) {
     std::vector<double> rL(Sr * z.p2 * 4), rU(Sr * z.p2 * (kutr + 1));
     parallel_for((int)(Sp + Sr), [&](int idx) {
       if (idx < (int)Sp)
-        ok[idx] = pack<cplx, double2>(fp[idx], idx, 8, kutp + 1, 4, z.p4, ppiv.data(), pL.data(),
+        ok[idx] = pack<cplxl, double2>(fp[idx], idx, 8, kutp + 1, 4, z.p4, ppiv.data(), pL.data(),
                                       pU.data(), pW.data(), pC.data(), pM.data());
       else
-        ok[idx] = pack<double, double>(fr[idx - Sp], idx - Sp, 4, kutr + 1, 2, z.p2, rpiv.data(),
+        ok[idx] = pack<long double, double>(fr[idx - Sp], idx - Sp, 4, kutr + 1, 2, z.p2, rpiv.data(),
                                        rL.data(), rU.data(), rW.data(), rC.data(), rM.data());
     });
     for (int v : ok)
@@ -514,10 +524,10 @@ qg_status refactor(qg_ctx* ctx, double adt) {
     std::vector<double> rL(Sr * z.q2 * 4), rU(Sr * z.q2 * 4), rui(Sr * z.q2);
     parallel_for((int)(Sp + Sr), [&](int idx) {
       if (idx < (int)Sp)
-        pack_np<cplx, double2>(fp[idx], idx, 8, 8, 4, z.q4, pL.data(), pU.data(), pui.data(),
+        pack_np<cplxl, double2>(fp[idx], idx, 8, 8, 4, z.q4, pL.data(), pU.data(), pui.data(),
                                pW.data(), pC.data(), pM.data());
       else
-        pack_np<double, double>(fr[idx - Sp], idx - Sp, 4, 4, 2, z.q2, rL.data(), rU.data(),
+        pack_np<long double, double>(fr[idx - Sp], idx - Sp, 4, 4, 2, z.q2, rL.data(), rU.data(),
                                 rui.data(), rW.data(), rC.data(), rM.data());
     });
     HIPCHK(up(w.p_L, pL.data(), pL.size() * sizeof(double2)));

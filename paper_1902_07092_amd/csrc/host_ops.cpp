@@ -288,5 +288,9 @@ template bool factor_bordered<double>(const std::vector<double>&, int, int, int,
                                       BorderedFactor<double>&);
 template bool factor_bordered<cplx>(const std::vector<cplx>&, int, int, int, int, bool,
                                     BorderedFactor<cplx>&);
+template bool factor_bordered<long double>(const std::vector<long double>&, int, int, int, int,
+                                           bool, BorderedFactor<long double>&);
+template bool factor_bordered<cplxl>(const std::vector<cplxl>&, int, int, int, int, bool,
+                                     BorderedFactor<cplxl>&);
 
 }  // namespace qg

@@ -8,6 +8,7 @@
 namespace qg {
 
 using cplx = std::complex<double>;
+using cplxl = std::complex<long double>;
 
 // Width of every stored operator band: offsets -8..+8 around the diagonal.
 constexpr int BANDW = 17;
@@ -44,9 +45,13 @@ struct BorderedFactor {
 };
 
 // Full bordered K x K matrix given as dense rows; builds the factor.
+// Instantiated for double, complex<double> and their long-double
+// counterparts (the factorisation in extended precision, every entry then
+// rounded once to binary64 when the device layout is packed).
 template <typename T>
 bool factor_bordered(const std::vector<T>& full, int K, int p, int kl, int ku, bool pivot,
                      BorderedFactor<T>& out);
+
 
 // Tau rows: Dirichlet at s_o, Dirichlet at s_i, third derivative at s_o,
 // Neumann at s_i (first p of them).

@@ -35,11 +35,9 @@ __device__ __forceinline__ double2 z2() { return make_double2(0.0, 0.0); }
 // Value of lane LANE of each 16-lane row.
 template <int LANE>
 __device__ __forceinline__ double bcast(double v) {
-  const long long b = __double_as_longlong(v);
-  // every lane has a source under row_newbcast, so no "old" value is needed
-  const int lo = __builtin_amdgcn_mov_dpp((int)(b & 0xffffffffLL), 0x150 + LANE, 0xF, 0xF, true);
-  const int hi = __builtin_amdgcn_mov_dpp((int)(b >> 32), 0x150 + LANE, 0xF, 0xF, true);
-  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+  // one 64-bit DPP move (row_newbcast was made for FP64 operands); every
+  // lane has a source, so the "old" value is never used
+  return __builtin_amdgcn_update_dpp(0.0, v, 0x150 + LANE, 0xF, 0xF, true);
 }
 template <int LANE>
 __device__ __forceinline__ double2 bcast2(double2 v) {
@@ -170,19 +168,24 @@ struct Solver4 {
 #pragma unroll
     for (int i = 0; i < P; ++i) wh[i] = z2();
     const TF* Wr = F.W + (size_t)so * P * n;
-    // eight rows per lane in flight: the loads of a chunk issue together
-    for (int j0 = 0; j0 < n; j0 += 8 * SB) {
-      double2 h[8];
-      TF w[8][P];
+    // four rows per lane per chunk, two chunks in flight: the loads of the
+    // next chunk are issued before the current one is summed (every lane
+    // still adds its rows in increasing order)
+    constexpr int U = 4;
+    double2 hA[U], hB[U];
+    TF wA[U][P], wB[U][P];
+    auto load = [&](int j0, double2 (&h)[U], TF (&w)[U][P]) {
 #pragma unroll
-      for (int u = 0; u < 8; ++u) {
+      for (int u = 0; u < U; ++u) {
         const int j = min(j0 + u * SB + lane, n - 1);
         h[u] = hg[j];
 #pragma unroll
         for (int i = 0; i < P; ++i) w[u][i] = Wr[(size_t)i * n + j];
       }
+    };
+    auto add = [&](int j0, const double2 (&h)[U], const TF (&w)[U][P]) {
 #pragma unroll
-      for (int u = 0; u < 8; ++u) {
+      for (int u = 0; u < U; ++u) {
         if (j0 + u * SB + lane < n) {
 #pragma unroll
           for (int i = 0; i < P; ++i) {
@@ -192,6 +195,13 @@ struct Solver4 {
           }
         }
       }
+    };
+    load(0, hA, wA);
+    for (int j0 = 0; j0 < n; j0 += 2 * U * SB) {
+      load(j0 + U * SB, hB, wB);
+      add(j0, hA, wA);
+      load(j0 + 2 * U * SB, hA, wA);
+      add(j0 + U * SB, hB, wB);
     }
 #pragma unroll
     for (int i = 0; i < P; ++i)

@@ -83,11 +83,14 @@ MEDIUM = _wl("medium_768x257_E1e-6_bpr353", 1e-6, 5.0, 768, 257, "bpr353",
              1e-7, 500, "decaying", 2)
 LARGE = _wl("large_3072x1025_E1e-8_cnab2", 1e-8, 20.0, 3072, 1025, "cnab2",
             2.5e-10, 50, "kolmogorov", 3)
+LARGE_MID = _wl("large_6144x2049_E1e-8_cnab2", 1e-8, 20.0, 6144, 2049,
+                "cnab2", 1e-10, 50, "kolmogorov", 3)
 LARGE_TOP = _wl("large_12288x4097_E1e-8_cnab2", 1e-8, 20.0, 12288, 4097,
                 "cnab2", 2e-11, 50, "kolmogorov", 3)
 ADJOINT = _wl("adjoint_768x257_E1e-6_cnab2", 1e-6, 5.0, 768, 257, "cnab2",
               1e-7, 200, "decaying", 2)
-WORKLOADS = {w.name: w for w in (SMALL, MEDIUM, LARGE, LARGE_TOP, ADJOINT)}
+WORKLOADS = {w.name: w for w in (SMALL, MEDIUM, LARGE, LARGE_MID, LARGE_TOP,
+                                   ADJOINT)}
 
 # Ensemble of independent runs (sizes across the paper's range of problem
 # sizes): N_r uniform on {65, 129, 257}, N_phi = 3 (N_r - 1), Ra

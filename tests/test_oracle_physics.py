@@ -23,7 +23,10 @@ TAB3_PUMP_EPS_TAU = 2.148113e2
 TAB3_PUMP_EPS_OMEGA = -9.436745e3
 
 
-def test_bordered_solve_equals_dense():
+@pytest.mark.parametrize("pivot", [True, False])
+def test_bordered_solve_equals_dense(pivot):
+    """Both band LUs (LAPACK with row interchanges, and the plain one
+    without) solve the bordered systems to FP64 accuracy."""
     o = QGOracle(1e-3, 8e4, 1.0, 0.35, 96, 33)
     rng = np.random.Generator(np.random.PCG64(11))
     K = o.K
@@ -31,7 +34,7 @@ def test_bordered_solve_equals_dense():
         L = bordered_lhs(tau_rows_psi(K),
                          o.ops.A(m) - 0.5e-4 * o.ops.B(m, o.E))
         f = rng.standard_normal(K) + 1j * rng.standard_normal(K)
-        x = BorderedSolver(L, 4).solve(f)
+        x = BorderedSolver(L, 4, pivot).solve(f)
         # reference: dense LU of the row-equilibrated matrix (the raw tau
         # matrix mixes rows of size ~n^6 and ~k^-4)
         r = 1.0 / np.abs(L).max(axis=1)
@@ -39,7 +42,7 @@ def test_bordered_solve_equals_dense():
         assert np.max(np.abs(x - ref)) < 1e-13 * np.abs(ref).max()
         Lt = bordered_lhs(tau_rows_dirichlet(K), o.ops.D
                           - 0.5e-4 * o.ops.F(m))
-        xt = BorderedSolver(Lt, 2).solve(f)
+        xt = BorderedSolver(Lt, 2, pivot).solve(f)
         r = 1.0 / np.abs(Lt).max(axis=1)
         ref = np.linalg.solve(Lt * r[:, None], f * r)
         assert np.max(np.abs(xt - ref)) < 1e-13 * np.abs(ref).max()
