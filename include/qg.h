@@ -276,6 +276,53 @@ qg_status qg_adjoint_solve(qg_ctx *ctx, double dt, double *psi, double *theta,
 qg_status qg_adjoint_mass_lin(qg_ctx *ctx, double c, double *psi,
                               double *theta, double *uphi, int on_device);
 
+/* Reverse mode (discrete adjoint of the CNAB2 step, Sect. 4 eq. multistep1
+ * with E^{-1} := E^0, through the bordered solves of Appendix A).
+ *
+ * qg_gradient runs nsteps CNAB2 steps of size dt from the current state
+ * y^0 (its CNAB2 history restarts there, as after qg_set_state) and
+ * returns
+ *   J = energy_weight * dt * sum_{n=0}^{N} w_n E_K(y^n)
+ *       (w_n trapezoid weights, 1/2 at n = 0 and N; E_K the kinetic energy
+ *       of Sect. 6.2 as in qg_diagnostics)
+ * in *J (host), and, when the three grad_* pointers are given, the
+ * gradient of J + <ybar_N, y^N> with respect to y^0 in grad_* (ybar_N the
+ * terminal co-state adj_*, or zero when those three are NULL): the
+ * co-state of each complex entry z is dJ/dRe z + i dJ/dIm z, so that for a
+ * perturbation d of y^0, dJ = sum Re(conj(grad) d).  The reverse sweep
+ * keeps the forward state and E^{n-1} at every interval-th step and
+ * recomputes each block of `interval` steps before its reverse steps.
+ * All arrays are device memory in the state layout of qg_set_state (psi
+ * [M][K] complex with its row 0 unused, theta [M][K] complex, uphi [K]).
+ * work: device memory of at least qg_gradient_workspace_size bytes,
+ * 256-byte aligned, owned by the caller and free again on return.  The
+ * context ends at y^N with the CNAB2 history of that run (qg_step may
+ * continue it).  Synchronous.  Single-run FP64 contexts without Ekman
+ * pumping (else QG_EINVAL / QG_EUNSUPPORTED); the gradient needs the
+ * unpivoted band LU (QG_EUNSUPPORTED otherwise; J alone does not).  A
+ * non-finite forward state returns QG_ENONFINITE with the context
+ * unchanged; the reverse sweep itself is not checked. */
+qg_status qg_gradient_workspace_size(const qg_ctx *ctx, int nsteps,
+                                     int interval, size_t *bytes);
+qg_status qg_gradient(qg_ctx *ctx, double dt, int nsteps, int interval,
+                      double energy_weight, const double *adj_psi,
+                      const double *adj_theta, const double *adj_uphi,
+                      double *grad_psi, double *grad_theta, double *grad_uphi,
+                      double *J, void *work, size_t work_bytes);
+
+/* The transposed explicit terms at a state y (Sect. 3.2, eq. psi_int,
+ * temp_int, uphi_int): bar <- E'(y)^H bar + kappa grad E_K(y), in place on
+ * the co-state bar; y and bar are device arrays in the state layout, y
+ * need not be the context's state.  work: as for qg_gradient with
+ * nsteps = 0, interval = 1.  The piece of the reverse sweep that holds the
+ * transforms; for checking it against a reference.  Synchronous; the same
+ * contexts as qg_gradient. */
+qg_status qg_adjoint_explicit(qg_ctx *ctx, const double *psi,
+                              const double *theta, const double *uphi,
+                              double *bar_psi, double *bar_theta,
+                              double *bar_uphi, double kappa, void *work,
+                              size_t work_bytes);
+
 /* Diagnostics of the current state (synchronises the stream). */
 qg_status qg_diagnostics(qg_ctx *ctx, qg_diag *out);
 

@@ -23,7 +23,7 @@ def _run(cmd, verbose):
 
 
 SOURCES = ("transforms.hip", "bands.hip", "kernels.hip", "solve.hip", "adjoint.hip",
-           "api.hip")
+           "reverse.hip", "api.hip")
 
 
 def build(verbose: bool = False) -> str:

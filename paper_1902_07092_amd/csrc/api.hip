@@ -36,6 +36,14 @@ int solve_batch();
 bool launch_solve_np(const Geom& g, const FactorSet<double2>& Fp, const FactorSet<double>& Fr,
                      double2* rhs, const RhsSpec& rs, int qp, int qr, hipStream_t st);
 int solve_np_pad();
+bool launch_explicit_T(const Geom& g, const Bands& b, const double2* X, const double2* Ebp,
+                       const double2* Ebt, double kappa, double2* NLb, double* zb,
+                       double2* thb0, double2* Xb, double2* psib, double2* thb, hipStream_t st);
+void launch_energy_accum(const double* diag, int M, double w, double* J, hipStream_t st);
+void launch_to_internal(int M, int K, const double2* psi, const double2* th, const double* u,
+                        double2* dp, double2* dt, hipStream_t st);
+void launch_to_api(int M, int K, const double2* sp, const double2* sth, double2* psi,
+                   double2* th, double* u, hipStream_t st);
 }  // namespace qg
 
 using namespace qg;
@@ -574,11 +582,13 @@ void timed(qg_ctx* ctx, int cls, F launch) {
   if (a && b) ctx->ev_marks.push_back({cls, {a, b}});
 }
 
+// E(y) into (Ep, Et); diag (optional): the synthesis's per-m diagnostics
+// of y (kinetic energy and the rest, see synth_kernel).
 qg_status explicit_terms(qg_ctx* ctx, const double2* psi, const double2* th, double2* Ep,
-                         double2* Et) {
+                         double2* Et, double* diag = nullptr) {
   bool ok = true;
   timed(ctx, K_SYNTH, [&] {
-    ok = launch_synth(ctx->g, psi, th, ctx->ptr2(ctx->w.X), nullptr, ctx->mixed, ctx->st) && ok;
+    ok = launch_synth(ctx->g, psi, th, ctx->ptr2(ctx->w.X), diag, ctx->mixed, ctx->st) && ok;
   });
   timed(ctx, K_RING, [&] {
     ok = launch_ring(ctx->g, ctx->ptr2(ctx->w.X), ctx->ptr2(ctx->w.NL), ctx->ptrd(ctx->w.zonal),
@@ -1593,6 +1603,318 @@ qg_status qg_step_timed(qg_ctx* ctx, double dt, int scheme, int nsteps, double* 
     launches[mk.first] += 1;
   }
   ctx->ev_marks.clear();
+  return QG_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------- reverse mode
+// Gradient of the time-integrated kinetic energy through CNAB2 steps
+// (eq. multistep1 with E^{-1} := E^0, Sect. 4), by the discrete adjoint:
+// with y^{n+1} = P S^-1 Z r^n, S = M - (dt/2) L, r^n = (M + (dt/2) L) y^n +
+// dt (c_n E(y^n) - (1/2) E(y^{n-1})), c_0 = 1/2 + 1/2 (E^{-1} := E^0),
+// else 3/2, the co-states run backwards as
+//   rb^{n-1} = Z S^-H P ybar^n,
+//   ybar^n   = kappa_n grad E_K(y^n) + (M + (dt/2) L)^H rb^n
+//              + E'(y^n)^H (c_n dt rb^n - (1/2) dt rb^{n+1}),
+// kappa_n = w_E dt w_n (trapezoid weights w_n, 1/2 at both ends), and
+// ybar^N adds the caller's terminal co-state.  The forward trajectory is
+// kept at every `interval`-th step (state and E^{n-1}); each block is
+// recomputed from its checkpoint before its reverse steps.
+namespace {
+
+struct GradMap {
+  size_t ck, blk, E2, Xb, thb0, rb, acc, eb, ml, ex, J, total;
+};
+
+GradMap map_gradient(const qg_ctx* c, int nsteps, int interval) {
+  Layout L;
+  GradMap w;
+  const size_t S = 2 * c->mk() * sizeof(double2);   // a (Psi and u, theta) pair
+  const int nblk = nsteps > 0 ? (nsteps + interval - 1) / interval : 0;
+  const int per = std::max(1, std::min(interval, nsteps));
+  w.ck = L.take((size_t)nblk * 2 * S);    // y^{n0} and E^{n0-1} of each block
+  w.blk = L.take((size_t)(per + 1) * S);  // the states of one block
+  w.E2 = L.take(2 * S);                   // explicit terms of the recomputation
+  w.Xb = L.take((size_t)6 * c->z.R * c->z.M * sizeof(double2));
+  w.thb0 = L.take(c->mk() * sizeof(double2));
+  w.rb = L.take(2 * S);
+  w.acc = L.take(S);
+  w.eb = L.take(S);
+  w.ml = L.take(S);
+  w.ex = L.take(S);
+  w.J = L.take(sizeof(double));
+  w.total = L.total;
+  return w;
+}
+
+struct Pair {
+  double2* p;   // Psi of m >= 1, the zonal flow in row 0
+  double2* t;   // theta
+};
+
+Pair pair_at(char* base, size_t off, size_t i, size_t mk) {
+  double2* p = reinterpret_cast<double2*>(base + off) + 2 * i * mk;
+  return {p, p + mk};
+}
+
+qg_status reverse_ok(qg_ctx* ctx) {
+  if (ctx->nmem != 1 || !ctx->single)
+    return fail(ctx, QG_EINVAL, "reverse mode needs a single-run context");
+  if (ctx->mixed) return fail(ctx, QG_EUNSUPPORTED, "reverse mode runs in FP64 only");
+  if (ctx->z.pump) return fail(ctx, QG_EUNSUPPORTED, "reverse mode has no Ekman pumping terms");
+  return QG_OK;
+}
+
+// One CNAB2 step y -> out with E(y) into En and E^{n-1} in Ep (nullptr:
+// E^{-1} := E^n); diag: the synthesis's diagnostics of y.
+qg_status cnab2_into(qg_ctx* ctx, double dt, Pair y, Pair En, const Pair* Ep, Pair out,
+                     double* diag) {
+  qg_status s = explicit_terms(ctx, y.p, y.t, En.p, En.t, diag);
+  if (s != QG_OK) return s;
+  RhsSpec rs{};
+  rs.base_psi = y.p;
+  rs.base_th = y.t;
+  rs.cL = 0.5 * dt;
+  rs.nterm = 2;
+  rs.term_psi[0] = En.p;
+  rs.term_th[0] = En.t;
+  rs.coef[0] = 1.5 * dt;
+  rs.term_psi[1] = Ep ? Ep->p : En.p;
+  rs.term_th[1] = Ep ? Ep->t : En.t;
+  rs.coef[1] = -0.5 * dt;
+  rs.out_psi = out.p;
+  rs.out_th = out.t;
+  return implicit_solve(ctx, rs);
+}
+
+// (psib, thb) = E'(y)^H eb + kappa grad E_K(y); diag/J/w: also J += w E_K(y).
+qg_status explicit_T(qg_ctx* ctx, Pair y, Pair eb, double kappa, char* base, const GradMap& w,
+                     Pair out, double* J, double wJ) {
+  double* diag = J ? ctx->ptrd(ctx->w.diag) : nullptr;
+  if (!launch_synth(ctx->g, y.p, y.t, ctx->ptr2(ctx->w.X), diag, false, ctx->st))
+    return fail(ctx, QG_EUNSUPPORTED, "no transform kernel for these sizes");
+  if (J) launch_energy_accum(diag, ctx->z.M, wJ, J, ctx->st);
+  if (!launch_explicit_T(ctx->g, ctx->b, ctx->ptr2(ctx->w.X), eb.p, eb.t, kappa,
+                         ctx->ptr2(ctx->w.NL), ctx->ptrd(ctx->w.zonal),
+                         reinterpret_cast<double2*>(base + w.thb0),
+                         reinterpret_cast<double2*>(base + w.Xb), out.p, out.t, ctx->st))
+    return fail(ctx, QG_EUNSUPPORTED, "no reverse transform kernel for these sizes");
+  HIPCHK(hipGetLastError());
+  return QG_OK;
+}
+
+void combine2(qg_ctx* ctx, Pair out, int nb, const Pair* in, const double* c) {
+  Combine cb{};
+  cb.nb = nb;
+  for (int i = 0; i < nb; ++i) {
+    cb.in[i] = in[i].p;
+    cb.c[i] = c[i];
+  }
+  launch_combine(cb, out.p, 2 * ctx->mk(), nullptr, ctx->st);
+}
+
+qg_status gradient_run(qg_ctx* ctx, double dt, int N, int C, double ew, const double* adj_psi,
+                       const double* adj_th, const double* adj_u, double* g_psi, double* g_th,
+                       double* g_u, double* J, char* base, const GradMap& w) {
+  const size_t mk = ctx->mk();
+  const int M = ctx->z.M, K = ctx->z.K;
+  const bool grad = g_psi != nullptr;
+  qg_status s = prepare(ctx, 0.5 * dt);
+  if (s != QG_OK) return s;
+  if (grad && ctx->pivoted)
+    return fail(ctx, QG_EUNSUPPORTED, "the adjoint solves use the unpivoted factors");
+  double* Jd = reinterpret_cast<double*>(base + w.J);
+  double* diag = ctx->ptrd(ctx->w.diag);
+  HIPCHK(hipMemsetAsync(Jd, 0, sizeof(double), ctx->st));
+  HIPCHK(hipMemsetAsync(ctx->nf_flag(), 0, sizeof(int), ctx->st));
+  auto wt = [&](int n) { return (n == 0 || n == N) ? 0.5 : 1.0; };
+  // ---- forward pass: checkpoints, J, the final state and history
+  Pair E2[2] = {pair_at(base, w.E2, 0, mk), pair_at(base, w.E2, 1, mk)};
+  Pair Y[2] = {pair_at(base, w.blk, 0, mk), pair_at(base, w.blk, 1, mk)};
+  launch_copy(ctx->psi(), Y[0].p, 2 * mk, nullptr, ctx->st);
+  for (int n = 0; n < N; ++n) {
+    Pair y = Y[n % 2], En = E2[n % 2], Ep = E2[(n + 1) % 2];
+    if (n % C == 0) {
+      Pair ck = pair_at(base, w.ck, 2 * (size_t)(n / C), mk);
+      launch_copy(y.p, ck.p, 2 * mk, nullptr, ctx->st);
+      if (n > 0) launch_copy(Ep.p, pair_at(base, w.ck, 2 * (size_t)(n / C) + 1, mk).p, 2 * mk,
+                             nullptr, ctx->st);
+    }
+    ctx->tag = n + 1;
+    s = cnab2_into(ctx, dt, y, En, n > 0 ? &Ep : nullptr, Y[(n + 1) % 2], diag);
+    if (s != QG_OK) return s;
+    launch_energy_accum(diag, M, ew * dt * wt(n), Jd, ctx->st);
+  }
+  {
+    Pair yN = Y[N % 2];
+    if (!launch_synth(ctx->g, yN.p, yN.t, ctx->ptr2(ctx->w.X), diag, false, ctx->st))
+      return fail(ctx, QG_EUNSUPPORTED, "no transform kernel for these sizes");
+    launch_energy_accum(diag, M, ew * dt * wt(N), Jd, ctx->st);
+  }
+  HIPCHK(hipGetLastError());
+  int flag = 0;
+  HIPCHK(hipMemcpyAsync(&flag, ctx->nf_flag(), sizeof(int), hipMemcpyDeviceToHost, ctx->st));
+  HIPCHK(hipMemcpyAsync(J, Jd, sizeof(double), hipMemcpyDeviceToHost, ctx->st));
+  HIPCHK(hipStreamSynchronize(ctx->st));
+  if (flag) {
+    HIPCHK(hipMemsetAsync(ctx->nf_flag(), 0, sizeof(int), ctx->st));
+    HIPCHK(hipStreamSynchronize(ctx->st));
+    return fail(ctx, QG_ENONFINITE, "non-finite state at step " + std::to_string(flag) +
+                                        " of the forward pass; the state is unchanged");
+  }
+  // the context continues from y^N with its CNAB2 history, as after
+  // qg_step(dt, CNAB2, N) from a fresh history
+  if (N > 0) {
+    launch_copy(Y[N % 2].p, ctx->psi(), 2 * mk, nullptr, ctx->st);
+    ctx->last_scheme = QG_CNAB2;
+    ctx->last_dt = dt;
+    ctx->cur = 0;
+    ctx->have_prev = 1;
+    launch_copy(E2[(N - 1) % 2].p, ctx->slot(ctx->w.eslot, 1, 0), 2 * mk, nullptr, ctx->st);
+    ctx->ms_n = 0;
+    ctx->t += N * dt;
+    ctx->step += N;
+    ctx->t_set = 0;
+  }
+  if (!grad) {
+    HIPCHK(hipStreamSynchronize(ctx->st));
+    return QG_OK;
+  }
+  // ---- reverse pass
+  Pair rb[2] = {pair_at(base, w.rb, 0, mk), pair_at(base, w.rb, 1, mk)};
+  Pair acc = pair_at(base, w.acc, 0, mk), eb = pair_at(base, w.eb, 0, mk);
+  Pair ml = pair_at(base, w.ml, 0, mk), ex = pair_at(base, w.ex, 0, mk);
+  int cur = 0;   // rb[cur] = rb^n, rb[1 - cur] = rb^{n+1}
+  const int nblk = N > 0 ? (N + C - 1) / C : 0;
+  Pair adj{nullptr, nullptr};
+  if (adj_psi || adj_th || adj_u) {
+    adj = ml;   // the terminal co-state, consumed at n = N before ml is used
+    launch_to_internal(M, K, reinterpret_cast<const double2*>(adj_psi),
+                       reinterpret_cast<const double2*>(adj_th), adj_u, adj.p, adj.t, ctx->st);
+  }
+  auto reverse_step = [&](int n, Pair y) -> qg_status {
+    const double kappa = ew * dt * wt(n);
+    if (n < N) {
+      const double cn = (n == 0) ? 1.0 : 1.5;
+      Pair in[2] = {rb[cur], rb[1 - cur]};
+      double c[2] = {cn * dt, -0.5 * dt};
+      combine2(ctx, eb, n + 1 < N ? 2 : 1, in, c);
+      launch_band_adjoint(ctx->g, ctx->b, 0.5 * dt, rb[cur].p, rb[cur].t, ml.p, ml.t, ctx->st);
+    } else {
+      // no step follows the last state: its E has a zero co-state
+      HIPCHK(hipMemsetAsync(eb.p, 0, 2 * mk * sizeof(double2), ctx->st));
+    }
+    qg_status st = explicit_T(ctx, y, eb, kappa, base, w, ex, nullptr, 0.0);
+    if (st != QG_OK) return st;
+    Pair in[2] = {ex, ml};
+    double c[2] = {1.0, 1.0};
+    const bool more = (n < N) || adj.p != nullptr;
+    Pair out = (n > 0) ? rb[1 - cur] : acc;   // rb^{n+1} is no longer needed
+    combine2(ctx, out, more ? 2 : 1, in, c);
+    if (n > 0) {
+      launch_solve_adjoint(ctx->g, ctx->Fp, ctx->Fr, ctx->z.q4, ctx->z.q2, out.p, out.t,
+                           ctx->st);
+      cur = 1 - cur;
+    }
+    HIPCHK(hipGetLastError());
+    return QG_OK;
+  };
+  for (int b = nblk - 1; b >= 0; --b) {
+    const int n0 = b * C, n1 = std::min(N, n0 + C);
+    const bool last = (b == nblk - 1);
+    const int top = last ? N : n1 - 1;   // highest state of this block's reverse steps
+    Pair ck = pair_at(base, w.ck, 2 * (size_t)b, mk);
+    Pair ckE = pair_at(base, w.ck, 2 * (size_t)b + 1, mk);
+    launch_copy(ck.p, pair_at(base, w.blk, 0, mk).p, 2 * mk, nullptr, ctx->st);
+    if (n0 > 0) launch_copy(ckE.p, E2[1].p, 2 * mk, nullptr, ctx->st);
+    for (int n = n0; n < top; ++n) {
+      const int j = n - n0;
+      Pair Ep = E2[(j + 1) % 2];
+      s = cnab2_into(ctx, dt, pair_at(base, w.blk, j, mk), E2[j % 2], n > 0 ? &Ep : nullptr,
+                     pair_at(base, w.blk, j + 1, mk), nullptr);
+      if (s != QG_OK) return s;
+    }
+    for (int n = top; n >= n0; --n) {
+      s = reverse_step(n, pair_at(base, w.blk, n - n0, mk));
+      if (s != QG_OK) return s;
+    }
+  }
+  if (N == 0) {
+    s = reverse_step(0, pair_at(base, w.blk, 0, mk));
+    if (s != QG_OK) return s;
+  }
+  launch_to_api(M, K, acc.p, acc.t, reinterpret_cast<double2*>(g_psi),
+                reinterpret_cast<double2*>(g_th), g_u, ctx->st);
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipStreamSynchronize(ctx->st));
+  return QG_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+qg_status qg_gradient_workspace_size(const qg_ctx* ctx, int nsteps, int interval,
+                                     size_t* bytes) {
+  if (!ctx || !bytes || nsteps < 0 || interval < 1) return QG_EINVAL;
+  *bytes = map_gradient(ctx, nsteps, interval).total;
+  return QG_OK;
+}
+
+qg_status qg_gradient(qg_ctx* ctx, double dt, int nsteps, int interval, double energy_weight,
+                      const double* adj_psi, const double* adj_theta, const double* adj_uphi,
+                      double* grad_psi, double* grad_theta, double* grad_uphi, double* J,
+                      void* work, size_t work_bytes) {
+  if (!ctx) return QG_EINVAL;
+  qg_status s = reverse_ok(ctx);
+  if (s != QG_OK) return s;
+  if (!(dt > 0) || !std::isfinite(dt)) return fail(ctx, QG_EINVAL, "dt must be positive");
+  if (nsteps < 0 || interval < 1) return fail(ctx, QG_EINVAL, "nsteps >= 0, interval >= 1");
+  if (!std::isfinite(energy_weight)) return fail(ctx, QG_EINVAL, "energy_weight must be finite");
+  if (!J) return fail(ctx, QG_EINVAL, "null J");
+  const bool any_g = grad_psi || grad_theta || grad_uphi;
+  if (any_g && !(grad_psi && grad_theta && grad_uphi))
+    return fail(ctx, QG_EINVAL, "gradient outputs: all three or none");
+  const GradMap w = map_gradient(ctx, nsteps, interval);
+  if (!work || work_bytes < w.total) return fail(ctx, QG_EINVAL, "gradient workspace too small");
+  if (reinterpret_cast<uintptr_t>(work) % 256)
+    return fail(ctx, QG_EINVAL, "gradient workspace must be 256-byte aligned");
+  s = gradient_run(ctx, dt, nsteps, interval, energy_weight, adj_psi, adj_theta, adj_uphi,
+                   grad_psi, grad_theta, grad_uphi, J, static_cast<char*>(work), w);
+  if (s == QG_OK) ctx->err.clear();
+  return s;
+}
+
+qg_status qg_adjoint_explicit(qg_ctx* ctx, const double* psi, const double* theta,
+                              const double* uphi, double* bar_psi, double* bar_theta,
+                              double* bar_uphi, double kappa, void* work, size_t work_bytes) {
+  if (!ctx) return QG_EINVAL;
+  qg_status s = reverse_ok(ctx);
+  if (s != QG_OK) return s;
+  if (!psi || !theta || !uphi || !bar_psi || !bar_theta || !bar_uphi)
+    return fail(ctx, QG_EINVAL, "null pointer");
+  if (!std::isfinite(kappa)) return fail(ctx, QG_EINVAL, "kappa must be finite");
+  const GradMap w = map_gradient(ctx, 0, 1);
+  if (!work || work_bytes < w.total) return fail(ctx, QG_EINVAL, "workspace too small");
+  if (reinterpret_cast<uintptr_t>(work) % 256)
+    return fail(ctx, QG_EINVAL, "workspace must be 256-byte aligned");
+  char* base = static_cast<char*>(work);
+  const size_t mk = ctx->mk();
+  const int M = ctx->z.M, K = ctx->z.K;
+  Pair y = pair_at(base, w.blk, 0, mk), eb = pair_at(base, w.eb, 0, mk);
+  Pair out = pair_at(base, w.ex, 0, mk);
+  HIPCHK(hipMemsetAsync(ctx->nf_flag(), 0, sizeof(int), ctx->st));
+  launch_to_internal(M, K, reinterpret_cast<const double2*>(psi),
+                     reinterpret_cast<const double2*>(theta), uphi, y.p, y.t, ctx->st);
+  launch_to_internal(M, K, reinterpret_cast<const double2*>(bar_psi),
+                     reinterpret_cast<const double2*>(bar_theta), bar_uphi, eb.p, eb.t, ctx->st);
+  s = explicit_T(ctx, y, eb, kappa, base, w, out, nullptr, 0.0);
+  if (s != QG_OK) return s;
+  launch_to_api(M, K, out.p, out.t, reinterpret_cast<double2*>(bar_psi),
+                reinterpret_cast<double2*>(bar_theta), bar_uphi, ctx->st);
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipStreamSynchronize(ctx->st));
   return QG_OK;
 }
 

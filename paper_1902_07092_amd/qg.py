@@ -85,6 +85,12 @@ def load():
         "qg_step_tangent": (i, [vp, d, i]),
         "qg_adjoint_solve": (i, [vp, d, vp, vp, vp, i]),
         "qg_adjoint_mass_lin": (i, [vp, d, vp, vp, vp, i]),
+        "qg_gradient_workspace_size": (i, [vp, i, i,
+                                           ctypes.POINTER(ctypes.c_size_t)]),
+        "qg_gradient": (i, [vp, d, i, i, d, vp, vp, vp, vp, vp, vp,
+                            ctypes.POINTER(d), vp, ctypes.c_size_t]),
+        "qg_adjoint_explicit": (i, [vp, vp, vp, vp, vp, vp, vp, d, vp,
+                                    ctypes.c_size_t]),
         "qg_checkpoint_size": (i, [vp, ctypes.POINTER(ctypes.c_size_t)]),
         "qg_checkpoint_save": (i, [vp, vp, ctypes.c_size_t, i]),
         "qg_checkpoint_load": (i, [vp, vp, ctypes.c_size_t, i]),
@@ -443,6 +449,62 @@ class QGSolver:
             ctypes.c_void_p(th.ctypes.data), ctypes.c_void_p(up.ctypes.data), 0))
         return ps, th, up
 
+    # ------------------------------------------------------ reverse mode
+    def _work(self, nsteps, interval):
+        torch = self.torch
+        n = ctypes.c_size_t(0)
+        _check(self.ctx, load().qg_gradient_workspace_size(
+            self.ctx, int(nsteps), int(interval), ctypes.byref(n)))
+        buf = torch.empty(n.value + 256, dtype=torch.uint8, device=self.device)
+        base = (buf.data_ptr() + 255) // 256 * 256
+        return buf, base, n.value
+
+    def _dev_state(self, psi, theta, uphi):
+        torch = self.torch
+        return (torch.as_tensor(psi, dtype=torch.complex128, device=self.device).contiguous(),
+                torch.as_tensor(theta, dtype=torch.complex128, device=self.device).contiguous(),
+                torch.as_tensor(uphi, dtype=torch.float64, device=self.device).contiguous())
+
+    def gradient(self, dt, nsteps, interval=20, energy_weight=1.0,
+                 terminal=None, want_grad=True):
+        """qg_gradient from the current state: returns (J, (gpsi, gtheta,
+        guphi)) with device tensors (None without want_grad); terminal:
+        an optional co-state (psi, theta, uphi) of y^N.  The context ends
+        at y^N."""
+        torch = self.torch
+        buf, base, nbytes = self._work(nsteps, interval)
+        adj = self._dev_state(*terminal) if terminal is not None else None
+        if want_grad:
+            g = (torch.empty((self.M, self.K), dtype=torch.complex128, device=self.device),
+                 torch.empty((self.M, self.K), dtype=torch.complex128, device=self.device),
+                 torch.empty(self.K, dtype=torch.float64, device=self.device))
+        J = ctypes.c_double(0.0)
+        ap = [ctypes.c_void_p(a.data_ptr()) for a in adj] if adj else [None] * 3
+        gp = [ctypes.c_void_p(a.data_ptr()) for a in g] if want_grad else [None] * 3
+        _check(self.ctx, load().qg_gradient(
+            self.ctx, float(dt), int(nsteps), int(interval), float(energy_weight),
+            *ap, *gp, ctypes.byref(J), ctypes.c_void_p(base), nbytes))
+        del buf
+        return J.value, (g if want_grad else None)
+
+    def energy_integral(self, dt, nsteps):
+        """J = dt sum_n w_n E_K(y^n) over nsteps CNAB2 steps (forward only)."""
+        return self.gradient(dt, nsteps, interval=max(1, nsteps),
+                             want_grad=False)[0]
+
+    def adjoint_explicit(self, state, costate, kappa=0.0):
+        """qg_adjoint_explicit: E'(y)^H costate + kappa grad E_K(y) for a
+        state y = (psi, theta, uphi); returns device tensors."""
+        buf, base, nbytes = self._work(0, 1)
+        y = self._dev_state(*state)
+        b = [x.clone() for x in self._dev_state(*costate)]
+        _check(self.ctx, load().qg_adjoint_explicit(
+            self.ctx, *[ctypes.c_void_p(x.data_ptr()) for x in y],
+            *[ctypes.c_void_p(x.data_ptr()) for x in b], float(kappa),
+            ctypes.c_void_p(base), nbytes))
+        del buf
+        return tuple(b)
+
     def step_autotune(self, dt, scheme="cnab2", n=9):
         """n steps while timing the band-product shapes; returns the
         chosen systems per thread."""
@@ -450,6 +512,45 @@ class QGSolver:
 
     def diagnostics(self):
         return qg_diagnostics(self.ctx)
+
+
+def _energy_gradient_function():
+    import torch
+
+    class EnergyGradient(torch.autograd.Function):
+        """J(theta^0) = dt sum_n w_n E_K(y^n) over nsteps CNAB2 steps from
+        (psi0, theta^0, uphi0), as a differentiable function of the initial
+        temperature coefficients theta^0 ((M, K) complex tensor on the
+        solver's device; it must meet the boundary conditions, as for
+        set_state).  Forward and backward run in the HIP library
+        (qg_gradient): the forward pass computes the gradient as well and
+        keeps it for backward.  PyTorch's complex convention matches the
+        library's (dJ/dRe + i dJ/dIm)."""
+
+        @staticmethod
+        def forward(ctx, theta0, solver, psi0, uphi0, dt, nsteps, interval):
+            solver.set_state(*solver._dev_state(psi0, theta0.detach(), uphi0))
+            J, g = solver.gradient(dt, nsteps, interval)
+            ctx.save_for_backward(g[1])
+            return torch.tensor(J, dtype=torch.float64, device=theta0.device)
+
+        @staticmethod
+        def backward(ctx, gJ):
+            (gth,) = ctx.saved_tensors
+            return gJ * gth, None, None, None, None, None, None
+
+    return EnergyGradient
+
+
+def energy_integral(theta0, solver, psi0, uphi0, dt, nsteps, interval=20):
+    """Differentiable J(theta^0) (see _energy_gradient_function)."""
+    global _EG
+    if _EG is None:
+        _EG = _energy_gradient_function()
+    return _EG.apply(theta0, solver, psi0, uphi0, dt, nsteps, interval)
+
+
+_EG = None
 
 
 class QGEnsemble:

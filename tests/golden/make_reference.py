@@ -7,11 +7,10 @@ every product, transform and operator in long double, bordered solves
 refined to long-double accuracy).  The file holds the long-double state
 (rounded to binary64) on the sampled rows, the maxima of the full fields,
 and the FP64 oracle's error against it, over the full fields and over the
-sampled entries, also per sampled row.  For the small cases the file
-also holds the error of a second binary64 implementation of the same step
-(the oracle with band LUs without row interchanges, pivot=False): the
-spread between two correct FP64 implementations.  The GPU parity tests
-(tests/refcheck.py) hold the HIP path to the same reference.
+sampled entries, also per sampled row, and the same errors of a second
+binary64 implementation of the step (the oracle with band LUs without row
+interchanges, pivot=False).  The GPU parity tests (tests/refcheck.py) hold
+the HIP path to the same reference.
 
 The 12288 x 4097 case (mixed precision on the GPU only) stores the FP64
 oracle's state as its reference: its rounding is far below the FP32
@@ -19,6 +18,8 @@ transforms' that case measures.
 
 Calls only the oracle and the seeded input generators.  Usage:
     python tests/golden/make_reference.py [case ...]     (default: all)
+    python tests/golden/make_reference.py --add-variant case ...
+(the second form adds the unpivoted run's errors to existing files).
 """
 import json
 import os
@@ -46,7 +47,7 @@ def _cases():
     c = {}
     for scheme, n in SMALL_RUNS:
         c[f"small_{scheme}_{n}"] = dict(w="SMALL", scheme=scheme, steps=n,
-                                        rows=None, stride=1, variant=True)
+                                        rows=None, stride=1)
     for n in (2, 20, 500):
         c[f"medium_bpr353_{n}"] = dict(w="MEDIUM", scheme="bpr353", steps=n,
                                        rows=MED_ROWS, stride=1)
@@ -59,7 +60,7 @@ def _cases():
                             rows=(0, 1, 20, 2048, 4096), stride=8, fp64_ref=True)
     # member 7 of the seeded 64-run ensemble (192 x 65, Ra = 4.02 Ra_c)
     c["ensemble7_cnab2_10"] = dict(w="ensemble:7", scheme="cnab2", steps=10,
-                                   rows=None, stride=1, variant=True)
+                                   rows=None, stride=1)
     return c
 
 
@@ -91,11 +92,6 @@ def make(name):
               f"in {time.time() - t0:.0f} s", flush=True)
     ref = runs[kinds[-1]]
     orc = runs[np.float64]
-    var = None
-    if spec.get("variant"):
-        var = QGOracle(w.E, w.Ra, w.Pr, w.eta, w.n_phi, w.n_r, w.n_c, pivot=False)
-        var.set_state(st.psi, st.theta, st.uphi0)
-        var.step(w.dt, spec["scheme"], spec["steps"])
     rows, stride = spec["rows"], spec["stride"]
     fields = ("psi", "theta", "uphi")
     out = dict(case=name, workload=w.name, n_phi=w.n_phi, n_r=w.n_r,
@@ -113,9 +109,6 @@ def make(name):
     out["oracle_err"] = {}
     out["oracle_err_sampled"] = {}
     out["oracle_row_err"] = {}
-    if var is not None:
-        out["variant_err_sampled"] = {}
-        out["variant_row_err"] = {}
     for f in fields:
         R = getattr(ref, f)
         X = getattr(orc, f)
@@ -126,9 +119,6 @@ def make(name):
             out["oracle_err"][f] = float(d.max() / scale) if scale else 0.0
             out["oracle_err_sampled"][f] = (float(d[::stride].max() / scale)
                                             if scale else 0.0)
-            if var is not None:
-                dv = np.abs(getattr(var, f) - R)[::stride]
-                out["variant_err_sampled"][f] = float(dv.max() / scale) if scale else 0.0
             continue
         Rs, Xs = _sample(R, rows, stride), _sample(X, rows, stride)
         mlist = list(rows) if rows is not None else list(range(R.shape[0]))
@@ -138,21 +128,65 @@ def make(name):
                                         if scale else 0.0)
         out["oracle_row_err"][f] = {
             str(m): float(np.abs(Xs[i] - Rs[i]).max()) for i, m in enumerate(mlist)}
-        if var is not None:
-            Vs = _sample(getattr(var, f), rows, stride)
-            out["variant_err_sampled"][f] = (float(np.abs(Vs - Rs).max() / scale)
-                                             if scale else 0.0)
-            out["variant_row_err"][f] = {
-                str(m): float(np.abs(Vs[i] - Rs[i]).max()) for i, m in enumerate(mlist)}
+    if not spec.get("fp64_ref"):
+        _variant(name, w, st, spec, out)
+    _write(name, out)
+
+
+def _write(name, out):
     os.makedirs(OUT, exist_ok=True)
     path = os.path.join(OUT, f"{name}.json")
-    with open(path, "w") as fh:
+    with open(path + ".tmp", "w") as fh:
         json.dump(out, fh, separators=(",", ":"))
+    os.replace(path + ".tmp", path)
     print(f"[{name}] wrote {path} ({os.path.getsize(path)} bytes); FP64 oracle "
-          f"error {out['oracle_err']}; unpivoted {out.get('variant_err_sampled')}",
-          flush=True)
+          f"error {out['oracle_err_sampled']}; unpivoted "
+          f"{out.get('variant_err_sampled')}", flush=True)
+
+
+def _variant(name, w, st, spec, out):
+    """The second FP64 implementation (band LUs without row interchanges)
+    against the stored reference entries."""
+    t0 = time.time()
+    v = QGOracle(w.E, w.Ra, w.Pr, w.eta, w.n_phi, w.n_r, w.n_c, pivot=False)
+    v.set_state(st.psi, st.theta, st.uphi0)
+    v.step(w.dt, spec["scheme"], spec["steps"])
+    print(f"[{name}] unpivoted float64: {spec['steps']} {spec['scheme']} steps "
+          f"in {time.time() - t0:.0f} s", flush=True)
+    stride = out["stride"]
+    out["variant_err_sampled"], out["variant_row_err"] = {}, {}
+    for f in ("psi", "theta", "uphi"):
+        scale = out["max_abs"][f]
+        a = np.asarray(getattr(v, f))
+        if f == "uphi":
+            d = np.abs(a[::stride] - np.array(out["ref"][f]))
+            out["variant_err_sampled"][f] = float(d.max() / scale) if scale else 0.0
+            continue
+        rows = {}
+        for m, r in out["ref"][f].items():
+            r = np.array([complex(x, y) for x, y in r])
+            rows[m] = float(np.abs(a[int(m), ::stride] - r).max())
+        out["variant_row_err"][f] = rows
+        out["variant_err_sampled"][f] = (max(rows.values()) / scale) if scale else 0.0
+
+
+def add_variant(name):
+    """Adds the unpivoted FP64 run's errors to an existing reference file."""
+    spec = CASES[name]
+    with open(os.path.join(OUT, f"{name}.json")) as fh:
+        out = json.load(fh)
+    w = (inputs.ensemble_workloads()[int(spec["w"].split(":")[1])]
+         if spec["w"].startswith("ensemble:") else getattr(inputs, spec["w"]))
+    assert out["workload"] == w.name and out["steps"] == spec["steps"]
+    _variant(name, w, inputs.workload_state(w), spec, out)
+    _write(name, out)
 
 
 if __name__ == "__main__":
-    for name in (sys.argv[1:] or list(CASES)):
-        make(name)
+    args = sys.argv[1:]
+    if args and args[0] == "--add-variant":
+        for name in args[1:]:
+            add_variant(name)
+    else:
+        for name in (args or list(CASES)):
+            make(name)

@@ -2,17 +2,21 @@
 (written by tests/golden/make_reference.py from the oracle alone).
 
 For a reference case the FP64 oracle's own distance from the long-double
-state is stored, field by field and sampled row by sampled row; for the
-small cases also that of a second FP64 implementation (the oracle with band
-LUs without row interchanges).  Let e_f be the larger of the two.  A GPU
-state passes when, on the same sampled entries,
+state is stored, field by field and sampled row by sampled row, and that
+of a second FP64 implementation (the oracle with band LUs without row
+interchanges).  Let e_f be the smaller of the two: the error plain FP64
+reaches.  A GPU state passes when, on the same sampled entries,
 
     max |gpu - ref| / max |ref|   <= 2 e_f + 1e-13             per field
                                      (zonal flow: 2 e_f + 1e-12)
     max_row |gpu - ref|           <= 2 e_f,row + 1e-12 max |ref|   per row,
 
-i.e. the HIP path rounds no worse than a plain FP64 implementation of the
-same algorithm, measured where FP64 itself is exact to the digits shown.
+i.e. the HIP path rounds no worse than the better of two plain FP64
+implementations of the same algorithm, measured where FP64 itself is exact
+to the digits shown.  (At 3072 x 1025 and above the two differ by 40x:
+partial pivoting picks pivots across rows of very different scale in these
+integration-operator bands, and LAPACK's solves lose 5e-9 where the
+unpivoted LU loses 1.5e-10.)
 
 The zonal flow's floor: in the small workloads the mean flow is a tiny
 field (about 1e-3 of Psi) driven by a Reynolds stress, mean(u_s omega),
@@ -78,15 +82,16 @@ ROW_FLOOR = 1e-12
 
 
 def fp64_spread(ref):
-    """Per field (and per row): the larger of the two FP64 implementations'
-    errors against the reference."""
+    """Per field (and per row): the smaller of the two FP64
+    implementations' errors against the reference (the oracle's alone
+    where the second is not stored)."""
     var = ref.get("variant_err_sampled")
-    field = {f: max(ref["oracle_err_sampled"][f], var[f] if var else 0.0)
-             for f in FIELDS}
+    field = {f: min(ref["oracle_err_sampled"][f], var[f]) if var else
+             ref["oracle_err_sampled"][f] for f in FIELDS}
     rows = {}
     for f, per in ref.get("oracle_row_err", {}).items():
-        vr = ref.get("variant_row_err", {}).get(f, {})
-        rows[f] = {m: max(v, vr.get(m, 0.0)) for m, v in per.items()}
+        vr = ref.get("variant_row_err", {}).get(f)
+        rows[f] = {m: min(v, vr[m]) if vr else v for m, v in per.items()}
     return field, rows
 
 
