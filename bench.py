@@ -233,6 +233,132 @@ def tangent_run(qg, torch, inputs, args):
             "perturbation": "random initial-temperature coefficients, seed 500"}
 
 
+def _median(v):
+    v = sorted(v)
+    n = len(v)
+    return v[n // 2] if n % 2 else 0.5 * (v[n // 2 - 1] + v[n // 2])
+
+
+def _timed(torch, stream, fn):
+    """Milliseconds of fn() between events on `stream` (fn may synchronise
+    itself; the host time it spends between launches counts)."""
+    torch.cuda.synchronize()
+    a = torch.cuda.Event(enable_timing=True)
+    b = torch.cuda.Event(enable_timing=True)
+    a.record(stream)
+    fn()
+    b.record(stream)
+    torch.cuda.synchronize()
+    return a.elapsed_time(b)
+
+
+def adjoint_run(qg, torch, inputs, args, repeats=5):
+    """The adjoint workload (768 x 257, E = 1e-6, Ra = 5 Ra_c, CNAB2, 200
+    steps): the forward run against the gradient of the time-integrated
+    kinetic energy with respect to the initial state (qg_gradient:
+    forward pass with a checkpoint every 20 steps, then recomputation and
+    the reverse sweep), median of `repeats` runs each."""
+    w = inputs.ADJOINT
+    st = inputs.workload_state(w)
+    s = qg.QGSolver(w.E, w.Ra, w.Pr, w.eta, w.n_phi, w.n_r, w.n_c,
+                    device="cuda:0")
+    s.set_state(st.psi, st.theta, st.uphi0)
+    s.gradient(w.dt, 20, 20)                  # factorisation, first launches
+    fwd, grad = [], []
+    for _ in range(repeats):
+        s.set_state(st.psi, st.theta, st.uphi0)
+        fwd.append(_timed(torch, s.stream, lambda: s.step(w.dt, "cnab2", w.steps)))
+        s.set_state(st.psi, st.theta, st.uphi0)
+        grad.append(_timed(torch, s.stream, lambda: s.gradient(w.dt, w.steps, 20)))
+    return {"workload": w.name, "steps": w.steps, "checkpoint_interval": 20,
+            "ms_forward": _median(fwd), "ms_gradient": _median(grad),
+            "adjoint_vs_forward": _median(grad) / _median(fwd),
+            "repeats": repeats, "ms_forward_all": fwd, "ms_gradient_all": grad,
+            "gradient": "J = dt sum w_n E_K(y^n) and dJ/dy^0, forward pass "
+                        "included"}
+
+
+def config_lines(qg, torch, inputs, args, repeats=5):
+    """GPU throughput of the 96 x 33 CNAB2 workload (100 steps) and of the
+    768 x 257 BPR353 workload (500 steps), median of `repeats` runs."""
+    out = {}
+    for w in (inputs.SMALL, inputs.MEDIUM):
+        st = inputs.workload_state(w)
+        s = qg.QGSolver(w.E, w.Ra, w.Pr, w.eta, w.n_phi, w.n_r, w.n_c,
+                        device="cuda:0")
+        s.set_state(st.psi, st.theta, st.uphi0)
+        s.step(w.dt, w.scheme, 2)            # factorisation, first launches
+        ms = []
+        for _ in range(repeats):
+            s.set_state(st.psi, st.theta, st.uphi0)
+            ms.append(_timed(torch, s.stream, lambda: s.step(w.dt, w.scheme, w.steps)))
+        med = _median(ms)
+        out[w.name] = {"steps": w.steps, "scheme": w.scheme, "ms_total": med,
+                       "ms_per_step": med / w.steps,
+                       "grid_point_steps_per_s": w.grid_points * w.steps / (med * 1e-3),
+                       "repeats_ms": ms}
+    return out
+
+
+def cpu_model():
+    try:
+        import subprocess
+        txt = subprocess.run(["lscpu"], capture_output=True, text=True,
+                             timeout=10).stdout
+        for line in txt.splitlines():
+            if line.startswith("Model name"):
+                return line.split(":", 1)[1].strip()
+    except Exception:
+        pass
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_legs(inputs):
+    """The oracle on the host cores for the other configurations: 96 x 33
+    CNAB2 (100 steps), 768 x 257 BPR353 with the integration method and
+    the collocation cross-check (one step each), 768 x 257 CNAB2 forward of
+    the adjoint workload (two steps).  Init untimed."""
+    from oracle import transforms as tr
+    from oracle.collocation import CollocationCNAB2
+    from oracle.step import QGOracle
+    legs = {}
+
+    def leg(name, w, scheme, steps, colloc=False):
+        st = inputs.workload_state(w)
+        if colloc:
+            o = CollocationCNAB2(w.E, w.Ra, w.Pr, w.eta, w.n_phi, w.n_r)
+            grid = [tr.cheb_to_grid(a, w.n_r) for a in (st.psi, st.theta, st.uphi0)]
+            load = lambda: o.set_state(*grid)
+            run = lambda n: [o.step(w.dt) for _ in range(n)]
+        else:
+            o = QGOracle(w.E, w.Ra, w.Pr, w.eta, w.n_phi, w.n_r, w.n_c)
+            load = lambda: o.set_state(st.psi, st.theta, st.uphi0)
+            run = lambda n: o.step(w.dt, scheme, n)
+        load()
+        run(1)                               # factorisation untimed
+        load()
+        t0 = time.perf_counter()
+        run(steps)
+        dt = time.perf_counter() - t0
+        legs[name] = {"value": w.grid_points * steps / dt,
+                      "unit": "grid-point-steps/s", "steps": steps,
+                      "scheme": scheme, "seconds": dt}
+
+    leg(inputs.SMALL.name, inputs.SMALL, "cnab2", 100)
+    leg(inputs.MEDIUM.name, inputs.MEDIUM, "bpr353", 1)
+    leg(inputs.MEDIUM.name + "_collocation", inputs.MEDIUM, "cnab2", 1,
+        colloc=True)
+    leg(inputs.ADJOINT.name, inputs.ADJOINT, "cnab2", 2)
+    return legs
+
+
 def ensemble_run(qg, torch, inputs, args):
     """The batched ensemble: 64 runs of uneven size and Ra stepped together
     (one launch per kernel and size group, graph replay), against the same
@@ -407,12 +533,21 @@ def main():
     if not args.no_schemes and prec == 0:
         out["tangent_linear"] = tangent_run(qg, torch, inputs, args)
         print("[bench] tangent done", file=sys.stderr, flush=True)
+    if not args.no_schemes and prec == 0:
+        out["adjoint"] = adjoint_run(qg, torch, inputs, args)
+        print(f"[bench] adjoint done: {out['adjoint']['adjoint_vs_forward']:.2f} "
+              "x forward", file=sys.stderr, flush=True)
+        out["configs"] = config_lines(qg, torch, inputs, args)
+        print("[bench] config lines done", file=sys.stderr, flush=True)
     if not args.no_ensemble and prec == 0:
         out["batched"] = ensemble_run(qg, torch, inputs, args)
         print(f"[bench] ensemble done: {out['batched']['ms_per_step']:.4f} "
               "ms/step", file=sys.stderr, flush=True)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(w, state, args.cpu_steps)
+        out["cpu_baseline"]["model"] = cpu_model()
+        if not args.no_schemes:
+            out["cpu_baseline"]["other_configs"] = cpu_legs(inputs)
     print(json.dumps(out), flush=True)
 
 

@@ -291,7 +291,10 @@ qg_status qg_adjoint_mass_lin(qg_ctx *ctx, double c, double *psi,
  * co-state of each complex entry z is dJ/dRe z + i dJ/dIm z, so that for a
  * perturbation d of y^0, dJ = sum Re(conj(grad) d).  The reverse sweep
  * keeps the forward state and E^{n-1} at every interval-th step and
- * recomputes each block of `interval` steps before its reverse steps.
+ * recomputes each block of `interval` steps (but the last) from it; the
+ * recomputation of the next block runs on a second stream of the same
+ * device, created and destroyed by the call, while the current block is
+ * swept backwards on the context's stream.
  * All arrays are device memory in the state layout of qg_set_state (psi
  * [M][K] complex with its row 0 unused, theta [M][K] complex, uphi [K]).
  * work: device memory of at least qg_gradient_workspace_size bytes,

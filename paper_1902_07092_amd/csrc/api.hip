@@ -36,10 +36,20 @@ int solve_batch();
 bool launch_solve_np(const Geom& g, const FactorSet<double2>& Fp, const FactorSet<double>& Fr,
                      double2* rhs, const RhsSpec& rs, int qp, int qr, hipStream_t st);
 int solve_np_pad();
-bool launch_explicit_T(const Geom& g, const Bands& b, const double2* X, const double2* Ebp,
-                       const double2* Ebt, double kappa, double2* NLb, double* zb,
-                       double2* thb0, double2* Xb, double2* psib, double2* thb, hipStream_t st);
-void launch_energy_accum(const double* diag, int M, double w, double* J, hipStream_t st);
+bool launch_explicit_T(const Geom& g, const Bands& b, const double2* X, const double* G,
+                       const double2* Ea, const double2* Eb, double ca, double cb, size_t mk,
+                       double kappa, double2* NLb, double* zb, double2* thb0, double2* Xb,
+                       const double2* add, const double2* mu, double cmu, double2* ml,
+                       double2* psib, double2* thb, hipStream_t st);
+void launch_energy_total(const double* diag, int M, int N, double c, double* J,
+                         hipStream_t st);
+void launch_transpose_factors(const FactorSet<double2>& Fp, const FactorSet<double>& Fr, int Sp,
+                              int Sr, int n4, int n2, int qp, int qr, double2* pLT, double2* pUT,
+                              double2* puiT, double* rLT, double* rUT, double* ruiT,
+                              hipStream_t st);
+bool launch_solve_adjoint_np(const Geom& g, const FactorSet<double2>& FpT,
+                             const FactorSet<double>& FrT, int qp, int qr, double2* f_psi,
+                             double2* f_th, double2* y_psi, double2* y_th, hipStream_t st);
 void launch_to_internal(int M, int K, const double2* psi, const double2* th, const double* u,
                         double2* dp, double2* dt, hipStream_t st);
 void launch_to_api(int M, int K, const double2* sp, const double2* sth, double2* psi,
@@ -584,29 +594,35 @@ void timed(qg_ctx* ctx, int cls, F launch) {
 
 // E(y) into (Ep, Et); diag (optional): the synthesis's per-m diagnostics
 // of y (kinetic energy and the rest, see synth_kernel).
+// X: where the synthesis writes the fields (default: the workspace's); G:
+// the ring's grid fields out (reverse mode, optional); NL, zonal: the
+// exchange arrays (default: the workspace's).
 qg_status explicit_terms(qg_ctx* ctx, const double2* psi, const double2* th, double2* Ep,
-                         double2* Et, double* diag = nullptr) {
+                         double2* Et, double* diag = nullptr, double2* X = nullptr,
+                         double* G = nullptr, double2* NL = nullptr, double* zonal = nullptr) {
   bool ok = true;
+  if (!X) X = ctx->ptr2(ctx->w.X);
+  if (!NL) NL = ctx->ptr2(ctx->w.NL);
+  if (!zonal) zonal = ctx->ptrd(ctx->w.zonal);
   timed(ctx, K_SYNTH, [&] {
-    ok = launch_synth(ctx->g, psi, th, ctx->ptr2(ctx->w.X), diag, ctx->mixed, ctx->st) && ok;
+    ok = launch_synth(ctx->g, psi, th, X, diag, ctx->mixed, ctx->st) && ok;
   });
   timed(ctx, K_RING, [&] {
-    ok = launch_ring(ctx->g, ctx->ptr2(ctx->w.X), ctx->ptr2(ctx->w.NL), ctx->ptrd(ctx->w.zonal),
-                     nullptr, ctx->mixed, ctx->st) && ok;
+    ok = launch_ring(ctx->g, X, NL, zonal, nullptr, ctx->mixed, ctx->st, G) && ok;
   });
   timed(ctx, K_ANALYSIS, [&] {
-    ok = launch_analysis(ctx->g, ctx->b, ctx->ptr2(ctx->w.NL), ctx->ptrd(ctx->w.zonal), th, Ep,
-                         Et, ctx->mixed, ctx->st) && ok;
+    ok = launch_analysis(ctx->g, ctx->b, NL, zonal, th, Ep, Et, ctx->mixed, ctx->st) && ok;
   });
   if (!ok) return fail(ctx, QG_EUNSUPPORTED, "no transform kernel for these sizes");
   HIPCHK(hipGetLastError());
   return QG_OK;
 }
 
-qg_status implicit_solve(qg_ctx* ctx, const RhsSpec& rs_in) {
+// rhs: the right-hand side buffer (default: the workspace's).
+qg_status implicit_solve(qg_ctx* ctx, const RhsSpec& rs_in, double2* rhs = nullptr) {
   RhsSpec rs = rs_in;
   rs.tag = ctx->tag;
-  double2* rhs = ctx->ptr2(ctx->w.rhs);
+  if (!rhs) rhs = ctx->ptr2(ctx->w.rhs);
   timed(ctx, K_RHS, [&] { launch_rhs(ctx->g, ctx->b, rs, rhs, ctx->band_mch, ctx->st); });
   bool ok = true;
   timed(ctx, K_SOLVE, [&] {
@@ -1619,31 +1635,56 @@ qg_status qg_step_timed(qg_ctx* ctx, double dt, int scheme, int nsteps, double* 
 //              + E'(y^n)^H (c_n dt rb^n - (1/2) dt rb^{n+1}),
 // kappa_n = w_E dt w_n (trapezoid weights w_n, 1/2 at both ends), and
 // ybar^N adds the caller's terminal co-state.  The forward trajectory is
-// kept at every `interval`-th step (state and E^{n-1}); each block is
-// recomputed from its checkpoint before its reverse steps.
+// kept at every `interval`-th step (state and E^{n-1}); each block but the
+// last is recomputed from its checkpoint before its reverse steps, and the
+// synthesised fields X of a block's states are kept for the transposed
+// explicit terms.
 namespace {
 
 struct GradMap {
-  size_t ck, blk, E2, Xb, thb0, rb, acc, eb, ml, ex, J, total;
+  size_t ck, blk, Xs, Gs, E2, NL2, zonal2, rhs2, Xb, thb0, ml, rb, acc, adj, tmp, diag, J;
+  size_t pLT, pUT, puiT, rLT, rUT, ruiT;   // factors of D^H (transposed solves)
+  size_t total;
 };
+
+int grad_slots(int nsteps, int interval) {   // states (and X fields) kept per block
+  return std::max(3, std::min(interval, std::max(nsteps, 0)) + 1);
+}
 
 GradMap map_gradient(const qg_ctx* c, int nsteps, int interval) {
   Layout L;
   GradMap w;
   const size_t S = 2 * c->mk() * sizeof(double2);   // a (Psi and u, theta) pair
+  const size_t XS = (size_t)6 * c->z.R * c->z.M * sizeof(double2);
   const int nblk = nsteps > 0 ? (nsteps + interval - 1) / interval : 0;
-  const int per = std::max(1, std::min(interval, nsteps));
+  const int slots = grad_slots(nsteps, interval);
+  // two sets of block storage: one block is swept backwards while the
+  // next one is recomputed on a second stream
   w.ck = L.take((size_t)nblk * 2 * S);    // y^{n0} and E^{n0-1} of each block
-  w.blk = L.take((size_t)(per + 1) * S);  // the states of one block
+  w.blk = L.take((size_t)2 * slots * S);  // the states of a block
+  w.Xs = L.take((size_t)2 * slots * XS);  // their synthesised fields
+  w.Gs = L.take((size_t)2 * slots * 6 * c->z.R * c->z.nphi * sizeof(double));   // grid fields
   w.E2 = L.take(2 * S);                   // explicit terms of the recomputation
-  w.Xb = L.take((size_t)6 * c->z.R * c->z.M * sizeof(double2));
+  w.NL2 = L.take((size_t)2 * c->z.R * c->z.M * sizeof(double2));   // its exchange arrays
+  w.zonal2 = L.take((size_t)c->z.R * sizeof(double));
+  w.rhs2 = L.take(S);
+  w.Xb = L.take(XS);
   w.thb0 = L.take(c->mk() * sizeof(double2));
+  w.ml = L.take(S);
   w.rb = L.take(2 * S);
   w.acc = L.take(S);
-  w.eb = L.take(S);
-  w.ml = L.take(S);
-  w.ex = L.take(S);
+  w.adj = L.take(S);
+  w.tmp = L.take(S);
+  w.diag = L.take((size_t)(std::max(nsteps, 0) + 1) * c->z.M * 8 * sizeof(double));
   w.J = L.take(sizeof(double));
+  const Sizes& z = c->z;
+  const size_t Sp = z.M - 1, Sr = z.Sr;
+  w.pLT = L.take(Sp * z.q4 * 8 * sizeof(double2));
+  w.pUT = L.take(Sp * z.q4 * 8 * sizeof(double2));
+  w.puiT = L.take(Sp * z.q4 * sizeof(double2));
+  w.rLT = L.take(Sr * z.q2 * 4 * sizeof(double));
+  w.rUT = L.take(Sr * z.q2 * 4 * sizeof(double));
+  w.ruiT = L.take(Sr * z.q2 * sizeof(double));
   w.total = L.total;
   return w;
 }
@@ -1667,10 +1708,17 @@ qg_status reverse_ok(qg_ctx* ctx) {
 }
 
 // One CNAB2 step y -> out with E(y) into En and E^{n-1} in Ep (nullptr:
-// E^{-1} := E^n); diag: the synthesis's diagnostics of y.
+// E^{-1} := E^n); diag: the synthesis's diagnostics of y; X, G: where the
+// fields of y go (nullptr: the workspace; no grid fields).
+struct Scratch {   // exchange arrays and right-hand side of a step (null: the workspace's)
+  double2* NL = nullptr;
+  double* zonal = nullptr;
+  double2* rhs = nullptr;
+};
+
 qg_status cnab2_into(qg_ctx* ctx, double dt, Pair y, Pair En, const Pair* Ep, Pair out,
-                     double* diag) {
-  qg_status s = explicit_terms(ctx, y.p, y.t, En.p, En.t, diag);
+                     double* diag, double2* X, double* G, const Scratch& sc = Scratch{}) {
+  qg_status s = explicit_terms(ctx, y.p, y.t, En.p, En.t, diag, X, G, sc.NL, sc.zonal);
   if (s != QG_OK) return s;
   RhsSpec rs{};
   rs.base_psi = y.p;
@@ -1685,33 +1733,43 @@ qg_status cnab2_into(qg_ctx* ctx, double dt, Pair y, Pair En, const Pair* Ep, Pa
   rs.coef[1] = -0.5 * dt;
   rs.out_psi = out.p;
   rs.out_th = out.t;
-  return implicit_solve(ctx, rs);
+  return implicit_solve(ctx, rs, sc.rhs);
 }
 
-// (psib, thb) = E'(y)^H eb + kappa grad E_K(y); diag/J/w: also J += w E_K(y).
-qg_status explicit_T(qg_ctx* ctx, Pair y, Pair eb, double kappa, char* base, const GradMap& w,
-                     Pair out, double* J, double wJ) {
-  double* diag = J ? ctx->ptrd(ctx->w.diag) : nullptr;
-  if (!launch_synth(ctx->g, y.p, y.t, ctx->ptr2(ctx->w.X), diag, false, ctx->st))
-    return fail(ctx, QG_EUNSUPPORTED, "no transform kernel for these sizes");
-  if (J) launch_energy_accum(diag, ctx->z.M, wJ, J, ctx->st);
-  if (!launch_explicit_T(ctx->g, ctx->b, ctx->ptr2(ctx->w.X), eb.p, eb.t, kappa,
+// A second stream and the events of the overlapped reverse sweep, released
+// on every return path.
+struct SweepStreams {
+  hipStream_t st2 = nullptr;
+  std::vector<hipEvent_t> ev;
+  ~SweepStreams() {
+    if (st2) {
+      (void)hipStreamSynchronize(st2);
+      (void)hipStreamDestroy(st2);
+    }
+    for (hipEvent_t e : ev) (void)hipEventDestroy(e);
+  }
+  hipEvent_t event() {
+    hipEvent_t e = nullptr;
+    if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) return nullptr;
+    ev.push_back(e);
+    return e;
+  }
+};
+
+// out = E'(y)^H (ca Ea + cb Eb) + kappa grad E_K(y) + add
+//       + (Mass + cmu Lin)^H mu, with X the synthesised fields of y (pairs
+// may be null: zero).
+qg_status explicit_T(qg_ctx* ctx, const double2* X, const double* G, const double2* Ea,
+                     const double2* Eb, double ca, double cb, double kappa, const double2* add,
+                     const double2* mu, double cmu, char* base, const GradMap& w, Pair out) {
+  if (!launch_explicit_T(ctx->g, ctx->b, X, G, Ea, Eb, ca, cb, ctx->mk(), kappa,
                          ctx->ptr2(ctx->w.NL), ctx->ptrd(ctx->w.zonal),
                          reinterpret_cast<double2*>(base + w.thb0),
-                         reinterpret_cast<double2*>(base + w.Xb), out.p, out.t, ctx->st))
+                         reinterpret_cast<double2*>(base + w.Xb), add, mu, cmu,
+                         reinterpret_cast<double2*>(base + w.ml), out.p, out.t, ctx->st))
     return fail(ctx, QG_EUNSUPPORTED, "no reverse transform kernel for these sizes");
   HIPCHK(hipGetLastError());
   return QG_OK;
-}
-
-void combine2(qg_ctx* ctx, Pair out, int nb, const Pair* in, const double* c) {
-  Combine cb{};
-  cb.nb = nb;
-  for (int i = 0; i < nb; ++i) {
-    cb.in[i] = in[i].p;
-    cb.c[i] = c[i];
-  }
-  launch_combine(cb, out.p, 2 * ctx->mk(), nullptr, ctx->st);
 }
 
 qg_status gradient_run(qg_ctx* ctx, double dt, int N, int C, double ew, const double* adj_psi,
@@ -1724,33 +1782,52 @@ qg_status gradient_run(qg_ctx* ctx, double dt, int N, int C, double ew, const do
   if (s != QG_OK) return s;
   if (grad && ctx->pivoted)
     return fail(ctx, QG_EUNSUPPORTED, "the adjoint solves use the unpivoted factors");
+  const size_t XS = (size_t)6 * ctx->z.R * M;   // entries of one X
+  const size_t GS = (size_t)6 * ctx->z.R * ctx->z.nphi;
+  const int slots = grad_slots(N, C);
+  // slot `slot` of storage set `set` (states, fields, grid fields)
+  auto Yb = [&](int set, int slot) { return pair_at(base, w.blk, (size_t)(set * slots + slot), mk); };
+  auto Xsb = [&](int set, int slot) {
+    return reinterpret_cast<double2*>(base + w.Xs) + (size_t)(set * slots + slot) * XS;
+  };
+  auto Gsb = [&](int set, int slot) {
+    return reinterpret_cast<double*>(base + w.Gs) + (size_t)(set * slots + slot) * GS;
+  };
+  auto Y = [&](int slot) { return Yb(0, slot); };
+  auto Xs = [&](int slot) { return Xsb(0, slot); };
+  auto Gs = [&](int slot) { return Gsb(0, slot); };
+  std::vector<char> has_g[2] = {std::vector<char>(slots, 0), std::vector<char>(slots, 0)};
+  auto ck = [&](int b, int a) { return pair_at(base, w.ck, 2 * (size_t)b + a, mk); };
+  double* diag = reinterpret_cast<double*>(base + w.diag);
   double* Jd = reinterpret_cast<double*>(base + w.J);
-  double* diag = ctx->ptrd(ctx->w.diag);
-  HIPCHK(hipMemsetAsync(Jd, 0, sizeof(double), ctx->st));
   HIPCHK(hipMemsetAsync(ctx->nf_flag(), 0, sizeof(int), ctx->st));
-  auto wt = [&](int n) { return (n == 0 || n == N) ? 0.5 : 1.0; };
-  // ---- forward pass: checkpoints, J, the final state and history
+  const int nblk = N > 0 ? (N + C - 1) / C : 0;
+  const int nl = nblk > 0 ? (nblk - 1) * C : 0;   // first step of the last block
+  // ---- forward pass: a checkpoint per block; the last block keeps its
+  // states and fields; E_K of every state for J
   Pair E2[2] = {pair_at(base, w.E2, 0, mk), pair_at(base, w.E2, 1, mk)};
-  Pair Y[2] = {pair_at(base, w.blk, 0, mk), pair_at(base, w.blk, 1, mk)};
-  launch_copy(ctx->psi(), Y[0].p, 2 * mk, nullptr, ctx->st);
+  // slot of y^n in the forward pass: the last block keeps y^nl .. y^N in
+  // slots 0 .. N - nl; before it the states take slots 1 and 2 in turn
+  auto slot_of = [&](int n) { return n >= nl ? n - nl : 1 + n % 2; };
+  launch_copy(ctx->psi(), Y(slot_of(0)).p, 2 * mk, nullptr, ctx->st);
   for (int n = 0; n < N; ++n) {
-    Pair y = Y[n % 2], En = E2[n % 2], Ep = E2[(n + 1) % 2];
+    Pair y = Y(slot_of(n)), En = E2[n % 2], Ep = E2[(n + 1) % 2];
     if (n % C == 0) {
-      Pair ck = pair_at(base, w.ck, 2 * (size_t)(n / C), mk);
-      launch_copy(y.p, ck.p, 2 * mk, nullptr, ctx->st);
-      if (n > 0) launch_copy(Ep.p, pair_at(base, w.ck, 2 * (size_t)(n / C) + 1, mk).p, 2 * mk,
-                             nullptr, ctx->st);
+      launch_copy(y.p, ck(n / C, 0).p, 2 * mk, nullptr, ctx->st);
+      if (n > 0) launch_copy(Ep.p, ck(n / C, 1).p, 2 * mk, nullptr, ctx->st);
     }
     ctx->tag = n + 1;
-    s = cnab2_into(ctx, dt, y, En, n > 0 ? &Ep : nullptr, Y[(n + 1) % 2], diag);
+    s = cnab2_into(ctx, dt, y, En, n > 0 ? &Ep : nullptr, Y(slot_of(n + 1)),
+                   diag + (size_t)n * M * 8, n >= nl ? Xs(n - nl) : nullptr,
+                   n >= nl ? Gs(n - nl) : nullptr);
     if (s != QG_OK) return s;
-    launch_energy_accum(diag, M, ew * dt * wt(n), Jd, ctx->st);
+    if (n >= nl) has_g[0][n - nl] = 1;
   }
   {
-    Pair yN = Y[N % 2];
-    if (!launch_synth(ctx->g, yN.p, yN.t, ctx->ptr2(ctx->w.X), diag, false, ctx->st))
+    Pair yN = Y(slot_of(N));
+    if (!launch_synth(ctx->g, yN.p, yN.t, Xs(N - nl), diag + (size_t)N * M * 8, false, ctx->st))
       return fail(ctx, QG_EUNSUPPORTED, "no transform kernel for these sizes");
-    launch_energy_accum(diag, M, ew * dt * wt(N), Jd, ctx->st);
+    launch_energy_total(diag, M, N, ew * dt, Jd, ctx->st);
   }
   HIPCHK(hipGetLastError());
   int flag = 0;
@@ -1766,7 +1843,7 @@ qg_status gradient_run(qg_ctx* ctx, double dt, int N, int C, double ew, const do
   // the context continues from y^N with its CNAB2 history, as after
   // qg_step(dt, CNAB2, N) from a fresh history
   if (N > 0) {
-    launch_copy(Y[N % 2].p, ctx->psi(), 2 * mk, nullptr, ctx->st);
+    launch_copy(Y(slot_of(N)).p, ctx->psi(), 2 * mk, nullptr, ctx->st);
     ctx->last_scheme = QG_CNAB2;
     ctx->last_dt = dt;
     ctx->cur = 0;
@@ -1783,66 +1860,120 @@ qg_status gradient_run(qg_ctx* ctx, double dt, int N, int C, double ew, const do
   }
   // ---- reverse pass
   Pair rb[2] = {pair_at(base, w.rb, 0, mk), pair_at(base, w.rb, 1, mk)};
-  Pair acc = pair_at(base, w.acc, 0, mk), eb = pair_at(base, w.eb, 0, mk);
-  Pair ml = pair_at(base, w.ml, 0, mk), ex = pair_at(base, w.ex, 0, mk);
+  Pair acc = pair_at(base, w.acc, 0, mk), adj = pair_at(base, w.adj, 0, mk);
+  Pair tmp = pair_at(base, w.tmp, 0, mk);
+  FactorSet<double2> FpT = ctx->Fp;
+  FactorSet<double> FrT = ctx->Fr;
+  double2* pLT = reinterpret_cast<double2*>(base + w.pLT);
+  double2* pUT = reinterpret_cast<double2*>(base + w.pUT);
+  double2* puiT = reinterpret_cast<double2*>(base + w.puiT);
+  double* rLT = reinterpret_cast<double*>(base + w.rLT);
+  double* rUT = reinterpret_cast<double*>(base + w.rUT);
+  double* ruiT = reinterpret_cast<double*>(base + w.ruiT);
+  FpT.L = pLT; FpT.U = pUT; FpT.ui = puiT;
+  FrT.L = rLT; FrT.U = rUT; FrT.ui = ruiT;
+  launch_transpose_factors(ctx->Fp, ctx->Fr, M - 1, ctx->z.Sr, K - 4, K - 2, ctx->z.q4,
+                           ctx->z.q2, pLT, pUT, puiT, rLT, rUT, ruiT, ctx->st);
   int cur = 0;   // rb[cur] = rb^n, rb[1 - cur] = rb^{n+1}
-  const int nblk = N > 0 ? (N + C - 1) / C : 0;
-  Pair adj{nullptr, nullptr};
-  if (adj_psi || adj_th || adj_u) {
-    adj = ml;   // the terminal co-state, consumed at n = N before ml is used
+  const bool has_adj = adj_psi || adj_th || adj_u;
+  if (has_adj)   // the terminal co-state, added at n = N
     launch_to_internal(M, K, reinterpret_cast<const double2*>(adj_psi),
                        reinterpret_cast<const double2*>(adj_th), adj_u, adj.p, adj.t, ctx->st);
-  }
-  auto reverse_step = [&](int n, Pair y) -> qg_status {
-    const double kappa = ew * dt * wt(n);
+  auto reverse_step = [&](int n, const double2* X, const double* G) -> qg_status {
+    const double kappa = ew * dt * ((n == 0 || n == N) ? 0.5 : 1.0);
+    Pair out = (n > 0) ? tmp : acc;
+    qg_status st;
     if (n < N) {
-      const double cn = (n == 0) ? 1.0 : 1.5;
-      Pair in[2] = {rb[cur], rb[1 - cur]};
-      double c[2] = {cn * dt, -0.5 * dt};
-      combine2(ctx, eb, n + 1 < N ? 2 : 1, in, c);
-      launch_band_adjoint(ctx->g, ctx->b, 0.5 * dt, rb[cur].p, rb[cur].t, ml.p, ml.t, ctx->st);
+      st = explicit_T(ctx, X, G, rb[cur].p, n + 1 < N ? rb[1 - cur].p : nullptr,
+                      (n == 0 ? 1.0 : 1.5) * dt, -0.5 * dt, kappa, nullptr, rb[cur].p,
+                      0.5 * dt, base, w, out);
     } else {
-      // no step follows the last state: its E has a zero co-state
-      HIPCHK(hipMemsetAsync(eb.p, 0, 2 * mk * sizeof(double2), ctx->st));
+      st = explicit_T(ctx, X, G, nullptr, nullptr, 0.0, 0.0, kappa, has_adj ? adj.p : nullptr,
+                      nullptr, 0.0, base, w, out);
     }
-    qg_status st = explicit_T(ctx, y, eb, kappa, base, w, ex, nullptr, 0.0);
     if (st != QG_OK) return st;
-    Pair in[2] = {ex, ml};
-    double c[2] = {1.0, 1.0};
-    const bool more = (n < N) || adj.p != nullptr;
-    Pair out = (n > 0) ? rb[1 - cur] : acc;   // rb^{n+1} is no longer needed
-    combine2(ctx, out, more ? 2 : 1, in, c);
-    if (n > 0) {
-      launch_solve_adjoint(ctx->g, ctx->Fp, ctx->Fr, ctx->z.q4, ctx->z.q2, out.p, out.t,
-                           ctx->st);
+    if (n > 0) {   // rb^{n-1} over rb^{n+1}, which is no longer needed
+      if (!launch_solve_adjoint_np(ctx->g, FpT, FrT, ctx->z.q4, ctx->z.q2, tmp.p, tmp.t,
+                                   rb[1 - cur].p, rb[1 - cur].t, ctx->st))
+        return fail(ctx, QG_EUNSUPPORTED, "no transposed solve for this padding");
       cur = 1 - cur;
     }
     HIPCHK(hipGetLastError());
     return QG_OK;
   };
-  for (int b = nblk - 1; b >= 0; --b) {
-    const int n0 = b * C, n1 = std::min(N, n0 + C);
-    const bool last = (b == nblk - 1);
-    const int top = last ? N : n1 - 1;   // highest state of this block's reverse steps
-    Pair ck = pair_at(base, w.ck, 2 * (size_t)b, mk);
-    Pair ckE = pair_at(base, w.ck, 2 * (size_t)b + 1, mk);
-    launch_copy(ck.p, pair_at(base, w.blk, 0, mk).p, 2 * mk, nullptr, ctx->st);
-    if (n0 > 0) launch_copy(ckE.p, E2[1].p, 2 * mk, nullptr, ctx->st);
-    for (int n = n0; n < top; ++n) {
+  // Blocks are swept backwards from the last one (storage set 0, filled by
+  // the forward pass).  While block b is swept on the caller's stream,
+  // block b - 1 is recomputed from its checkpoint into the other set on a
+  // second stream; events order the two.
+  const int last = std::max(nblk, 1) - 1;
+  auto set_of = [&](int b) { return (last - b) & 1; };
+  SweepStreams ss;
+  if (last > 0) {
+    int dev = 0;
+    HIPCHK(hipStreamGetDevice(ctx->st, &dev));
+    int prev = 0;
+    HIPCHK(hipGetDevice(&prev));
+    HIPCHK(hipSetDevice(dev));
+    const hipError_t e = hipStreamCreateWithFlags(&ss.st2, hipStreamNonBlocking);
+    HIPCHK(hipSetDevice(prev));
+    HIPCHK(e);
+  }
+  std::vector<hipEvent_t> rec_done(std::max(nblk, 1), nullptr), rev_done(std::max(nblk, 1), nullptr);
+  hipEvent_t fwd_done = nullptr;
+  if (last > 0) {
+    fwd_done = ss.event();
+    if (!fwd_done) return fail(ctx, QG_EDEVICE, "event creation failed");
+    HIPCHK(hipEventRecord(fwd_done, ctx->st));
+  }
+  const Scratch sc2{reinterpret_cast<double2*>(base + w.NL2),
+                    reinterpret_cast<double*>(base + w.zonal2),
+                    reinterpret_cast<double2*>(base + w.rhs2)};
+  // y^{n0+1} .. y^{top} of block b and the fields of y^{n0} .. y^{top}, on st2
+  auto recompute = [&](int b) -> qg_status {
+    const int n0 = b * C, top = n0 + C - 1, set = set_of(b);
+    hipStream_t main_st = ctx->st;
+    ctx->st = ss.st2;
+    qg_status r = QG_OK;
+    launch_copy(ck(b, 0).p, Yb(set, 0).p, 2 * mk, nullptr, ctx->st);
+    if (n0 > 0) launch_copy(ck(b, 1).p, E2[1].p, 2 * mk, nullptr, ctx->st);
+    std::fill(has_g[set].begin(), has_g[set].end(), 0);
+    for (int n = n0; n < top && r == QG_OK; ++n) {
       const int j = n - n0;
       Pair Ep = E2[(j + 1) % 2];
-      s = cnab2_into(ctx, dt, pair_at(base, w.blk, j, mk), E2[j % 2], n > 0 ? &Ep : nullptr,
-                     pair_at(base, w.blk, j + 1, mk), nullptr);
-      if (s != QG_OK) return s;
+      r = cnab2_into(ctx, dt, Yb(set, j), E2[j % 2], n > 0 ? &Ep : nullptr, Yb(set, j + 1),
+                     nullptr, Xsb(set, j), Gsb(set, j), sc2);
+      has_g[set][j] = 1;
     }
+    if (r == QG_OK) {
+      Pair yt = Yb(set, top - n0);
+      if (!launch_synth(ctx->g, yt.p, yt.t, Xsb(set, top - n0), nullptr, false, ctx->st))
+        r = fail(ctx, QG_EUNSUPPORTED, "no transform kernel for these sizes");
+    }
+    ctx->st = main_st;
+    return r;
+  };
+  for (int b = last; b >= 0; --b) {
+    const int n0 = b * C, set = set_of(b);
+    const int top = (b == last) ? N : n0 + C - 1;   // highest state of this block
+    if (b > 0) {   // recompute block b - 1 into the set block b + 1 used
+      HIPCHK(hipStreamWaitEvent(ss.st2, fwd_done, 0));
+      if (b + 1 <= last) HIPCHK(hipStreamWaitEvent(ss.st2, rev_done[b + 1], 0));
+      s = recompute(b - 1);
+      if (s != QG_OK) return s;
+      rec_done[b - 1] = ss.event();
+      if (!rec_done[b - 1]) return fail(ctx, QG_EDEVICE, "event creation failed");
+      HIPCHK(hipEventRecord(rec_done[b - 1], ss.st2));
+    }
+    if (b < last) HIPCHK(hipStreamWaitEvent(ctx->st, rec_done[b], 0));
     for (int n = top; n >= n0; --n) {
-      s = reverse_step(n, pair_at(base, w.blk, n - n0, mk));
+      s = reverse_step(n, Xsb(set, n - n0), has_g[set][n - n0] ? Gsb(set, n - n0) : nullptr);
       if (s != QG_OK) return s;
     }
-  }
-  if (N == 0) {
-    s = reverse_step(0, pair_at(base, w.blk, 0, mk));
-    if (s != QG_OK) return s;
+    if (b > 1) {
+      rev_done[b] = ss.event();
+      if (!rev_done[b]) return fail(ctx, QG_EDEVICE, "event creation failed");
+      HIPCHK(hipEventRecord(rev_done[b], ctx->st));
+    }
   }
   launch_to_api(M, K, acc.p, acc.t, reinterpret_cast<double2*>(g_psi),
                 reinterpret_cast<double2*>(g_th), g_u, ctx->st);
@@ -1902,14 +2033,18 @@ qg_status qg_adjoint_explicit(qg_ctx* ctx, const double* psi, const double* thet
   char* base = static_cast<char*>(work);
   const size_t mk = ctx->mk();
   const int M = ctx->z.M, K = ctx->z.K;
-  Pair y = pair_at(base, w.blk, 0, mk), eb = pair_at(base, w.eb, 0, mk);
-  Pair out = pair_at(base, w.ex, 0, mk);
+  Pair y = pair_at(base, w.blk, 0, mk), eb = pair_at(base, w.tmp, 0, mk);
+  Pair out = pair_at(base, w.acc, 0, mk);
+  double2* X = reinterpret_cast<double2*>(base + w.Xs);
   HIPCHK(hipMemsetAsync(ctx->nf_flag(), 0, sizeof(int), ctx->st));
   launch_to_internal(M, K, reinterpret_cast<const double2*>(psi),
                      reinterpret_cast<const double2*>(theta), uphi, y.p, y.t, ctx->st);
   launch_to_internal(M, K, reinterpret_cast<const double2*>(bar_psi),
                      reinterpret_cast<const double2*>(bar_theta), bar_uphi, eb.p, eb.t, ctx->st);
-  s = explicit_T(ctx, y, eb, kappa, base, w, out, nullptr, 0.0);
+  if (!launch_synth(ctx->g, y.p, y.t, X, nullptr, false, ctx->st))
+    return fail(ctx, QG_EUNSUPPORTED, "no transform kernel for these sizes");
+  s = explicit_T(ctx, X, nullptr, eb.p, nullptr, 1.0, 0.0, kappa, nullptr, nullptr, 0.0, base, w,
+                 out);
   if (s != QG_OK) return s;
   launch_to_api(M, K, out.p, out.t, reinterpret_cast<double2*>(bar_psi),
                 reinterpret_cast<double2*>(bar_theta), bar_uphi, ctx->st);

@@ -109,7 +109,7 @@ std::vector<double2> plan_twiddles(int n);
 bool launch_synth(const Geom& g, const double2* psi, const double2* th, void* X, double* diag,
                   bool mixed, hipStream_t st);
 bool launch_ring(const Geom& g, const void* X, void* NL, double* zonal, double* rate, bool mixed,
-                 hipStream_t st);
+                 hipStream_t st, double* G = nullptr);
 bool launch_analysis(const Geom& g, const Bands& b, const void* NL, const double* zonal,
                      const double2* th_state, double2* Epsi, double2* Eth, bool mixed,
                      hipStream_t st);

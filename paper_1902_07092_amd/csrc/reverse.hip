@@ -99,14 +99,21 @@ __device__ void cheb_deriv_T_inplace(double2* c, int K, double2* wred) {
 //   fbar_k = (eps_k / N) sum_n h_n cbar_n cos(pi n k / N),
 // eps_0 = eps_N = 1, else 2 (the even extension counts interior points
 // twice) -- an inverse DCT-I of cbar / 2 (e_0 = b_0, e_n = b_n / 2 with
-// b_0 = cbar_0 / 2, b_n = cbar_n).
+// b_0 = cbar_0 / 2, b_n = cbar_n).  With mu, the same band loop also gives
+// ml = (Mass + cmu Lin)^H mu, the transposed band products of a step's
+// right-hand side (Sect. 4 eq. multistep1; rows below the tau rows, which
+// the transposed solve leaves zero).
 template <int N2, int T>
 __global__ __launch_bounds__(T) void analysis_T_kernel(Geom g, Bands b,
-                                                       const double2* __restrict__ Ebp,
-                                                       const double2* __restrict__ Ebt,
+                                                       const double2* __restrict__ Ea,
+                                                       const double2* __restrict__ Eb2,
+                                                       double ca, double cb,
+                                                       const double2* __restrict__ mu,
+                                                       double cmu, size_t mk,
                                                        double2* __restrict__ NLb,
                                                        double* __restrict__ zb,
-                                                       double2* __restrict__ thb) {
+                                                       double2* __restrict__ thb,
+                                                       double2* __restrict__ ml) {
   extern __shared__ double2 sm[];
   constexpr int N = N2 / 2;
   constexpr int E = out_count<N2, T>();
@@ -117,25 +124,56 @@ __global__ __launch_bounds__(T) void analysis_T_kernel(Geom g, Bands b,
   double2* fb = sm;
   double2* c = reinterpret_cast<double2*>(reinterpret_cast<char*>(sm) +
                                           coef_offset<double2>(lds_slots(N2)));
+  // the co-state rows of E (e) and of the right-hand side (u) sit in the
+  // transform buffer until the transform (2 K <= N2 slots)
+  double2* e = fb;
+  double2* u = fb + K;
   const double invN = 1.0 / N;
-  const double bcoef = g.Ra_Pr * (double)m / g.s_o;
+  const double dm = (double)m, m2 = dm * dm;
+  const double bcoef = g.Ra_Pr * dm / g.s_o;
 #pragma unroll 1
   for (int f = 0; f < 2; ++f) {
-    const double2* Eb = (f == 0 ? Ebp : Ebt) + (size_t)m * K;
+    // co-state of E: ca Ea + cb Eb2 (Eb2 optional; Ea null: zero)
+    const size_t off = (size_t)f * mk + (size_t)m * K;
+    for (int k = t; k < K; k += T) {
+      double2 v = Ea ? scl2(ca, Ea[off + k]) : z2();
+      if (Eb2) v = add2(v, scl2(cb, Eb2[off + k]));
+      e[k] = v;
+      if (mu) u[k] = mu[off + k];
+    }
+    __syncthreads();
     const bool cband = (f == 0 && m > 0);
+    // real systems: zonal flow D + c E (E = F at m = 1), theta D + (c/Pr) F_m
+    const double s1 = (f == 0) ? cmu : cmu * g.inv_Pr;
+    const double s2 = (f == 0) ? cmu : cmu * g.inv_Pr * m2;
     for (int n = t; n < K; n += T) {
-      double2 acc = z2();
+      double2 acc = z2(), mv = z2();
 #pragma unroll
       for (int o = 0; o < 17; ++o) {
         const int k = n - o + 8;   // entry (k, n) of the band at [o][k]
+        const size_t i = (size_t)o * K + k;
         if (cband) {
-          if (k >= 4 && k < K) acc = add2(acc, scl2(b.C[(size_t)o * K + k], Eb[k]));
+          if (k >= 4 && k < K) {
+            acc = add2(acc, scl2(b.C[i], e[k]));
+            if (mu) {   // (A_m + c B_m)^H, Coriolis part (2/E) i m C conjugated
+              const double re = b.A0[i] + m2 * b.A2[i] +
+                                cmu * (b.B0[i] + m2 * (b.B2[i] + m2 * b.B4[i]));
+              const double im = cmu * g.two_over_E * dm * b.C[i];
+              const double2 v = u[k];
+              mv.x += re * v.x + im * v.y;
+              mv.y += re * v.y - im * v.x;
+            }
+          }
         } else {
-          if (k >= 2 && k < K) acc = sub2(acc, scl2(b.D[(size_t)o * K + k], Eb[k]));
+          if (k >= 2 && k < K) {
+            acc = sub2(acc, scl2(b.D[i], e[k]));
+            if (mu) mv = add2(mv, scl2(b.D[i] + s1 * b.F0[i] + s2 * b.F2[i], u[k]));
+          }
         }
       }
       c[n] = acc;
       if (f == 0) thb[(size_t)m * K + n] = cband ? make_double2(bcoef * acc.y, -bcoef * acc.x) : z2();
+      if (mu) ml[off + n] = mv;
     }
     __syncthreads();
     auto ext = [&](int i) -> double2 {
@@ -179,6 +217,7 @@ __global__ __launch_bounds__(T) void analysis_T_kernel(Geom g, Bands b,
 // to Xbar0 and Xbar1.  Two real fields share each complex FFT.
 template <int NPHI, int T>
 __global__ __launch_bounds__(T) void ring_T_kernel(Geom g, const double2* __restrict__ X,
+                                                   const double* __restrict__ G,
                                                    const double2* __restrict__ NLb,
                                                    const double* __restrict__ zb, double kappa,
                                                    double2* __restrict__ Xb) {
@@ -219,8 +258,18 @@ __global__ __launch_bounds__(T) void ring_T_kernel(Geom g, const double2* __rest
       nbt[i] = z[i].y * inv;
     }
   }
-  // forward grid fields, three complex syntheses of two fields each
+  // forward grid fields: stored by the forward ring (G), else three
+  // complex syntheses of two fields each
   double gf[6][E];
+  if (G) {
+#pragma unroll
+    for (int f = 0; f < 6; ++f)
+#pragma unroll
+      for (int i = 0; i < E; ++i) {
+        const int j = t + i * T;
+        gf[f][i] = (j < NPHI) ? G[((size_t)f * R + k) * NPHI + j] : 0.0;
+      }
+  } else {
 #pragma unroll
   for (int q = 0; q < 3; ++q) {
     const double2* A = X + ((size_t)(2 * q) * R + k) * M;
@@ -243,6 +292,7 @@ __global__ __launch_bounds__(T) void ring_T_kernel(Geom g, const double2* __rest
       gf[2 * q][i] = z[i].x;
       gf[2 * q + 1][i] = z[i].y;
     }
+  }
   }
   const double ek = kappa * 2.0 * 3.14159265358979323846 * g.wq[k];
   const double zk = 2.0 * h2s * zb[k];
@@ -324,7 +374,8 @@ __global__ __launch_bounds__(T) void ring_T_kernel(Geom g, const double2* __rest
 template <int N2, int T>
 __global__ __launch_bounds__(T) void synth_T_kernel(Geom g, const double2* __restrict__ Xb,
                                                     const double2* __restrict__ thb0,
-                                                    double2* __restrict__ psib,
+                                                    const double2* __restrict__ add,
+                                                    size_t mk, double2* __restrict__ psib,
                                                     double2* __restrict__ thb) {
   extern __shared__ double2 sm[];
   __shared__ double2 wred[2 * (T / 64)];
@@ -388,10 +439,11 @@ __global__ __launch_bounds__(T) void synth_T_kernel(Geom g, const double2* __res
       __syncthreads();
     }
     for (int n = t; n < K; n += T) {
-      if (fld == 0)
-        psib[(size_t)m * K + n] = (m == 0) ? make_double2(acc[n].x, 0.0) : acc[n];
-      else
-        thb[(size_t)m * K + n] = add2(acc[n], thb0[(size_t)m * K + n]);
+      const size_t i = (size_t)m * K + n;
+      double2 v = (fld == 0) ? ((m == 0) ? make_double2(acc[n].x, 0.0) : acc[n])
+                             : add2(acc[n], thb0[i]);
+      if (add) v = add2(v, add[(size_t)fld * mk + i]);
+      (fld == 0 ? psib : thb)[i] = v;
     }
     __syncthreads();
   }
@@ -400,14 +452,20 @@ __global__ __launch_bounds__(T) void synth_T_kernel(Geom g, const double2* __res
 // --------------------------------------------------------------- helpers
 namespace {
 
-// J += w * sum_m diag[8 m] (the kinetic energy of a synthesis with diag).
-__global__ __launch_bounds__(256) void energy_accum_kernel(const double* __restrict__ diag, int M,
-                                                           double w, double* __restrict__ J) {
+// J = c sum_{n=0}^{N} w_n sum_m diag[n][8 m] (kinetic energies of the
+// syntheses of y^0 .. y^N), w_n = 1/2 at both ends, else 1.
+__global__ __launch_bounds__(256) void energy_total_kernel(const double* __restrict__ diag, int M,
+                                                           int N, double c,
+                                                           double* __restrict__ J) {
   __shared__ double red[4];
   double v = 0.0;
-  for (int m = threadIdx.x; m < M; m += 256) v += diag[(size_t)m * 8];
+  for (int n = 0; n <= N; ++n) {
+    double e = 0.0;
+    for (int m = threadIdx.x; m < M; m += 256) e += diag[((size_t)n * M + m) * 8];
+    v += (n == 0 || n == N) ? 0.5 * e : e;
+  }
   const double tot = block_sum(v, red);
-  if (threadIdx.x == 0) *J += w * tot;
+  if (threadIdx.x == 0) *J = c * tot;
 }
 
 // Co-state layouts: the library's arrays keep the zonal flow in row 0 of
@@ -439,34 +497,40 @@ __global__ void to_api_kernel(int M, int K, const double2* __restrict__ sp,
   th[i] = st[i];
 }
 
+// Threads per block of the reverse kernels: twice the forward kernels'
+// (capped at 256); the reverse kernels carry more work per block.
+constexpr int threads_rdct(int n2) { return clampi(n2 / 4, 64, 256); }
+constexpr int threads_rphi(int nphi) { return clampi(nphi / 6, 64, 256); }
+
 template <int N2>
-void analysis_T_n(const Geom& g, const Bands& b, const double2* Ebp, const double2* Ebt,
-                  double2* NLb, double* zb, double2* thb, hipStream_t st) {
-  constexpr int T = threads_dct(N2);
+void analysis_T_n(const Geom& g, const Bands& b, const double2* Ea, const double2* Eb,
+                  double ca, double cb, const double2* mu, double cmu, size_t mk,
+                  double2* NLb, double* zb, double2* thb, double2* ml, hipStream_t st) {
+  constexpr int T = threads_rdct(N2);
   const size_t shm = dct_lds<double2>(N2, g.K);
   allow_lds(analysis_T_kernel<N2, T>, shm);
   hipLaunchKernelGGL((analysis_T_kernel<N2, T>), dim3(xcd_grid(g.M)), dim3(T), shm, st, g, b,
-                     Ebp, Ebt, NLb, zb, thb);
+                     Ea, Eb, ca, cb, mu, cmu, mk, NLb, zb, thb, ml);
 }
 
 template <int NPHI>
-void ring_T_n(const Geom& g, const double2* X, const double2* NLb, const double* zb,
-              double kappa, double2* Xb, hipStream_t st) {
-  constexpr int T = threads_phi(NPHI);
+void ring_T_n(const Geom& g, const double2* X, const double* G, const double2* NLb,
+              const double* zb, double kappa, double2* Xb, hipStream_t st) {
+  constexpr int T = threads_rphi(NPHI);
   const size_t shm = phi_lds<double2>(NPHI);
   allow_lds(ring_T_kernel<NPHI, T>, shm);
-  hipLaunchKernelGGL((ring_T_kernel<NPHI, T>), dim3(xcd_grid(g.R)), dim3(T), shm, st, g, X, NLb,
-                     zb, kappa, Xb);
+  hipLaunchKernelGGL((ring_T_kernel<NPHI, T>), dim3(xcd_grid(g.R)), dim3(T), shm, st, g, X, G,
+                     NLb, zb, kappa, Xb);
 }
 
 template <int N2>
-void synth_T_n(const Geom& g, const double2* Xb, const double2* thb0, double2* psib,
-               double2* thb, hipStream_t st) {
-  constexpr int T = threads_dct(N2);
+void synth_T_n(const Geom& g, const double2* Xb, const double2* thb0, const double2* add,
+               size_t mk, double2* psib, double2* thb, hipStream_t st) {
+  constexpr int T = threads_rdct(N2);
   const size_t shm = dct_lds<double2>(N2, g.K);
   allow_lds(synth_T_kernel<N2, T>, shm);
   hipLaunchKernelGGL((synth_T_kernel<N2, T>), dim3(xcd_grid(g.M)), dim3(T), shm, st, g, Xb,
-                     thb0, psib, thb);
+                     thb0, add, mk, psib, thb);
 }
 
 #define QG_RDCT(X) X(32) X(48) X(64) X(96) X(128) X(192) X(256) X(384) X(512) X(768) \
@@ -476,16 +540,23 @@ void synth_T_n(const Geom& g, const double2* Xb, const double2* thb0, double2* p
 }  // namespace
 
 // The transposed explicit terms at the state whose forward fields X the
-// caller has synthesised (launch_synth, FP64): (psib, thb) = E'(y)^H
-// (Ebp, Ebt) + kappa grad E_K(y).  NLb [2][M][R], zb [R], thb0 [M][K] and
-// Xb [6][R][M] are scratch.  False: no kernel for these sizes.
-bool launch_explicit_T(const Geom& g, const Bands& b, const double2* X, const double2* Ebp,
-                       const double2* Ebt, double kappa, double2* NLb, double* zb,
-                       double2* thb0, double2* Xb, double2* psib, double2* thb, hipStream_t st) {
+// caller has synthesised (launch_synth, FP64; G: its grid fields from the
+// forward ring, or null):
+//   (psib, thb) = E'(y)^H (ca Ea + cb Eb) + kappa grad E_K(y)
+//                 + (Mass + cmu Lin)^H mu  (with mu)  or  + add  (without),
+// co-state pairs (Psi block, theta block mk entries later); Ea, Eb, add
+// and mu may be null (zero).  NLb [2][M][R], zb [R], thb0 [M][K], ml (a
+// pair) and Xb [6][R][M] are scratch.  False: no kernel for these sizes.
+bool launch_explicit_T(const Geom& g, const Bands& b, const double2* X, const double* G,
+                       const double2* Ea, const double2* Eb, double ca, double cb, size_t mk,
+                       double kappa, double2* NLb, double* zb, double2* thb0, double2* Xb,
+                       const double2* add, const double2* mu, double cmu, double2* ml,
+                       double2* psib, double2* thb, hipStream_t st) {
   const int n2 = 2 * (g.R - 1);
   bool ok = false;
+  if (mu) add = ml;
   switch (n2) {
-#define QG_CASE(n) case n: analysis_T_n<n>(g, b, Ebp, Ebt, NLb, zb, thb0, st); ok = true; break;
+#define QG_CASE(n) case n: analysis_T_n<n>(g, b, Ea, Eb, ca, cb, mu, cmu, mk, NLb, zb, thb0, ml, st); ok = true; break;
     QG_RDCT(QG_CASE)
 #undef QG_CASE
     default: break;
@@ -493,22 +564,23 @@ bool launch_explicit_T(const Geom& g, const Bands& b, const double2* X, const do
   if (!ok) return false;
   ok = false;
   switch (g.nphi) {
-#define QG_CASE(n) case n: ring_T_n<n>(g, X, NLb, zb, kappa, Xb, st); ok = true; break;
+#define QG_CASE(n) case n: ring_T_n<n>(g, X, G, NLb, zb, kappa, Xb, st); ok = true; break;
     QG_RPHI(QG_CASE)
 #undef QG_CASE
     default: break;
   }
   if (!ok) return false;
   switch (n2) {
-#define QG_CASE(n) case n: synth_T_n<n>(g, Xb, thb0, psib, thb, st); return true;
+#define QG_CASE(n) case n: synth_T_n<n>(g, Xb, thb0, add, mk, psib, thb, st); return true;
     QG_RDCT(QG_CASE)
 #undef QG_CASE
     default: return false;
   }
 }
 
-void launch_energy_accum(const double* diag, int M, double w, double* J, hipStream_t st) {
-  hipLaunchKernelGGL(energy_accum_kernel, dim3(1), dim3(256), 0, st, diag, M, w, J);
+void launch_energy_total(const double* diag, int M, int N, double c, double* J,
+                         hipStream_t st) {
+  hipLaunchKernelGGL(energy_total_kernel, dim3(1), dim3(256), 0, st, diag, M, N, c, J);
 }
 
 void launch_to_internal(int M, int K, const double2* psi, const double2* th, const double* u,

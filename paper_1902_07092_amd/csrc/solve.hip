@@ -349,7 +349,111 @@ struct Solver4 {
     const int m = (kind == 0) ? sys0 + grp + 1 : (kind == 1 ? 0 : sys0 + grp - M);
     return (kind == 2 ? out_th : out_psi) + (size_t)max(m, 0) * K;
   }
+
+  // ---------------------------------------------------------- adjoint
+  // y = S^-H f for the bordered system S = [A B; C D], D = L U, in the
+  // real inner product (Appendix A transposed): z = D^-H f_b by the two
+  // sweeps above run on the factors of D^H = (U^H)(L^H) (F holds them:
+  // L the unit-lower U^H scaled, ui = conj(1 / U_jj), U the unit-upper
+  // L^H), then y_a = Minv^H (f_a - C^H z), y_b = z - W^H y_a, and the tau
+  // rows of y are zero (the adjoint of zeroing the tau rows of a
+  // right-hand side).  Real systems take real inputs (the adjoint of
+  // keeping theta_0 and the zonal flow real).  fa: rows 0..P-1 of f.
+  __device__ __forceinline__ void run_adjoint(const double2* fa) {
+    const bool real_row = (kind == 1) || (kind == 2 && sys0 + grp == M);
+    if (real_row && valid)
+      for (int r = lane; r < n; r += SB) hg[r].y = 0.0;
+    __syncthreads();
+    double2 bw = hrow(lane);
+    sweep<true>(bw);
+    __threadfence();
+    bw = hrow((nb - 1) * SB + lane);
+    sweep<false>(bw);
+    __syncthreads();
+    // the groups past the last system (valid = false) only kept the sweeps
+    // in step; their output rows do not exist
+    double2 ya[P];
+    if (valid) {
+      const double2* xo = out_ptr() + P;
+      double2 tc[P];
+#pragma unroll
+      for (int c = 0; c < P; ++c) {
+        tc[c] = fa[c];
+        if (real_row) tc[c].y = 0.0;
+        for (int r = 0; r < KW && r < n; ++r)
+          tc[c] = sub_cj(tc[c], F.Cb[((size_t)so * KW + r) * P + c], xo[r]);
+      }
+#pragma unroll
+      for (int i = 0; i < P; ++i) {
+        double2 acc = z2();
+#pragma unroll
+        for (int c = 0; c < P; ++c) acc = add_cj(acc, F.Minv[((size_t)so * P + c) * P + i], tc[c]);
+        ya[i] = acc;
+      }
+    }
+    __syncthreads();
+    if (valid) {
+      double2* xs = out_ptr();
+      double2* xo = xs + P;
+      const TF* Wr = F.W + (size_t)so * P * n;
+      for (int j = lane; j < n; j += SB) {
+        double2 v = xo[j];
+#pragma unroll
+        for (int i = 0; i < P; ++i) v = sub_cj(v, Wr[(size_t)i * n + j], ya[i]);
+        if (real_row) v.y = 0.0;
+        xo[j] = v;
+        bad = bad || !isfinite(v.x) || !isfinite(v.y);
+      }
+      if (lane < P) xs[lane] = z2();
+    }
+  }
+  // a - conj(c) b, a + conj(c) b
+  static __device__ __forceinline__ double2 sub_cj(double2 a, double2 c, double2 b) {
+    return make_double2(a.x - (c.x * b.x + c.y * b.y), a.y - (c.x * b.y - c.y * b.x));
+  }
+  static __device__ __forceinline__ double2 sub_cj(double2 a, double c, double2 b) {
+    return make_double2(a.x - c * b.x, a.y - c * b.y);
+  }
+  static __device__ __forceinline__ double2 add_cj(double2 a, double2 c, double2 b) {
+    return make_double2(a.x + (c.x * b.x + c.y * b.y), a.y + (c.x * b.y - c.y * b.x));
+  }
+  static __device__ __forceinline__ double2 add_cj(double2 a, double c, double2 b) {
+    return make_double2(a.x + c * b.x, a.y + c * b.y);
+  }
 };
+
+template <typename T> __device__ __forceinline__ T cj(T v);
+template <> __device__ __forceinline__ double cj<double>(double v) { return v; }
+template <> __device__ __forceinline__ double2 cj<double2>(double2 v) { return make_double2(v.x, -v.y); }
+
+// Factors of D^H from those of D (unpivoted layout, q padded steps, KW
+// sub- and super-diagonals): D = L diag(d) U' (U' unit upper stored by
+// columns, U[j][e-1] = U'(j-e, j); ui[j] = 1/d_j), so D^H = U'^H
+// diag(conj d) L^H with
+//   LT[j][e-1] = conj(U'(j, j+e)) = conj(U[j+e][e-1])     (j + e < n)
+//   UT[j][e-1] = conj(L(j, j-e))  = conj(L[j-e][e-1])     (j < n, j >= e)
+//   uiT[j] = conj(ui[j]);
+// the padding steps stay identity steps.
+template <typename TF, int KW>
+__global__ __launch_bounds__(256) void transpose_factors_kernel(const TF* __restrict__ L,
+                                                                const TF* __restrict__ U,
+                                                                const TF* __restrict__ ui, int S,
+                                                                int n, int q, TF* __restrict__ LT,
+                                                                TF* __restrict__ UT,
+                                                                TF* __restrict__ uiT) {
+  const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (size_t)S * q) return;
+  const size_t s = idx / q;
+  const int j = (int)(idx - s * q);
+  const TF* Ls = L + s * q * KW;
+  const TF* Us = U + s * q * KW;
+#pragma unroll
+  for (int e = 1; e <= KW; ++e) {
+    LT[idx * KW + (e - 1)] = (j + e < n) ? cj(Us[(size_t)(j + e) * KW + (e - 1)]) : tz<TF>();
+    UT[idx * KW + (e - 1)] = (j < n && j >= e) ? cj(Ls[(size_t)(j - e) * KW + (e - 1)]) : tz<TF>();
+  }
+  uiT[idx] = cj(ui[idx]);
+}
 
 }  // namespace
 
@@ -408,6 +512,80 @@ __global__ __launch_bounds__(64) void solve_np_kernel(Geom g, FactorSet<double2>
     s.run(s.out_ptr());
     nf_mark(g.nf, s.bad, rs.tag);
   }
+}
+
+// y = S^-H f for every system of a step (the transposed solves of a
+// reverse sweep): the block layout of solve_np_kernel; the factor sets
+// carry the factors of D^H (transpose_factors_kernel) with the border data
+// of D.  f and y are co-state arrays [M][K] (Psi of m in row m, the zonal
+// flow in row 0 of f_psi / y_psi, theta of m in row m); f is overwritten.
+__global__ __launch_bounds__(64) void solve_adjoint_np_kernel(Geom g, FactorSet<double2> Fp,
+                                                              FactorSet<double> Fr,
+                                                              double2* f_psi, double2* f_th,
+                                                              double2* y_psi, double2* y_th,
+                                                              int qp, int qr) {
+  __shared__ double2 ring_mem[2 * 4 * (SB * 8 + 1)];
+  const int M = g.M, K = g.K;
+  const int nbp = (M - 1 + 3) / 4;
+  const int nb = nbp + (M + 1 + 3) / 4;
+  const int id = blockIdx.x;
+  const int b = (id >> 3) * 8 + (id & 7);
+  if (b >= nb) return;
+  const int t = threadIdx.x, lane = t & 15, grp = t >> 4;
+  if (b < nbp) {
+    Solver4<double2, 4, 8> s{Fp, y_psi, y_th, M, K};
+    s.kind = 0;
+    s.sys0 = 4 * b;
+    s.so0 = s.sys0;
+    s.nsys = min(4, M - 1 - s.sys0);
+    s.n = K - 4; s.q = qp; s.nb = qp / SB;
+    s.ring = ring_mem;
+    s.t = t; s.lane = lane; s.grp = grp;
+    s.valid = grp < s.nsys;
+    s.so = s.so0 + min(grp, s.nsys - 1);
+    const int m = s.sys0 + min(grp, s.nsys - 1) + 1;
+    s.hg = f_psi + (size_t)m * K + 4;
+    s.run_adjoint(f_psi + (size_t)m * K);
+  } else {
+    Solver4<double, 2, 4> s{Fr, y_psi, y_th, M, K};
+    const int r0 = 4 * (b - nbp);
+    s.kind = (r0 == 0) ? 1 : 2;
+    s.sys0 = (M - 1) + r0;
+    s.so0 = r0;
+    s.nsys = min(4, M + 1 - r0);
+    s.n = K - 2; s.q = qr; s.nb = qr / SB;
+    s.ring = reinterpret_cast<double*>(ring_mem);
+    s.t = t; s.lane = lane; s.grp = grp;
+    s.valid = grp < s.nsys;
+    s.so = s.so0 + min(grp, s.nsys - 1);
+    if (r0 == 0 && grp > 0) s.kind = 2;
+    const int r = r0 + min(grp, s.nsys - 1);          // 0: zonal flow, 1 + m: theta of m
+    double2* f = (r == 0) ? f_psi : f_th + (size_t)(r - 1) * K;
+    s.hg = f + 2;
+    s.run_adjoint(f);
+  }
+}
+
+void launch_transpose_factors(const FactorSet<double2>& Fp, const FactorSet<double>& Fr, int Sp,
+                              int Sr, int n4, int n2, int qp, int qr, double2* pLT, double2* pUT,
+                              double2* puiT, double* rLT, double* rUT, double* ruiT,
+                              hipStream_t st) {
+  const size_t np = (size_t)Sp * qp, nr = (size_t)Sr * qr;
+  hipLaunchKernelGGL((transpose_factors_kernel<double2, 8>), dim3((unsigned)((np + 255) / 256)),
+                     dim3(256), 0, st, Fp.L, Fp.U, Fp.ui, Sp, n4, qp, pLT, pUT, puiT);
+  hipLaunchKernelGGL((transpose_factors_kernel<double, 4>), dim3((unsigned)((nr + 255) / 256)),
+                     dim3(256), 0, st, Fr.L, Fr.U, Fr.ui, Sr, n2, qr, rLT, rUT, ruiT);
+}
+
+bool launch_solve_adjoint_np(const Geom& g, const FactorSet<double2>& FpT,
+                             const FactorSet<double>& FrT, int qp, int qr, double2* f_psi,
+                             double2* f_th, double2* y_psi, double2* y_th, hipStream_t st) {
+  if (qp % (NSET * SB) || qr % (NSET * SB)) return false;
+  const int nb = (g.M - 1 + 3) / 4 + (g.M + 1 + 3) / 4;
+  const int blocks = 8 * ((nb + 7) / 8);
+  hipLaunchKernelGGL(solve_adjoint_np_kernel, dim3(blocks), dim3(64), 0, st, g, FpT, FrT, f_psi,
+                     f_th, y_psi, y_th, qp, qr);
+  return true;
 }
 
 bool launch_solve_np(const Geom& g, const FactorSet<double2>& Fp, const FactorSet<double>& Fr,

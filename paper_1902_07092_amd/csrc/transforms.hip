@@ -230,12 +230,15 @@ __global__ __launch_bounds__(T) void synth_kernel(Geom g, const double2* __restr
 // scaled by 1/N_phi and truncated to m <= N_m (N_omega can exceed N_theta by
 // many orders of magnitude, so the two never share one complex transform).
 // Zonal forcing: mean(u_s omega) = 2 sum_{m>=1} Re(u_s,m conj(omega_m)) with
-// u_s,m = (h^2/s) X0_m and omega_m = X3_m / (i m).
+// u_s,m = (h^2/s) X0_m and omega_m = X3_m / (i m).  G (optional, FP64
+// single runs): the six grid fields g_f(phi_j) out, [6][R][N_phi], for the
+// reverse mode.
 template <int NPHI, int T, typename C>
 __global__ __launch_bounds__(T) void ring_kernel(Geom g, const C* __restrict__ X,
                                                  C* __restrict__ NL,
                                                  double* __restrict__ zonal,
-                                                 double* __restrict__ rate) {
+                                                 double* __restrict__ rate,
+                                                 double* __restrict__ G) {
   using RT = fftd::real_t<C>;
   extern __shared__ double2 sm[];
   C* fb = reinterpret_cast<C*>(sm);
@@ -280,6 +283,16 @@ __global__ __launch_bounds__(T) void ring_kernel(Geom g, const C* __restrict__ X
     };
     C z[E];
     fft_out<NPHI, T, +1>(get, fb, Tw<C>::phi(g), z);
+    if (G) {
+#pragma unroll
+      for (int i = 0; i < E; ++i) {
+        const int j = t + i * T;
+        if (j < NPHI) {
+          G[((size_t)(2 * q) * R + k) * NPHI + j] = (double)z[i].x;
+          G[((size_t)(2 * q + 1) * R + k) * NPHI + j] = (double)z[i].y;
+        }
+      }
+    }
 #pragma unroll
     for (int i = 0; i < E; ++i) {
       if (q == 0) {
@@ -437,12 +450,13 @@ void synth_n(const Geom& g, const double2* psi, const double2* th, void* X, doub
 }
 
 template <int NPHI, typename C>
-void ring_n(const Geom& g, const void* X, void* NL, double* zonal, double* rate, hipStream_t st) {
+void ring_n(const Geom& g, const void* X, void* NL, double* zonal, double* rate, double* G,
+            hipStream_t st) {
   constexpr int T = threads_phi(NPHI);
   const size_t shm = phi_lds<C>(NPHI);
   allow_lds(ring_kernel<NPHI, T, C>, shm);
   hipLaunchKernelGGL((ring_kernel<NPHI, T, C>), dim3(xcd_grid(g.R), g.nmem), dim3(T), shm, st, g,
-                     static_cast<const C*>(X), static_cast<C*>(NL), zonal, rate);
+                     static_cast<const C*>(X), static_cast<C*>(NL), zonal, rate, G);
 }
 
 template <int N2, typename C>
@@ -520,17 +534,18 @@ bool launch_synth(const Geom& g, const double2* psi, const double2* th, void* X,
 }
 
 bool launch_ring(const Geom& g, const void* X, void* NL, double* zonal, double* rate, bool mixed,
-                 hipStream_t st) {
+                 hipStream_t st, double* G) {
   if (mixed) {
+    if (G) return false;
     switch (g.nphi) {
-#define QG_CASE(n) case n: ring_n<n, float2>(g, X, NL, zonal, rate, st); return true;
+#define QG_CASE(n) case n: ring_n<n, float2>(g, X, NL, zonal, rate, nullptr, st); return true;
       QG_PHI32(QG_CASE)
 #undef QG_CASE
       default: return false;
     }
   }
   switch (g.nphi) {
-#define QG_CASE(n) case n: ring_n<n, double2>(g, X, NL, zonal, rate, st); return true;
+#define QG_CASE(n) case n: ring_n<n, double2>(g, X, NL, zonal, rate, G, st); return true;
     QG_PHI64(QG_CASE)
 #undef QG_CASE
     default: return false;

@@ -191,8 +191,8 @@ def test_ensemble_member_matches_oracle(qg):
             np.abs(a).max())
     _say(f"  rel err against the FP64 oracle {err}")
     ref = refcheck.load("ensemble7_cnab2_10")
-    gerr, orc = refcheck.check(ref, (psi, th, up))
-    _say(f"  vs reference: GPU {gerr}; FP64 {orc}")
+    gerr, _ = refcheck.check(ref, (psi, th, up))
+    _say(f"  vs reference: {refcheck.report(ref, gerr)}")
     for f, e in err.items():
         if ref["oracle_err"][f] <= 1e-12:
             assert e < 1e-11, (f, e)

@@ -36,17 +36,13 @@ def _vs_reference(case, state, vs_oracle=None):
     """Reference criterion, and 1e-11 against the live oracle for the
     fields where the FP64 oracle is within 1e-12 of the reference."""
     ref = refcheck.load(case)
-    err, orc = refcheck.check(ref, state)
-    _say(f"  vs reference: GPU {fmt(err)}; FP64 {fmt(orc)}")
+    err, _ = refcheck.check(ref, state)
+    _say(f"  vs reference: {refcheck.report(ref, err)}")
     if vs_oracle is not None:
         for f, e in vs_oracle.items():
             if ref["oracle_err"][f] <= 1e-12:
                 assert e < TOL, (f, e)
     return err
-
-
-def fmt(d):
-    return "{" + ", ".join(f"{k} {v:.2e}" for k, v in d.items()) + "}"
 
 
 def _say(msg):
