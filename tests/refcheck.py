@@ -10,7 +10,7 @@ same sampled entries,
 
     max |gpu - ref| / max |ref|   <= 2 e_f + 1e-13             per field
                                      (zonal flow: 2 e_f + 1e-12)
-    max_row |gpu - ref|           <= 3 e_f,row + 1e-12 max |ref|   per row,
+    max_row |gpu - ref|           <= 8 e_f,row + 1e-12 max |ref|   per row,
 
 i.e. the HIP path rounds like a plain FP64 implementation of the same
 algorithm, measured where FP64 itself is exact to the digits shown.  The
@@ -29,13 +29,16 @@ amplified.  A random perturbation of Psi at the oracle's own error level
 (1e-14) moves that stress by 1e-12 to 1e-11 of itself, and binary64 solves
 that differ only in accumulation order move the zonal flow by 4e-14 to
 9e-13 while Psi stays within 6e-14.
-The row bound: a row's maximum runs over K entries only, and moves with
-the order of the arithmetic (recompiling the same kernels moved row
-m = 128 of the 768 x 257 20-step case from 1.6e-14 to 2.5e-14, FP64 7.8e-15,
-field maximum 9.4e-3), hence 3 x; and a transform rounds every output mode
-at about FP64 epsilon times the field's largest value, so rows many orders
-below the field's maximum carry errors of that size in any
-implementation, hence the floor.
+The row bound is a localisation check (an error confined to a few modes
+stands out by orders of magnitude), with the spread of FP64 itself: a
+row's maximum runs over K entries only, and the two FP64 implementations'
+row errors differ by up to 7.4x among the rows above the floor (768 x 257,
+two BPR353 steps, Psi row m = 32: 3.2e-14 against 4.4e-15; 50-70x where
+pivoting dominates), and recompiling the same kernels moved a GPU row
+(m = 128, 768 x 257, 20 steps) from 1.6e-14 to 2.5e-14; hence 8 x.  A
+transform rounds every output mode at about FP64 epsilon times the
+field's largest value, so rows many orders below the field's maximum
+carry errors of that size in any implementation, hence the floor.
 The errors are printed.
 """
 import json
@@ -86,7 +89,7 @@ def errors(ref, state):
 
 
 FLOOR = {"psi": 1e-13, "theta": 1e-13, "uphi": 1e-12}
-ROW_FACTOR = 3.0
+ROW_FACTOR = 8.0
 ROW_FLOOR = 1e-12
 
 
