@@ -435,6 +435,9 @@ def main():
                     help="untimed steps of the band-product autotuner "
                     "before the warm-up (0: compiled default shape)")
     ap.add_argument("--ens-tune-steps", type=int, default=21)
+    ap.add_argument("--adjoint-only", action="store_true",
+                    help="print only the adjoint workload's forward and "
+                         "gradient times")
     ap.add_argument("--ensemble-only", action="store_true",
                     help="only the batched-ensemble run (for profiling it)")
     ap.add_argument("--precision", choices=("fp64", "mixed"), default="fp64",
@@ -457,6 +460,10 @@ def main():
         return
 
     from paper_1902_07092_amd import inputs, qg
+    if args.adjoint_only:
+        print(json.dumps({"adjoint": adjoint_run(qg, torch, inputs, args)}),
+              flush=True)
+        return
     if args.ensemble_only:
         print(json.dumps({"batched": ensemble_run(qg, torch, inputs, args)}),
               flush=True)
