@@ -7,6 +7,9 @@ A: p x p, B: p x (K-p) dense boundary rows, C: (K-p) x p sparse, D: band.
 Solve D x = h and D y = C (band LU, LAPACK ?gbtrf/?gbtrs), form the Schur
 complement M = A - B y, solve M psi_1 = g - B x, then psi_2 = x - y psi_1.
 
+BandLU is the band factorisation alone (also the whole solve of the pure
+band systems of the Galerkin bases, oracle.galerkin).
+
 pivot=False replaces the LAPACK band LU by a plain band LU without row
 interchanges (Doolittle, written out below).  The appendix does not fix
 the elimination order; the two are equally valid binary64 implementations
@@ -33,25 +36,20 @@ def _to_lapack_band(D, kl, ku):
     return ab
 
 
-class BorderedSolver:
-    """Factor once (init or on a dt change), then solve many right-hand
-    sides; matrix real or complex, right-hand sides complex or real."""
+class BandLU:
+    """LU of a band matrix D (kl sub-, ku super-diagonals taken from its
+    nonzero pattern): LAPACK ?gbtrf/?gbtrs with partial pivoting, or with
+    pivot=False the plain band LU without row interchanges below."""
 
-    def __init__(self, L, p, pivot=True):
-        L = np.asarray(L)
-        self.p = p
+    def __init__(self, D, pivot=True):
+        D = np.asarray(D)
         self.pivot = pivot
-        self.cplx = np.iscomplexobj(L)
-        self.A = L[:p, :p].copy()        # copies: the dense L is not kept
-        self.B = L[:p, p:].copy()
-        C = L[p:, :p]
-        D = L[p:, p:]
+        self.cplx = np.iscomplexobj(D)
+        self.n = D.shape[0]
         self.kl, self.ku = _bandwidths(D)
+        self.dmax = float(np.abs(D).max())
         if not pivot:
             self._factor_plain(D)
-            self.y = self._band_solve(C)
-            self.M = self.A - self.B @ self.y
-            self.Mlu = sla.lu_factor(self.M)
             return
         ab = _to_lapack_band(D, self.kl, self.ku)
         if self.cplx:
@@ -61,9 +59,6 @@ class BorderedSolver:
         self.lu, self.piv, info = self._trf(ab, self.kl, self.ku)
         if info != 0:
             raise np.linalg.LinAlgError(f"band LU failed, info={info}")
-        self.y = self._band_solve(C)
-        self.M = self.A - self.B @ self.y
-        self.Mlu = sla.lu_factor(self.M)
 
     def _factor_plain(self, D):
         """Band LU without row interchanges: column j's multipliers
@@ -81,6 +76,10 @@ class BorderedSolver:
             a[lo:hi, lo:ce] -= np.outer(a[lo:hi, j], a[j, lo:ce])
         self._plain = a
 
+    def growth(self):
+        """max |U| / max |D| of the plain factorisation (pivot=False)."""
+        return float(np.abs(np.triu(self._plain)).max()) / self.dmax
+
     def _plain_solve(self, rhs):
         a, kl, ku = self._plain, self.kl, self.ku
         n = a.shape[0]
@@ -94,17 +93,38 @@ class BorderedSolver:
             x[lo:j] -= np.multiply.outer(a[lo:j, j], x[j])
         return x
 
-    def _band_solve(self, rhs):
+    def solve(self, rhs):
         rhs = np.asarray(rhs)
         if not self.pivot:
             return self._plain_solve(rhs)
         if not self.cplx and np.iscomplexobj(rhs):
-            return (self._band_solve(rhs.real)
-                    + 1j * self._band_solve(rhs.imag))
+            return self.solve(rhs.real) + 1j * self.solve(rhs.imag)
         x, info = self._trs(self.lu, self.kl, self.ku, rhs, self.piv)
         if info != 0:
             raise np.linalg.LinAlgError(f"band solve failed, info={info}")
         return x
+
+
+class BorderedSolver:
+    """Factor once (init or on a dt change), then solve many right-hand
+    sides; matrix real or complex, right-hand sides complex or real."""
+
+    def __init__(self, L, p, pivot=True):
+        L = np.asarray(L)
+        self.p = p
+        self.pivot = pivot
+        self.cplx = np.iscomplexobj(L)
+        self.A = L[:p, :p].copy()        # copies: the dense L is not kept
+        self.B = L[:p, p:].copy()
+        C = L[p:, :p]
+        self.band = BandLU(L[p:, p:], pivot)
+        self.kl, self.ku = self.band.kl, self.band.ku
+        self.y = self._band_solve(C)
+        self.M = self.A - self.B @ self.y
+        self.Mlu = sla.lu_factor(self.M)
+
+    def _band_solve(self, rhs):
+        return self.band.solve(rhs)
 
     def solve(self, f):
         """f: (K,) or (K, nrhs)."""

@@ -51,6 +51,8 @@ import scipy.sparse as sp
 
 from . import grid, transforms as tr
 from .bordered import BorderedSolver
+from .galerkin import (BAND_DIRICHLET, BAND_PSI, GalerkinSolver,
+                       stencil_dirichlet, stencil_psi)
 from .operators import (D1, IntegrationOperators, bordered_lhs, evaluate_op,
                         mono, mult, op_compose, qg_operators,
                         tau_rows_dirichlet, tau_rows_psi)
@@ -133,10 +135,20 @@ class QGOracle:
     pivot=False factors the band blocks without row interchanges
     (oracle.bordered): a second binary64 implementation of the same step,
     whose distance from the first measures the rounding spread of the
-    solves."""
+    solves.
+
+    method="galerkin" imposes the boundary conditions with the Galerkin
+    bases of Sect. 3.2.2 (oracle.galerkin) instead of tau rows: pure band
+    systems on the Galerkin coefficients, the state still held as
+    Chebyshev coefficients (FP64 only)."""
 
     def __init__(self, E, Ra, Pr, eta, n_phi, n_r, n_c=None, ekman_eps=None,
-                 dtype=np.float64, pivot=True):
+                 dtype=np.float64, pivot=True, method="tau"):
+        if method not in ("tau", "galerkin"):
+            raise ValueError(method)
+        if method == "galerkin" and dtype is not np.float64:
+            raise ValueError("the Galerkin solves are FP64 only")
+        self.method = method
         if n_phi % 3:
             raise ValueError("N_phi must be a multiple of 3 (N_m = N_phi/3)")
         self.E, self.Ra, self.Pr, self.eta = E, Ra, Pr, eta
@@ -208,6 +220,8 @@ class QGOracle:
         if key in self._factors:
             return self._factors[key]
         o = self.ops64
+        if self.method == "galerkin":
+            return self._factor_galerkin(key, o, a_dt)
         bp, bd = tau_rows_psi(self.K), tau_rows_dirichlet(self.K)
         fp = [None]
         for m in range(1, self.M):
@@ -221,9 +235,24 @@ class QGOracle:
         self._factors = {key: (fp, ft, fu)}
         return self._factors[key]
 
+    def _factor_galerkin(self, key, o, a_dt):
+        """Pure band LUs of P_q (mass - a dt L) S (eq. psiint_galerkin,
+        uphi_galerkin, temp_galerkin) for every m."""
+        Sp, Sd = stencil_psi(self.K), stencil_dirichlet(self.K)
+        fp = [None] + [GalerkinSolver(o.A(m) - a_dt * o.B(m, self.E), Sp,
+                                      BAND_PSI, self.pivot)
+                       for m in range(1, self.M)]
+        ft = [GalerkinSolver(o.D - a_dt * o.F(m) / self.Pr, Sd,
+                             BAND_DIRICHLET, self.pivot)
+              for m in range(self.M)]
+        fu = GalerkinSolver(o.D - a_dt * o.E, Sd, BAND_DIRICHLET, self.pivot)
+        self._factors = {key: (fp, ft, fu)}
+        return self._factors[key]
+
     def _bordered_solve(self, a_dt, rp, rt, ru):
         """The bordered systems of every m with right-hand sides whose tau
-        rows are taken as given (FP64 solves)."""
+        rows are taken as given (FP64 solves); with the Galerkin bases the
+        band systems, whose right-hand sides have no such rows."""
         fp, ft, fu = self.factor(a_dt)
         c128 = np.complex128
         psi = np.zeros(rp.shape, c128)

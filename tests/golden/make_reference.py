@@ -9,8 +9,12 @@ refined to long-double accuracy).  The file holds the long-double state
 and the FP64 oracle's error against it, over the full fields and over the
 sampled entries, also per sampled row, and the same errors of a second
 binary64 implementation of the step (the oracle with band LUs without row
-interchanges, pivot=False).  The GPU parity tests (tests/refcheck.py) hold
-the HIP path to the same reference.
+interchanges, pivot=False).  Where added (--add-galerkin), the errors of
+the two FP64 Galerkin implementations (oracle method="galerkin", with and
+without row interchanges) are stored as well: the Galerkin bases solve for
+the same Chebyshev coefficients, so the same reference serves both
+formulations.  The GPU parity tests (tests/refcheck.py) hold the HIP path
+to the same reference.
 
 The 12288 x 4097 case (mixed precision on the GPU only) stores the FP64
 oracle's state as its reference: its rounding is far below the FP32
@@ -19,7 +23,9 @@ transforms' that case measures.
 Calls only the oracle and the seeded input generators.  Usage:
     python tests/golden/make_reference.py [case ...]     (default: all)
     python tests/golden/make_reference.py --add-variant case ...
-(the second form adds the unpivoted run's errors to existing files).
+    python tests/golden/make_reference.py --add-galerkin case ...
+(the second form adds the unpivoted run's errors to existing files, the
+third the two Galerkin runs' errors).
 """
 import json
 import os
@@ -141,44 +147,54 @@ def _write(name, out):
     os.replace(path + ".tmp", path)
     print(f"[{name}] wrote {path} ({os.path.getsize(path)} bytes); FP64 oracle "
           f"error {out['oracle_err_sampled']}; unpivoted "
-          f"{out.get('variant_err_sampled')}", flush=True)
+          f"{out.get('variant_err_sampled')}; Galerkin "
+          f"{out.get('galerkin_err_sampled')}, {out.get('galerkin_np_err_sampled')}",
+          flush=True)
 
 
-def _variant(name, w, st, spec, out):
-    """The second FP64 implementation (band LUs without row interchanges)
-    against the stored reference entries."""
+# Further FP64 implementations: key prefix -> oracle options.
+IMPLS = {"variant": dict(pivot=False),
+         "galerkin": dict(method="galerkin"),
+         "galerkin_np": dict(method="galerkin", pivot=False)}
+
+
+def _variant(name, w, st, spec, out, key="variant"):
+    """Another FP64 implementation (IMPLS[key]) against the stored
+    reference entries."""
     t0 = time.time()
-    v = QGOracle(w.E, w.Ra, w.Pr, w.eta, w.n_phi, w.n_r, w.n_c, pivot=False)
+    v = QGOracle(w.E, w.Ra, w.Pr, w.eta, w.n_phi, w.n_r, w.n_c, **IMPLS[key])
     v.set_state(st.psi, st.theta, st.uphi0)
     v.step(w.dt, spec["scheme"], spec["steps"])
-    print(f"[{name}] unpivoted float64: {spec['steps']} {spec['scheme']} steps "
+    print(f"[{name}] {key} float64: {spec['steps']} {spec['scheme']} steps "
           f"in {time.time() - t0:.0f} s", flush=True)
     stride = out["stride"]
-    out["variant_err_sampled"], out["variant_row_err"] = {}, {}
+    out[f"{key}_err_sampled"], out[f"{key}_row_err"] = {}, {}
     for f in ("psi", "theta", "uphi"):
         scale = out["max_abs"][f]
         a = np.asarray(getattr(v, f))
         if f == "uphi":
             d = np.abs(a[::stride] - np.array(out["ref"][f]))
-            out["variant_err_sampled"][f] = float(d.max() / scale) if scale else 0.0
+            out[f"{key}_err_sampled"][f] = float(d.max() / scale) if scale else 0.0
             continue
         rows = {}
         for m, r in out["ref"][f].items():
             r = np.array([complex(x, y) for x, y in r])
             rows[m] = float(np.abs(a[int(m), ::stride] - r).max())
-        out["variant_row_err"][f] = rows
-        out["variant_err_sampled"][f] = (max(rows.values()) / scale) if scale else 0.0
+        out[f"{key}_row_err"][f] = rows
+        out[f"{key}_err_sampled"][f] = (max(rows.values()) / scale) if scale else 0.0
 
 
-def add_variant(name):
-    """Adds the unpivoted FP64 run's errors to an existing reference file."""
+def add_variant(name, keys=("variant",)):
+    """Adds further FP64 implementations' errors to an existing reference
+    file."""
     spec = CASES[name]
     with open(os.path.join(OUT, f"{name}.json")) as fh:
         out = json.load(fh)
     w = (inputs.ensemble_workloads()[int(spec["w"].split(":")[1])]
          if spec["w"].startswith("ensemble:") else getattr(inputs, spec["w"]))
     assert out["workload"] == w.name and out["steps"] == spec["steps"]
-    _variant(name, w, inputs.workload_state(w), spec, out)
+    for key in keys:
+        _variant(name, w, inputs.workload_state(w), spec, out, key)
     _write(name, out)
 
 
@@ -187,6 +203,9 @@ if __name__ == "__main__":
     if args and args[0] == "--add-variant":
         for name in args[1:]:
             add_variant(name)
+    elif args and args[0] == "--add-galerkin":
+        for name in args[1:]:
+            add_variant(name, ("galerkin", "galerkin_np"))
     else:
         for name in (args or list(CASES)):
             make(name)

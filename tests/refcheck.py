@@ -5,7 +5,10 @@ For a reference case the FP64 oracle's own distance from the long-double
 state is stored, field by field and sampled row by sampled row, and that
 of a second FP64 implementation (the oracle with band LUs without row
 interchanges).  Let e_f be the larger of the two: the rounding spread of
-plain FP64 implementations of the step.  A GPU state passes when, on the
+plain FP64 implementations of the step.  A run with the Galerkin bases
+takes e_f from the two FP64 Galerkin implementations instead (the
+reference is the same: both formulations solve for the same Chebyshev
+coefficients).  A GPU state passes when, on the
 same sampled entries,
 
     max |gpu - ref| / max |ref|   <= 2 e_f + 1e-13             per field
@@ -93,32 +96,45 @@ ROW_FACTOR = 8.0
 ROW_FLOOR = 1e-12
 
 
-def fp64_spread(ref):
-    """Per field (and per row): the larger of the two FP64
-    implementations' errors against the reference (the oracle's alone
-    where the second is not stored)."""
-    var = ref.get("variant_err_sampled")
-    field = {f: max(ref["oracle_err_sampled"][f], var[f]) if var else
-             ref["oracle_err_sampled"][f] for f in FIELDS}
+# The FP64 implementations whose errors bound a formulation's GPU run:
+# tau (the oracle, and the oracle without row interchanges) and Galerkin
+# (oracle method="galerkin", with and without row interchanges).
+IMPLS = {"tau": ("oracle", "variant"), "galerkin": ("galerkin", "galerkin_np")}
+
+
+def fp64_spread(ref, method="tau"):
+    """Per field (and per row): the largest of the formulation's FP64
+    implementations' errors against the reference (those stored)."""
+    keys = [k for k in IMPLS[method] if f"{k}_err_sampled" in ref]
+    assert keys, f"no FP64 errors of the {method} formulation stored"
+    field = {f: max(ref[f"{k}_err_sampled"][f] for k in keys) for f in FIELDS}
     rows = {}
-    for f, per in ref.get("oracle_row_err", {}).items():
-        vr = ref.get("variant_row_err", {}).get(f)
-        rows[f] = {m: max(v, vr[m]) if vr else v for m, v in per.items()}
+    for f in ref.get("oracle_row_err", {}):
+        per = [ref[f"{k}_row_err"][f] for k in keys]
+        rows[f] = {m: max(p[m] for p in per) for m in per[0]}
     return field, rows
 
 
-def report(ref, err):
-    """One line: the GPU's and both FP64 implementations' errors."""
-    var = ref.get("variant_err_sampled")
+NAMES = {"oracle": "FP64 pivoted", "variant": "FP64 unpivoted",
+         "galerkin": "FP64 Galerkin pivoted",
+         "galerkin_np": "FP64 Galerkin unpivoted"}
+
+
+def report(ref, err, method="tau"):
+    """One line: the GPU's and the FP64 implementations' errors."""
     fmt = lambda d: "{" + ", ".join(f"{k} {d[k]:.2e}" for k in FIELDS) + "}"
-    return (f"GPU {fmt(err)}; FP64 pivoted {fmt(ref['oracle_err_sampled'])}"
-            + (f"; FP64 unpivoted {fmt(var)}" if var else ""))
+    parts = [f"GPU {fmt(err)}"]
+    for k in IMPLS[method]:
+        if f"{k}_err_sampled" in ref:
+            parts.append(f"{NAMES[k]} {fmt(ref[f'{k}_err_sampled'])}")
+    return "; ".join(parts)
 
 
-def check(ref, state, factor=2.0):
-    """Asserts the criterion above; returns (gpu errors, FP64 spread)."""
+def check(ref, state, factor=2.0, method="tau"):
+    """Asserts the criterion above (the FP64 spread of the formulation
+    `method`); returns (gpu errors, FP64 spread)."""
     err, rows = errors(ref, state)
-    spread, spread_rows = fp64_spread(ref)
+    spread, spread_rows = fp64_spread(ref, method)
     for f in FIELDS:
         assert err[f] <= factor * spread[f] + FLOOR[f], (
             f"{f}: GPU {err[f]:.3e} against the reference, FP64 "
