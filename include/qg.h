@@ -120,6 +120,22 @@ typedef struct {
                     zonal wind's self-interaction in N_uphi); 0: none */
   double eps;    /* eps of F_eps (h_eps^2 = (s_o + eps)^2 - s^2); > 0 and
                     finite when ekman = 1, ignored otherwise */
+  int method;    /* boundary conditions of the integration method
+                    (Sect. 3.2.2):
+                    0 = tau rows on top of every operator, bordered solves
+                        (Appendix A);
+                    1 = Galerkin bases (eq. psiint_galerkin, uphi_galerkin,
+                        temp_galerkin; Appendix B): Psi on
+                        phi_n = sum_i gamma_i^n T_{n+i}, zonal flow and
+                        temperature on T_{n+2} - T_n, pure band systems
+                        (8 sub- and 12 super-diagonals for Psi, 4 and 6 for
+                        the others) solved without row interchanges.  The
+                        state stays in Chebyshev coefficients.  Needs
+                        pivoting = 0 (QG_EUNSUPPORTED otherwise, and from a
+                        factorisation whose growth factor exceeds 1e4); the
+                        reverse-mode entries (qg_gradient,
+                        qg_adjoint_explicit, qg_adjoint_solve) return
+                        QG_EUNSUPPORTED. */
 } qg_params;
 
 typedef struct {

@@ -34,7 +34,8 @@ bool launch_solve(const Geom& g, const FactorSet<double2>& Fp, const FactorSet<d
                   hipStream_t st);
 int solve_batch();
 bool launch_solve_np(const Geom& g, const FactorSet<double2>& Fp, const FactorSet<double>& Fr,
-                     double2* rhs, const RhsSpec& rs, int qp, int qr, hipStream_t st);
+                     double2* rhs, const RhsSpec& rs, int qp, int qr, bool galerkin,
+                     hipStream_t st);
 int solve_np_pad();
 bool launch_explicit_T(const Geom& g, const Bands& b, const double2* X, const double* G,
                        const double2* Ea, const double2* Eb, double ca, double cb, size_t mk,
@@ -148,6 +149,7 @@ struct Layout {
 struct Sizes {
   int M, K, R, nphi, n4, n2, Sr;
   bool pump;    // Ekman pumping terms
+  bool gal;     // Galerkin bases (qg_params.method = 1)
   int p4, p2;   // n4, n2 padded to whole 16-step batches (pivoted solve)
   int q4, q2;   // n4, n2 padded to whole groups of solve batches (unpivoted solve)
 };
@@ -163,11 +165,13 @@ bool sizes_of(const qg_params* p, Sizes& z, std::string& why) {
   if (p->precision != 0 && p->precision != 1) { why = "precision must be 0 or 1"; return false; }
   if (p->pivoting != 0 && p->pivoting != 1) { why = "pivoting must be 0 or 1"; return false; }
   if (p->ekman != 0 && p->ekman != 1) { why = "ekman must be 0 or 1"; return false; }
+  if (p->method != 0 && p->method != 1) { why = "method must be 0 (tau) or 1 (Galerkin)"; return false; }
   if (p->ekman && !(p->eps > 0 && std::isfinite(p->eps))) {
     why = "eps must be positive with Ekman pumping";
     return false;
   }
   z.pump = p->ekman == 1;
+  z.gal = p->method == 1;
   z.M = p->n_phi / 3 + 1;
   z.K = K;
   z.R = p->n_r;
@@ -187,7 +191,7 @@ struct WsMap {
   size_t ra, flag;
   size_t state, ybuf, eslot, lslot, mE, mY, pump, tan, X, NL, zonal, rate, diag, xk, wq, dsk, twd, twp, twh, wphi,
       twd32, twp32, twh32, wphi32, bands, rhs;
-  size_t p_piv, p_L, p_U, p_W, p_C, p_Mi, p_ui;
+  size_t p_piv, p_L, p_U, p_W, p_C, p_Mi, p_ui, p_gam;
   size_t r_piv, r_L, r_U, r_W, r_C, r_Mi, r_ui;
   size_t total;
 };
@@ -233,7 +237,8 @@ WsMap map_workspace(const Sizes& z, int nmem, bool single) {
   w.rhs = L.take(2 * MK);
   w.p_piv = L.take(Sp * z.p4 * sizeof(int));
   w.p_L = L.take(Sp * std::max(z.p4, z.q4) * 8 * sizeof(double2));
-  w.p_U = L.take(Sp * std::max(z.p4 * 17, z.q4 * 8) * sizeof(double2));
+  // U: pivoted 17 columns, unpivoted 8 (tau) or 12 (Galerkin)
+  w.p_U = L.take(Sp * std::max(z.p4 * 17, z.q4 * (z.gal ? 12 : 8)) * sizeof(double2));
   w.p_ui = L.take(Sp * z.q4 * sizeof(double2));
   w.p_W = L.take(Sp * 4 * z.n4 * sizeof(double2));
   w.p_C = L.take(Sp * 8 * 4 * sizeof(double2));
@@ -241,11 +246,12 @@ WsMap map_workspace(const Sizes& z, int nmem, bool single) {
   const size_t Sr = z.Sr;
   w.r_piv = L.take(Sr * z.p2 * sizeof(int));
   w.r_L = L.take(Sr * std::max(z.p2, z.q2) * 4 * sizeof(double));
-  w.r_U = L.take(Sr * std::max(z.p2 * 9, z.q2 * 4) * sizeof(double));
+  w.r_U = L.take(Sr * std::max(z.p2 * 9, z.q2 * (z.gal ? 6 : 4)) * sizeof(double));
   w.r_ui = L.take(Sr * z.q2 * sizeof(double));
   w.r_W = L.take(Sr * 2 * z.n2 * sizeof(double));
   w.r_C = L.take(Sr * 4 * 2 * sizeof(double));
   w.r_Mi = L.take(Sr * 4 * sizeof(double));
+  w.p_gam = L.take(z.gal ? (size_t)z.n4 * 5 * sizeof(double) : 0);   // Galerkin stencil of Psi
   w.total = L.total;
   return w;
 }
@@ -269,6 +275,7 @@ struct qg_ctx {
   int kutp = 16, kutr = 8;   // stored U super-diagonals (Psi, real systems)
   int band_mch = 16;         // systems per thread of the band products
   bool pivoted = true;       // band LU with row interchanges in use
+  bool galerkin = false;     // Galerkin bases (pure band systems, no border)
   bool mixed = false;        // FP32 transforms and products (qg_params.precision = 1)
   bool diag64 = true;        // FP64 transform kernels exist for the diagnostics
   double growth = 0.0;       // largest growth factor of the band LUs in use
@@ -466,7 +473,90 @@ void parallel_for(int count, F fn) {
 // all systems are refactored with partial pivoting.
 constexpr double MAX_UNPIVOTED_GROWTH = 1e4;
 
+// Galerkin bases (Sect. 3.2.2): for every system P_q (mass - a dt L) S,
+// formed and factored without row interchanges in long double, every
+// factor entry then rounded once to binary64 (as for the tau systems); the
+// Psi stencil's gamma_i^j rounded the same way for the device's y = S x~.
+qg_status refactor_galerkin(qg_ctx* ctx, double adt) {
+  const Sizes& z = ctx->z;
+  const size_t Sp = z.M - 1, Sr = z.Sr;
+  std::vector<BorderedFactor<cplxl>> fp(Sp);
+  std::vector<BorderedFactor<long double>> fr(Sr);
+  std::vector<int> ok(Sp + Sr, 1);
+  // G must vanish outside its stated band (the factorisation reads only
+  // the band)
+  auto banded = [](const auto& G, int n, int kl, int ku) {
+    for (int i = 0; i < n; ++i)
+      for (int j = 0; j < n; ++j)
+        if ((j - i > ku || i - j > kl) && G[(size_t)i * n + j] != decltype(G[0])(0)) return false;
+    return true;
+  };
+  parallel_for((int)(Sp + Sr), [&](int idx) {
+    int p;
+    if (idx < (int)Sp) {
+      std::vector<cplx> full;
+      assemble<cplx>(ctx, 0, idx + 1, adt, full, p);
+      std::vector<cplxl> fl(full.begin(), full.end()), G;
+      galerkin_matrix<cplxl>(fl, z.K, 4, G);
+      ok[idx] = banded(G, z.n4, 8, 12) &&
+                factor_bordered<cplxl>(G, z.n4, 0, 8, 12, false, fp[idx]);
+    } else {
+      const int s = idx - (int)Sp;
+      std::vector<double> full;
+      assemble<double>(ctx, s == 0 ? 1 : 2, s == 0 ? 0 : s - 1, adt, full, p);
+      std::vector<long double> fl(full.begin(), full.end()), G;
+      galerkin_matrix<long double>(fl, z.K, 2, G);
+      ok[idx] = banded(G, z.n2, 4, 6) &&
+                factor_bordered<long double>(G, z.n2, 0, 4, 6, false, fr[s]);
+    }
+  });
+  double growth = 0.0;
+  for (auto& f : fp) growth = std::max(growth, f.growth);
+  for (auto& f : fr) growth = std::max(growth, f.growth);
+  ctx->growth = growth;
+  for (int v : ok)
+    if (!v) return fail(ctx, QG_EINVAL, "singular Galerkin matrix (dt too large or bad parameters)");
+  if (growth > MAX_UNPIVOTED_GROWTH)
+    return fail(ctx, QG_EUNSUPPORTED,
+                "Galerkin band LU without row interchanges grew by " + std::to_string(growth));
+  const WsMap& w = ctx->w;
+  auto up = [&](size_t off, const void* src, size_t bytes) {
+    return hipMemcpyAsync(ctx->ws + off, src, bytes, hipMemcpyHostToDevice, ctx->st);
+  };
+  std::vector<double2> pL(Sp * z.q4 * 8), pU(Sp * z.q4 * 12), pui(Sp * z.q4);
+  std::vector<double> rL(Sr * z.q2 * 4), rU(Sr * z.q2 * 6), rui(Sr * z.q2);
+  double2 d2;
+  double d1;
+  parallel_for((int)(Sp + Sr), [&](int idx) {
+    if (idx < (int)Sp)
+      pack_np<cplxl, double2>(fp[idx], idx, 8, 12, 0, z.q4, pL.data(), pU.data(), pui.data(),
+                             &d2, &d2, &d2);
+    else
+      pack_np<long double, double>(fr[idx - Sp], idx - Sp, 4, 6, 0, z.q2, rL.data(), rU.data(),
+                                  rui.data(), &d1, &d1, &d1);
+  });
+  std::vector<double> gam((size_t)z.n4 * 5);
+  for (int j = 0; j < z.n4; ++j) {
+    long double g[5];
+    galerkin_gamma(j, g);
+    for (int i = 0; i < 5; ++i) gam[(size_t)j * 5 + i] = (double)g[i];
+  }
+  HIPCHK(up(w.p_L, pL.data(), pL.size() * sizeof(double2)));
+  HIPCHK(up(w.p_U, pU.data(), pU.size() * sizeof(double2)));
+  HIPCHK(up(w.p_ui, pui.data(), pui.size() * sizeof(double2)));
+  HIPCHK(up(w.r_L, rL.data(), rL.size() * sizeof(double)));
+  HIPCHK(up(w.r_U, rU.data(), rU.size() * sizeof(double)));
+  HIPCHK(up(w.r_ui, rui.data(), rui.size() * sizeof(double)));
+  HIPCHK(up(w.p_gam, gam.data(), gam.size() * sizeof(double)));
+  HIPCHK(hipStreamSynchronize(ctx->st));
+  ctx->pivoted = false;
+  ctx->galerkin = true;
+  ctx->factored_adt = adt;
+  return QG_OK;
+}
+
 qg_status refactor(qg_ctx* ctx, double adt) {
+  if (ctx->z.gal) return refactor_galerkin(ctx, adt);
   const Sizes& z = ctx->z;
   const size_t Sp = z.M - 1, Sr = z.Sr;
   std::vector<BorderedFactor<cplxl>> fp(Sp);
@@ -629,7 +719,7 @@ qg_status implicit_solve(qg_ctx* ctx, const RhsSpec& rs_in, double2* rhs = nullp
     ok = ctx->pivoted
              ? launch_solve(ctx->g, ctx->Fp, ctx->Fr, rhs, rs, ctx->kutp, ctx->kutr, true,
                             ctx->st)
-             : launch_solve_np(ctx->g, ctx->Fp, ctx->Fr, rhs, rs, ctx->z.q4, ctx->z.q2,
+             : launch_solve_np(ctx->g, ctx->Fp, ctx->Fr, rhs, rs, ctx->z.q4, ctx->z.q2, ctx->galerkin,
                                ctx->st);
   });
   if (!ok) return fail(ctx, QG_EUNSUPPORTED, "no solve kernel for this band width");
@@ -898,6 +988,7 @@ qg_status create_ctx(qg_ctx** out, const qg_params* p, int nmem, const double* r
   if (!sizes_of(p, z, why) || nmem < 1) return QG_EINVAL;
   const bool mixed = p->precision == 1;
   if (z.nphi % 6 || !transform_sizes_ok(2 * (z.R - 1), z.nphi, mixed)) return QG_EUNSUPPORTED;
+  if (z.gal && p->pivoting) return QG_EUNSUPPORTED;   // Galerkin bands: no row interchanges
   if (!workspace || ((uintptr_t)workspace & 255)) return QG_EINVAL;
   WsMap w = map_workspace(z, nmem, single);
   if (workspace_bytes < w.total) return QG_ENOMEM;
@@ -1030,7 +1121,7 @@ qg_status create_ctx(qg_ctx** out, const qg_params* p, int nmem, const double* r
   ctx->Fp = FactorSet<double2>{reinterpret_cast<const int*>(ctx->ws + w.p_piv), ctx->ptr2(w.p_L),
                                ctx->ptr2(w.p_U), ctx->ptr2(w.p_W), ctx->ptr2(w.p_C),
                                ctx->ptr2(w.p_Mi), ctx->ptr2(w.p_L), ctx->ptr2(w.p_U),
-                               ctx->ptr2(w.p_ui)};
+                               ctx->ptr2(w.p_ui), z.gal ? ctx->ptrd(w.p_gam) : nullptr};
   ctx->Fr = FactorSet<double>{reinterpret_cast<const int*>(ctx->ws + w.r_piv), ctx->ptrd(w.r_L),
                               ctx->ptrd(w.r_U), ctx->ptrd(w.r_W), ctx->ptrd(w.r_C),
                               ctx->ptrd(w.r_Mi), ctx->ptrd(w.r_L), ctx->ptrd(w.r_U),
@@ -1367,6 +1458,8 @@ qg_status qg_adjoint_solve(qg_ctx* ctx, double dt, double* psi, double* theta, d
   if (s != QG_OK) return s;
   if (ctx->pivoted)
     return fail(ctx, QG_EUNSUPPORTED, "adjoint solves use the unpivoted factors");
+  if (ctx->galerkin)
+    return fail(ctx, QG_EUNSUPPORTED, "adjoint solves need the tau formulation");
   const Sizes& z = ctx->z;
   const size_t MK = (size_t)z.M * z.K;
   std::vector<double2> hp(MK);
@@ -1782,6 +1875,8 @@ qg_status gradient_run(qg_ctx* ctx, double dt, int N, int C, double ew, const do
   if (s != QG_OK) return s;
   if (grad && ctx->pivoted)
     return fail(ctx, QG_EUNSUPPORTED, "the adjoint solves use the unpivoted factors");
+  if (grad && ctx->galerkin)
+    return fail(ctx, QG_EUNSUPPORTED, "the adjoint solves need the tau formulation");
   const size_t XS = (size_t)6 * ctx->z.R * M;   // entries of one X
   const size_t GS = (size_t)6 * ctx->z.R * ctx->z.nphi;
   const int slots = grad_slots(N, C);
@@ -2093,7 +2188,7 @@ qg_status efail(qg_ensemble* e, qg_status s, const std::string& msg) {
 bool same_group(const qg_params& a, const qg_params& b, const Sizes& za, const Sizes& zb) {
   return a.E == b.E && a.Pr == b.Pr && a.eta == b.eta && za.nphi == zb.nphi && za.R == zb.R &&
          za.K == zb.K && a.precision == b.precision && a.pivoting == b.pivoting &&
-         a.ekman == b.ekman && (!a.ekman || a.eps == b.eps);
+         a.ekman == b.ekman && (!a.ekman || a.eps == b.eps) && a.method == b.method;
 }
 
 struct Grouping {

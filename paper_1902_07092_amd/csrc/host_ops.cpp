@@ -284,6 +284,49 @@ bool factor_bordered(const std::vector<T>& full, int K, int p, int kl, int ku, b
   return true;
 }
 
+void galerkin_gamma(int j, long double g[5]) {
+  const long double n = j;
+  const long double n2 = n * n, n3 = n2 * n, n4 = n3 * n;
+  const long double q = 2 * n4 + 20 * n3 + 78 * n2 + 140 * n + 95;
+  g[0] = 1.0L;
+  g[1] = 8 * (n + 1) * (n2 + 4 * n + 5) / q;
+  g[2] = -2 * (n + 2) * (2 * n4 + 16 * n3 + 58 * n2 + 104 * n + 75) / ((n + 3) * q);
+  g[3] = -g[1];
+  g[4] = (n + 1) * (2 * n4 + 12 * n3 + 30 * n2 + 36 * n + 15) / ((n + 3) * q);
+}
+
+template <typename T>
+void galerkin_matrix(const std::vector<T>& full, int K, int q, std::vector<T>& G) {
+  const int n = K - q;
+  G.assign((size_t)n * n, T(0));
+  // column j of S: rows j..j+4 (gamma_i^j) or rows j (-1) and j+2 (+1)
+  for (int j = 0; j < n; ++j) {
+    long double s[5] = {0, 0, 0, 0, 0};
+    int ns;
+    if (q == 4) {
+      galerkin_gamma(j, s);
+      ns = 5;
+    } else {
+      s[0] = -1.0L;
+      s[2] = 1.0L;
+      ns = 3;
+    }
+    // rows i of P_q Op with a nonzero in columns j..j+ns-1: the operator
+    // band reaches 8 columns either side of its row q + i
+    const int lo = std::max(0, j - 8 - q), hi = std::min(n - 1, j + ns - 1 + 8 - q);
+    for (int i = lo; i <= hi; ++i) {
+      T acc(0);
+      for (int r = 0; r < ns && j + r < K; ++r)
+        if (s[r] != 0.0L) acc += full[(size_t)(q + i) * K + j + r] * T(s[r]);
+      G[(size_t)i * n + j] = acc;
+    }
+  }
+}
+
+template void galerkin_matrix<long double>(const std::vector<long double>&, int, int,
+                                           std::vector<long double>&);
+template void galerkin_matrix<cplxl>(const std::vector<cplxl>&, int, int, std::vector<cplxl>&);
+
 template bool factor_bordered<double>(const std::vector<double>&, int, int, int, int, bool,
                                       BorderedFactor<double>&);
 template bool factor_bordered<cplx>(const std::vector<cplx>&, int, int, int, int, bool,

@@ -53,6 +53,18 @@ bool factor_bordered(const std::vector<T>& full, int K, int p, int kl, int ku, b
                      BorderedFactor<T>& out);
 
 
+// Galerkin bases (Sect. 3.2.2, Appendix B).  gamma_0..4 of the Psi basis
+// function phi_j = sum_i gamma_i^j T_{j+i} (gamma_0 = 1), from the closed
+// forms of Appendix B.
+void galerkin_gamma(int j, long double g[5]);
+
+// P_q Op S: the (K - q) x (K - q) Galerkin system (dense rows) from the
+// full K x K operator `full` (rows q.. used): S the Psi stencil (q = 4) or
+// the Dirichlet stencil T_{n+2} - T_n (q = 2).  A band with 8 / 12 (q = 4)
+// or 4 / 6 (q = 2) sub- / super-diagonals.
+template <typename T>
+void galerkin_matrix(const std::vector<T>& full, int K, int q, std::vector<T>& G);
+
 // Tau rows: Dirichlet at s_o, Dirichlet at s_i, third derivative at s_o,
 // Neumann at s_i (first p of them).
 void tau_row(int which, int K, double* row);

@@ -71,6 +71,9 @@ struct FactorSet {
   const TF* L;        // [S][q][kl]  multipliers of column j, rows j+1..j+kl
   const TF* U;        // [S][q][ku]  U(j-e, j) / U(j-e, j-e), e = 1..ku
   const TF* ui;       // [S][q]      1 / U(j, j)
+  // Galerkin bases (unpivoted layout, no border): gamma_i^j of the Psi
+  // stencil, [n][5] (nullptr with tau rows)
+  const double* gam;
 };
 
 constexpr int MAX_TERMS = 8;

@@ -14,6 +14,16 @@
 // Per system: h = rhs rows p.. ; Schur part psi_1 = -Minv (w . h),
 // h <- h - C psi_1 (first kl rows); forward L y = h with y' = y / U_jj
 // stored over h; backward U' x = y'; the new state [psi_1, x] is written.
+//
+// Galerkin bases (Sect. 3.2.2, eq. psiint_galerkin, uphi_galerkin,
+// temp_galerkin): the systems are pure bands (no border) on the Galerkin
+// coefficients x~, with 8 sub- and 12 super-diagonals for Psi and 4 and 6
+// for the Dirichlet systems; the right-hand side is the same rows p.. .
+// The backward sweep of a 12-wide U' stores and refills lanes every four
+// steps instead of eight (the 16-row window must hold the pivot and the 12
+// rows above it).  x~ goes over h, then the Chebyshev coefficients
+// y = S x~ (the stencil: Appendix B's gamma_i^n for Psi, T_{n+2} - T_n for
+// the Dirichlet systems) are written as the new state.
 #include <hip/hip_runtime.h>
 
 #include <utility>
@@ -64,13 +74,20 @@ template <typename TF> __device__ __forceinline__ TF tz();
 template <> __device__ __forceinline__ double tz<double>() { return 0.0; }
 template <> __device__ __forceinline__ double2 tz<double2>() { return z2(); }
 
-// One kind of system (P border rows, KW band width, factor type TF) for the
+// One kind of system (P boundary rows, KL sub- and KU super-diagonals of
+// the band, factor type TF; GAL: Galerkin band without border) for the
 // four systems of this wavefront.
-template <typename TF, int P, int KW>
+template <typename TF, int P, int KL, int KU = KL, bool GAL = false>
 struct Solver4 {
-  static constexpr int CPS = SB * KW * (int)sizeof(TF) / 16;   // 16-byte chunks per system batch
-  static constexpr int NCH = 4 * CPS / 64;                     // chunks per lane per batch
-  static_assert(NCH * 64 == 4 * CPS, "batch does not divide over the wavefront");
+  static_assert(KL <= 8 && KU <= 12, "band wider than the 16-row window");
+  static_assert(GAL || KL == KU, "bordered systems have a symmetric band");
+  static constexpr int KW = KL > KU ? KL : KU;                 // widest factor column
+  template <int W>
+  static constexpr int cps() { return SB * W * (int)sizeof(TF) / 16; }   // 16-byte chunks per system batch
+  template <int W>
+  static constexpr int nch() { return 4 * cps<W>() / 64; }              // chunks per lane per batch
+  static_assert(nch<KL>() * 64 == 4 * cps<KL>() && nch<KU>() * 64 == 4 * cps<KU>(),
+                "batch does not divide over the wavefront");
 
   // (plain copies: references to the kernel's by-value arguments would
   // place those structures in scratch memory)
@@ -87,41 +104,51 @@ struct Solver4 {
   double2* hg;                 // this system's h / y' (rhs rows p..)
   bool bad = false;            // a stored entry of the new state is not finite
 
+  // a batch of factor columns of width W (KL for L, KU for U')
+  template <int W>
   struct Batch {
-    double2 v[NCH];
+    double2 v[nch<W>()];
   };
   // chunk I of this lane: wave chunk c = t + 64 I, system c / CPS
-  template <int I>
+  template <int W, int I>
   __device__ __forceinline__ double2 load_chunk(const TF* base, int b) const {
+    constexpr int CPS = cps<W>();
     const int c = t + 64 * I;
     const int gs = c / CPS, e = c - gs * CPS;
     const int s = min(so0 + gs, so0 + nsys - 1);
-    return reinterpret_cast<const double2*>(base + ((size_t)s * q + (size_t)b * SB) * KW)[e];
+    return reinterpret_cast<const double2*>(base + ((size_t)s * q + (size_t)b * SB) * W)[e];
   }
-  template <int... I>
-  __device__ __forceinline__ Batch load_batch(const TF* base, int b,
-                                              std::integer_sequence<int, I...>) const {
-    return Batch{{load_chunk<I>(base, b)...}};
+  template <int W, int... I>
+  __device__ __forceinline__ Batch<W> load_batch(const TF* base, int b,
+                                                 std::integer_sequence<int, I...>) const {
+    return Batch<W>{{load_chunk<W, I>(base, b)...}};
   }
-  __device__ __forceinline__ Batch load_batch(const TF* base, int b) const {
-    return load_batch(base, b, std::make_integer_sequence<int, NCH>{});
+  template <int W>
+  __device__ __forceinline__ Batch<W> load_batch(const TF* base, int b) const {
+    return load_batch<W>(base, b, std::make_integer_sequence<int, nch<W>()>{});
   }
-  // LDS ring slot: [4 systems][SB][KW], each system's block followed by a
+  // LDS ring slot: [4 systems][SB][W], each system's block followed by a
   // 16-byte pad so that the four systems' reads fall in different banks
-  static constexpr int SYS_CH = CPS + 1;   // 16-byte chunks per system block
-  template <int... I>
-  __device__ __forceinline__ void stage(int slot, const Batch& r,
+  static constexpr int SYS_CH = cps<KW>() + 1;   // 16-byte chunks per system block (room for either width)
+  template <int W, int... I>
+  __device__ __forceinline__ void stage(int slot, const Batch<W>& r,
                                         std::integer_sequence<int, I...>) const {
+    constexpr int CPS = cps<W>();
     double2* dst = reinterpret_cast<double2*>(ring) + (size_t)slot * 4 * SYS_CH;
-    ((dst[(t + 64 * I) + (t + 64 * I) / CPS] = r.v[I]), ...);
+    if constexpr (CPS + 1 == SYS_CH)   // chunk c of system c / CPS
+      ((dst[(t + 64 * I) + (t + 64 * I) / CPS] = r.v[I]), ...);
+    else
+      ((dst[((t + 64 * I) / CPS) * SYS_CH + (t + 64 * I) % CPS] = r.v[I]), ...);
   }
-  __device__ __forceinline__ void stage(int slot, const Batch& r) const {
-    stage(slot, r, std::make_integer_sequence<int, NCH>{});
+  template <int W>
+  __device__ __forceinline__ void stage(int slot, const Batch<W>& r) const {
+    stage<W>(slot, r, std::make_integer_sequence<int, nch<W>()>{});
   }
-  __device__ __forceinline__ TF coef(int slot, int jj, int d) const {   // d in [1, KW]
+  template <int W>
+  __device__ __forceinline__ TF coef(int slot, int jj, int d) const {   // d in [1, W]
     const TF* blk = reinterpret_cast<const TF*>(reinterpret_cast<const double2*>(ring) +
                                                 (size_t)(slot * 4 + grp) * SYS_CH);
-    return blk[jj * KW + (d - 1)];
+    return blk[jj * W + (d - 1)];
   }
   __device__ __forceinline__ double2 hrow(int r) const { return (r < n) ? hg[r] : z2(); }
   __device__ __forceinline__ TF uirow(int r) const {
@@ -129,21 +156,21 @@ struct Solver4 {
   }
 
   // ---------------------------------------------------------- forward
-  // The eight coefficients of a half batch are read from LDS before its
+  // The coefficients of a group of steps are read from LDS before its
   // first step (the compiler barrier keeps the reads together), so that the
   // elimination chain never waits on LDS.
   template <int JJ>
   __device__ __forceinline__ TF fcoef(int slot) const {   // this lane's L entry at step JJ
     const int d = (lane - JJ) & 15;
-    const bool act = (d >= 1 && d <= KW);
-    const TF l = coef(slot, JJ, act ? d : 1);
+    const bool act = (d >= 1 && d <= KL);
+    const TF l = coef<KL>(slot, JJ, act ? d : 1);
     return act ? l : tz<TF>();
   }
   template <int JJ>
   __device__ __forceinline__ TF bcoef(int slot) const {   // this lane's U' entry at column JJ
     const int e = (JJ - lane) & 15;
-    const bool act = (e >= 1 && e <= KW);
-    const TF u = coef(slot, JJ, act ? e : 1);
+    const bool act = (e >= 1 && e <= KU);
+    const TF u = coef<KU>(slot, JJ, act ? e : 1);
     return act ? u : tz<TF>();
   }
   template <int J0, int... J>
@@ -153,16 +180,26 @@ struct Solver4 {
     asm volatile("" ::: "memory");
     ((fms(bw, c[J], bcast2<J0 + J>(bw))), ...);
   }
-  // backward: columns J0 + 7 - J, J = 0..7
+  // backward: columns J0 + G - 1 - J, J = 0..G-1 (G = 8 or 4 steps)
   template <int J0, int... J>
-  __device__ __forceinline__ void bhalf(double2& bw, int slot, std::integer_sequence<int, J...>)
+  __device__ __forceinline__ void bgroup(double2& bw, int slot, std::integer_sequence<int, J...>)
       const {
-    TF c[sizeof...(J)] = {bcoef<J0 + 7 - J>(slot)...};
+    constexpr int G = sizeof...(J);
+    TF c[G] = {bcoef<J0 + G - 1 - J>(slot)...};
     asm volatile("" ::: "memory");
-    ((fms(bw, c[J], bcast2<J0 + 7 - J>(bw))), ...);
+    ((fms(bw, c[J], bcast2<J0 + G - 1 - J>(bw))), ...);
   }
 
   __device__ __forceinline__ void run(double2* out_state) {
+    if constexpr (GAL) {
+      run_galerkin(out_state);
+      return;
+    } else {
+      run_bordered(out_state);
+    }
+  }
+
+  __device__ __forceinline__ void run_bordered(double2* out_state) {
     // ---- Schur part for the p border unknowns
     double2 wh[P];
 #pragma unroll
@@ -221,9 +258,9 @@ struct Solver4 {
 
     // ---- forward: L y = h, y' = y / U_jj over h
     double2 bw = hrow(lane);
-    if (lane < KW) {
+    if (lane < KL) {
 #pragma unroll
-      for (int i = 0; i < P; ++i) fms(bw, F.Cb[((size_t)so * KW + lane) * P + i], psi1[i]);
+      for (int i = 0; i < P; ++i) fms(bw, F.Cb[((size_t)so * KL + lane) * P + i], psi1[i]);
     }
     sweep<true>(bw);
     __threadfence();
@@ -244,21 +281,61 @@ struct Solver4 {
     }
   }
 
-  // One full sweep; FWD: batches 0..nb-1, else nb-1..0.
+  // Galerkin band: forward and backward sweeps with x~ written over h, then
+  // the K Chebyshev coefficients y = S x~ of the new state.
+  __device__ __forceinline__ void run_galerkin(double2* out_state) {
+    double2 bw = hrow(lane);
+    sweep<true>(bw);
+    __threadfence();
+    bw = hrow((nb - 1) * SB + lane);
+    sweep<false>(bw);
+    __threadfence();   // x~ rows of the other lanes of the group
+    if (!valid) return;
+    const bool real_row = (kind == 1) || (kind == 2 && sys0 + grp == M);
+    for (int k = lane; k < K; k += SB) {
+      double2 v = z2();
+      if constexpr (P == 4) {   // Psi: y_k = sum_i gamma_i^{k-i} x~_{k-i}
+#pragma unroll
+        for (int i = 0; i < 5; ++i) {
+          const int j = k - i;
+          if (j >= 0 && j < n) {
+            const double gm = F.gam[(size_t)j * 5 + i];
+            v.x = fma(gm, hg[j].x, v.x);
+            v.y = fma(gm, hg[j].y, v.y);
+          }
+        }
+      } else {                  // Dirichlet: y_k = x~_{k-2} - x~_k
+        if (k - 2 >= 0 && k - 2 < n) v = hg[k - 2];
+        if (k < n) {
+          v.x -= hg[k].x;
+          v.y -= hg[k].y;
+        }
+      }
+      if (real_row) v.y = 0.0;
+      out_state[k] = v;
+      bad = bad || !isfinite(v.x) || !isfinite(v.y);
+    }
+  }
+
+  // One full sweep; FWD: batches 0..nb-1 (factor columns of width KL),
+  // else nb-1..0 (width KU).
   template <bool FWD>
   __device__ __forceinline__ void sweep(double2& bw) {
+    constexpr int W = FWD ? KL : KU;
     const TF* base = FWD ? F.L : F.U;
     const bool real_row = (kind == 1) || (kind == 2 && sys0 + grp == M);
-    double2* xo = out_ptr() + P;
+    // the bordered solve writes x below the border rows of the state; the
+    // Galerkin solve writes x~ over h
+    double2* xo = GAL ? hg : out_ptr() + P;
     auto bidx = [&](int i) { return FWD ? i : nb - 1 - i; };
     // sets[k] holds a batch i = k (mod NSET) ahead of its use; hs / us
     // the refill rows and 1 / U(j, j) of batches k (mod NSET)
-    Batch sets[NSET];
+    Batch<W> sets[NSET];
     double2 hs[NSET];
     TF us[NSET];
     {   // batch 0 to the ring, batches 1..NSET in flight (loads past the
         // last batch re-read it)
-      stage(0, load_batch(base, bidx(0)));
+      stage<W>(0, load_batch<W>(base, bidx(0)));
       prologue<FWD>(sets, hs, us, std::make_integer_sequence<int, NSET>{});
     }
     for (int i0 = 0; i0 < nb; i0 += NSET)   // nb is a multiple of NSET
@@ -267,11 +344,13 @@ struct Solver4 {
   }
 
   template <bool FWD, int... KK>
-  __device__ __forceinline__ void prologue(Batch (&sets)[NSET], double2 (&hs)[NSET],
-                                           TF (&us)[NSET], std::integer_sequence<int, KK...>) {
+  __device__ __forceinline__ void prologue(Batch<FWD ? KL : KU> (&sets)[NSET],
+                                           double2 (&hs)[NSET], TF (&us)[NSET],
+                                           std::integer_sequence<int, KK...>) {
+    constexpr int W = FWD ? KL : KU;
     // batch k + 1 goes to sets[(k + 1) mod NSET]
-    ((sets[(KK + 1) % NSET] =
-          load_batch(base_of<FWD>(), FWD ? min(KK + 1, nb - 1) : nb - 1 - min(KK + 1, nb - 1))),
+    ((sets[(KK + 1) % NSET] = load_batch<W>(
+          base_of<FWD>(), FWD ? min(KK + 1, nb - 1) : nb - 1 - min(KK + 1, nb - 1))),
      ...);
     ((hs[KK] = refill_row<FWD>(KK)), ...);
     if (FWD) ((us[KK] = uirow(KK * SB + lane)), ...);
@@ -285,9 +364,30 @@ struct Solver4 {
   }
   template <bool FWD, int... KK>
   __device__ __forceinline__ void batches(double2& bw, int i0, const TF* base, bool real_row,
-                                          double2* xo, Batch (&sets)[NSET], double2 (&hs)[NSET],
-                                          TF (&us)[NSET], std::integer_sequence<int, KK...>) {
+                                          double2* xo, Batch<FWD ? KL : KU> (&sets)[NSET],
+                                          double2 (&hs)[NSET], TF (&us)[NSET],
+                                          std::integer_sequence<int, KK...>) {
     (batch<FWD>(bw, i0 + KK, base, real_row, xo, sets[(KK + 1) % NSET], hs[KK], us[KK]), ...);
+  }
+
+  // Row `row` of lanes [L0, L0 + G) is final: store it (backward: the
+  // solution, real rows with zero imaginary part) and take the refill row.
+  template <bool FWD, int L0, int G>
+  __device__ __forceinline__ void retire(double2& bw, int row, bool real_row, double2* xo,
+                                         double2 hr, TF ur) {
+    if (lane >= L0 && lane < L0 + G) {
+      if (valid && row < n) {
+        if (FWD) {
+          hg[row] = mul(ur, bw);
+        } else {
+          double2 v = bw;
+          if (real_row && !GAL) v.y = 0.0;
+          xo[row] = v;
+          if (!GAL) bad = bad || !isfinite(v.x) || !isfinite(v.y);
+        }
+      }
+      bw = hr;
+    }
   }
 
   // Batch i of a sweep.  nxt holds batch i + 1 (staged to the ring now)
@@ -295,51 +395,42 @@ struct Solver4 {
   // refill rows and scalings, reloaded for batch i + NSET.
   template <bool FWD>
   __device__ __forceinline__ void batch(double2& bw, int i, const TF* base, bool real_row,
-                                        double2* xo, Batch& nxt, double2& hr, TF& ur) {
+                                        double2* xo, Batch<FWD ? KL : KU>& nxt, double2& hr,
+                                        TF& ur) {
+    constexpr int W = FWD ? KL : KU;
     const int b = FWD ? i : nb - 1 - i;
     const int slot = i & 1;
     // next batch to the ring, and the batch NSET after it in flight
-    if (i + 1 < nb) stage((i + 1) & 1, nxt);
+    if (i + 1 < nb) stage<W>((i + 1) & 1, nxt);
     {
       const int inext = min(i + 1 + NSET, nb - 1);
-      nxt = load_batch(base, FWD ? inext : nb - 1 - inext);
+      nxt = load_batch<W>(base, FWD ? inext : nb - 1 - inext);
     }
     const int row = b * SB + lane;          // this lane's row in batch b
     if (FWD) {
       fhalf<0>(bw, slot, std::make_integer_sequence<int, 8>{});
-      if (lane < 8) {                        // rows b SB + 0..7 are final
-        if (valid && row < n) hg[row] = mul(ur, bw);
-        bw = hr;
-      }
+      retire<true, 0, 8>(bw, row, real_row, xo, hr, ur);      // rows b SB + 0..7 are final
       fhalf<8>(bw, slot, std::make_integer_sequence<int, 8>{});
-      if (lane >= 8) {
-        if (valid && row < n) hg[row] = mul(ur, bw);
-        bw = hr;
-      }
+      retire<true, 8, 8>(bw, row, real_row, xo, hr, ur);
       // refills and scalings of batch i + NSET
       const int rn = (b + NSET + 1) * SB + lane;
       hr = (rn < q) ? hrow(rn) : z2();
       ur = uirow((b + NSET) * SB + lane);
     } else {
-      bhalf<8>(bw, slot, std::make_integer_sequence<int, 8>{});   // columns 15..8
-      if (lane >= 8) {                       // rows b SB + 8..15 are final
-        if (valid && row < n) {
-          double2 v = bw;
-          if (real_row) v.y = 0.0;
-          xo[row] = v;
-          bad = bad || !isfinite(v.x) || !isfinite(v.y);
-        }
-        bw = hr;
-      }
-      bhalf<0>(bw, slot, std::make_integer_sequence<int, 8>{});   // columns 7..0
-      if (lane < 8) {
-        if (valid && row < n) {
-          double2 v = bw;
-          if (real_row) v.y = 0.0;
-          xo[row] = v;
-          bad = bad || !isfinite(v.x) || !isfinite(v.y);
-        }
-        bw = hr;
+      if constexpr (KU <= 8) {   // two groups of eight columns
+        bgroup<8>(bw, slot, std::make_integer_sequence<int, 8>{});   // columns 15..8
+        retire<false, 8, 8>(bw, row, real_row, xo, hr, ur);          // rows b SB + 8..15 are final
+        bgroup<0>(bw, slot, std::make_integer_sequence<int, 8>{});   // columns 7..0
+        retire<false, 0, 8>(bw, row, real_row, xo, hr, ur);
+      } else {                   // four groups of four columns
+        bgroup<12>(bw, slot, std::make_integer_sequence<int, 4>{});
+        retire<false, 12, 4>(bw, row, real_row, xo, hr, ur);
+        bgroup<8>(bw, slot, std::make_integer_sequence<int, 4>{});
+        retire<false, 8, 4>(bw, row, real_row, xo, hr, ur);
+        bgroup<4>(bw, slot, std::make_integer_sequence<int, 4>{});
+        retire<false, 4, 4>(bw, row, real_row, xo, hr, ur);
+        bgroup<0>(bw, slot, std::make_integer_sequence<int, 4>{});
+        retire<false, 0, 4>(bw, row, real_row, xo, hr, ur);
       }
       const int rn = (b - NSET - 1) * SB + lane;
       hr = (rn >= 0) ? hrow(rn) : z2();
@@ -464,10 +555,15 @@ __global__ __launch_bounds__(256) void transpose_factors_kernel(const TF* __rest
 // ids to the eight XCDs round robin) and back to back, so each XCD reads
 // a factor batch from HBM once for all runs:
 //   id = ((b / 8) nmem + run) 8 + b % 8,   b < nb (padded ids exit).
+// GAL: the Galerkin bands (8 / 12 and 4 / 6 diagonals, no border).
+template <bool GAL>
 __global__ __launch_bounds__(64) void solve_np_kernel(Geom g, FactorSet<double2> Fp,
                                                       FactorSet<double> Fr, double2* rhs,
                                                       RhsSpec rs, int qp, int qr) {
-  __shared__ double2 ring_mem[2 * 4 * (SB * 8 + 1)];
+  using SolverP = Solver4<double2, 4, 8, GAL ? 12 : 8, GAL>;
+  using SolverR = Solver4<double, 2, 4, GAL ? 6 : 4, GAL>;
+  __shared__ double2 ring_mem[2 * 4 * SolverP::SYS_CH];
+  static_assert(SolverR::SYS_CH <= SolverP::SYS_CH, "ring too small for the real systems");
   const int M = g.M, K = g.K;
   const int nbp = (M - 1 + 3) / 4;
   const int nb = nbp + (M + 1 + 3) / 4;
@@ -481,7 +577,7 @@ __global__ __launch_bounds__(64) void solve_np_kernel(Geom g, FactorSet<double2>
   rs.out_psi += moff;
   rs.out_th += moff;
   if (b < nbp) {
-    Solver4<double2, 4, 8> s{Fp, rs.out_psi, rs.out_th, M, K};
+    SolverP s{Fp, rs.out_psi, rs.out_th, M, K};
     s.kind = 0;
     s.sys0 = 4 * b;
     s.so0 = s.sys0;
@@ -495,7 +591,7 @@ __global__ __launch_bounds__(64) void solve_np_kernel(Geom g, FactorSet<double2>
     s.run(s.out_ptr());
     nf_mark(g.nf, s.bad, rs.tag);
   } else {
-    Solver4<double, 2, 4> s{Fr, rs.out_psi, rs.out_th, M, K};
+    SolverR s{Fr, rs.out_psi, rs.out_th, M, K};
     const int r0 = 4 * (b - nbp);              // first real-system index
     s.kind = (r0 == 0) ? 1 : 2;                // the zonal flow leads the first block
     s.sys0 = (M - 1) + r0;
@@ -589,11 +685,18 @@ bool launch_solve_adjoint_np(const Geom& g, const FactorSet<double2>& FpT,
 }
 
 bool launch_solve_np(const Geom& g, const FactorSet<double2>& Fp, const FactorSet<double>& Fr,
-                     double2* rhs, const RhsSpec& rs, int qp, int qr, hipStream_t st) {
+                     double2* rhs, const RhsSpec& rs, int qp, int qr, bool galerkin,
+                     hipStream_t st) {
   if (qp % (NSET * SB) || qr % (NSET * SB)) return false;
+  if (galerkin && !Fp.gam) return false;
   const int nb = (g.M - 1 + 3) / 4 + (g.M + 1 + 3) / 4;
   const int blocks = 8 * ((nb + 7) / 8) * g.nmem;
-  hipLaunchKernelGGL(solve_np_kernel, dim3(blocks), dim3(64), 0, st, g, Fp, Fr, rhs, rs, qp, qr);
+  if (galerkin)
+    hipLaunchKernelGGL(solve_np_kernel<true>, dim3(blocks), dim3(64), 0, st, g, Fp, Fr, rhs, rs,
+                       qp, qr);
+  else
+    hipLaunchKernelGGL(solve_np_kernel<false>, dim3(blocks), dim3(64), 0, st, g, Fp, Fr, rhs, rs,
+                       qp, qr);
   return true;
 }
 

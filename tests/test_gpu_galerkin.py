@@ -1,0 +1,172 @@
+"""GPU parity of the Galerkin bases (qg_params.method = 1; Sect. 3.2.2,
+eq. psiint_galerkin, uphi_galerkin, temp_galerkin, Appendix B) through the
+C ABI.
+
+The Galerkin formulation solves for the same Chebyshev coefficients as the
+tau formulation (oracle.galerkin), so both are held to the same
+extended-precision references of tests/golden/reference, here with the
+rounding spread of the two FP64 Galerkin implementations of the oracle
+(with and without row interchanges; tests/refcheck.py).  Where every FP64
+implementation is within 1e-12 of the reference (the small cases), the GPU
+run is also compared with the live FP64 Galerkin oracle at 1e-11.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import refcheck
+from oracle.operators import tau_rows_dirichlet, tau_rows_psi
+from oracle.step import QGOracle
+from paper_1902_07092_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-11
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def qg():
+    import torch
+    assert torch.cuda.is_available(), "GPU test needs a HIP device"
+    from paper_1902_07092_amd import qg as mod
+    mod.load()
+    return mod
+
+
+def _rel(a, b):
+    scale = np.abs(b).max()
+    return float(np.abs(a - b).max() / scale) if scale > 0 else float(
+        np.abs(a).max())
+
+
+def _run(qg, w, scheme, nsteps, method="galerkin"):
+    s = qg.QGSolver(w.E, w.Ra, w.Pr, w.eta, w.n_phi, w.n_r, w.n_c,
+                    method=method)
+    st = inputs.workload_state(w)
+    s.set_state(st.psi, st.theta, st.uphi0)
+    s.step(w.dt, scheme, nsteps)
+    return s
+
+
+def _vs_reference(case, state):
+    ref = refcheck.load(case)
+    if "galerkin_err_sampled" not in ref:
+        pytest.skip(f"no Galerkin FP64 errors stored for {case}")
+    err, _ = refcheck.check(ref, state, method="galerkin")
+    _say(f"  vs reference: {refcheck.report(ref, err, 'galerkin')}")
+    _say(f"  (tau: {refcheck.report(ref, refcheck.fp64_spread(ref)[0])})")
+    return err
+
+
+def _boundary_residual(state, K):
+    """Largest boundary-row residual of a state relative to its size:
+    the Galerkin state satisfies the boundary conditions by construction."""
+    psi, th, up = state
+    bp, bd = tau_rows_psi(K), tau_rows_dirichlet(K)
+    r = [np.abs(psi @ bp.T).max() / (np.abs(psi).max() * np.abs(bp).max(axis=1).max()),
+         np.abs(th @ bd.T).max() / np.abs(th).max(),
+         np.abs(bd @ up).max() / max(np.abs(up).max(), 1e-300)]
+    return max(float(x) for x in r)
+
+
+@pytest.mark.parametrize("scheme,nsteps", [("cnab2", 1), ("cnab2", 20),
+                                           ("bpr353", 5), ("ars222", 6),
+                                           ("ars443", 5), ("sbdf2", 8),
+                                           ("sbdf3", 8), ("sbdf4", 8),
+                                           ("cnab2", 100)])
+def test_small_galerkin_parity(qg, scheme, nsteps):
+    w = inputs.SMALL
+    _say(f"[galerkin] small {w.n_phi}x{w.n_r} {scheme} x{nsteps}")
+    s = _run(qg, w, scheme, nsteps)
+    o = QGOracle(w.E, w.Ra, w.Pr, w.eta, w.n_phi, w.n_r, w.n_c,
+                 method="galerkin")
+    st = inputs.workload_state(w)
+    o.set_state(st.psi, st.theta, st.uphi0)
+    o.step(w.dt, scheme, nsteps)
+    got = s.get_state()
+    err = {f: _rel(a, b) for f, a, b in zip(refcheck.FIELDS, got,
+                                            (o.psi, o.theta, o.uphi))}
+    _say(f"  rel err against the FP64 Galerkin oracle {err}")
+    assert max(err.values()) < TOL, err
+    _vs_reference(f"small_{scheme}_{nsteps}", got)
+    res = _boundary_residual(got, w.n_c)
+    _say(f"  boundary-row residual {res:.2e}")
+    assert res < 1e-13
+    d = s.diagnostics()
+    assert d["pivoted"] == 0 and 1.0 <= d["growth"] <= 1e4
+
+
+def test_galerkin_equals_tau_on_gpu(qg):
+    """The two formulations on the GPU, 20 CNAB2 steps of the small
+    workload: the same coefficients to rounding."""
+    w = inputs.SMALL
+    a = _run(qg, w, "cnab2", 20)
+    b = _run(qg, w, "cnab2", 20, method="tau")
+    err = {f: _rel(x, y) for f, x, y in zip(refcheck.FIELDS, a.get_state(),
+                                            b.get_state())}
+    _say(f"[galerkin] Galerkin vs tau on the GPU: {err}")
+    assert max(err.values()) < 1e-12, err
+
+
+@pytest.mark.parametrize("nsteps", [2, 20])
+def test_medium_galerkin_parity(qg, nsteps):
+    w = inputs.MEDIUM
+    _say(f"[galerkin] medium {w.n_phi}x{w.n_r} bpr353 x{nsteps}")
+    s = _run(qg, w, "bpr353", nsteps)
+    _vs_reference(f"medium_bpr353_{nsteps}", s.get_state())
+    assert _boundary_residual(s.get_state(), w.n_c) < 1e-12
+
+
+def test_large_galerkin_parity(qg):
+    """3072 x 1025, two CNAB2 steps, in the benchmark's launch
+    configuration."""
+    w = inputs.LARGE
+    _say(f"[galerkin] large {w.n_phi}x{w.n_r} cnab2 x2")
+    s = _run(qg, w, "cnab2", 2)
+    _vs_reference("large_cnab2_2", s.get_state())
+    d = s.diagnostics()
+    _say(f"  growth {d['growth']:.3g}")
+    assert d["pivoted"] == 0 and 1.0 <= d["growth"] <= 1e4
+
+
+def test_ensemble_galerkin_member(qg):
+    """Ensemble member 7 (192 x 65) with the Galerkin bases inside a
+    mixed ensemble (tau and Galerkin members form separate groups)."""
+    mem = inputs.ensemble_workloads()[7]
+    members = [dict(E=mem.E, Ra=mem.Ra, Pr=mem.Pr, eta=mem.eta,
+                    n_phi=mem.n_phi, n_r=mem.n_r, n_c=mem.n_c, method=m)
+               for m in ("galerkin", "tau")]
+    ens = qg.QGEnsemble(members)
+    st = inputs.workload_state(mem)
+    for i in range(2):
+        ens.set_state(i, st.psi, st.theta, st.uphi0)
+    ens.step(mem.dt, "cnab2", 10)
+    got = ens.get_state(0)
+    _say(f"[galerkin] ensemble member 7, cnab2 x10")
+    _vs_reference("ensemble7_cnab2_10", got)
+    tau = ens.get_state(1)
+    err = {f: _rel(x, y) for f, x, y in zip(refcheck.FIELDS, got, tau)}
+    _say(f"  Galerkin vs tau member {err}")
+    assert err["psi"] < 1e-11 and err["theta"] < 1e-12
+
+
+def test_galerkin_statuses(qg):
+    w = inputs.SMALL
+    with pytest.raises(qg.QGError) as e:
+        qg.QGSolver(w.E, w.Ra, w.Pr, w.eta, w.n_phi, w.n_r, w.n_c,
+                    method="galerkin", pivoting=1)
+    assert e.value.status == qg.QG_EUNSUPPORTED
+    s = _run(qg, w, "cnab2", 1)
+    with pytest.raises(qg.QGError) as e:
+        s.gradient(w.dt, 2)
+    assert e.value.status == qg.QG_EUNSUPPORTED
+    # the energy integral alone needs no adjoint solve
+    st = inputs.workload_state(w)
+    s.set_state(st.psi, st.theta, st.uphi0)
+    assert s.energy_integral(w.dt, 2) > 0
