@@ -18,7 +18,13 @@ Readings (where the paper is silent or inconsistent):
       N_omega = u_s d_s omega + (u_phi/s) d_phi omega + omega dPsi/dphi,
       N_theta = u_s (d_s theta + dTc/ds) + (u_phi/s) d_phi theta,
     the second one carrying the background advection u_s dTc/ds of eq. temp.
-  * Buoyancy and background advection are explicit (allowed by Sect. 4).
+  * Buoyancy and background advection are explicit (allowed by Sect. 4),
+    unless buoyancy="implicit": then the buoyancy term (Ra/Pr)(i m/s_o) C
+    theta belongs to the implicit operator L (and leaves E_psi), and every
+    implicit solve advances theta first and then Psi with the new theta's
+    buoyancy on its right-hand side (the order Sect. 4 gives: the
+    temperature system does not involve Psi, so the coupled system is
+    block triangular).
   * Chebyshev coefficients n >= N_c of every nonlinear term are zeroed
     (radial dealiasing, Sect. 3.2.1); N_c = floor(2(N_r-1)/3) by default.
   * Multistep schemes carry the mass matrix (A_m or D) on both sides of
@@ -143,9 +149,13 @@ class QGOracle:
     Chebyshev coefficients (FP64 only)."""
 
     def __init__(self, E, Ra, Pr, eta, n_phi, n_r, n_c=None, ekman_eps=None,
-                 dtype=np.float64, pivot=True, method="tau"):
+                 dtype=np.float64, pivot=True, method="tau",
+                 buoyancy="explicit"):
         if method not in ("tau", "galerkin"):
             raise ValueError(method)
+        if buoyancy not in ("explicit", "implicit"):
+            raise ValueError(buoyancy)
+        self.implicit_buoyancy = buoyancy == "implicit"
         if method == "galerkin" and dtype is not np.float64:
             raise ValueError("the Galerkin solves are FP64 only")
         self.method = method
@@ -203,8 +213,17 @@ class QGOracle:
             mp[m] = o.A(m) @ psi[m]
         return mp, theta @ o.D.T, o.D @ uphi
 
+    def buoyancy(self, theta):
+        """C [(Ra/Pr)(i m/s_o) theta] for every m (row 0 zero)."""
+        d = self.rdt
+        im = 1j * self.mvec[:, None]
+        b = ((d(self.Ra) / d(self.Pr)) * im / self.s_o * theta) @ self.ops.C.T
+        b[0] = 0
+        return b
+
     def linear(self, psi, theta, uphi):
-        """Implicit operator L y: B_m Psi, F_m theta / Pr, E u."""
+        """Implicit operator L y: B_m Psi (+ the buoyancy of theta when it
+        is implicit), F_m theta / Pr, E u."""
         o = self.ops
         lp = np.zeros_like(psi)
         lt = np.zeros_like(theta)
@@ -212,6 +231,8 @@ class QGOracle:
             if m:
                 lp[m] = o.B(m, self.E) @ psi[m]
             lt[m] = o.F(m) @ theta[m] / self.Pr
+        if self.implicit_buoyancy:
+            lp = lp + self.buoyancy(theta)
         return lp, lt, o.E @ uphi
 
     def factor(self, a_dt):
@@ -255,11 +276,17 @@ class QGOracle:
         band systems, whose right-hand sides have no such rows."""
         fp, ft, fu = self.factor(a_dt)
         c128 = np.complex128
+        theta = np.stack([ft[m].solve(rt[m].astype(c128))
+                          for m in range(self.M)])
+        if self.implicit_buoyancy:
+            # (A - a dt B) Psi = r + a dt C[(Ra/Pr)(i m/s_o) theta_new]
+            # (rows 4.. only: the tau rows keep their given values)
+            rp = rp.astype(c128, copy=True)
+            rp[:, 4:] += (a_dt * self.buoyancy(
+                theta.astype(self.cdt))).astype(c128)[:, 4:]
         psi = np.zeros(rp.shape, c128)
         for m in range(1, self.M):
             psi[m] = fp[m].solve(rp[m].astype(c128))
-        theta = np.stack([ft[m].solve(rt[m].astype(c128))
-                          for m in range(self.M)])
         return psi, theta, fu.solve(ru.astype(np.float64))
 
     def _apply_bordered(self, a_dt, xp, xt, xu):
@@ -280,6 +307,8 @@ class QGOracle:
         yp = (S["A0"] @ X + (S["A2"] @ X) * m2
               - a * (S["B0"] @ X + (S["B2"] @ X) * m2 + (S["B4"] @ X) * m2 * m2
                      + (S["C"] @ X) * (1j * (d(2) * m / d(self.E)))))
+        if self.implicit_buoyancy:
+            yp = yp - a * self.buoyancy(xt).T
         yp[:4] = self.bc_psi @ X
         T = xt.T
         yt = S["D"] @ T - (a / d(self.Pr)) * (S["F0"] @ T + (S["F2"] @ T) * m2)
@@ -414,8 +443,11 @@ class QGOracle:
             Nu = Nu + Fk[0].real
         o = self.ops
         d = self.rdt
-        buoy = (d(self.Ra) / d(self.Pr)) * im / self.s_o * theta
-        Ep = (buoy + Nom) @ o.C.T
+        if self.implicit_buoyancy:      # buoyancy is in L
+            Ep = Nom @ o.C.T
+        else:
+            buoy = (d(self.Ra) / d(self.Pr)) * im / self.s_o * theta
+            Ep = (buoy + Nom) @ o.C.T
         Ep[0] = 0
         Et = -(Nth @ o.D.T)
         Eu = -(o.D @ Nu)
