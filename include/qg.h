@@ -136,6 +136,18 @@ typedef struct {
                         reverse-mode entries (qg_gradient,
                         qg_adjoint_explicit, qg_adjoint_solve) return
                         QG_EUNSUPPORTED. */
+  int buoyancy;  /* buoyancy term of the vorticity equation (Sect. 4):
+                    0 = explicit, with the advection (E_psi carries
+                        C[(Ra/Pr)(i m/s_o) theta]);
+                    1 = implicit: the term belongs to the implicit operator
+                        (Crank-Nicolson in CNAB2, the implicit tableau in a
+                        DIRK stage, b_0 in SBDF) and every implicit solve
+                        advances theta first, then Psi with a dt C[(Ra/Pr)
+                        (i m/s_o) theta_new] added to its right-hand side.
+                        Needs the unpivoted factors (pivoting = 1, or a
+                        factorisation that falls back to pivoting, gives
+                        QG_EUNSUPPORTED); the tangent-linear and
+                        reverse-mode entries return QG_EUNSUPPORTED. */
 } qg_params;
 
 typedef struct {

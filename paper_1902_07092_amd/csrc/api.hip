@@ -33,9 +33,9 @@ bool launch_solve(const Geom& g, const FactorSet<double2>& Fp, const FactorSet<d
                   double2* rhs, const RhsSpec& rs, int kutp, int kutr, bool pivoted,
                   hipStream_t st);
 int solve_batch();
-bool launch_solve_np(const Geom& g, const FactorSet<double2>& Fp, const FactorSet<double>& Fr,
-                     double2* rhs, const RhsSpec& rs, int qp, int qr, bool galerkin,
-                     hipStream_t st);
+bool launch_solve_np(const Geom& g, const Bands& bd, const FactorSet<double2>& Fp,
+                     const FactorSet<double>& Fr, double2* rhs, const RhsSpec& rs, int qp, int qr,
+                     bool galerkin, hipStream_t st);
 int solve_np_pad();
 bool launch_explicit_T(const Geom& g, const Bands& b, const double2* X, const double* G,
                        const double2* Ea, const double2* Eb, double ca, double cb, size_t mk,
@@ -166,6 +166,7 @@ bool sizes_of(const qg_params* p, Sizes& z, std::string& why) {
   if (p->pivoting != 0 && p->pivoting != 1) { why = "pivoting must be 0 or 1"; return false; }
   if (p->ekman != 0 && p->ekman != 1) { why = "ekman must be 0 or 1"; return false; }
   if (p->method != 0 && p->method != 1) { why = "method must be 0 (tau) or 1 (Galerkin)"; return false; }
+  if (p->buoyancy != 0 && p->buoyancy != 1) { why = "buoyancy must be 0 (explicit) or 1 (implicit)"; return false; }
   if (p->ekman && !(p->eps > 0 && std::isfinite(p->eps))) {
     why = "eps must be positive with Ekman pumping";
     return false;
@@ -712,6 +713,10 @@ qg_status explicit_terms(qg_ctx* ctx, const double2* psi, const double2* th, dou
 qg_status implicit_solve(qg_ctx* ctx, const RhsSpec& rs_in, double2* rhs = nullptr) {
   RhsSpec rs = rs_in;
   rs.tag = ctx->tag;
+  rs.buoy_adt = ctx->g.buoy_implicit ? ctx->factored_adt : 0.0;
+  if (ctx->g.buoy_implicit && ctx->pivoted)
+    return fail(ctx, QG_EUNSUPPORTED,
+                "implicit buoyancy needs the unpivoted factors (growth factor above the bound)");
   if (!rhs) rhs = ctx->ptr2(ctx->w.rhs);
   timed(ctx, K_RHS, [&] { launch_rhs(ctx->g, ctx->b, rs, rhs, ctx->band_mch, ctx->st); });
   bool ok = true;
@@ -719,7 +724,7 @@ qg_status implicit_solve(qg_ctx* ctx, const RhsSpec& rs_in, double2* rhs = nullp
     ok = ctx->pivoted
              ? launch_solve(ctx->g, ctx->Fp, ctx->Fr, rhs, rs, ctx->kutp, ctx->kutr, true,
                             ctx->st)
-             : launch_solve_np(ctx->g, ctx->Fp, ctx->Fr, rhs, rs, ctx->z.q4, ctx->z.q2, ctx->galerkin,
+             : launch_solve_np(ctx->g, ctx->b, ctx->Fp, ctx->Fr, rhs, rs, ctx->z.q4, ctx->z.q2, ctx->galerkin,
                                ctx->st);
   });
   if (!ok) return fail(ctx, QG_EUNSUPPORTED, "no solve kernel for this band width");
@@ -989,6 +994,7 @@ qg_status create_ctx(qg_ctx** out, const qg_params* p, int nmem, const double* r
   const bool mixed = p->precision == 1;
   if (z.nphi % 6 || !transform_sizes_ok(2 * (z.R - 1), z.nphi, mixed)) return QG_EUNSUPPORTED;
   if (z.gal && p->pivoting) return QG_EUNSUPPORTED;   // Galerkin bands: no row interchanges
+  if (p->buoyancy && p->pivoting) return QG_EUNSUPPORTED;   // the coupled solve is unpivoted
   if (!workspace || ((uintptr_t)workspace & 255)) return QG_EINVAL;
   WsMap w = map_workspace(z, nmem, single);
   if (workspace_bytes < w.total) return QG_ENOMEM;
@@ -1102,6 +1108,7 @@ qg_status create_ctx(qg_ctx** out, const qg_params* p, int nmem, const double* r
   g.pump_so2e = z.pump ? (s_o + p->eps) * (s_o + p->eps) : 0.0;
   g.half_E = 0.5 * p->E;
   g.nf = single ? ctx->nf_flag() : nullptr;
+  g.buoy_implicit = p->buoyancy == 1;
   g.ra_pr = ctx->ptrd(w.ra);
   g.xk = ctx->ptrd(w.xk);
   g.wq = ctx->ptrd(w.wq);
@@ -1428,6 +1435,8 @@ qg_status qg_step(qg_ctx* ctx, double dt, int scheme, int nsteps) {
 qg_status qg_tangent_set(qg_ctx* ctx, const double* dpsi, const double* dtheta,
                          const double* duphi, int on_device) {
   if (!ctx) return QG_EINVAL;
+  if (ctx->g.buoy_implicit)
+    return fail(ctx, QG_EUNSUPPORTED, "tangent and adjoint runs need explicit buoyancy");
   if (ctx->nmem != 1) return fail(ctx, QG_EINVAL, "tangent runs need a single-run context");
   double dmax = 0.0;
   qg_status s = load_state(ctx, dpsi, dtheta, duphi, on_device, ctx->tng(0), ctx->tng(0) + ctx->mk(),
@@ -1460,6 +1469,8 @@ qg_status qg_adjoint_solve(qg_ctx* ctx, double dt, double* psi, double* theta, d
     return fail(ctx, QG_EUNSUPPORTED, "adjoint solves use the unpivoted factors");
   if (ctx->galerkin)
     return fail(ctx, QG_EUNSUPPORTED, "adjoint solves need the tau formulation");
+  if (ctx->g.buoy_implicit)
+    return fail(ctx, QG_EUNSUPPORTED, "tangent and adjoint runs need explicit buoyancy");
   const Sizes& z = ctx->z;
   const size_t MK = (size_t)z.M * z.K;
   std::vector<double2> hp(MK);
@@ -1482,6 +1493,8 @@ qg_status qg_adjoint_solve(qg_ctx* ctx, double dt, double* psi, double* theta, d
 qg_status qg_adjoint_mass_lin(qg_ctx* ctx, double c, double* psi, double* theta,
                               double* uphi, int on_device) {
   if (!ctx) return QG_EINVAL;
+  if (ctx->g.buoy_implicit)
+    return fail(ctx, QG_EUNSUPPORTED, "tangent and adjoint runs need explicit buoyancy");
   if (ctx->nmem != 1) return fail(ctx, QG_EINVAL, "adjoint products need a single-run context");
   if (!psi || !theta || !uphi) return fail(ctx, QG_EINVAL, "null pointer");
   if (!std::isfinite(c)) return fail(ctx, QG_EINVAL, "c must be finite");
@@ -1513,6 +1526,8 @@ qg_status qg_tangent_get(qg_ctx* ctx, double* dpsi, double* dtheta, double* duph
 
 qg_status qg_step_tangent(qg_ctx* ctx, double dt, int nsteps) {
   if (!ctx) return QG_EINVAL;
+  if (ctx->g.buoy_implicit)
+    return fail(ctx, QG_EUNSUPPORTED, "tangent and adjoint runs need explicit buoyancy");
   qg_status s = check_step_args(ctx, dt, QG_CNAB2, nsteps);
   if (s != QG_OK) return s;
   if (!ctx->t_set) return fail(ctx, QG_ESTATE, "no tangent state (qg_tangent_set)");
@@ -1797,6 +1812,8 @@ qg_status reverse_ok(qg_ctx* ctx) {
     return fail(ctx, QG_EINVAL, "reverse mode needs a single-run context");
   if (ctx->mixed) return fail(ctx, QG_EUNSUPPORTED, "reverse mode runs in FP64 only");
   if (ctx->z.pump) return fail(ctx, QG_EUNSUPPORTED, "reverse mode has no Ekman pumping terms");
+  if (ctx->g.buoy_implicit)
+    return fail(ctx, QG_EUNSUPPORTED, "reverse mode transposes the explicit buoyancy");
   return QG_OK;
 }
 
@@ -1877,6 +1894,8 @@ qg_status gradient_run(qg_ctx* ctx, double dt, int N, int C, double ew, const do
     return fail(ctx, QG_EUNSUPPORTED, "the adjoint solves use the unpivoted factors");
   if (grad && ctx->galerkin)
     return fail(ctx, QG_EUNSUPPORTED, "the adjoint solves need the tau formulation");
+  if (grad && ctx->g.buoy_implicit)
+    return fail(ctx, QG_EUNSUPPORTED, "tangent and adjoint runs need explicit buoyancy");
   const size_t XS = (size_t)6 * ctx->z.R * M;   // entries of one X
   const size_t GS = (size_t)6 * ctx->z.R * ctx->z.nphi;
   const int slots = grad_slots(N, C);
@@ -2188,7 +2207,8 @@ qg_status efail(qg_ensemble* e, qg_status s, const std::string& msg) {
 bool same_group(const qg_params& a, const qg_params& b, const Sizes& za, const Sizes& zb) {
   return a.E == b.E && a.Pr == b.Pr && a.eta == b.eta && za.nphi == zb.nphi && za.R == zb.R &&
          za.K == zb.K && a.precision == b.precision && a.pivoting == b.pivoting &&
-         a.ekman == b.ekman && (!a.ekman || a.eps == b.eps) && a.method == b.method;
+         a.ekman == b.ekman && (!a.ekman || a.eps == b.eps) && a.method == b.method &&
+         a.buoyancy == b.buoyancy;
 }
 
 struct Grouping {

@@ -4,7 +4,8 @@
 // zonal flow (eq. uphi_int: Mass = D, Lin = E) and theta (eq. temp_int:
 // Mass = D, Lin = F_m / Pr).  alpha = 1 gives the right-hand side of an
 // implicit solve (CNAB2, BPR353 stages); alpha = 0, cL = 1 the product
-// Lin y of a new stage value (BPR353).
+// Lin y of a new stage value (BPR353).  With implicit buoyancy (Sect. 4)
+// Lin of Psi also carries C[(Ra/Pr)(i m/s_o) theta] (BUOY).
 //
 // The operators split in powers of m (A_m = A0 + m^2 A2, B_m = B0 + m^2 B2
 // + m^4 B4 + (2/E) i m C, F_m = F0 + m^2 F2), so a thread keeps the
@@ -40,7 +41,7 @@ __device__ __forceinline__ double2 ld(const double2* p, int i, int K) {
 // sys_out: out rows are system indices (Psi m -> m - 1, zonal -> M - 1,
 // theta m -> M + m) in out_psi; else out_psi[m] (Psi, zonal at m = 0) and
 // out_th[m].
-template <int MCH>
+template <int MCH, bool BUOY>
 __global__ __launch_bounds__(64) void band_kernel(Geom g, Bands b, RhsSpec rs, double alpha,
                                                   double2* __restrict__ out_psi,
                                                   double2* __restrict__ out_th, int sys_out) {
@@ -55,7 +56,7 @@ __global__ __launch_bounds__(64) void band_kernel(Geom g, Bands b, RhsSpec rs, d
   out_psi += sys_out ? 2 * moff : moff;
   if (!sys_out) out_th += moff;
   if (kind == 0) {
-    double P0[BW], P1[BW], P2[BW], P3[BW];
+    double P0[BW], P1[BW], P2[BW], P3[BW], PC[BUOY ? BW : 1];
 #pragma unroll
     for (int o = 0; o < BW; ++o) {
       const size_t i = (size_t)o * K + k;
@@ -63,7 +64,9 @@ __global__ __launch_bounds__(64) void band_kernel(Geom g, Bands b, RhsSpec rs, d
       P1[o] = alpha * b.A2[i] + cL * b.B2[i];
       P2[o] = cL * b.B4[i];
       P3[o] = cL * g.two_over_E * b.C[i];
+      if constexpr (BUOY) PC[o] = cL * b.C[i];
     }
+    const double ra_pr = g.ra_pr ? g.ra_pr[mem] : g.Ra_Pr;
     for (int i = 0; i < MCH; ++i) {
       const int m = 1 + u0 + i;
       if (m >= M) break;
@@ -78,6 +81,19 @@ __global__ __launch_bounds__(64) void band_kernel(Geom g, Bands b, RhsSpec rs, d
           const double2 v = ld(y, k + o - 8, K);
           acc.x += re * v.x - im * v.y;
           acc.y += re * v.y + im * v.x;
+        }
+        if constexpr (BUOY) {   // cL C[(Ra/Pr)(i m/s_o) theta]
+          const double2* th = rs.base_th + moff + (size_t)m * K;
+          double2 cb = make_double2(0.0, 0.0);
+#pragma unroll
+          for (int o = 0; o < BW; ++o) {
+            const double2 v = ld(th, k + o - 8, K);
+            cb.x += PC[o] * v.x;
+            cb.y += PC[o] * v.y;
+          }
+          const double gb = ra_pr * dm / g.s_o;
+          acc.x -= gb * cb.y;
+          acc.y += gb * cb.x;
         }
         for (int q = 0; q < rs.nterm; ++q) {
           const double2 v = rs.term_psi[q][moff + (size_t)m * K + k];
@@ -133,23 +149,36 @@ dim3 band_grid(const Geom& g, int mch) {
   return dim3((g.K + RB - 1) / RB, chunks, 2 * g.nmem);
 }
 
-void launch_band(const Geom& g, const Bands& b, const RhsSpec& rs, double alpha, double2* o1,
-                 double2* o2, int sys_out, int mch, hipStream_t st) {
+template <bool BUOY>
+void launch_band_t(const Geom& g, const Bands& b, const RhsSpec& rs, double alpha, double2* o1,
+                   double2* o2, int sys_out, int mch, hipStream_t st) {
   const dim3 grid = band_grid(g, mch);
   switch (mch) {
     case 4:
-      hipLaunchKernelGGL(band_kernel<4>, grid, dim3(RB), 0, st, g, b, rs, alpha, o1, o2, sys_out);
+      hipLaunchKernelGGL((band_kernel<4, BUOY>), grid, dim3(RB), 0, st, g, b, rs, alpha, o1, o2,
+                         sys_out);
       break;
     case 8:
-      hipLaunchKernelGGL(band_kernel<8>, grid, dim3(RB), 0, st, g, b, rs, alpha, o1, o2, sys_out);
+      hipLaunchKernelGGL((band_kernel<8, BUOY>), grid, dim3(RB), 0, st, g, b, rs, alpha, o1, o2,
+                         sys_out);
       break;
     case 32:
-      hipLaunchKernelGGL(band_kernel<32>, grid, dim3(RB), 0, st, g, b, rs, alpha, o1, o2, sys_out);
+      hipLaunchKernelGGL((band_kernel<32, BUOY>), grid, dim3(RB), 0, st, g, b, rs, alpha, o1, o2,
+                         sys_out);
       break;
     default:
-      hipLaunchKernelGGL(band_kernel<16>, grid, dim3(RB), 0, st, g, b, rs, alpha, o1, o2, sys_out);
+      hipLaunchKernelGGL((band_kernel<16, BUOY>), grid, dim3(RB), 0, st, g, b, rs, alpha, o1, o2,
+                         sys_out);
       break;
   }
+}
+
+void launch_band(const Geom& g, const Bands& b, const RhsSpec& rs, double alpha, double2* o1,
+                 double2* o2, int sys_out, int mch, hipStream_t st) {
+  if (g.buoy_implicit)
+    launch_band_t<true>(g, b, rs, alpha, o1, o2, sys_out, mch, st);
+  else
+    launch_band_t<false>(g, b, rs, alpha, o1, o2, sys_out, mch, st);
 }
 }  // namespace
 

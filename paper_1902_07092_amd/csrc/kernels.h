@@ -40,6 +40,10 @@ struct Geom {
   // every kernel of the step sequence returns at once, so that nothing
   // after the failing step overwrites the last finite state or history.
   int* nf;
+  // Implicit buoyancy (Sect. 4): the analysis leaves C[(Ra/Pr)(i m/s_o)
+  // theta] out of E_psi, the band products put it into Lin, and the solve
+  // advances theta before Psi.
+  int buoy_implicit;
 };
 
 // True when the non-finite guard is set: the kernel must return.
@@ -93,6 +97,8 @@ struct RhsSpec {
   double2* lin_psi;          // optional: Lin y_new (nullptr: not needed)
   double2* lin_th;
   int tag;                   // non-finite tag of this step (Geom::nf)
+  double buoy_adt;           // implicit buoyancy: a dt of the solve (Psi gets
+                             // a dt C[(Ra/Pr)(i m/s_o) theta_new]); else 0
 };
 
 // A linear combination of up to MAX_LEVELS arrays (multistep levels).

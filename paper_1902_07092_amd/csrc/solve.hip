@@ -290,30 +290,52 @@ struct Solver4 {
     bw = hrow((nb - 1) * SB + lane);
     sweep<false>(bw);
     __threadfence();   // x~ rows of the other lanes of the group
-    if (!valid) return;
+    // Row k = lane + 16 t needs x~_{k-i}, i <= 4: lane (lane - i) mod 16
+    // holds it, in this chunk of 16 rows or (lane < i) in the previous one.
+    // Each lane loads only its own rows, eight chunks per round with every
+    // load in flight before the first is used; the neighbours come by
+    // shuffles within the 16-lane group.
     const bool real_row = (kind == 1) || (kind == 2 && sys0 + grp == M);
-    for (int k = lane; k < K; k += SB) {
-      double2 v = z2();
-      if constexpr (P == 4) {   // Psi: y_k = sum_i gamma_i^{k-i} x~_{k-i}
+    constexpr int U = 8;
+    double2 prev = z2();
+    for (int k0 = 0; k0 < K; k0 += U * SB) {
+      double2 x[U];
 #pragma unroll
-        for (int i = 0; i < 5; ++i) {
-          const int j = k - i;
-          if (j >= 0 && j < n) {
-            const double gm = F.gam[(size_t)j * 5 + i];
-            v.x = fma(gm, hg[j].x, v.x);
-            v.y = fma(gm, hg[j].y, v.y);
-          }
-        }
-      } else {                  // Dirichlet: y_k = x~_{k-2} - x~_k
-        if (k - 2 >= 0 && k - 2 < n) v = hg[k - 2];
-        if (k < n) {
-          v.x -= hg[k].x;
-          v.y -= hg[k].y;
-        }
+      for (int u = 0; u < U; ++u) {
+        const int k = k0 + u * SB + lane;
+        x[u] = (k < n) ? hg[min(k, n - 1)] : z2();
       }
-      if (real_row) v.y = 0.0;
-      out_state[k] = v;
-      bad = bad || !isfinite(v.x) || !isfinite(v.y);
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int k = k0 + u * SB + lane;
+        auto nb_row = [&](int i) {   // x~_{k-i}
+          const int src = (lane - i) & 15;
+          const double2 a = make_double2(__shfl(x[u].x, src, 16), __shfl(x[u].y, src, 16));
+          const double2 b = make_double2(__shfl(prev.x, src, 16), __shfl(prev.y, src, 16));
+          return lane >= i ? a : b;
+        };
+        double2 v;
+        if constexpr (P == 4) {   // Psi: y_k = sum_i gamma_i^{k-i} x~_{k-i}
+          v = z2();
+#pragma unroll
+          for (int i = 0; i < 5; ++i) {
+            const double2 xi = i ? nb_row(i) : x[u];
+            const int j = k - i;
+            const double gm = (j >= 0 && j < n) ? F.gam[(size_t)j * 5 + i] : 0.0;
+            v.x = fma(gm, xi.x, v.x);
+            v.y = fma(gm, xi.y, v.y);
+          }
+        } else {                  // Dirichlet: y_k = x~_{k-2} - x~_k
+          const double2 x2 = nb_row(2);
+          v = make_double2(x2.x - x[u].x, x2.y - x[u].y);
+        }
+        if (real_row) v.y = 0.0;
+        if (valid && k < K) {
+          out_state[k] = v;
+          bad = bad || !isfinite(v.x) || !isfinite(v.y);
+        }
+        prev = x[u];
+      }
     }
   }
 
@@ -556,21 +578,26 @@ __global__ __launch_bounds__(256) void transpose_factors_kernel(const TF* __rest
 // a factor batch from HBM once for all runs:
 //   id = ((b / 8) nmem + run) 8 + b % 8,   b < nb (padded ids exit).
 // GAL: the Galerkin bands (8 / 12 and 4 / 6 diagonals, no border).
+// part 0: every system; 1: the real systems only; 2: the Psi systems only,
+// whose right-hand sides first take rs.buoy_adt C[(Ra/Pr)(i m/s_o) theta]
+// of the new theta when rs.buoy_adt != 0 (implicit buoyancy: part 1, then
+// part 2).
 template <bool GAL>
-__global__ __launch_bounds__(64) void solve_np_kernel(Geom g, FactorSet<double2> Fp,
+__global__ __launch_bounds__(64) void solve_np_kernel(Geom g, Bands bd, FactorSet<double2> Fp,
                                                       FactorSet<double> Fr, double2* rhs,
-                                                      RhsSpec rs, int qp, int qr) {
+                                                      RhsSpec rs, int qp, int qr, int part) {
   using SolverP = Solver4<double2, 4, 8, GAL ? 12 : 8, GAL>;
   using SolverR = Solver4<double, 2, 4, GAL ? 6 : 4, GAL>;
   __shared__ double2 ring_mem[2 * 4 * SolverP::SYS_CH];
   static_assert(SolverR::SYS_CH <= SolverP::SYS_CH, "ring too small for the real systems");
   const int M = g.M, K = g.K;
   const int nbp = (M - 1 + 3) / 4;
-  const int nb = nbp + (M + 1 + 3) / 4;
+  const int nb = (part == 1 ? 0 : nbp) + (part == 2 ? 0 : (M + 1 + 3) / 4);
   const int id = blockIdx.x, rest = id >> 3;
   const int run = rest % g.nmem;
-  const int b = (rest / g.nmem) * 8 + (id & 7);   // system block
+  int b = (rest / g.nmem) * 8 + (id & 7);   // system block
   if (b >= nb || nf_stop(g.nf)) return;
+  if (part == 1) b += nbp;                   // real systems only
   const int t = threadIdx.x, lane = t & 15, grp = t >> 4;
   const size_t moff = (size_t)run * M * K;   // run of an ensemble
   rhs += 2 * moff;
@@ -588,6 +615,30 @@ __global__ __launch_bounds__(64) void solve_np_kernel(Geom g, FactorSet<double2>
     s.valid = grp < s.nsys;
     s.so = s.so0 + min(grp, s.nsys - 1);
     s.hg = rhs + (size_t)(s.sys0 + min(grp, s.nsys - 1)) * K + 4;
+    if (rs.buoy_adt != 0.0 && s.valid) {
+      // h_k += a dt (Ra/Pr)(i m/s_o) sum_n C_kn theta_n, rows k >= 4; each
+      // lane updates the rows it reads first in the sweeps
+      const int m = s.sys0 + grp + 1;
+      const double ra_pr = g.ra_pr ? g.ra_pr[run] : g.Ra_Pr;
+      const double gb = rs.buoy_adt * ra_pr * (double)m / g.s_o;
+      const double2* th = rs.out_th + (size_t)m * K;
+      for (int k = 4 + lane; k < K; k += SB) {
+        double2 cb = z2();
+#pragma unroll
+        for (int o = 0; o < 17; ++o) {
+          const int n = k + o - 8;
+          const double c = bd.C[(size_t)o * K + k];
+          const double2 v = (n >= 0 && n < K) ? th[min(max(n, 0), K - 1)] : z2();
+          cb.x = fma(c, v.x, cb.x);
+          cb.y = fma(c, v.y, cb.y);
+        }
+        double2 h = s.hg[k - 4];
+        h.x -= gb * cb.y;
+        h.y += gb * cb.x;
+        s.hg[k - 4] = h;
+      }
+      __threadfence();
+    }
     s.run(s.out_ptr());
     nf_mark(g.nf, s.bad, rs.tag);
   } else {
@@ -684,19 +735,27 @@ bool launch_solve_adjoint_np(const Geom& g, const FactorSet<double2>& FpT,
   return true;
 }
 
-bool launch_solve_np(const Geom& g, const FactorSet<double2>& Fp, const FactorSet<double>& Fr,
-                     double2* rhs, const RhsSpec& rs, int qp, int qr, bool galerkin,
-                     hipStream_t st) {
+bool launch_solve_np(const Geom& g, const Bands& bd, const FactorSet<double2>& Fp,
+                     const FactorSet<double>& Fr, double2* rhs, const RhsSpec& rs, int qp, int qr,
+                     bool galerkin, hipStream_t st) {
   if (qp % (NSET * SB) || qr % (NSET * SB)) return false;
   if (galerkin && !Fp.gam) return false;
-  const int nb = (g.M - 1 + 3) / 4 + (g.M + 1 + 3) / 4;
-  const int blocks = 8 * ((nb + 7) / 8) * g.nmem;
-  if (galerkin)
-    hipLaunchKernelGGL(solve_np_kernel<true>, dim3(blocks), dim3(64), 0, st, g, Fp, Fr, rhs, rs,
-                       qp, qr);
-  else
-    hipLaunchKernelGGL(solve_np_kernel<false>, dim3(blocks), dim3(64), 0, st, g, Fp, Fr, rhs, rs,
-                       qp, qr);
+  const int nbp = (g.M - 1 + 3) / 4, nbr = (g.M + 1 + 3) / 4;
+  auto go = [&](int part, int nb) {
+    const int blocks = 8 * ((nb + 7) / 8) * g.nmem;
+    if (galerkin)
+      hipLaunchKernelGGL(solve_np_kernel<true>, dim3(blocks), dim3(64), 0, st, g, bd, Fp, Fr, rhs,
+                         rs, qp, qr, part);
+    else
+      hipLaunchKernelGGL(solve_np_kernel<false>, dim3(blocks), dim3(64), 0, st, g, bd, Fp, Fr,
+                         rhs, rs, qp, qr, part);
+  };
+  if (rs.buoy_adt != 0.0) {   // theta first, then Psi with the new theta's buoyancy
+    go(1, nbr);
+    go(2, nbp);
+  } else {
+    go(0, nbp + nbr);
+  }
   return true;
 }
 

@@ -378,7 +378,9 @@ __global__ __launch_bounds__(T) void analysis_kernel(Geom g, Bands b,
   const double invN = 1.0 / N;
   const double2* thm = th_state + (size_t)m * K;
   const double ra_pr = g.ra_pr ? g.ra_pr[mem] : g.Ra_Pr;
-  const double bcoef = ra_pr * (double)m / g.s_o;   // (Ra/Pr)(m/s_o), times i
+  // (Ra/Pr)(m/s_o), times i; zero when the buoyancy is implicit (then it
+  // belongs to the implicit operator)
+  const double bcoef = g.buoy_implicit ? 0.0 : ra_pr * (double)m / g.s_o;
 #pragma unroll
   for (int f = 0; f < 2; ++f) {
     auto get = [&](int i) -> C {
