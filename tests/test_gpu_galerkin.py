@@ -125,14 +125,33 @@ def test_medium_galerkin_parity(qg, nsteps):
 
 def test_large_galerkin_parity(qg):
     """3072 x 1025, two CNAB2 steps, in the benchmark's launch
-    configuration."""
+    configuration.  With the Galerkin bases the GPU state is within 1e-12
+    of the extended-precision reference in every field (measured: Psi
+    2.2e-14, theta 1.8e-15, zonal flow 1.9e-13), closer than the FP64
+    Galerkin oracle itself (Psi 4.9e-12 pivoted, 1.0e-11 unpivoted: its
+    band LU is factored in FP64, the GPU's in long double and rounded
+    once).  Against the live FP64 oracle the difference is therefore the
+    oracle's own rounding (measured 1.01e-11 in Psi), bounded here at
+    2e-11; the tau formulation's FP64 implementations lose 6e-10 .. 1e-8
+    of Psi at this size."""
     w = inputs.LARGE
     _say(f"[galerkin] large {w.n_phi}x{w.n_r} cnab2 x2")
     s = _run(qg, w, "cnab2", 2)
-    _vs_reference("large_cnab2_2", s.get_state())
+    got = s.get_state()
+    err_ref = _vs_reference("large_cnab2_2", got)
+    assert max(err_ref.values()) < 1e-12, err_ref
     d = s.diagnostics()
     _say(f"  growth {d['growth']:.3g}")
     assert d["pivoted"] == 0 and 1.0 <= d["growth"] <= 1e4
+    o = QGOracle(w.E, w.Ra, w.Pr, w.eta, w.n_phi, w.n_r, w.n_c,
+                 method="galerkin")
+    st = inputs.workload_state(w)
+    o.set_state(st.psi, st.theta, st.uphi0)
+    o.step(w.dt, "cnab2", 2)
+    err = {f: _rel(a, b) for f, a, b in zip(refcheck.FIELDS, got,
+                                            (o.psi, o.theta, o.uphi))}
+    _say(f"  rel err against the FP64 Galerkin oracle {err}")
+    assert max(err.values()) < 2e-11, err
 
 
 def test_ensemble_galerkin_member(qg):
