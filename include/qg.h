@@ -148,6 +148,14 @@ typedef struct {
                         factorisation that falls back to pivoting, gives
                         QG_EUNSUPPORTED); the tangent-linear and
                         reverse-mode entries return QG_EUNSUPPORTED. */
+  int dct;       /* radial transforms (eq. cheb, icheb) of the synthesis and
+                    the analysis: 0 = the library's choice for the size;
+                    1 = FFTs of the even extension (every size);
+                    2 = dense products on the FP64 matrix cores (per m one
+                        [N_r x N_c] x [N_c x 12] product for the six
+                        synthesised series, one [N_c x N_r] x [N_r x 4]
+                        for the two analysed fields), FP64 only and
+                        2 (n_r - 1) <= 512, else QG_EUNSUPPORTED. */
 } qg_params;
 
 typedef struct {

@@ -146,10 +146,15 @@ struct Layout {
   }
 };
 
+// qg_params.dct = 0: the radial transforms of FP64 contexts with
+// 2 (N_r - 1) <= MFMA_DCT_MAX_N2 run on the matrix cores when this is set.
+constexpr bool MFMA_DCT_DEFAULT = false;
+
 struct Sizes {
   int M, K, R, nphi, n4, n2, Sr;
   bool pump;    // Ekman pumping terms
   bool gal;     // Galerkin bases (qg_params.method = 1)
+  bool mfdct;   // radial transforms on the matrix cores (qg_params.dct)
   int p4, p2;   // n4, n2 padded to whole 16-step batches (pivoted solve)
   int q4, q2;   // n4, n2 padded to whole groups of solve batches (unpivoted solve)
 };
@@ -167,12 +172,17 @@ bool sizes_of(const qg_params* p, Sizes& z, std::string& why) {
   if (p->ekman != 0 && p->ekman != 1) { why = "ekman must be 0 or 1"; return false; }
   if (p->method != 0 && p->method != 1) { why = "method must be 0 (tau) or 1 (Galerkin)"; return false; }
   if (p->buoyancy != 0 && p->buoyancy != 1) { why = "buoyancy must be 0 (explicit) or 1 (implicit)"; return false; }
+  if (p->dct < 0 || p->dct > 2) { why = "dct must be 0 (default), 1 (FFT) or 2 (matrix cores)"; return false; }
   if (p->ekman && !(p->eps > 0 && std::isfinite(p->eps))) {
     why = "eps must be positive with Ekman pumping";
     return false;
   }
   z.pump = p->ekman == 1;
   z.gal = p->method == 1;
+  {
+    const bool mf_ok = p->precision == 0 && 2 * (p->n_r - 1) <= MFMA_DCT_MAX_N2;
+    z.mfdct = mf_ok && (p->dct == 2 || (p->dct == 0 && MFMA_DCT_DEFAULT));
+  }
   z.M = p->n_phi / 3 + 1;
   z.K = K;
   z.R = p->n_r;
@@ -193,6 +203,7 @@ struct WsMap {
   size_t state, ybuf, eslot, lslot, mE, mY, pump, tan, X, NL, zonal, rate, diag, xk, wq, dsk, twd, twp, twh, wphi,
       twd32, twp32, twh32, wphi32, bands, rhs;
   size_t p_piv, p_L, p_U, p_W, p_C, p_Mi, p_ui, p_gam;
+  size_t dct_s, dct_a;   // matrix-core radial transform tables
   size_t r_piv, r_L, r_U, r_W, r_C, r_Mi, r_ui;
   size_t total;
 };
@@ -253,6 +264,8 @@ WsMap map_workspace(const Sizes& z, int nmem, bool single) {
   w.r_C = L.take(Sr * 4 * 2 * sizeof(double));
   w.r_Mi = L.take(Sr * 4 * sizeof(double));
   w.p_gam = L.take(z.gal ? (size_t)z.n4 * 5 * sizeof(double) : 0);   // Galerkin stencil of Psi
+  w.dct_s = L.take(z.mfdct ? mfma_dct_table_bytes(z.R, z.K, false) : 0);
+  w.dct_a = L.take(z.mfdct ? mfma_dct_table_bytes(z.R, z.K, true) : 0);
   w.total = L.total;
   return w;
 }
@@ -994,6 +1007,7 @@ qg_status create_ctx(qg_ctx** out, const qg_params* p, int nmem, const double* r
   const bool mixed = p->precision == 1;
   if (z.nphi % 6 || !transform_sizes_ok(2 * (z.R - 1), z.nphi, mixed)) return QG_EUNSUPPORTED;
   if (z.gal && p->pivoting) return QG_EUNSUPPORTED;   // Galerkin bands: no row interchanges
+  if (p->dct == 2 && !z.mfdct) return QG_EUNSUPPORTED;   // matrix-core DCT: FP64, small N_r
   if (p->buoyancy && p->pivoting) return QG_EUNSUPPORTED;   // the coupled solve is unpivoted
   if (!workspace || ((uintptr_t)workspace & 255)) return QG_EINVAL;
   WsMap w = map_workspace(z, nmem, single);
@@ -1061,6 +1075,8 @@ qg_status create_ctx(qg_ctx** out, const qg_params* p, int nmem, const double* r
   };
   const std::vector<float2> twd32 = to32(twd), twp32 = to32(twp), twh32 = to32(twh),
                             wphi32 = to32(wphi);
+  std::vector<double> dct_s, dct_a;
+  if (z.mfdct) mfma_dct_tables(z.R, z.K, dct_s, dct_a);
   std::vector<double> bandbuf((size_t)9 * z.K * BANDW);
   const std::vector<double>* bl[9] = {&ctx->ops.A0, &ctx->ops.A2, &ctx->ops.B0,
                                       &ctx->ops.B2, &ctx->ops.B4, &ctx->ops.C,
@@ -1085,6 +1101,8 @@ qg_status create_ctx(qg_ctx** out, const qg_params* p, int nmem, const double* r
       up(w.wphi32, wphi32.data(), wphi32.size() * 8) != hipSuccess ||
       up(w.bands, bandbuf.data(), bandbuf.size() * 8) != hipSuccess ||
       up(w.ra, ra_pr.data(), ra_pr.size() * 8) != hipSuccess ||
+      (z.mfdct && (up(w.dct_s, dct_s.data(), dct_s.size() * 8) != hipSuccess ||
+                   up(w.dct_a, dct_a.data(), dct_a.size() * 8) != hipSuccess)) ||
       hipMemsetAsync(ctx->ws + w.state, 0, (single ? 4 : 2) * ctx->mk() * sizeof(double2),
                      ctx->st) != hipSuccess ||
       hipMemsetAsync(ctx->ws + w.flag, 0, sizeof(int), ctx->st) != hipSuccess ||
@@ -1109,6 +1127,8 @@ qg_status create_ctx(qg_ctx** out, const qg_params* p, int nmem, const double* r
   g.half_E = 0.5 * p->E;
   g.nf = single ? ctx->nf_flag() : nullptr;
   g.buoy_implicit = p->buoyancy == 1;
+  g.dct_s = z.mfdct ? ctx->ptrd(w.dct_s) : nullptr;
+  g.dct_a = z.mfdct ? ctx->ptrd(w.dct_a) : nullptr;
   g.ra_pr = ctx->ptrd(w.ra);
   g.xk = ctx->ptrd(w.xk);
   g.wq = ctx->ptrd(w.wq);
@@ -2208,7 +2228,7 @@ bool same_group(const qg_params& a, const qg_params& b, const Sizes& za, const S
   return a.E == b.E && a.Pr == b.Pr && a.eta == b.eta && za.nphi == zb.nphi && za.R == zb.R &&
          za.K == zb.K && a.precision == b.precision && a.pivoting == b.pivoting &&
          a.ekman == b.ekman && (!a.ekman || a.eps == b.eps) && a.method == b.method &&
-         a.buoyancy == b.buoyancy;
+         a.buoyancy == b.buoyancy && za.mfdct == zb.mfdct;
 }
 
 struct Grouping {

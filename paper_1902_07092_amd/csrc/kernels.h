@@ -44,6 +44,14 @@ struct Geom {
   // theta] out of E_psi, the band products put it into Lin, and the solve
   // advances theta before Psi.
   int buoy_implicit;
+  // Radial transforms as dense products on the FP64 matrix cores (nullptr:
+  // FFT of the even extension).  dct_s [KP][RP]: T_n(x_k) = cos(pi n k / N)
+  // for the synthesis (KP = K rounded up to 4, RP = R rounded up to 16);
+  // dct_a [R4][K16]: the forward DCT-I weights (1/N)(1/2 at n = 0)(1 at
+  // k = 0, N else 2) cos(pi n k / N) for the analysis (R4 = R rounded up to
+  // 4, K16 = K rounded up to 16); zero outside n < K, k <= N.
+  const double* dct_s;
+  const double* dct_a;
 };
 
 // True when the non-finite guard is set: the kernel must return.
@@ -113,6 +121,10 @@ struct Combine {
 // transforms and products (exchange arrays X and NL in float2).  The
 // launchers return false for a size without a compiled plan.
 bool transform_sizes_ok(int n2, int nphi, bool mixed);
+// Largest 2 (N_r - 1) with matrix-core radial transforms (FP64 only).
+constexpr int MFMA_DCT_MAX_N2 = 512;
+size_t mfma_dct_table_bytes(int R, int K, bool analysis);
+void mfma_dct_tables(int R, int K, std::vector<double>& syn, std::vector<double>& ana);
 size_t transform_lds_bytes(int n2, int nphi, int K, bool mixed);
 std::vector<double2> plan_twiddles(int n);
 bool launch_synth(const Geom& g, const double2* psi, const double2* th, void* X, double* diag,

@@ -19,6 +19,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <type_traits>
 #include <vector>
 
 #include "fft.h"
@@ -26,6 +27,112 @@
 #include "transform_util.h"
 
 namespace qg {
+
+// ----------------------------------------------- radial transforms on MFMA
+// At small N_r the radial transforms are short dense products: per m the
+// six coefficient series of the synthesis (Psi and its first three
+// derivatives, theta, theta') go to the grid as one [R x K] x [K x 12]
+// product, the two fields of the analysis to coefficients as one
+// [K x R] x [R x 4] product, on the FP64 matrix cores
+// (v_mfma_f64_16x16x4f64: A[r][k] from lane 16 k + r, B[k][c] from lane
+// 16 k + c, D[r][c] in lane 16 (r mod 4) + c, register r / 4).  The tables
+// (Geom::dct_s, dct_a) are built on the host in long double.
+typedef double v4d __attribute__((ext_vector_type(4)));
+
+template <int N2>
+constexpr int threads_mf() { return clampi(N2 / 2, 64, 256); }
+
+__host__ __device__ constexpr int mf_kp(int K) { return (K + 3) & ~3; }
+__host__ __device__ constexpr int mf_rp(int R) { return (R + 15) & ~15; }
+__host__ __device__ constexpr int mf_r4(int R) { return (R + 3) & ~3; }
+__host__ __device__ constexpr int mf_k16(int K) { return (K + 15) & ~15; }
+
+// Synthesis: levels 0..3 of Psi_m and 0..1 of theta_m (Chebyshev
+// derivatives by the same in-place recurrence as the FFT path) into LDS,
+// then P[d][k] = sum_n T_n(x_k) c_d[n] for all six levels at once.
+// Returns P, [6][RP] in LDS (levels 4, 5: theta, theta').
+template <int T>
+__device__ const double2* mf_synth_levels(const Geom& g, const double2* __restrict__ pm,
+                                          const double2* __restrict__ tm, double2* sm,
+                                          double2* wred) {
+  const int K = g.K, t = threadIdx.x;
+  const int KP = mf_kp(K), RP = mf_rp(g.R);
+  double2* Cl = sm;            // [6][KP] coefficient levels
+  double2* Pl = sm + 6 * KP;   // [6][RP] grid values
+  for (int nn = t; nn < KP; nn += T) {
+    Cl[nn] = nn < K ? pm[nn] : z2();
+    Cl[4 * KP + nn] = nn < K ? tm[nn] : z2();
+  }
+  __syncthreads();
+  for (int d = 1; d < 6; ++d) {
+    if (d == 4) continue;
+    for (int nn = t; nn < KP; nn += T) Cl[d * KP + nn] = Cl[(d - 1) * KP + nn];
+    __syncthreads();
+    cheb_deriv_inplace<T>(Cl + d * KP, K, wred);   // ends with a barrier
+  }
+  constexpr int NW = T / 64;
+  const int lane = t & 63, w = t >> 6, r16 = lane & 15, kq = lane >> 4;
+  const int dc = r16 >> 1, comp = r16 & 1;   // B column: level, real or imaginary part
+  const double* cl = reinterpret_cast<const double*>(Cl);
+  double* pl = reinterpret_cast<double*>(Pl);
+  for (int rt = w; rt < RP / 16; rt += NW) {
+    v4d acc = {0.0, 0.0, 0.0, 0.0};
+    const double* ta = g.dct_s + 16 * rt + r16;
+#pragma unroll 4
+    for (int kb = 0; kb < KP / 4; ++kb) {
+      const int n = 4 * kb + kq;
+      const double a = ta[(size_t)n * RP];
+      const double b = (dc < 6) ? cl[2 * (dc * KP + n) + comp] : 0.0;
+      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
+    }
+    if (dc < 6) {
+#pragma unroll
+      for (int i = 0; i < 4; ++i) pl[2 * (dc * RP + 16 * rt + 4 * i + kq) + comp] = acc[i];
+    }
+  }
+  __syncthreads();
+  return Pl;
+}
+
+// Grid values of level d at this thread's points k = t + i T.
+template <int N2, int T, typename C>
+__device__ __forceinline__ void mf_read(const double2* Pl, int R, int d,
+                                        C (&P)[out_count<N2, T>()]) {
+  const int RP = mf_rp(R);
+#pragma unroll
+  for (int i = 0; i < out_count<N2, T>(); ++i) {
+    const int k = threadIdx.x + i * T;
+    P[i] = (k < RP) ? to_c<C>(Pl[d * RP + k]) : zc<C>();
+  }
+}
+
+// Analysis: the two fields (their grid values, [2][R4] in LDS, zero past
+// k = N) to their Chebyshev coefficients, [2][K16] in LDS.
+template <int T>
+__device__ void mf_analysis_gemm(const Geom& g, const double2* Fl, double2* Cw) {
+  const int R4 = mf_r4(g.R), K16 = mf_k16(g.K), t = threadIdx.x;
+  constexpr int NW = T / 64;
+  const int lane = t & 63, w = t >> 6, r16 = lane & 15, kq = lane >> 4;
+  const int fc = r16 >> 1, comp = r16 & 1;   // B column: field, real or imaginary part
+  const double* fl = reinterpret_cast<const double*>(Fl);
+  double* cw = reinterpret_cast<double*>(Cw);
+  for (int rt = w; rt < K16 / 16; rt += NW) {
+    v4d acc = {0.0, 0.0, 0.0, 0.0};
+    const double* ta = g.dct_a + 16 * rt + r16;
+#pragma unroll 4
+    for (int kb = 0; kb < R4 / 4; ++kb) {
+      const int k = 4 * kb + kq;
+      const double a = ta[(size_t)k * K16];
+      const double b = (fc < 2) ? fl[2 * (fc * R4 + k) + comp] : 0.0;
+      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
+    }
+    if (fc < 2) {
+#pragma unroll
+      for (int i = 0; i < 4; ++i) cw[2 * (fc * K16 + 16 * rt + 4 * i + kq) + comp] = acc[i];
+    }
+  }
+  __syncthreads();
+}
 
 // -------------------------------------------------------------- synth
 // Fields (Fourier coefficient m at s_k), written X[f][k][m]:
@@ -37,7 +144,7 @@ namespace qg {
 // coefficient row a_n (n < K) is the FFT of the even extension e_0 = a_0,
 // e_n = e_{2N-n} = a_n / 2 (eq. cheb).  Thread t owns the radial points
 // k = t + i T, and the fields are accumulated derivative by derivative.
-template <int N2, int T, typename C, bool PUMP>
+template <int N2, int T, typename C, bool PUMP, bool MF = false>
 __global__ __launch_bounds__(T) void synth_kernel(Geom g, const double2* __restrict__ psi,
                                                   const double2* __restrict__ th,
                                                   C* __restrict__ X,
@@ -91,14 +198,23 @@ __global__ __launch_bounds__(T) void synth_kernel(Geom g, const double2* __restr
   double2 a1[NP], a2[NP], a3[NP];   // m > 0: u_phi, omega, c_w accumulators
   double ek = 0.0, et = 0.0, ens = 0.0, ez = 0.0;
 
-  for (int nn = t; nn < K; nn += T) c[nn] = psi[(size_t)m * K + nn];
-  __syncthreads();
+  [[maybe_unused]] const double2* Pl = nullptr;   // MF: grid values of all six levels
+  if constexpr (MF) {
+    Pl = mf_synth_levels<T>(g, psi + (size_t)m * K, th + (size_t)m * K, sm, wred);
+  } else {
+    for (int nn = t; nn < K; nn += T) c[nn] = psi[(size_t)m * K + nn];
+    __syncthreads();
+  }
   const int nder = (m > 0) ? 4 : 3;
 #pragma unroll 1
   for (int d = 0; d < nder; ++d) {
-    if (d > 0) cheb_deriv_inplace<T>(c, K, wred);
     C P[E];
-    fft_out<N2, T, -1>(ext, fb, Tw<C>::dct(g), P);
+    if constexpr (MF) {
+      mf_read<N2, T>(Pl, R, d, P);
+    } else {
+      if (d > 0) cheb_deriv_inplace<T>(c, K, wred);
+      fft_out<N2, T, -1>(ext, fb, Tw<C>::dct(g), P);
+    }
 #pragma unroll
     for (int i = 0; i < NP; ++i) {
       int k = t + i * T;
@@ -170,14 +286,20 @@ __global__ __launch_bounds__(T) void synth_kernel(Geom g, const double2* __restr
     }
   }
   // theta, theta'
-  __syncthreads();
-  for (int nn = t; nn < K; nn += T) c[nn] = th[(size_t)m * K + nn];
-  __syncthreads();
+  if constexpr (!MF) {
+    __syncthreads();
+    for (int nn = t; nn < K; nn += T) c[nn] = th[(size_t)m * K + nn];
+    __syncthreads();
+  }
 #pragma unroll 1
   for (int d = 0; d < 2; ++d) {
-    if (d > 0) cheb_deriv_inplace<T>(c, K, wred);
     C P[E];
-    fft_out<N2, T, -1>(ext, fb, Tw<C>::dct(g), P);
+    if constexpr (MF) {
+      mf_read<N2, T>(Pl, R, 4 + d, P);
+    } else {
+      if (d > 0) cheb_deriv_inplace<T>(c, K, wred);
+      fft_out<N2, T, -1>(ext, fb, Tw<C>::dct(g), P);
+    }
 #pragma unroll
     for (int i = 0; i < NP; ++i) {
       int k = t + i * T;
@@ -352,7 +474,7 @@ __global__ __launch_bounds__(T) void ring_kernel(Geom g, const C* __restrict__ X
 //   all m:  E_th  = -D [ N_theta ]                           (eq. temp_int)
 // Forward DCT-I (eq. icheb): a_n = (h_n / N) FFT(e)_n with the even
 // extension e_i = f_{|i|}, h_0 = 1/2, else 1, kept for n < K.
-template <int N2, int T, typename C>
+template <int N2, int T, typename C, bool MF = false>
 __global__ __launch_bounds__(T) void analysis_kernel(Geom g, Bands b,
                                                      const C* __restrict__ NL,
                                                      const double* __restrict__ zonal,
@@ -381,23 +503,41 @@ __global__ __launch_bounds__(T) void analysis_kernel(Geom g, Bands b,
   // (Ra/Pr)(m/s_o), times i; zero when the buoyancy is implicit (then it
   // belongs to the implicit operator)
   const double bcoef = g.buoy_implicit ? 0.0 : ra_pr * (double)m / g.s_o;
-#pragma unroll
-  for (int f = 0; f < 2; ++f) {
-    auto get = [&](int i) -> C {
-      const int kk = (i <= N) ? i : N2 - i;
-      if (f == 0 && m == 0)
-        return to_c<C>(make_double2(zonal[kk] + (pump ? pump[kk].x : 0.0), 0.0));
-      if (f == 0 && pump) return to_c<C>(sub2(to_d2(NL[(size_t)m * R + kk]), pump[kk]));
-      return NL[((size_t)f * M + m) * R + kk];
-    };
-    C o[E];
-    fft_out<N2, T, -1>(get, fb, Tw<C>::dct(g), o);
-#pragma unroll
-    for (int i = 0; i < E; ++i) {
-      const int nn = t + i * T;
-      if (nn < K) c[nn] = scl2(nn == 0 ? 0.5 * invN : invN, to_d2(o[i]));
+  // the field transformed for f (0: N_omega less the pumping term, or the
+  // zonal forcing at m = 0; 1: N_theta) at radial point kk
+  auto field = [&](int f, int kk) -> C {
+    if (f == 0 && m == 0)
+      return to_c<C>(make_double2(zonal[kk] + (pump ? pump[kk].x : 0.0), 0.0));
+    if (f == 0 && pump) return to_c<C>(sub2(to_d2(NL[(size_t)m * R + kk]), pump[kk]));
+    return NL[((size_t)f * M + m) * R + kk];
+  };
+  [[maybe_unused]] double2* Cw = nullptr;   // MF: coefficients of both fields, [2][K16]
+  if constexpr (MF) {
+    const int R4 = mf_r4(R);
+    double2* Fl = sm;
+    Cw = sm + 2 * R4;
+    for (int kk = t; kk < R4; kk += T) {
+      Fl[kk] = kk < R ? to_d2(field(0, kk)) : z2();
+      Fl[R4 + kk] = kk < R ? to_d2(field(1, kk)) : z2();
     }
     __syncthreads();
+    mf_analysis_gemm<T>(g, Fl, Cw);
+  }
+#pragma unroll
+  for (int f = 0; f < 2; ++f) {
+    if constexpr (MF) {
+      c = Cw + f * mf_k16(K);
+    } else {
+      auto get = [&](int i) -> C { return field(f, (i <= N) ? i : N2 - i); };
+      C o[E];
+      fft_out<N2, T, -1>(get, fb, Tw<C>::dct(g), o);
+#pragma unroll
+      for (int i = 0; i < E; ++i) {
+        const int nn = t + i * T;
+        if (nn < K) c[nn] = scl2(nn == 0 ? 0.5 * invN : invN, to_d2(o[i]));
+      }
+      __syncthreads();
+    }
     // band rows: fixed 17 terms (entries outside the matrix are stored as
     // zeros), so that every load of a row is issued at once
     for (int k = t; k < K; k += T) {
@@ -433,6 +573,16 @@ namespace {
 template <int N2, typename C, bool PUMP>
 void synth_np(const Geom& g, const double2* psi, const double2* th, void* X, double* diag,
               hipStream_t st) {
+  if constexpr (std::is_same<C, double2>::value && N2 <= MFMA_DCT_MAX_N2) {
+    if (g.dct_s) {   // radial transform on the matrix cores
+      constexpr int T = threads_mf<N2>();
+      const size_t shm = sizeof(double2) * 6 * (mf_kp(g.K) + mf_rp(g.R));
+      allow_lds(synth_kernel<N2, T, C, PUMP, true>, shm);
+      hipLaunchKernelGGL((synth_kernel<N2, T, C, PUMP, true>), dim3(xcd_grid(g.M), g.nmem),
+                         dim3(T), shm, st, g, psi, th, static_cast<C*>(X), diag);
+      return;
+    }
+  }
   constexpr int T = threads_dct(N2);
   const size_t shm = dct_lds<C>(N2, g.K);
   allow_lds(synth_kernel<N2, T, C, PUMP>, shm);
@@ -464,6 +614,16 @@ void ring_n(const Geom& g, const void* X, void* NL, double* zonal, double* rate,
 template <int N2, typename C>
 void analysis_n(const Geom& g, const Bands& b, const void* NL, const double* zonal,
                 const double2* th, double2* Ep, double2* Et, hipStream_t st) {
+  if constexpr (std::is_same<C, double2>::value && N2 <= MFMA_DCT_MAX_N2) {
+    if (g.dct_a) {   // radial transform on the matrix cores
+      constexpr int T = threads_mf<N2>();
+      const size_t shm = sizeof(double2) * 2 * (mf_r4(g.R) + mf_k16(g.K));
+      allow_lds(analysis_kernel<N2, T, C, true>, shm);
+      hipLaunchKernelGGL((analysis_kernel<N2, T, C, true>), dim3(xcd_grid(g.M), g.nmem),
+                         dim3(T), shm, st, g, b, static_cast<const C*>(NL), zonal, th, Ep, Et);
+      return;
+    }
+  }
   constexpr int T = threads_dct(N2);
   const size_t shm = dct_lds<C>(N2, g.K);
   allow_lds(analysis_kernel<N2, T, C>, shm);
@@ -499,6 +659,30 @@ size_t transform_lds_bytes(int n2, int nphi, int K, bool mixed) {
   const size_t d = mixed ? dct_lds<float2>(n2, K) : dct_lds<double2>(n2, K);
   const size_t p = mixed ? phi_lds<float2>(nphi) : phi_lds<double2>(nphi);
   return d > p ? d : p;
+}
+
+size_t mfma_dct_table_bytes(int R, int K, bool analysis) {
+  return sizeof(double) * (analysis ? (size_t)mf_r4(R) * mf_k16(K) : (size_t)mf_kp(K) * mf_rp(R));
+}
+
+// cos(pi n k / N) in long double with the argument reduced mod 2N, rounded
+// once; the analysis table carries the forward DCT-I weights.
+void mfma_dct_tables(int R, int K, std::vector<double>& syn, std::vector<double>& ana) {
+  const int N = R - 1, KP = mf_kp(K), RP = mf_rp(R), R4 = mf_r4(R), K16 = mf_k16(K);
+  const long double pi = 3.14159265358979323846264338327950288L;
+  auto cs = [&](int n, int k) {
+    const long long a = ((long long)n * k) % (2LL * N);
+    return cosl(pi * (long double)a / (long double)N);
+  };
+  syn.assign((size_t)KP * RP, 0.0);
+  ana.assign((size_t)R4 * K16, 0.0);
+  for (int n = 0; n < K; ++n)
+    for (int k = 0; k <= N; ++k) {
+      syn[(size_t)n * RP + k] = (double)cs(n, k);
+      const long double wn = (n == 0 ? 0.5L : 1.0L) / (long double)N;
+      const long double wk = (k == 0 || k == N) ? 1.0L : 2.0L;
+      ana[(size_t)k * K16 + n] = (double)(wn * wk * cs(n, k));
+    }
 }
 
 std::vector<double2> plan_twiddles(int n) {

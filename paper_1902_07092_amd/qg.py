@@ -30,13 +30,15 @@ class qg_params(ctypes.Structure):
                 ("n_c", ctypes.c_int), ("precision", ctypes.c_int),
                 ("pivoting", ctypes.c_int), ("ekman", ctypes.c_int),
                 ("eps", ctypes.c_double), ("method", ctypes.c_int),
-                ("buoyancy", ctypes.c_int)]
+                ("buoyancy", ctypes.c_int), ("dct", ctypes.c_int)]
 
 # qg_params.method: boundary conditions by tau rows or Galerkin bases
 QG_TAU, QG_GALERKIN = 0, 1
 METHODS = {"tau": QG_TAU, "galerkin": QG_GALERKIN}
 # qg_params.buoyancy
 BUOYANCY = {"explicit": 0, "implicit": 1}
+# qg_params.dct: radial transforms
+DCT = {"default": 0, "fft": 1, "mfma": 2}
 
 
 class qg_diag(ctypes.Structure):
@@ -301,14 +303,15 @@ class QGSolver:
 
     def __init__(self, E, Ra, Pr, eta, n_phi, n_r, n_c=0, device="cuda:0",
                  stream=None, pivoting=0, precision=0, ekman_eps=None,
-                 static_workspace=False, method="tau", buoyancy="explicit"):
+                 static_workspace=False, method="tau", buoyancy="explicit",
+                 dct="default"):
         import torch
         self.torch = torch
         self.device = torch.device(device)
         self.params = qg_params(E, Ra, Pr, eta, n_phi, n_r, n_c, precision,
                                 pivoting, 0 if ekman_eps is None else 1,
                                 0.0 if ekman_eps is None else ekman_eps,
-                                METHODS[method], BUOYANCY[buoyancy])
+                                METHODS[method], BUOYANCY[buoyancy], DCT[dct])
         self.M = n_phi // 3 + 1
         self.K = n_c if n_c else (2 * (n_r - 1)) // 3
         nbytes = qg_workspace_size(self.params)
@@ -565,8 +568,9 @@ class QGEnsemble:
     """Many runs stepped together (qg_ensemble_*); members is a list of
     dicts with the QGSolver parameters E, Ra, Pr, eta, n_phi, n_r and
     optionally n_c, precision, pivoting, ekman_eps, method ("tau" or
-    "galerkin"), buoyancy ("explicit" or "implicit").  The ensemble gets a
-    stream of its own (graph capture needs one)."""
+    "galerkin"), buoyancy ("explicit" or "implicit"), dct ("default",
+    "fft" or "mfma").  The ensemble gets a stream of its own (graph capture
+    needs one)."""
 
     def __init__(self, members, device="cuda:0"):
         import torch
@@ -578,7 +582,8 @@ class QGEnsemble:
                                  0 if m.get("ekman_eps") is None else 1,
                                  m.get("ekman_eps") or 0.0,
                                  METHODS[m.get("method", "tau")],
-                                 BUOYANCY[m.get("buoyancy", "explicit")])
+                                 BUOYANCY[m.get("buoyancy", "explicit")],
+                                 DCT[m.get("dct", "default")])
                        for m in members]
         self.shapes = [(p.n_phi // 3 + 1,
                         p.n_c if p.n_c else (2 * (p.n_r - 1)) // 3)
