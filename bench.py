@@ -196,6 +196,29 @@ def schemes_run(qg, torch, w, state, args):
     return out
 
 
+def variants_run(qg, torch, w, state, args):
+    """The method variants on the headline workload: the Galerkin bases
+    (Sect. 3.2.2) and implicit buoyancy (Sect. 4), each from a fresh start,
+    warm-up steps past the factorisation, then args.steps timed steps
+    (median of 3 repeats) with the solve's launch time."""
+    out = {}
+    for name, kw in (("galerkin", dict(method="galerkin")),
+                     ("implicit_buoyancy", dict(buoyancy="implicit"))):
+        s = qg.QGSolver(w.E, w.Ra, w.Pr, w.eta, w.n_phi, w.n_r, w.n_c,
+                        device="cuda:0", **kw)
+        s.set_state(state.psi, state.theta, state.uphi0)
+        s.step(w.dt, w.scheme, args.warmup)
+        reps = [timed_steps(torch, s, w, args.steps) / args.steps for _ in range(3)]
+        ms = _median(reps)
+        kern = s.step_timed(w.dt, w.scheme, args.steps)
+        out[name] = {"ms_per_step": ms, "repeats_ms_per_step": reps,
+                     "value": w.grid_points / (ms * 1e-3),
+                     "unit": "grid-point-steps/s",
+                     "solve_avg_launch_us": kern["solve"][0] / kern["solve"][1] * 1e3,
+                     "solve_launches_per_step": kern["solve"][1] / args.steps}
+    return out
+
+
 def tangent_run(qg, torch, inputs, args):
     """The 768 x 257 adjoint-study workload (E = 1e-6, Ra = 5 Ra_c, CNAB2):
     forward steps against tangent-linear steps (state and perturbation
@@ -378,15 +401,27 @@ def ensemble_run(qg, torch, inputs, args):
         _, grp = ens.groups()
         tuned = {f"{ws[i].n_phi}x{ws[i].n_r}": picks[grp[i]]
                  for i in range(len(ws))}
-    torch.cuda.synchronize()
-    start = torch.cuda.Event(enable_timing=True)
-    stop = torch.cuda.Event(enable_timing=True)
-    start.record(ens.stream)
-    ens.step(dt, "cnab2", args.ens_steps)
-    stop.record(ens.stream)
-    torch.cuda.synchronize()
-    ms = start.elapsed_time(stop) / args.ens_steps
+    def timed(e):
+        torch.cuda.synchronize()
+        start = torch.cuda.Event(enable_timing=True)
+        stop = torch.cuda.Event(enable_timing=True)
+        start.record(e.stream)
+        e.step(dt, "cnab2", args.ens_steps)
+        stop.record(e.stream)
+        torch.cuda.synchronize()
+        return start.elapsed_time(stop) / args.ens_steps
+    reps = [timed(ens) for _ in range(5)]
+    ms = _median(reps)
     gp = sum(w.grid_points for w in ws)
+    # the same ensemble with the radial transforms on the matrix cores
+    mf = qg.QGEnsemble([dict(m, dct="mfma") for m in members])
+    for i, st in enumerate(states):
+        mf.set_state(i, st.psi, st.theta, st.uphi0)
+    mf.step(dt, "cnab2", args.warmup)
+    if args.ens_tune_steps:
+        mf.step_autotune(dt, "cnab2", args.ens_tune_steps)
+    mf_reps = [timed(mf) for _ in range(3)]
+    del mf
     bad = [i for i in range(len(ws)) if ens.diagnostics(i)["nonfinite"]]
     # the same runs, one single-run context after another
     solos = []
@@ -406,7 +441,10 @@ def ensemble_run(qg, torch, inputs, args):
     for w in ws:
         sizes[f"{w.n_phi}x{w.n_r}"] = sizes.get(f"{w.n_phi}x{w.n_r}", 0) + 1
     return {"value": gp / (ms * 1e-3), "unit": "grid-point-steps/s",
-            "ms_per_step": ms, "members": len(ws), "sizes": sizes,
+            "ms_per_step": ms, "repeats_ms_per_step": reps,
+            "mfma_dct_ms_per_step": _median(mf_reps),
+            "mfma_dct_repeats_ms_per_step": mf_reps,
+            "members": len(ws), "sizes": sizes,
             "grid_points_per_step": gp, "steps": args.ens_steps,
             "band_systems_per_thread": tuned,
             "nonfinite_members": bad,
@@ -440,6 +478,9 @@ def main():
                          "gradient times")
     ap.add_argument("--ensemble-only", action="store_true",
                     help="only the batched-ensemble run (for profiling it)")
+    ap.add_argument("--method", choices=("tau", "galerkin"), default="tau",
+                    help="boundary conditions of the headline run: tau rows "
+                         "(default) or the Galerkin bases")
     ap.add_argument("--precision", choices=("fp64", "mixed"), default="fp64",
                     help="precision of the headline run (mixed also runs the "
                          "12288 x 4097 workload, which FP64 does not fit)")
@@ -472,7 +513,7 @@ def main():
     state = inputs.workload_state(w)
     prec = 1 if args.precision == "mixed" else 0
     solver = qg.QGSolver(w.E, w.Ra, w.Pr, w.eta, w.n_phi, w.n_r, w.n_c,
-                         device="cuda:0", precision=prec)
+                         device="cuda:0", precision=prec, method=args.method)
     solver.set_state(state.psi, state.theta, state.uphi0)
     solver.step(w.dt, w.scheme, 0)            # factorise (untimed)
     # band-product launch shape picked by the library's autotuner (untimed
@@ -523,6 +564,7 @@ def main():
            "config": {"workload": w.name, "n_phi": w.n_phi, "n_r": w.n_r,
                       "n_c": w.n_c, "E": w.E, "Ra": w.Ra, "Pr": w.Pr,
                       "eta": w.eta, "scheme": w.scheme, "dt": w.dt,
+                      "method": args.method,
                       "band_systems_per_thread": tuned,
                       "parallelism": "single GPU"},
            "roofline": roofline, "kernels": kernels}
@@ -537,6 +579,9 @@ def main():
     if not args.no_schemes and prec == 0:
         out["schemes"] = schemes_run(qg, torch, w, state, args)
         print("[bench] schemes done", file=sys.stderr, flush=True)
+    if not args.no_schemes and prec == 0:
+        out["variants"] = variants_run(qg, torch, w, state, args)
+        print("[bench] variants done", file=sys.stderr, flush=True)
     if not args.no_schemes and prec == 0:
         out["tangent_linear"] = tangent_run(qg, torch, inputs, args)
         print("[bench] tangent done", file=sys.stderr, flush=True)
