@@ -352,7 +352,8 @@ __global__ __launch_bounds__(T) void synth_kernel(Geom g, const double2* __restr
 // scaled by 1/N_phi and truncated to m <= N_m (N_omega can exceed N_theta by
 // many orders of magnitude, so the two never share one complex transform).
 // Zonal forcing: mean(u_s omega) = 2 sum_{m>=1} Re(u_s,m conj(omega_m)) with
-// u_s,m = (h^2/s) X0_m and omega_m = X3_m / (i m).  G (optional, FP64
+// u_s,m = (h^2/s) X0_m and omega_m = X3_m / (i m).  The two wall rings
+// store zero products and forcing (ring_index).  G (optional, FP64
 // single runs): the six grid fields g_f(phi_j) out, [6][R][N_phi], for the
 // reverse mode.
 template <int NPHI, int T, typename C>
@@ -369,14 +370,28 @@ __global__ __launch_bounds__(T) void ring_kernel(Geom g, const C* __restrict__ X
   constexpr int NH = NPHI / 2;
   const int R = g.R, M = g.M;
   const int t = threadIdx.x;
-  const int k = xcd_index(R);
-  if (k >= R || nf_stop(g.nf)) return;
+  const int k = ring_index(R);
+  if (k < 0 || nf_stop(g.nf)) return;
   {
     const size_t mem = blockIdx.y;
     X += mem * 6 * R * M;
     NL += mem * 2 * M * R;
     zonal += mem * R;
     if (rate) rate += mem * R;
+  }
+  // a wall: no advection (see ring_index).  Reverse-mode passes (G) still
+  // store the ring's grid fields, which the transposed products use.
+  const bool wall = (k == 0 || k == R - 1);
+  if (wall && !G) {
+    for (int m = t; m < M; m += T) {
+      NL[(size_t)m * R + k] = zc<C>();
+      NL[((size_t)M + m) * R + k] = zc<C>();
+    }
+    if (t == 0) {
+      zonal[k] = 0.0;
+      if (rate) rate[k] = 0.0;
+    }
+    return;
   }
   const double s = g.half * g.xk[k] + g.mid;
   const double h2s = (g.s_o * g.s_o - s * s) / s;
@@ -456,14 +471,14 @@ __global__ __launch_bounds__(T) void ring_kernel(Geom g, const C* __restrict__ X
       const C o = fftd::mk<C>((RT)0.5 * dd.y, (RT)-0.5 * dd.x);   // (Z_m - Z*)/(2i)
       C xm = fftd::add(e, fftd::mul(w, o));
       if (m == 0) xm.y = 0;
-      NL[((size_t)f * M + m) * R + k] = fftd::scl(inv, xm);
+      NL[((size_t)f * M + m) * R + k] = wall ? zc<C>() : fftd::scl(inv, xm);
     }
   }
   const double tot = block_sum(zs, red);
-  if (t == 0) zonal[k] = -2.0 * h2s * tot;
+  if (t == 0) zonal[k] = wall ? 0.0 : -2.0 * h2s * tot;
   if (rate) {
     const double rm = block_max(rmax, red);
-    if (t == 0) rate[k] = rm;
+    if (t == 0) rate[k] = wall ? 0.0 : rm;
   }
 }
 
@@ -607,7 +622,7 @@ void ring_n(const Geom& g, const void* X, void* NL, double* zonal, double* rate,
   constexpr int T = threads_phi(NPHI);
   const size_t shm = phi_lds<C>(NPHI);
   allow_lds(ring_kernel<NPHI, T, C>, shm);
-  hipLaunchKernelGGL((ring_kernel<NPHI, T, C>), dim3(xcd_grid(g.R), g.nmem), dim3(T), shm, st, g,
+  hipLaunchKernelGGL((ring_kernel<NPHI, T, C>), dim3(ring_grid(g.R), g.nmem), dim3(T), shm, st, g,
                      static_cast<const C*>(X), static_cast<C*>(NL), zonal, rate, G);
 }
 
