@@ -226,8 +226,8 @@ __global__ __launch_bounds__(T) void ring_T_kernel(Geom g, const double2* __rest
   constexpr int E = out_count<NPHI, T>();
   const int R = g.R, M = g.M;
   const int t = threadIdx.x;
-  const int k = ring_index(R);
-  if (k < 0 || nf_stop(g.nf)) return;
+  const int k = xcd_index(R);
+  if (k >= R || nf_stop(g.nf)) return;
   const double s = g.half * g.xk[k] + g.mid;
   const double h2s = (g.s_o * g.s_o - s * s) / s;
   // products' co-state on the grid: N_omega in the real part, N_theta in
@@ -519,7 +519,7 @@ void ring_T_n(const Geom& g, const double2* X, const double* G, const double2* N
   constexpr int T = threads_rphi(NPHI);
   const size_t shm = phi_lds<double2>(NPHI);
   allow_lds(ring_T_kernel<NPHI, T>, shm);
-  hipLaunchKernelGGL((ring_T_kernel<NPHI, T>), dim3(ring_grid(g.R)), dim3(T), shm, st, g, X, G,
+  hipLaunchKernelGGL((ring_T_kernel<NPHI, T>), dim3(xcd_grid(g.R)), dim3(T), shm, st, g, X, G,
                      NLb, zb, kappa, Xb);
 }
 
