@@ -1411,7 +1411,7 @@ qg_status diagnostics_run(qg_ctx* ctx, int mem, qg_diag* out) {
     ez += d[m * 8 + 1];
     et += d[m * 8 + 2];
     en += d[m * 8 + 3];
-    bad = std::max(bad, d[m * 8 + 4]);
+    bad = std::max(bad, std::max(d[m * 8 + 4], d[m * 8 + 5]));
   }
   for (int k = 0; k < z.R; ++k) rmax = std::max(rmax, rate[k]);
   const double s_o = ctx->g.s_o, s_i = ctx->g.s_i, pi = 3.14159265358979323846;

@@ -22,33 +22,12 @@ constexpr int threads_dct(int n2) { return clampi(n2 / 8, 64, 256); }
 constexpr int threads_phi(int nphi) { return clampi(nphi / 12, 64, 256); }
 
 // Block -> m: XCD x = block mod 8 takes the contiguous range [x per, (x+1) per).
-__device__ __forceinline__ int xcd_index(int count) {
+__device__ __forceinline__ int xcd_index_of(int b, int count) {
   const int per = (count + 7) >> 3;
-  return (blockIdx.x & 7) * per + (blockIdx.x >> 3);
+  return (b & 7) * per + (b >> 3);
 }
+__device__ __forceinline__ int xcd_index(int count) { return xcd_index_of(blockIdx.x, count); }
 inline int xcd_grid(int count) { return 8 * ((count + 7) / 8); }
-
-// Block -> radial ring of the ring kernels.  The velocity vanishes on the
-// walls (no slip: Psi = dPsi/ds = 0 at s_i, Psi = 0 at s_o and the zonal
-// flow is zero at both, eq. bc_varPsi), so the advection products and the
-// zonal forcing of rings k = 0 and R - 1 are zero and, in a plain step,
-// those two blocks only store zeros (a reverse-mode pass still stores their
-// grid fields: the transposed products need the derivatives there).  The
-// R - 2 interior rings go to the XCDs in contiguous runs
-// of at most ceil((R - 2) / 8) (128 for R = 1025, so that each XCD's share
-// fits two rounds of its resident blocks); the wall rings come last, on
-// XCDs 0 and 1.  -1: a padding block.
-__device__ __forceinline__ int ring_index(int R) {
-  const int I = R - 2, per = (I + 7) >> 3;
-  const int x = blockIdx.x & 7, j = blockIdx.x >> 3;
-  if (j < per) {
-    const int h = x * per + j;
-    return h < I ? 1 + h : -1;
-  }
-  if (j == per && x < 2) return x == 0 ? 0 : R - 1;
-  return -1;
-}
-inline int ring_grid(int R) { return 8 * ((R - 2 + 7) / 8 + 1); }
 
 // Hides a value from the optimiser for one use: the per-point factors of
 // the derivative loops would otherwise be hoisted out of those loops for all

@@ -148,7 +148,7 @@ template <int N2, int T, typename C, bool PUMP, bool MF = false>
 __global__ __launch_bounds__(T) void synth_kernel(Geom g, const double2* __restrict__ psi,
                                                   const double2* __restrict__ th,
                                                   C* __restrict__ X,
-                                                  double* __restrict__ diag) {
+                                                  double* __restrict__ diag, int split) {
   extern __shared__ double2 sm[];
   __shared__ double2 wred[2 * (T / 64)];
   __shared__ double red[T / 64];
@@ -157,7 +157,17 @@ __global__ __launch_bounds__(T) void synth_kernel(Geom g, const double2* __restr
   constexpr int NP = (N / T + 1) < E ? (N / T + 1) : E;   // registers holding k <= N
   const int K = g.K, R = g.R, M = g.M;
   const int t = threadIdx.x;
-  const int m = xcd_index(M);
+  // split: blocks [0, B) take the Psi part of their m (fields 0..3), blocks
+  // [B, 2B) the theta part (fields 4, 5), B = 8 ceil(M / 8); the Psi parts
+  // (about 2/3 of the work) are dispatched first, and the short theta
+  // parts fill the last round.  Otherwise one block does both.
+  int part = 0, bid = blockIdx.x;
+  if (split) {
+    const int B = 8 * ((M + 7) >> 3);
+    part = bid < B ? 1 : 2;
+    if (bid >= B) bid -= B;
+  }
+  const int m = xcd_index_of(bid, M);
   if (m >= M || nf_stop(g.nf)) return;
   double2* pump = g.pump;
   {
@@ -199,9 +209,9 @@ __global__ __launch_bounds__(T) void synth_kernel(Geom g, const double2* __restr
   double ek = 0.0, et = 0.0, ens = 0.0, ez = 0.0;
 
   [[maybe_unused]] const double2* Pl = nullptr;   // MF: grid values of all six levels
-  if constexpr (MF) {
-    Pl = mf_synth_levels<T>(g, psi + (size_t)m * K, th + (size_t)m * K, sm, wred);
-  } else {
+  if constexpr (MF) Pl = mf_synth_levels<T>(g, psi + (size_t)m * K, th + (size_t)m * K, sm, wred);
+  if (part != 2) {   // Psi (or, at m = 0, the zonal flow): fields 0..3
+  if constexpr (!MF) {
     for (int nn = t; nn < K; nn += T) c[nn] = psi[(size_t)m * K + nn];
     __syncthreads();
   }
@@ -285,7 +295,9 @@ __global__ __launch_bounds__(T) void synth_kernel(Geom g, const double2* __restr
       }
     }
   }
+  }   // Psi part
   // theta, theta'
+  if (part != 1) {
   if constexpr (!MF) {
     __syncthreads();
     for (int nn = t; nn < K; nn += T) c[nn] = th[(size_t)m * K + nn];
@@ -318,24 +330,39 @@ __global__ __launch_bounds__(T) void synth_kernel(Geom g, const double2* __restr
       }
     }
   }
+  }   // theta part
+  // diagnostics of this block's part: slots 0, 1, 3 and the non-finite flag
+  // of Psi in 4 (Psi part), slot 2 and the flag of theta in 5 (theta part)
   if (diag) {
     const double pi = 3.14159265358979323846;
-    double bad = 0.0;
+    double bad = 0.0, badt = 0.0;
     for (int nn = t; nn < K; nn += T) {
-      const double2 a = psi[(size_t)m * K + nn], b = th[(size_t)m * K + nn];
-      if (!isfinite(a.x) || !isfinite(a.y) || !isfinite(b.x) || !isfinite(b.y)) bad = 1.0;
+      if (part != 2) {
+        const double2 a = psi[(size_t)m * K + nn];
+        if (!isfinite(a.x) || !isfinite(a.y)) bad = 1.0;
+      }
+      if (part != 1) {
+        const double2 b = th[(size_t)m * K + nn];
+        if (!isfinite(b.x) || !isfinite(b.y)) badt = 1.0;
+      }
     }
     const double s0 = block_sum(ek, red);
     const double s1 = block_sum(ez, red);
     const double s2 = block_sum(et, red);
     const double s3 = block_sum(ens, red);
     const double s4 = block_max(bad, red);
+    const double s5 = block_max(badt, red);
     if (t == 0) {
-      diag[m * 8 + 0] = pi * s0;
-      diag[m * 8 + 1] = pi * s1;
-      diag[m * 8 + 2] = pi * s2;
-      diag[m * 8 + 3] = 2.0 * pi * s3;
-      diag[m * 8 + 4] = s4;
+      if (part != 2) {
+        diag[m * 8 + 0] = pi * s0;
+        diag[m * 8 + 1] = pi * s1;
+        diag[m * 8 + 3] = 2.0 * pi * s3;
+        diag[m * 8 + 4] = s4;
+      }
+      if (part != 1) {
+        diag[m * 8 + 2] = pi * s2;
+        diag[m * 8 + 5] = s5;
+      }
     }
   }
 }
@@ -352,8 +379,7 @@ __global__ __launch_bounds__(T) void synth_kernel(Geom g, const double2* __restr
 // scaled by 1/N_phi and truncated to m <= N_m (N_omega can exceed N_theta by
 // many orders of magnitude, so the two never share one complex transform).
 // Zonal forcing: mean(u_s omega) = 2 sum_{m>=1} Re(u_s,m conj(omega_m)) with
-// u_s,m = (h^2/s) X0_m and omega_m = X3_m / (i m).  The two wall rings
-// store zero products and forcing (ring_index).  G (optional, FP64
+// u_s,m = (h^2/s) X0_m and omega_m = X3_m / (i m).  G (optional, FP64
 // single runs): the six grid fields g_f(phi_j) out, [6][R][N_phi], for the
 // reverse mode.
 template <int NPHI, int T, typename C>
@@ -370,28 +396,14 @@ __global__ __launch_bounds__(T) void ring_kernel(Geom g, const C* __restrict__ X
   constexpr int NH = NPHI / 2;
   const int R = g.R, M = g.M;
   const int t = threadIdx.x;
-  const int k = ring_index(R);
-  if (k < 0 || nf_stop(g.nf)) return;
+  const int k = xcd_index(R);
+  if (k >= R || nf_stop(g.nf)) return;
   {
     const size_t mem = blockIdx.y;
     X += mem * 6 * R * M;
     NL += mem * 2 * M * R;
     zonal += mem * R;
     if (rate) rate += mem * R;
-  }
-  // a wall: no advection (see ring_index).  Reverse-mode passes (G) still
-  // store the ring's grid fields, which the transposed products use.
-  const bool wall = (k == 0 || k == R - 1);
-  if (wall && !G) {
-    for (int m = t; m < M; m += T) {
-      NL[(size_t)m * R + k] = zc<C>();
-      NL[((size_t)M + m) * R + k] = zc<C>();
-    }
-    if (t == 0) {
-      zonal[k] = 0.0;
-      if (rate) rate[k] = 0.0;
-    }
-    return;
   }
   const double s = g.half * g.xk[k] + g.mid;
   const double h2s = (g.s_o * g.s_o - s * s) / s;
@@ -471,14 +483,14 @@ __global__ __launch_bounds__(T) void ring_kernel(Geom g, const C* __restrict__ X
       const C o = fftd::mk<C>((RT)0.5 * dd.y, (RT)-0.5 * dd.x);   // (Z_m - Z*)/(2i)
       C xm = fftd::add(e, fftd::mul(w, o));
       if (m == 0) xm.y = 0;
-      NL[((size_t)f * M + m) * R + k] = wall ? zc<C>() : fftd::scl(inv, xm);
+      NL[((size_t)f * M + m) * R + k] = fftd::scl(inv, xm);
     }
   }
   const double tot = block_sum(zs, red);
-  if (t == 0) zonal[k] = wall ? 0.0 : -2.0 * h2s * tot;
+  if (t == 0) zonal[k] = -2.0 * h2s * tot;
   if (rate) {
     const double rm = block_max(rmax, red);
-    if (t == 0) rate[k] = wall ? 0.0 : rm;
+    if (t == 0) rate[k] = rm;
   }
 }
 
@@ -495,13 +507,23 @@ __global__ __launch_bounds__(T) void analysis_kernel(Geom g, Bands b,
                                                      const double* __restrict__ zonal,
                                                      const double2* __restrict__ th_state,
                                                      double2* __restrict__ Epsi,
-                                                     double2* __restrict__ Eth) {
+                                                     double2* __restrict__ Eth, int split) {
   extern __shared__ double2 sm[];
   constexpr int N = N2 / 2;
   constexpr int E = out_count<N2, T>();
   const int K = g.K, R = g.R, M = g.M;
   const int t = threadIdx.x;
-  const int m = xcd_index(M);
+  // split: blocks [0, B) transform field 0 (E_psi, or E_u at m = 0) of
+  // their m, blocks [B, 2B) field 1 (E_theta), B = 8 ceil(M / 8): two equal
+  // halves, so that the last round of resident blocks is half as long.
+  // Otherwise one block does both.
+  int only = -1, bid = blockIdx.x;
+  if (split) {
+    const int B = 8 * ((M + 7) >> 3);
+    only = bid < B ? 0 : 1;
+    if (bid >= B) bid -= B;
+  }
+  const int m = xcd_index_of(bid, M);
   if (m >= M || nf_stop(g.nf)) return;
   const size_t mem = blockIdx.y;
   NL += mem * 2 * M * R;
@@ -540,6 +562,7 @@ __global__ __launch_bounds__(T) void analysis_kernel(Geom g, Bands b,
   }
 #pragma unroll
   for (int f = 0; f < 2; ++f) {
+    if (only >= 0 && f != only) continue;
     if constexpr (MF) {
       c = Cw + f * mf_k16(K);
     } else {
@@ -594,15 +617,15 @@ void synth_np(const Geom& g, const double2* psi, const double2* th, void* X, dou
       const size_t shm = sizeof(double2) * 6 * (mf_kp(g.K) + mf_rp(g.R));
       allow_lds(synth_kernel<N2, T, C, PUMP, true>, shm);
       hipLaunchKernelGGL((synth_kernel<N2, T, C, PUMP, true>), dim3(xcd_grid(g.M), g.nmem),
-                         dim3(T), shm, st, g, psi, th, static_cast<C*>(X), diag);
+                         dim3(T), shm, st, g, psi, th, static_cast<C*>(X), diag, 0);
       return;
     }
   }
   constexpr int T = threads_dct(N2);
   const size_t shm = dct_lds<C>(N2, g.K);
   allow_lds(synth_kernel<N2, T, C, PUMP>, shm);
-  hipLaunchKernelGGL((synth_kernel<N2, T, C, PUMP>), dim3(xcd_grid(g.M), g.nmem), dim3(T), shm, st,
-                     g, psi, th, static_cast<C*>(X), diag);
+  hipLaunchKernelGGL((synth_kernel<N2, T, C, PUMP>), dim3(2 * xcd_grid(g.M), g.nmem), dim3(T), shm,
+                     st, g, psi, th, static_cast<C*>(X), diag, 1);
 }
 
 // The pumping terms are a separate instantiation: without them the kernel
@@ -622,7 +645,7 @@ void ring_n(const Geom& g, const void* X, void* NL, double* zonal, double* rate,
   constexpr int T = threads_phi(NPHI);
   const size_t shm = phi_lds<C>(NPHI);
   allow_lds(ring_kernel<NPHI, T, C>, shm);
-  hipLaunchKernelGGL((ring_kernel<NPHI, T, C>), dim3(ring_grid(g.R), g.nmem), dim3(T), shm, st, g,
+  hipLaunchKernelGGL((ring_kernel<NPHI, T, C>), dim3(xcd_grid(g.R), g.nmem), dim3(T), shm, st, g,
                      static_cast<const C*>(X), static_cast<C*>(NL), zonal, rate, G);
 }
 
@@ -635,15 +658,15 @@ void analysis_n(const Geom& g, const Bands& b, const void* NL, const double* zon
       const size_t shm = sizeof(double2) * 2 * (mf_r4(g.R) + mf_k16(g.K));
       allow_lds(analysis_kernel<N2, T, C, true>, shm);
       hipLaunchKernelGGL((analysis_kernel<N2, T, C, true>), dim3(xcd_grid(g.M), g.nmem),
-                         dim3(T), shm, st, g, b, static_cast<const C*>(NL), zonal, th, Ep, Et);
+                         dim3(T), shm, st, g, b, static_cast<const C*>(NL), zonal, th, Ep, Et, 0);
       return;
     }
   }
   constexpr int T = threads_dct(N2);
   const size_t shm = dct_lds<C>(N2, g.K);
   allow_lds(analysis_kernel<N2, T, C>, shm);
-  hipLaunchKernelGGL((analysis_kernel<N2, T, C>), dim3(xcd_grid(g.M), g.nmem), dim3(T), shm, st, g, b,
-                     static_cast<const C*>(NL), zonal, th, Ep, Et);
+  hipLaunchKernelGGL((analysis_kernel<N2, T, C>), dim3(2 * xcd_grid(g.M), g.nmem), dim3(T), shm, st,
+                     g, b, static_cast<const C*>(NL), zonal, th, Ep, Et, 1);
 }
 
 // Compiled lengths: 2 (N_r - 1) = 2^a or 3 * 2^a (the paper's radial
