@@ -300,10 +300,18 @@ struct Solver4 {
     double2 prev = z2();
     for (int k0 = 0; k0 < K; k0 += U * SB) {
       double2 x[U];
+      double gm[U][P == 4 ? 5 : 1];   // gamma_i^{k-i} of this lane's rows, loaded up front
 #pragma unroll
       for (int u = 0; u < U; ++u) {
         const int k = k0 + u * SB + lane;
         x[u] = (k < n) ? hg[min(k, n - 1)] : z2();
+        if constexpr (P == 4) {
+#pragma unroll
+          for (int i = 0; i < 5; ++i) {
+            const int j = k - i;
+            gm[u][i] = (j >= 0 && j < n) ? F.gam[(size_t)j * 5 + i] : 0.0;
+          }
+        }
       }
 #pragma unroll
       for (int u = 0; u < U; ++u) {
@@ -320,10 +328,8 @@ struct Solver4 {
 #pragma unroll
           for (int i = 0; i < 5; ++i) {
             const double2 xi = i ? nb_row(i) : x[u];
-            const int j = k - i;
-            const double gm = (j >= 0 && j < n) ? F.gam[(size_t)j * 5 + i] : 0.0;
-            v.x = fma(gm, xi.x, v.x);
-            v.y = fma(gm, xi.y, v.y);
+            v.x = fma(gm[u][i], xi.x, v.x);
+            v.y = fma(gm[u][i], xi.y, v.y);
           }
         } else {                  // Dirichlet: y_k = x~_{k-2} - x~_k
           const double2 x2 = nb_row(2);
