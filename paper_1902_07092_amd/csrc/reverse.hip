@@ -113,13 +113,21 @@ __global__ __launch_bounds__(T) void analysis_T_kernel(Geom g, Bands b,
                                                        double2* __restrict__ NLb,
                                                        double* __restrict__ zb,
                                                        double2* __restrict__ thb,
-                                                       double2* __restrict__ ml) {
+                                                       double2* __restrict__ ml, int split) {
   extern __shared__ double2 sm[];
   constexpr int N = N2 / 2;
   constexpr int E = out_count<N2, T>();
   const int K = g.K, R = g.R, M = g.M;
   const int t = threadIdx.x;
-  const int m = xcd_index(M);
+  // split: blocks [0, B) take field 0 of their m, blocks [B, 2B) field 1
+  // (B = 8 ceil(M / 8)); otherwise one block takes both
+  int only = -1, bid = blockIdx.x;
+  if (split) {
+    const int B = 8 * ((M + 7) >> 3);
+    only = bid < B ? 0 : 1;
+    if (bid >= B) bid -= B;
+  }
+  const int m = xcd_index_of(bid, M);
   if (m >= M || nf_stop(g.nf)) return;
   double2* fb = sm;
   double2* c = reinterpret_cast<double2*>(reinterpret_cast<char*>(sm) +
@@ -133,6 +141,7 @@ __global__ __launch_bounds__(T) void analysis_T_kernel(Geom g, Bands b,
   const double bcoef = g.Ra_Pr * dm / g.s_o;
 #pragma unroll 1
   for (int f = 0; f < 2; ++f) {
+    if (only >= 0 && f != only) continue;
     // co-state of E: ca Ea + cb Eb2 (Eb2 optional; Ea null: zero)
     const size_t off = (size_t)f * mk + (size_t)m * K;
     for (int k = t; k < K; k += T) {
@@ -376,14 +385,22 @@ __global__ __launch_bounds__(T) void synth_T_kernel(Geom g, const double2* __res
                                                     const double2* __restrict__ thb0,
                                                     const double2* __restrict__ add,
                                                     size_t mk, double2* __restrict__ psib,
-                                                    double2* __restrict__ thb) {
+                                                    double2* __restrict__ thb, int split) {
   extern __shared__ double2 sm[];
   __shared__ double2 wred[2 * (T / 64)];
   constexpr int N = N2 / 2;
   constexpr int E = out_count<N2, T>();
   const int K = g.K, R = g.R, M = g.M;
   const int t = threadIdx.x;
-  const int m = xcd_index(M);
+  // split: blocks [0, B) take Psi (or the zonal flow) of their m, blocks
+  // [B, 2B) theta (B = 8 ceil(M / 8)); otherwise one block takes both
+  int only = -1, bid = blockIdx.x;
+  if (split) {
+    const int B = 8 * ((M + 7) >> 3);
+    only = bid < B ? 0 : 1;
+    if (bid >= B) bid -= B;
+  }
+  const int m = xcd_index_of(bid, M);
   if (m >= M || nf_stop(g.nf)) return;
   double2* fb = sm;
   double2* acc = reinterpret_cast<double2*>(reinterpret_cast<char*>(sm) +
@@ -421,6 +438,7 @@ __global__ __launch_bounds__(T) void synth_T_kernel(Geom g, const double2* __res
   };
 #pragma unroll 1
   for (int fld = 0; fld < 2; ++fld) {
+    if (only >= 0 && fld != only) continue;
     const int nd = fld == 1 ? 2 : (m > 0 ? 4 : 3);
 #pragma unroll 1
     for (int d = nd - 1; d >= 0; --d) {
@@ -509,8 +527,8 @@ void analysis_T_n(const Geom& g, const Bands& b, const double2* Ea, const double
   constexpr int T = threads_rdct(N2);
   const size_t shm = dct_lds<double2>(N2, g.K);
   allow_lds(analysis_T_kernel<N2, T>, shm);
-  hipLaunchKernelGGL((analysis_T_kernel<N2, T>), dim3(xcd_grid(g.M)), dim3(T), shm, st, g, b,
-                     Ea, Eb, ca, cb, mu, cmu, mk, NLb, zb, thb, ml);
+  hipLaunchKernelGGL((analysis_T_kernel<N2, T>), dim3(2 * xcd_grid(g.M)), dim3(T), shm, st, g, b,
+                     Ea, Eb, ca, cb, mu, cmu, mk, NLb, zb, thb, ml, 1);
 }
 
 template <int NPHI>
@@ -529,8 +547,8 @@ void synth_T_n(const Geom& g, const double2* Xb, const double2* thb0, const doub
   constexpr int T = threads_rdct(N2);
   const size_t shm = dct_lds<double2>(N2, g.K);
   allow_lds(synth_T_kernel<N2, T>, shm);
-  hipLaunchKernelGGL((synth_T_kernel<N2, T>), dim3(xcd_grid(g.M)), dim3(T), shm, st, g, Xb,
-                     thb0, add, mk, psib, thb);
+  hipLaunchKernelGGL((synth_T_kernel<N2, T>), dim3(2 * xcd_grid(g.M)), dim3(T), shm, st, g, Xb,
+                     thb0, add, mk, psib, thb, 1);
 }
 
 #define QG_RDCT(X) X(32) X(48) X(64) X(96) X(128) X(192) X(256) X(384) X(512) X(768) \
