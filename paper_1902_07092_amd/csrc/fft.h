@@ -9,8 +9,9 @@
 // and writes y[(j / Ns) Ns R + (j mod Ns) + r Ns].  The first pass takes
 // its inputs from a caller functor (global memory or another LDS array),
 // and the last pass can leave its outputs in registers: thread t then owns
-// the outputs k = t + i T, i < n / T.  LDS indices are padded by one slot
-// per eight to spread the strided writes over the banks.
+// the outputs k = t + i T, i < n / T.  LDS slots are permuted within each
+// aligned group of eight (lds_pad) so that both the contiguous reads and
+// the strided first-pass writes spread over the banks.
 //
 // Twiddle tables: pass s (Ns = product of the radices before it) reads
 // tw[(Ns - 1) + (r - 1) Ns + k] = exp(-2 pi i k r / (Ns R)), k < Ns,
@@ -60,10 +61,19 @@ constexpr bool plan_valid(int n) {
   return p.np > 0 && plan_ns(p, p.np) == n;
 }
 
-constexpr int LDS_PAD_SHIFT = 3;
-__host__ __device__ constexpr int lds_pad(int i) { return i + (i >> LDS_PAD_SHIFT); }
-// LDS elements of `count` padded transforms of length n laid end to end
-__host__ __device__ constexpr int lds_slots(int n, int count = 1) { return lds_pad(n * count) + 1; }
+// LDS slot of transform element i.  gfx950 serves a 16-byte LDS read in
+// phases of 16 lanes and a 16-byte write in phases of 8 lanes; a phase is
+// free of bank conflicts when its slots differ modulo 16 (reads) or 8
+// (writes).  The low three bits of i are XORed with a function of bits 3..6
+// that is one-to-one both in bits 3..5 and in bits 4..6: contiguous runs
+// stay a permutation of their aligned groups (reads and the writes of
+// passes with Ns >= 8), and the first pass's writes at stride 8 (radix 8)
+// or 16 (radix 16) land on eight different slots modulo 8.  A padding of
+// one slot per eight, used before, cost a two-way conflict on every
+// contiguous read.
+__host__ __device__ constexpr int lds_pad(int i) { return i ^ (((i >> 3) ^ (i >> 4)) & 7); }
+// LDS elements of `count` transforms of length n laid end to end
+__host__ __device__ constexpr int lds_slots(int n, int count = 1) { return (n * count + 7) & ~7; }
 
 #ifdef __HIPCC__
 namespace fftd {
