@@ -21,6 +21,19 @@ constexpr int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi 
 constexpr int threads_dct(int n2) { return clampi(n2 / 8, 64, 256); }
 constexpr int threads_phi(int nphi) { return clampi(nphi / 12, 64, 256); }
 
+// Waves per SIMD asked of the register allocator for a kernel of T-thread
+// blocks that hold `lds` bytes of LDS each: as many as the CU's 160 KiB of
+// LDS lets run at once, at most 3.  Fewer registers than the allocator
+// would pick unconstrained cost a few spills, and the third wave per SIMD
+// hides more of the latency of the barriers and memory accesses between
+// the transform passes (3072 x 1025: synthesis 96 -> 86 us, ring 111 ->
+// 98 us, bit for bit the same results).  Where one block fills the LDS the
+// allocator stays unconstrained.
+constexpr int lds_waves(size_t lds, int T) {
+  const int blocks = (int)((160 * 1024) / lds);
+  return clampi(blocks * (T / 64) / 4, 1, 3);
+}
+
 // Block -> m: XCD x = block mod 8 takes the contiguous range [x per, (x+1) per).
 __device__ __forceinline__ int xcd_index_of(int b, int count) {
   const int per = (count + 7) >> 3;

@@ -134,6 +134,23 @@ __device__ void mf_analysis_gemm(const Geom& g, const double2* Fl, double2* Cw) 
   __syncthreads();
 }
 
+// Waves per SIMD for the register allocator (lds_waves): the synthesis
+// holds one transform buffer and the coefficients (K <= N2 / 3 + 1), the
+// ring one transform buffer.  Only the FP64 kernels of 256-thread blocks
+// are constrained: with the 64-thread blocks of the ensemble sizes the
+// spills cost more than the extra wave gives (64 runs of N_r = 65 .. 257:
+// 0.759 -> 0.794 ms per step), and the FP32 kernels fit unconstrained.
+template <int N2, int T, typename C>
+constexpr int synth_waves() {
+  if (T < 256 || sizeof(C) != sizeof(double2)) return 1;
+  return lds_waves(coef_offset<C>(lds_slots(N2)) + sizeof(double2) * (N2 / 3 + 1) + 256, T);
+}
+template <int NPHI, int T, typename C>
+constexpr int ring_waves() {
+  if (T < 256 || sizeof(C) != sizeof(double2)) return 1;
+  return lds_waves(sizeof(C) * lds_slots(NPHI) + 256, T);
+}
+
 // -------------------------------------------------------------- synth
 // Fields (Fourier coefficient m at s_k), written X[f][k][m]:
 //   0: dPsi/dphi = i m Psi          1: v = u_phi / s
@@ -145,7 +162,7 @@ __device__ void mf_analysis_gemm(const Geom& g, const double2* Fl, double2* Cw) 
 // e_n = e_{2N-n} = a_n / 2 (eq. cheb).  Thread t owns the radial points
 // k = t + i T, and the fields are accumulated derivative by derivative.
 template <int N2, int T, typename C, bool PUMP, bool MF = false>
-__global__ __launch_bounds__(T) void synth_kernel(Geom g, const double2* __restrict__ psi,
+__global__ __launch_bounds__(T, (synth_waves<N2, T, C>())) void synth_kernel(Geom g, const double2* __restrict__ psi,
                                                   const double2* __restrict__ th,
                                                   C* __restrict__ X,
                                                   double* __restrict__ diag, int split) {
@@ -383,7 +400,7 @@ __global__ __launch_bounds__(T) void synth_kernel(Geom g, const double2* __restr
 // single runs): the six grid fields g_f(phi_j) out, [6][R][N_phi], for the
 // reverse mode.
 template <int NPHI, int T, typename C>
-__global__ __launch_bounds__(T) void ring_kernel(Geom g, const C* __restrict__ X,
+__global__ __launch_bounds__(T, (ring_waves<NPHI, T, C>())) void ring_kernel(Geom g, const C* __restrict__ X,
                                                  C* __restrict__ NL,
                                                  double* __restrict__ zonal,
                                                  double* __restrict__ rate,
