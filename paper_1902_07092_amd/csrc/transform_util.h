@@ -187,6 +187,12 @@ template <typename C>
 size_t dct_lds(int n2, int K) { return coef_offset<C>(lds_slots(n2)) + sizeof(double2) * K; }
 template <typename C>
 size_t phi_lds(int nphi) { return sizeof(C) * lds_slots(nphi); }
+// The analysis writes its coefficients over the transform buffer.
+template <typename C>
+size_t analysis_lds(int n2, int K) {
+  const size_t a = sizeof(C) * lds_slots(n2), b = sizeof(double2) * K;
+  return a > b ? a : b;
+}
 
 }  // namespace
 }  // namespace qg

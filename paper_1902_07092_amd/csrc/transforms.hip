@@ -550,7 +550,9 @@ __global__ __launch_bounds__(T) void analysis_kernel(Geom g, Bands b,
   Epsi += mem * M * K;
   Eth += mem * M * K;
   C* fb = reinterpret_cast<C*>(sm);
-  double2* c = reinterpret_cast<double2*>(reinterpret_cast<char*>(sm) + coef_offset<C>(lds_slots(N2)));
+  // the coefficients take the transform buffer's place once the transform
+  // is done (analysis_lds: the larger of the two, not their sum)
+  double2* c = sm;
   const double invN = 1.0 / N;
   const double2* thm = th_state + (size_t)m * K;
   const double ra_pr = g.ra_pr ? g.ra_pr[mem] : g.Ra_Pr;
@@ -586,6 +588,7 @@ __global__ __launch_bounds__(T) void analysis_kernel(Geom g, Bands b,
       auto get = [&](int i) -> C { return field(f, (i <= N) ? i : N2 - i); };
       C o[E];
       fft_out<N2, T, -1>(get, fb, Tw<C>::dct(g), o);
+      __syncthreads();   // every read of fb is done before c overwrites it
 #pragma unroll
       for (int i = 0; i < E; ++i) {
         const int nn = t + i * T;
@@ -680,7 +683,7 @@ void analysis_n(const Geom& g, const Bands& b, const void* NL, const double* zon
     }
   }
   constexpr int T = threads_dct(N2);
-  const size_t shm = dct_lds<C>(N2, g.K);
+  const size_t shm = analysis_lds<C>(N2, g.K);
   allow_lds(analysis_kernel<N2, T, C>, shm);
   hipLaunchKernelGGL((analysis_kernel<N2, T, C>), dim3(2 * xcd_grid(g.M), g.nmem), dim3(T), shm, st,
                      g, b, static_cast<const C*>(NL), zonal, th, Ep, Et, 1);
