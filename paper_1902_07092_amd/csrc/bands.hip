@@ -229,6 +229,38 @@ void launch_rhs(const Geom& g, const Bands& b, const RhsSpec& rs, double2* rhs, 
   launch_band(g, b, rs, 1.0, rhs, nullptr, 1, mch, st);
 }
 
+// rhs += sum_q coef_q term_q on the rows k >= p of every system (system
+// layout of the band products' sys_out), with the same operations in the
+// same order as band_kernel's term loop: a band product stored by
+// band_kernel with no terms and completed here equals band_kernel with
+// the terms, bit for bit.  blockIdx.y: system row (Psi m -> m - 1, zonal
+// flow -> M - 1, theta m -> M + m), blockIdx.z: run.
+__global__ __launch_bounds__(256) void rhs_terms_kernel(Geom g, RhsSpec rs,
+                                                        double2* __restrict__ rhs) {
+  const int K = g.K, M = g.M;
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  const int r = blockIdx.y;
+  if (k >= K || nf_stop(g.nf)) return;
+  const size_t moff = (size_t)blockIdx.z * M * K;
+  const bool psi_row = r < M - 1, zonal = r == M - 1;
+  if (k < (psi_row ? 4 : 2)) return;
+  const int m = psi_row ? r + 1 : (zonal ? 0 : r - M);
+  const size_t src = moff + (size_t)m * K + k;
+  double2* o = rhs + 2 * moff + (size_t)r * K + k;
+  double2 acc = *o;
+  for (int q = 0; q < rs.nterm; ++q) {
+    const double2 v = (r < M ? rs.term_psi[q] : rs.term_th[q])[src];
+    acc.x += rs.coef[q] * v.x;
+    acc.y += rs.coef[q] * v.y;
+  }
+  *o = acc;
+}
+
+void launch_rhs_terms(const Geom& g, const RhsSpec& rs, double2* rhs, hipStream_t st) {
+  const dim3 grid((g.K + 255) / 256, 2 * g.M, g.nmem);
+  hipLaunchKernelGGL(rhs_terms_kernel, grid, dim3(256), 0, st, g, rs, rhs);
+}
+
 void launch_lin(const Geom& g, const Bands& b, const double2* ypsi, const double2* yth,
                 double2* lpsi, double2* lth, int mch, hipStream_t st) {
   RhsSpec rs{};
