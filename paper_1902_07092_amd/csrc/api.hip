@@ -798,6 +798,32 @@ struct SideStreamRelease {
   }
 };
 
+// The band product of a CNAB2 right-hand side, (A + (dt/2) L) y^n with no
+// explicit term, into rhs on the second stream once the context's stream
+// has reached this point (y^n written).
+qg_status fork_band(qg_ctx* ctx, const double2* psi, const double2* th, double dt,
+                    double2* rhs) {
+  RhsSpec band{};
+  band.base_psi = psi;
+  band.base_th = th;
+  band.cL = 0.5 * dt;
+  band.nterm = 0;
+  HIPCHK(hipEventRecord(ctx->ev_fork, ctx->st));
+  HIPCHK(hipStreamWaitEvent(ctx->st2, ctx->ev_fork, 0));
+  launch_rhs(ctx->g, ctx->b, band, rhs, ctx->band_mch, ctx->st2);
+  HIPCHK(hipEventRecord(ctx->ev_join, ctx->st2));
+  return QG_OK;
+}
+
+// The context's stream waits for the band product and adds the explicit
+// terms of rs to it (the band kernel's term loop: the one-stream result
+// bit for bit).
+qg_status join_terms(qg_ctx* ctx, const RhsSpec& rs, double2* rhs) {
+  HIPCHK(hipStreamWaitEvent(ctx->st, ctx->ev_join, 0));
+  launch_rhs_terms(ctx->g, rs, rhs, ctx->st);
+  return QG_OK;
+}
+
 qg_status step_cnab2(qg_ctx* ctx, double dt) {
   const int cur = ctx->cur, prev = 1 - cur;
   double2 *Ep = ctx->slot(ctx->w.eslot, cur, 0), *Et = ctx->slot(ctx->w.eslot, cur, 1);
@@ -806,15 +832,8 @@ qg_status step_cnab2(qg_ctx* ctx, double dt) {
   const bool ovl = overlap_rhs(ctx);
   double2* rhs = ctx->ptr2(ctx->w.rhs);
   if (ovl) {
-    RhsSpec band{};
-    band.base_psi = ctx->psi();
-    band.base_th = ctx->th();
-    band.cL = 0.5 * dt;
-    band.nterm = 0;
-    HIPCHK(hipEventRecord(ctx->ev_fork, ctx->st));
-    HIPCHK(hipStreamWaitEvent(ctx->st2, ctx->ev_fork, 0));
-    launch_rhs(ctx->g, ctx->b, band, rhs, ctx->band_mch, ctx->st2);
-    HIPCHK(hipEventRecord(ctx->ev_join, ctx->st2));
+    const qg_status f = fork_band(ctx, ctx->psi(), ctx->th(), dt, rhs);
+    if (f != QG_OK) return f;
   }
   qg_status s = explicit_terms(ctx, ctx->psi(), ctx->th(), Ep, Et);
   if (s != QG_OK) {
@@ -835,8 +854,8 @@ qg_status step_cnab2(qg_ctx* ctx, double dt) {
   rs.out_psi = ctx->nxt_psi();
   rs.out_th = ctx->nxt_th();
   if (ovl) {
-    HIPCHK(hipStreamWaitEvent(ctx->st, ctx->ev_join, 0));
-    launch_rhs_terms(ctx->g, rs, rhs, ctx->st);
+    s = join_terms(ctx, rs, rhs);
+    if (s != QG_OK) return s;
   }
   s = implicit_solve(ctx, rs, rhs, ovl);
   if (s != QG_OK) return s;
@@ -1920,10 +1939,22 @@ struct Scratch {   // exchange arrays and right-hand side of a step (null: the w
   double2* rhs = nullptr;
 };
 
+// overlap: the band product on the second stream, as in step_cnab2 (the
+// same trajectory bit for bit).
 qg_status cnab2_into(qg_ctx* ctx, double dt, Pair y, Pair En, const Pair* Ep, Pair out,
-                     double* diag, double2* X, double* G, const Scratch& sc = Scratch{}) {
+                     double* diag, double2* X, double* G, const Scratch& sc = Scratch{},
+                     bool overlap = false) {
+  double2* rhs = sc.rhs ? sc.rhs : ctx->ptr2(ctx->w.rhs);
+  const bool ovl = overlap && overlap_rhs(ctx);
+  if (ovl) {
+    const qg_status f = fork_band(ctx, y.p, y.t, dt, rhs);
+    if (f != QG_OK) return f;
+  }
   qg_status s = explicit_terms(ctx, y.p, y.t, En.p, En.t, diag, X, G, sc.NL, sc.zonal);
-  if (s != QG_OK) return s;
+  if (s != QG_OK) {
+    if (ovl) (void)hipStreamWaitEvent(ctx->st, ctx->ev_join, 0);
+    return s;
+  }
   RhsSpec rs{};
   rs.base_psi = y.p;
   rs.base_th = y.t;
@@ -1937,7 +1968,11 @@ qg_status cnab2_into(qg_ctx* ctx, double dt, Pair y, Pair En, const Pair* Ep, Pa
   rs.coef[1] = -0.5 * dt;
   rs.out_psi = out.p;
   rs.out_th = out.t;
-  return implicit_solve(ctx, rs, sc.rhs);
+  if (ovl) {
+    s = join_terms(ctx, rs, rhs);
+    if (s != QG_OK) return s;
+  }
+  return implicit_solve(ctx, rs, rhs, ovl);
 }
 
 // A second stream and the events of the overlapped reverse sweep, released
@@ -1979,6 +2014,7 @@ qg_status explicit_T(qg_ctx* ctx, const double2* X, const double* G, const doubl
 qg_status gradient_run(qg_ctx* ctx, double dt, int N, int C, double ew, const double* adj_psi,
                        const double* adj_th, const double* adj_u, double* g_psi, double* g_th,
                        double* g_u, double* J, char* base, const GradMap& w) {
+  SideStreamRelease release{ctx};
   const size_t mk = ctx->mk();
   const int M = ctx->z.M, K = ctx->z.K;
   const bool grad = g_psi != nullptr;
@@ -2027,7 +2063,7 @@ qg_status gradient_run(qg_ctx* ctx, double dt, int N, int C, double ew, const do
     ctx->tag = n + 1;
     s = cnab2_into(ctx, dt, y, En, n > 0 ? &Ep : nullptr, Y(slot_of(n + 1)),
                    diag + (size_t)n * M * 8, n >= nl ? Xs(n - nl) : nullptr,
-                   n >= nl ? Gs(n - nl) : nullptr);
+                   n >= nl ? Gs(n - nl) : nullptr, Scratch{}, true);
     if (s != QG_OK) return s;
     if (n >= nl) has_g[0][n - nl] = 1;
   }
