@@ -223,7 +223,16 @@ qg_status qg_get_state(qg_ctx *ctx, double *psi, double *theta, double *uphi,
  * history, time and step count from before that step (steps before it in
  * the same call are kept), and qg_last_error names the step.  The steps
  * queued after it do nothing.  The call synchronises the stream once at
- * its end to read the flag. */
+ * its end to read the flag.
+ *
+ * Streams: a context of qg_create stepping CNAB2 puts the band product of
+ * each right-hand side on a second HIP stream that the call creates
+ * (default priority, non-blocking) and destroys before it returns; events
+ * order it after the context's stream and the rest of the step after it,
+ * so that the caller sees one stream.  The results equal the one-stream
+ * sequence bit for bit.  Ensemble groups, qg_create_static contexts,
+ * qg_step_timed and a stream under graph capture use the context's
+ * stream alone. */
 qg_status qg_step(qg_ctx *ctx, double dt, int scheme, int nsteps);
 
 /* Checkpoints of a single-run context: the state and the multistep history
