@@ -769,21 +769,31 @@ bool overlap_rhs(qg_ctx* ctx) {
   hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
   if (hipStreamIsCapturing(ctx->st, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone)
     return false;
+  if (ctx->st2 && ctx->ev_fork && ctx->ev_join) return true;
+  // the stream and events belong to the device of the context's stream,
+  // whichever device is current
+  int dev = 0, prev = 0;
+  if (hipStreamGetDevice(ctx->st, &dev) != hipSuccess || hipGetDevice(&prev) != hipSuccess ||
+      hipSetDevice(dev) != hipSuccess)
+    return false;
+  bool ok = true;
   if (!ctx->ev_fork &&
       hipEventCreateWithFlags(&ctx->ev_fork, hipEventDisableTiming) != hipSuccess) {
     ctx->ev_fork = nullptr;
-    return false;
+    ok = false;
   }
-  if (!ctx->ev_join &&
+  if (ok && !ctx->ev_join &&
       hipEventCreateWithFlags(&ctx->ev_join, hipEventDisableTiming) != hipSuccess) {
     ctx->ev_join = nullptr;
-    return false;
+    ok = false;
   }
-  if (!ctx->st2 && hipStreamCreateWithFlags(&ctx->st2, hipStreamNonBlocking) != hipSuccess) {
+  if (ok && !ctx->st2 &&
+      hipStreamCreateWithFlags(&ctx->st2, hipStreamNonBlocking) != hipSuccess) {
     ctx->st2 = nullptr;
-    return false;
+    ok = false;
   }
-  return true;
+  (void)hipSetDevice(prev);
+  return ok;
 }
 
 // Ends a stepping call: the second stream goes (its queued work still
