@@ -169,6 +169,30 @@ def test_two_stream_cnab2_equals_one_stream(qg, kw):
         assert np.array_equal(x, y)
 
 
+def test_two_stream_cnab2_on_a_caller_stream(qg):
+    """A context on a stream of the caller's (not the current one): the
+    second stream is ordered after it by events, and the state equals the
+    static-workspace context's (one stream) bit for bit."""
+    import torch
+    w = inputs.MEDIUM
+    st = inputs.workload_state(w)
+    user = torch.cuda.Stream()
+    a = qg.QGSolver(w.E, w.Ra, w.Pr, w.eta, w.n_phi, w.n_r, w.n_c, stream=user)
+    b = qg.QGSolver(w.E, w.Ra, w.Pr, w.eta, w.n_phi, w.n_r, w.n_c,
+                    static_workspace=True)
+    try:
+        for s in (a, b):
+            s.set_state(st.psi, st.theta, st.uphi0)
+        a.step(w.dt, "cnab2", 9)
+        b.step(w.dt, "cnab2", 9)
+        user.synchronize()
+        got = [a.get_state(), b.get_state()]
+    finally:
+        del b   # the static workspace is handed out once per device at a time
+    for x, y in zip(*got):
+        assert np.array_equal(x, y)
+
+
 @pytest.mark.parametrize("n_phi,n_r", [(48, 49), (384, 193)])
 def test_radial_sizes_three_times_power_of_two(qg, n_phi, n_r):
     """2 (N_r - 1) = 3 * 2^a: the radial transforms end with a radix-3
